@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Throughput of the splat hot path on one MI355X.
+
+Workload: one 640x480 keyframe of pixel-aligned Gaussians (307,200) rendered
+into one view perturbed by up to 2 cm / 1 degree (synthetic box room, seed
+10).  One step = one mapping iteration of that frame through the HIP library:
+forward splat, L1 loss and upstream gradients, adjoint (colour, opacity,
+radius, offset and pose gradients) and the Adam update.  Inputs are resident
+in HBM before the timed region.
+
+Prints ONE JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12                   # bytes/s, MI355X HBM3E
+FP32_VECTOR_PEAK = 157.3e12         # flop/s, MI355X published FP32 vector peak
+# algorithmic bytes of one fwd+bwd of one view (per Gaussian: 28 B read by the
+# forward, 28 B read by the backward, 24 B of gradients written; per pixel:
+# 24 B of outputs and saved state, 20 B of upstream gradients, 8 B re-read)
+BYTES_PER_GAUSSIAN = 80
+BYTES_PER_PIXEL = 52
+# algorithmic flops per contributing (pixel, Gaussian) pair, counted from the
+# definition of the compositing step and its adjoint
+FLOPS_PER_PAIR = {"composite_fwd": 26, "composite_bwd": 60}
+BYTES_BY_KERNEL = {  # algorithmic bytes per Gaussian / per pixel of each kernel
+    "composite_fwd": (28, 24), "composite_bwd": (52, 28), "preprocess": (16, 0),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline():
+    """The FP64 oracle (unmodified) on one host core: one full 640x480 fwd+bwd."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import splat
+    from paper_2603_21055_amd import synth
+    sc = synth.c2_scene(10)
+    rng = np.random.default_rng(0)
+    H, W = 480, 640
+    gr = [rng.normal(size=(3, H, W)) / (H * W)]
+    gd = [rng.normal(size=(H, W)) / (H * W)]
+    ga = [rng.normal(size=(H, W)) / (H * W)]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        f = splat.render_job(sc["kfs"], sc["views"][0], [0])
+        splat.render_backward(sc["kfs"], sc["views"], [(0, [0])], [f], gr, gd, ga)
+        dt = time.perf_counter() - t0
+    return dict(value=1.0 / dt, unit="frames/s", cores=1, kind="oracle",
+                sample=f"one full 640x480 frame fwd+bwd (C2 scene seed 10), {dt:.1f} s on 1 thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--tile", type=str, default="16x16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path (--gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2603_21055_amd import sgad, synth
+    log("building scene")
+    dev = torch.device("cuda", 0)
+    sc = synth.c2_scene(10)
+    H, W = 480, 640
+    N = P = H * W
+    ctx = sgad.Context(0)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    ctx.set_tile(tw, th)
+    kfs_d = [sgad.to_device(k, dev) for k in sc["kfs"]]
+    views = sc["views"]
+    jobs = [(0, [0])]
+    from paper_2603_21055_amd.mapping import Mapper
+    t_rgb = torch.from_numpy(sc["target"]["rgb"]).to(dev)[None].contiguous()
+    t_dep = torch.from_numpy(sc["target"]["depth"]).to(dev)[None].contiguous()
+    mapper = Mapper(ctx, kfs_d, views, jobs, [0], t_rgb, t_dep, with_count=True)
+    step = mapper.step
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.sync()
+    pairs = int(mapper.cnt.sum().item())
+    loss0 = mapper.loss_value()
+    log(f"timed {args.steps} steps")
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = ctx.timing_report()
+    ctx.timing(False)
+    ctx.sync()
+    ms = (t1 - t0) * 1e3 / args.steps
+    fps = 1e3 / ms
+    kern = {k: v[1] / v[0] for k, v in rep.items()}       # average ms per launch
+    log("kernel avg ms: " + ", ".join(f"{k}={v:.4f}" for k, v in sorted(kern.items(), key=lambda x: -x[1])))
+    dom = max(kern, key=kern.get)
+    t_dom = kern[dom] * 1e-3
+    if dom in FLOPS_PER_PAIR:
+        achieved = pairs * FLOPS_PER_PAIR[dom] / t_dom
+        roof = dict(bound="alu", achieved=achieved / 1e12, peak=FP32_VECTOR_PEAK / 1e12, unit="TFLOP/s",
+                    frac=achieved / FP32_VECTOR_PEAK, traffic=None, kernel=dom,
+                    kernel_ms=kern[dom], pairs_per_launch=pairs, flops_per_pair=FLOPS_PER_PAIR[dom])
+    else:
+        bg, bp = BYTES_BY_KERNEL.get(dom, (0, 0))
+        achieved = (bg * N + bp * P) / t_dom
+        roof = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=achieved / HBM_PEAK, traffic=None, kernel=dom, kernel_ms=kern[dom])
+    algo_bytes = BYTES_PER_GAUSSIAN * N + BYTES_PER_PIXEL * P
+    out = dict(
+        metric="fwd+bwd splat frames/s at 640x480 (%HBM roofline); mapping iters to loss, warm vs plain",
+        value=fps, unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms,
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="one 640x480 keyframe (307,200 pixel-aligned Gaussians) splatted into one "
+                             "view perturbed <=2 cm / 1 deg; step = forward, L1 loss, adjoint, Adam",
+                    frame=[W, H], gaussians=N, tile=[tw, th]),
+        hbm_frac=algo_bytes / (ms * 1e-3) / HBM_PEAK,
+        roofline=roof,
+        kernels_ms=kern,
+        loss_after_warmup=loss0, loss_final=mapper.loss_value(),
+    )
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, ~20 s)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,245 @@
+/*
+ * sgad.h - C ABI of the MI355X splatting library (libsgad.so).
+ *
+ * Differentiable splatting of pixel-aligned simplified Gaussians at adjusted
+ * depth (SGAD-SLAM, arXiv 2603.21055): the renderer of Sec. 3.2,
+ * (V'_k, D'_k) = splat(G_i, p_k) for views k in {i, NN(i)}, its adjoint for
+ * the learnable attributes of Sec. 3.1 (colour, radius, opacity, depth
+ * offset) and the view pose, the per-pixel depth-distribution Gauss-Newton
+ * tracker (abstract; Sec. 3.3), the L1 terms of Eq. 1, Adam, and a BF16
+ * 3x3 conv net that warm-starts the offsets.
+ *
+ * Conventions (fixed here because the paper does not give formulas):
+ *  - Pixel (u, v) is evaluated at the integer point (u, v); a keyframe pixel
+ *    back-projects along ((u-cx)/fx, (v-cy)/fy, 1) to z-depth |D + delta|.
+ *  - Poses are world->camera, X_c = R X_w + t, R row-major.
+ *  - The Gaussian covariance is r^2 I (r a world-space standard deviation);
+ *    screen covariance r^2 J J^T + 0.3 I; a pixel takes a Gaussian iff
+ *    q <= 9 and alpha = min(0.99, o exp(-q/2)) >= 1/255; contributors are
+ *    composited front to back by (depth rounded to float, gid) with
+ *    gid = kf_index * H * W + v * W + u, stopping before the transmittance
+ *    would drop below 1e-4; Gaussians with z < 0.2 are culled.
+ *  - Outputs: RGB = sum w c, depth D' = sum w z (not divided by alpha),
+ *    alpha = 1 - T.
+ *  - Pose gradients are with respect to a left twist xi = (rho, phi) on the
+ *    view's world->camera pose, T <- Exp(xi) T.
+ *
+ * Memory: every data pointer is a device pointer owned by the caller unless
+ * stated otherwise; planes are float32 row-major [H][W]; colour is planar
+ * [3][H][W].  The library owns only its internal workspace.
+ *
+ * Streams: calls enqueue on the given hipStream_t (passed as void*; NULL is
+ * the null stream) and return without waiting unless documented.
+ *
+ * Errors: every call returns an sgad_status; no exception crosses the ABI.
+ * Conditions found on the device (non-finite inputs, instance-list overflow)
+ * are latched in the context and returned by sgad_sync().
+ */
+#ifndef SGAD_H
+#define SGAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SGAD_OK = 0,
+    SGAD_EINVAL = 1, /* bad argument: sizes <= 0, null required pointer, non-finite pose */
+    SGAD_ERANGE = 2, /* a size above a documented limit, or the instance list overflowed */
+    SGAD_EHIP = 3,   /* a HIP runtime call failed (message in sgad_last_error) */
+    SGAD_ENOMEM = 4, /* device or pinned allocation failed */
+    SGAD_EDATA = 5   /* non-finite depth / offset / radius seen by a kernel */
+} sgad_status;
+
+typedef struct sgad_ctx sgad_ctx;
+typedef struct sgad_saved sgad_saved;
+
+/* Pinhole camera: image H x W, focal lengths and principal point in pixels. */
+typedef struct {
+    int32_t H, W;
+    float fx, fy, cx, cy;
+} sgad_cam;
+
+/* World->camera pose: X_c = R X_w + t, R row-major. */
+typedef struct {
+    float R[9];
+    float t[3];
+} sgad_pose;
+
+/* One keyframe's pixel-aligned Gaussians (Sec. 3.1-3.2): one per pixel. */
+typedef struct {
+    sgad_cam cam;
+    sgad_pose T_cw;
+    const float* depth;   /* observed depth D, [H][W] */
+    const float* offset;  /* learnable depth offset delta, [H][W] */
+    const float* radius;  /* world-space std r, [H][W] */
+    const float* opacity; /* o, [H][W] */
+    const float* rgb;     /* colour, [3][H][W]; may be NULL for tracking */
+    const float* sigma;   /* per-pixel depth std (tracking only), else NULL */
+} sgad_keyframe;
+
+/* A render job: keyframes (bit f = keyframe f, f < 64) splatted into view. */
+typedef struct {
+    int32_t view;
+    uint32_t kf_mask_lo, kf_mask_hi;
+} sgad_job;
+
+/* Per-keyframe gradient outputs, same layouts as the inputs; ACCUMULATED. */
+typedef struct {
+    float* d_rgb;     /* [3][H][W] */
+    float* d_opacity; /* [H][W] */
+    float* d_radius;  /* [H][W] */
+    float* d_offset;  /* [H][W]; equals the gradient w.r.t. depth */
+} sgad_kf_grads;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  *out receives ownership. */
+sgad_status sgad_create(int device, sgad_ctx** out);
+/* Destroy a context and free its workspace (waits for its device work). */
+void sgad_destroy(sgad_ctx* ctx);
+/* Message of the last failing call on this context (never NULL). */
+const char* sgad_last_error(const sgad_ctx* ctx);
+/* Wait for all work the context enqueued and return the first latched
+ * device-side condition (SGAD_EDATA, SGAD_ERANGE) since the previous call,
+ * clearing it. */
+sgad_status sgad_sync(sgad_ctx* ctx);
+/* Tile shape of the compositing kernels: (8,8), (16,8), (16,16) or (32,8);
+ * (0,0) lets the autotuner choose per workload.  Results do not depend on
+ * the tile shape. */
+sgad_status sgad_set_tile(sgad_ctx* ctx, int tile_w, int tile_h);
+/* Tile shape used by the last forward (after autotuning). */
+sgad_status sgad_get_tile(const sgad_ctx* ctx, int* tile_w, int* tile_h);
+
+/* Per-kernel timing (tracing): when enabled, every library kernel is
+ * bracketed by hipEvents recorded on its launch stream.  Enabling or
+ * disabling resets the accumulators. */
+sgad_status sgad_timing_enable(sgad_ctx* ctx, int enable);
+/* Waits for the recorded events and writes one line per kernel name,
+ * "<name> <launches> <total_ms>\n", into buf (capacity cap bytes, NUL
+ * terminated); SGAD_ERANGE if it does not fit. */
+sgad_status sgad_timing_report(sgad_ctx* ctx, char* buf, size_t cap);
+
+/* ---------------------------------------------------------------- render */
+
+/*
+ * Forward splat (Sec. 3.2): for each job j, the Gaussians of the keyframes
+ * in its mask are rendered into view jobs[j].view.
+ *   kf[n_kf]               keyframes; all share H x W (1 <= n_kf <= 64)
+ *   vcam[n_views], vpose[n_views]  views; all share H x W
+ *   out_rgb   [n_jobs][3][Hv][Wv]  written
+ *   out_depth [n_jobs][Hv][Wv]     written (unnormalised)
+ *   out_alpha [n_jobs][Hv][Wv]     written
+ *   out_count [n_jobs][Hv][Wv]     int32 contributor count, or NULL
+ *   *saved    receives a handle to the sorted instance lists and per-pixel
+ *             state needed by sgad_render_bwd; owned by the context until
+ *             sgad_saved_release.  Input arrays must stay alive and unchanged
+ *             until the backward has been enqueued.
+ */
+sgad_status sgad_render_fwd(sgad_ctx* ctx, int n_kf, const sgad_keyframe* kf,
+                            int n_views, const sgad_cam* vcam, const sgad_pose* vpose,
+                            int n_jobs, const sgad_job* jobs,
+                            float* out_rgb, float* out_depth, float* out_alpha,
+                            int32_t* out_count, sgad_saved** saved, void* stream);
+
+/*
+ * Adjoint of sgad_render_fwd (gradient of Eq. 1's rendered terms).
+ *   g_rgb [n_jobs][3][Hv][Wv], g_depth, g_alpha [n_jobs][Hv][Wv]: upstream
+ *     grads; g_depth / g_alpha may be NULL (treated as zero).
+ *   grads[n_kf]: per-keyframe outputs, ACCUMULATED (+=); only keyframes whose
+ *     bit is set in the learnable mask (lo | hi << 32) are written, the others
+ *     stay fixed (Sec. 3.2: neighbours are not learnable).
+ *   d_pose [n_jobs][6]: WRITTEN, (rho, phi) left-twist gradient of each job's
+ *     view pose; may be NULL.
+ */
+sgad_status sgad_render_bwd(sgad_ctx* ctx, sgad_saved* saved,
+                            const float* g_rgb, const float* g_depth, const float* g_alpha,
+                            const sgad_kf_grads* grads, float* d_pose,
+                            uint32_t learn_lo, uint32_t learn_hi, void* stream);
+
+/* Return a saved handle to the context. */
+sgad_status sgad_saved_release(sgad_ctx* ctx, sgad_saved* saved);
+
+/*
+ * Debug export of job `job`'s sorted instance list (waits for the stream).
+ * tile_ranges: host [n_tiles][2] (start, end) relative to the job; keys: host
+ * [cap] of (float bits of z << 32 | gid); *n_keys and *n_tiles are written.
+ */
+sgad_status sgad_saved_instances(sgad_ctx* ctx, const sgad_saved* saved, int job,
+                                 uint32_t* tile_ranges, uint64_t* keys, size_t cap,
+                                 size_t* n_keys, int* n_tiles);
+
+/* ---------------------------------------------------------------- tracking */
+
+#define SGAD_TRACK_GRAPH 1u /* capture the iteration loop in a hipGraph and replay it */
+
+/*
+ * Gauss-Newton tracking of a new frame against the previous frame's
+ * per-pixel depth distributions (abstract; Sec. 3.3).
+ *   geo: pixel-aligned geometry Gaussians (depth, offset, radius, opacity
+ *     and the per-pixel depth std `sigma` are required; rgb is ignored).
+ *   vcam: the new frame's camera; obs_depth [H][W]: its observed depth
+ *     (<= 0 marks a missing value).
+ *   pose: DEVICE double[12] (R row-major, t) world->camera pose of the new
+ *     frame; read as the starting point and overwritten with the result.
+ *   iters: fixed number of iterations (no early exit), 1..1000.
+ *   trace: DEVICE double[iters][40] or NULL; record k holds H (upper
+ *     triangle, 21), g (6), log-likelihood, valid-pixel count, the damping
+ *     used (-1 when no step was taken) and the step dxi (6).
+ * Per iteration: splat sigma^2 into the view (same rule as the renderer),
+ * per pixel mu = D'/A, s^2 = S/A, valid iff A >= 0.9 and D_obs > 0,
+ * r = (D_obs - mu)/s, J = dr/dxi with s fixed; H = sum J^T J, g = sum J^T r
+ * summed in FP64; dxi = -H^-1 g by Cholesky (damping 1e-9 tr(H), x10 per
+ * retry); pose <- Exp(dxi) pose.  With SGAD_TRACK_GRAPH the loop is captured
+ * once per (shapes, pointers, iters) and replayed.
+ */
+sgad_status sgad_track_gn(sgad_ctx* ctx, const sgad_keyframe* geo, const sgad_cam* vcam,
+                          const float* obs_depth, double* pose, int iters, double* trace,
+                          uint32_t flags, void* stream);
+
+/* ---------------------------------------------------------------- mapping */
+
+/*
+ * L1 terms of Eq. 1 for n_jobs rendered views:
+ *   L_j = w_rgb * mean|rgb - t_rgb| + w_depth * sum_U |depth - t_depth| / |U|,
+ *   U = [t_depth > 0] (valid-depth mask).  The supplement's weights are
+ *   w_rgb = 0.8, w_depth = 1.0; the SSIM term is not part of this call.
+ *   rgb, t_rgb, g_rgb [n_jobs][3][H][W]; depth, t_depth, g_depth [n_jobs][H][W]
+ *   g_rgb, g_depth: WRITTEN with dL/d(rgb), dL/d(depth) (subgradient 0 at 0).
+ *   loss: device double [n_jobs], WRITTEN.
+ */
+sgad_status sgad_l1_loss(sgad_ctx* ctx, int n_jobs, int H, int W,
+                         const float* rgb, const float* depth, const float* t_rgb, const float* t_depth,
+                         float w_rgb, float w_depth, float* g_rgb, float* g_depth, double* loss,
+                         void* stream);
+
+/* One parameter tensor for sgad_adam_step (all device pointers, n floats). */
+typedef struct {
+    float* param;
+    float* grad;
+    float* m;
+    float* v;
+    int64_t n;
+    float lr;
+    float lo, hi; /* the parameter is clamped to [lo, hi] after the step */
+} sgad_adam_group;
+
+/*
+ * Adam step (t = step >= 1) over up to 32 tensors in one launch:
+ *   m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ *   p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), then clamp.
+ * The grads are zeroed afterwards when zero_grad != 0 (the backward
+ * accumulates).  The supplement gives the learning rates (colour 0.0025,
+ * radius 0.005, opacity 0.05, offset 0.01); Adam itself is this library's
+ * reading of the unnamed optimiser.
+ */
+sgad_status sgad_adam_step(sgad_ctx* ctx, int n_groups, const sgad_adam_group* groups, int step,
+                           float beta1, float beta2, float eps, int zero_grad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGAD_H */

@@ -1,0 +1,311 @@
+// Preprocess (FP64, fixed operation order), tile counting, scan, scatter and
+// the per-tile depth sort of the instance lists.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sgad_internal.h"
+
+namespace sgad {
+
+// ---------------------------------------------------------------------------
+// Preprocess one (pair, Gaussian): back-project at |D + delta|, move into the
+// view, project, form the dilated screen covariance, its conic and the tile
+// rectangle; count the tiles.  Every FP64 operation is written in the order
+// the binning contract fixes and none is fused, so the tile rectangles and
+// depth keys are reproducible bit for bit by an independent FP64 evaluation.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)G.n_pairs * G.N;
+    if (i >= total) return;
+    const int pair = (int)(i / G.N);
+    const int pix = (int)(i - (int64_t)pair * G.N);
+    const PairConst& pc = B.pairs[pair];
+    const KfPtrs kp = B.kfs[pc.kf];
+    const int u = pix % G.Wk;
+    const int v = pix / G.Wk;
+    const float Df = kp.depth[pix];
+    const float Of = kp.offset[pix];
+    const float Rf = kp.radius[pix];
+    bool ok = isfinite(Df) && isfinite(Of) && isfinite(Rf);
+    if (!ok) {
+        atomicOr(&B.status->nonfinite, 1u);
+        atomicOr(&B.status->sticky, 2u);
+    }
+
+    const double s = (double)Df + (double)Of;
+    const double d = fabs(s);
+    const double xn = ((double)u - pc.kcx) / pc.kfx;
+    const double yn = ((double)v - pc.kcy) / pc.kfy;
+    const double X0 = d * xn, X1 = d * yn, X2 = d;
+    const double* R = pc.R;
+    const double x = ((R[0] * X0 + R[1] * X1) + R[2] * X2) + pc.t[0];
+    const double y = ((R[3] * X0 + R[4] * X1) + R[5] * X2) + pc.t[1];
+    const double z = ((R[6] * X0 + R[7] * X1) + R[8] * X2) + pc.t[2];
+    ok = ok && (z >= kZNear);
+
+    uint32_t rx = 0, ry = 0;
+    float fdx = 0.f, fdy = 0.f, fa = 0.f, fb = 0.f, fc = 0.f;
+    if (ok) {
+        const double tx = x / z;
+        const double ty = y / z;
+        const double mx = pc.vfx * tx + pc.vcx;
+        const double my = pc.vfy * ty + pc.vcy;
+        const double jx = pc.vfx / z;
+        const double jy = pc.vfy / z;
+        const double k00 = (jx * jx) * (1.0 + tx * tx);
+        const double k01 = (jx * jy) * (tx * ty);
+        const double k11 = (jy * jy) * (1.0 + ty * ty);
+        const double r2 = (double)Rf * (double)Rf;
+        const double s00 = r2 * k00 + kLowpass;
+        const double s01 = r2 * k01;
+        const double s11 = r2 * k11 + kLowpass;
+        const double det = s00 * s11 - s01 * s01;
+        const double ca = s11 / det;
+        const double cb = -s01 / det;
+        const double cc = s00 / det;
+        const double hd = 0.5 * (s00 - s11);
+        const double lam = 0.5 * (s00 + s11) + sqrt(hd * hd + s01 * s01);
+        const double rho = ceil(3.0 * sqrt(lam));
+        double ax0 = floor((mx - rho) / (double)G.TW);
+        double ax1 = floor((mx + rho) / (double)G.TW) + 1.0;
+        double ay0 = floor((my - rho) / (double)G.TH);
+        double ay1 = floor((my + rho) / (double)G.TH) + 1.0;
+        ax0 = fmax(ax0, 0.0);
+        ay0 = fmax(ay0, 0.0);
+        ax1 = fmin(ax1, (double)G.ntx);
+        ay1 = fmin(ay1, (double)G.nty);
+        int x0 = (int)fmin(ax0, (double)G.ntx), x1 = (int)fmax(ax1, 0.0);
+        int y0 = (int)fmin(ay0, (double)G.nty), y1 = (int)fmax(ay1, 0.0);
+        if (x1 < x0) x1 = x0;
+        if (y1 < y0) y1 = y0;
+        rx = (uint32_t)x0 | ((uint32_t)x1 << 16);
+        ry = (uint32_t)y0 | ((uint32_t)y1 << 16);
+        fdx = (float)(mx - (double)u);
+        fdy = (float)(my - (double)v);
+        fa = (float)ca;
+        fb = (float)cb;
+        fc = (float)cc;
+        uint32_t* cnt = B.tile_count + (size_t)pc.job * G.ntiles;
+        for (int ty = y0; ty < y1; ++ty)
+            for (int tx = x0; tx < x1; ++tx) atomicAdd(&cnt[ty * G.ntx + tx], 1u);
+    }
+    B.pre.dx[i] = fdx;
+    B.pre.dy[i] = fdy;
+    B.pre.ca[i] = fa;
+    B.pre.cb[i] = fb;
+    B.pre.cc[i] = fc;
+    B.pre.z[i] = ok ? (float)z : 0.f;
+    B.pre.rx[i] = rx;
+    B.pre.ry[i] = ry;
+}
+
+// Zero an array with a kernel (no memset nodes, so the launch is graph-safe).
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+__global__ void k_zero_f32(float* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of the per-(job, tile) counts in one 1024-thread block; also
+// publishes the total, the overflow flag, and clears the fill counters and the
+// work-queue counter.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ count, uint32_t* start,
+                                               uint32_t* fill, int M, uint32_t capacity,
+                                               DevStatus* st) {
+    __shared__ uint32_t s_wave[16];
+    const int tid = threadIdx.x;
+    const int chunk = (M + 1023) / 1024;
+    const int b = tid * chunk;
+    const int e = min(M, b + chunk);
+    uint32_t sum = 0;
+    for (int k = b; k < e; ++k) sum += count[k];
+    // inclusive scan across the wave
+    const int lane = tid & 63, wave = tid >> 6;
+    uint32_t inc = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t w = lane < 16 ? s_wave[lane] : 0u;
+        uint32_t wi = w;
+        for (int off = 1; off < 16; off <<= 1) {
+            uint32_t o = __shfl_up(wi, off, 64);
+            if (lane >= off) wi += o;
+        }
+        if (lane < 16) s_wave[lane] = wi - w;  // exclusive wave offsets
+    }
+    __syncthreads();
+    uint32_t run = s_wave[wave] + inc - sum;
+    for (int k = b; k < e; ++k) {
+        start[k] = run;
+        run += count[k];
+        fill[k] = 0u;
+    }
+    if (tid == 1023) {
+        const uint32_t tot = s_wave[wave] + inc;
+        start[M] = tot;
+        st->total = tot;
+        st->overflow = tot > capacity ? 1u : 0u;
+        if (tot > capacity) st->sticky |= 1u;
+        st->queue = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scatter one key per (Gaussian, overlapped tile) into its tile's segment.
+// Key = float bits of z << 32 | gid; the order inside a segment is fixed later
+// by the sort, so the atomic slot order does not matter.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scatter(Geometry G, RenderBufs B) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)G.n_pairs * G.N;
+    if (i >= total) return;
+    const uint32_t rx = B.pre.rx[i], ry = B.pre.ry[i];
+    const int x0 = rx & 0xffff, x1 = rx >> 16, y0 = ry & 0xffff, y1 = ry >> 16;
+    if (x0 >= x1 || y0 >= y1) return;
+    const int pair = (int)(i / G.N);
+    const int pix = (int)(i - (int64_t)pair * G.N);
+    const PairConst& pc = B.pairs[pair];
+    const uint32_t gid = (uint32_t)pc.kf * (uint32_t)G.N + (uint32_t)pix;
+    const uint64_t key = ((uint64_t)__float_as_uint(B.pre.z[i]) << 32) | gid;
+    const size_t base = (size_t)pc.job * G.ntiles;
+    for (int ty = y0; ty < y1; ++ty)
+        for (int tx = x0; tx < x1; ++tx) {
+            const size_t t = base + ty * G.ntx + tx;
+            const uint32_t pos = B.tile_start[t] + atomicAdd(&B.tile_fill[t], 1u);
+            if (pos < B.capacity) B.keys[pos] = key;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Per-segment ascending sort of 64-bit keys.  Bitonic network in which every
+// comparator is ascending (the first step of each merge compares mirrored
+// positions), so positions past the segment end behave as +inf without
+// being stored.  Segments up to kSortLds keys are sorted in LDS; longer ones
+// in place in global memory by the same block.
+// ---------------------------------------------------------------------------
+constexpr int kSortLds = 4096;
+
+__device__ inline void cmpswap_lds(uint64_t* s, int a, int b) {
+    uint64_t x = s[a], y = s[b];
+    if (y < x) {
+        s[a] = y;
+        s[b] = x;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort(Geometry G, RenderBufs B) {
+    __shared__ uint64_t s[kSortLds];
+    const int seg = blockIdx.x;
+    if (B.status->overflow) return;
+    const uint32_t st = B.tile_start[seg];
+    const uint32_t en = B.tile_start[seg + 1];
+    const int n = (int)(en - st);
+    if (n <= 1) return;
+    uint64_t* g = B.keys + st;
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    const int tid = threadIdx.x;
+    if (np2 <= kSortLds) {
+        for (int k = tid; k < np2; k += blockDim.x) s[k] = k < n ? g[k] : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= np2; k <<= 1) {
+            const int h = k >> 1;
+            for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
+                const int blk = p / h, off = p - blk * h;
+                cmpswap_lds(s, blk * k + off, blk * k + k - 1 - off);
+            }
+            __syncthreads();
+            for (int j = k >> 2; j >= 1; j >>= 1) {
+                for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
+                    const int blk = p / j, off = p - blk * j;
+                    const int a = blk * 2 * j + off;
+                    cmpswap_lds(s, a, a + j);
+                }
+                __syncthreads();
+            }
+        }
+        for (int k = tid; k < n; k += blockDim.x) g[k] = s[k];
+        return;
+    }
+    // long segment: same network in global memory, virtual +inf padding
+    for (int k = 2; k <= np2; k <<= 1) {
+        const int h = k >> 1;
+        for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
+            const int blk = p / h, off = p - blk * h;
+            const int a = blk * k + off, b = blk * k + k - 1 - off;
+            if (b < n) {
+                uint64_t x = g[a], y = g[b];
+                if (y < x) {
+                    g[a] = y;
+                    g[b] = x;
+                }
+            }
+        }
+        __syncthreads();
+        for (int j = k >> 2; j >= 1; j >>= 1) {
+            for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
+                const int blk = p / j, off = p - blk * j;
+                const int a = blk * 2 * j + off, b = a + j;
+                if (b < n) {
+                    uint64_t x = g[a], y = g[b];
+                    if (y < x) {
+                        g[a] = y;
+                        g[b] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks), dim3(256), 0, s, p, n);
+}
+
+void launch_zero_f32(float* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_f32, dim3(blocks), dim3(256), 0, s, p, n);
+}
+
+void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s) {
+    const int64_t n = (int64_t)G.n_pairs * G.N;
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, B);
+}
+
+void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s) {
+    const int M = G.n_jobs * G.ntiles;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, B.tile_count, B.tile_start, B.tile_fill, M,
+                       B.capacity, B.status);
+}
+
+void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s) {
+    const int64_t n = (int64_t)G.n_pairs * G.N;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, B);
+}
+
+void launch_sort(const Geometry& G, const RenderBufs& B, hipStream_t s) {
+    const int M = G.n_jobs * G.ntiles;
+    hipLaunchKernelGGL(k_sort, dim3(M), dim3(256), 0, s, G, B);
+}
+
+}  // namespace sgad

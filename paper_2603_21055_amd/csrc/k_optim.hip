@@ -1,0 +1,104 @@
+// L1 terms of the mapping loss (Eq. 1) with their upstream gradients, and a
+// multi-tensor Adam step over the per-pixel Gaussian parameters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sgad_internal.h"
+
+namespace sgad {
+
+__device__ __forceinline__ float signf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Count the valid target-depth pixels (U = [D > 0]) of every job.
+__global__ __launch_bounds__(256) void k_count_valid(const float* __restrict__ t_depth, int P, uint32_t* count) {
+    const int job = blockIdx.y;
+    uint32_t c = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x)
+        c += t_depth[(size_t)job * P + i] > 0.f ? 1u : 0u;
+    c = wave_sum_u(c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&count[job], c);
+}
+
+// Loss value and upstream grads:
+//   L = w_rgb mean|rgb - t_rgb| + w_depth sum_U |D' - D_t| / |U|
+__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const float* __restrict__ dep,
+                                            const float* __restrict__ t_rgb, const float* __restrict__ t_dep,
+                                            int P, float w_rgb, float w_dep, const uint32_t* count,
+                                            float* g_rgb, float* g_dep, double* loss) {
+    const int job = blockIdx.y;
+    const uint32_t nv = count[job];
+    const float inv_rgb = w_rgb / (3.f * (float)P);
+    const float inv_dep = nv ? w_dep / (float)nv : 0.f;
+    double acc = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+        const size_t jp = (size_t)job * P + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t k = ((size_t)job * 3 + c) * P + i;
+            const float e = rgb[k] - t_rgb[k];
+            acc += (double)(fabsf(e) * inv_rgb);
+            g_rgb[k] = signf(e) * inv_rgb;
+        }
+        const float td = t_dep[jp];
+        const float e = td > 0.f ? dep[jp] - td : 0.f;
+        acc += (double)(fabsf(e) * inv_dep);
+        g_dep[jp] = signf(e) * inv_dep;
+    }
+    acc = wave_sum_d(acc);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&loss[job], acc);
+}
+
+// Multi-tensor Adam: group g owns elements [off[g], off[g+1]) of the flat range.
+
+__global__ __launch_bounds__(256) void k_adam(AdamGroups A, float b1, float b2, float eps, float c1, float c2,
+                                              int zero_grad) {
+    const int64_t total = A.off[A.n];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int gi = 0;
+        while (gi + 1 < A.n && i >= A.off[gi + 1]) ++gi;
+        const int64_t k = i - A.off[gi];
+        const float g = A.g[gi][k];
+        const float m = b1 * A.m[gi][k] + (1.f - b1) * g;
+        const float v = b2 * A.v[gi][k] + (1.f - b2) * g * g;
+        A.m[gi][k] = m;
+        A.v[gi][k] = v;
+        const float mh = m / c1, vh = v / c2;
+        float p = A.p[gi][k] - A.lr[gi] * mh / (sqrtf(vh) + eps);
+        p = fminf(fmaxf(p, A.lo[gi]), A.hi[gi]);
+        A.p[gi][k] = p;
+        if (zero_grad) A.g[gi][k] = 0.f;
+    }
+}
+
+void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const float* t_rgb, const float* t_dep,
+               float w_rgb, float w_dep, uint32_t* count, float* g_rgb, float* g_dep, double* loss,
+               hipStream_t s) {
+    const int bx = std::min(1024, (P + 255) / 256);
+    hipLaunchKernelGGL(k_count_valid, dim3(bx, n_jobs), dim3(256), 0, s, t_dep, P, count);
+    hipLaunchKernelGGL(k_l1, dim3(bx, n_jobs), dim3(256), 0, s, rgb, dep, t_rgb, t_dep, P, w_rgb, w_dep, count,
+                       g_rgb, g_dep, loss);
+}
+
+void launch_adam(const AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
+                 hipStream_t s) {
+    const int64_t total = A.off[A.n];
+    if (total <= 0) return;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, s, A, b1, b2, eps, c1, c2, zero_grad);
+}
+
+}  // namespace sgad

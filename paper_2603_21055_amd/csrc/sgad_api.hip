@@ -1,0 +1,912 @@
+// Host side of the C ABI: context, saved render state, workspace sizing,
+// relative-pose tables, launches and asynchronous error latching.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sgad_internal.h"
+
+namespace sgad {
+void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+void launch_zero_f32(float* p, int64_t n, hipStream_t s);
+void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s);
+void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s);
+void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s);
+void launch_sort(const Geometry& G, const RenderBufs& B, hipStream_t s);
+bool launch_fwd(const Geometry& G, const RenderBufs& B, float* rgb, float* depth, float* alpha, int32_t* count,
+                hipStream_t s);
+bool launch_bwd(const Geometry& G, const RenderBufs& B, const float* g_rgb, const float* g_depth,
+                const float* g_alpha, const KfGradPtrs* grads, uint32_t lo, uint32_t hi, float* pose_part,
+                float* d_pose, hipStream_t s);
+void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const float* t_rgb, const float* t_dep,
+               float w_rgb, float w_dep, uint32_t* count, float* g_rgb, float* g_dep, double* loss,
+               hipStream_t s);
+void launch_adam(const AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
+                 hipStream_t s);
+void launch_track_pair(const double* pose, const sgad_pose& kf_pose, const sgad_cam& kc, const sgad_cam& vc,
+                       PairConst* out, hipStream_t s);
+bool launch_track(const Geometry& G, const RenderBufs& B, const float* obs, float* part, hipStream_t s);
+void launch_track_solve(const float* part, int nitems, double* pose, double* trace, int it, const DevStatus* st,
+                        hipStream_t s);
+}  // namespace sgad
+
+using namespace sgad;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct PinBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sgad_saved {
+    bool in_use = false;
+    Geometry G{};
+    hipStream_t stream = nullptr;
+    // device buffers (grow-only)
+    DevBuf params, pre, tiles, keys, pix, pose_part, status, gradptrs;
+    uint32_t capacity = 0;
+    bool sized = false;
+    // pinned staging
+    PinBuf up, up_grad;
+    DevStatus* status_h = nullptr;
+    hipEvent_t ev_up = nullptr, ev_up_grad = nullptr, ev_status = nullptr;
+    bool up_pending = false, up_grad_pending = false, status_pending = false;
+    RenderBufs B{};
+};
+
+// Optional per-kernel timing: a pair of hipEvents recorded on the launch
+// stream around every library kernel, accumulated per kernel name.
+struct KernelTimer {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    size_t used = 0;
+    std::vector<std::pair<std::string, size_t>> pending;  // name, pool index
+    std::vector<std::string> names;
+    std::vector<double> ms;
+    std::vector<long> count;
+};
+
+struct sgad_ctx {
+    int device = 0;
+    std::string err;
+    sgad_status latched = SGAD_OK;
+    int tile_w = 16, tile_h = 16;
+    int last_tw = 16, last_th = 16;
+    std::vector<sgad_saved*> slots;
+    KernelTimer timer;
+    DevBuf scratch;  // small per-context scratch (loss counters)
+    struct Track {
+        bool sized = false;
+        Geometry G{};
+        RenderBufs B{};
+        DevBuf params, pre, tiles, keys, part, status, trace;
+        uint32_t capacity = 0;
+        // what a captured graph depends on
+        const void* key[8] = {};
+        int key_iters = 0, key_tw = 0, key_th = 0;
+        sgad_cam kc{}, vc{};
+        sgad_pose kpose{};
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipStream_t cap = nullptr;
+        DevStatus* status_h = nullptr;
+        hipEvent_t ev_status = nullptr;
+        bool status_pending = false;
+    } track;
+};
+
+namespace {
+
+// RAII scope that brackets one launch with timing events when enabled.
+struct TimeScope {
+    sgad_ctx* c;
+    size_t idx = (size_t)-1;
+    hipStream_t s;
+    TimeScope(sgad_ctx* ctx, const char* name, hipStream_t stream) : c(ctx), s(stream) {
+        KernelTimer& t = c->timer;
+        if (!t.on) return;
+        if (t.used == t.pool.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return;
+            }
+            t.pool.emplace_back(a, b);
+        }
+        idx = t.used++;
+        (void)hipEventRecord(t.pool[idx].first, s);
+        t.pending.emplace_back(name, idx);
+    }
+    ~TimeScope() {
+        if (idx != (size_t)-1) (void)hipEventRecord(c->timer.pool[idx].second, s);
+    }
+};
+
+void timer_collect(sgad_ctx* c) {
+    KernelTimer& t = c->timer;
+    for (auto& pr : t.pending) {
+        auto& ev = t.pool[pr.second];
+        (void)hipEventSynchronize(ev.second);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) != hipSuccess) continue;
+        size_t k = 0;
+        while (k < t.names.size() && t.names[k] != pr.first) ++k;
+        if (k == t.names.size()) {
+            t.names.push_back(pr.first);
+            t.ms.push_back(0.0);
+            t.count.push_back(0);
+        }
+        t.ms[k] += ms;
+        t.count[k] += 1;
+    }
+    t.pending.clear();
+    t.used = 0;
+}
+
+}  // namespace
+
+namespace {
+
+sgad_status fail(sgad_ctx* c, sgad_status s, const std::string& m) {
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess)                                                                 \
+            return fail(ctx, SGAD_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));  \
+    } while (0)
+
+hipError_t ensure(DevBuf& b, size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) return e;
+    b.bytes = bytes;
+    return hipSuccess;
+}
+
+hipError_t ensure_pin(PinBuf& b, size_t bytes) {
+    if (b.bytes >= bytes) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipHostFree(b.p);
+        if (e != hipSuccess) return e;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+    hipError_t e = hipHostMalloc(&b.p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    b.bytes = bytes;
+    return hipSuccess;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void latch_status(sgad_ctx* c, const DevStatus& st) {
+    if ((st.nonfinite || (st.sticky & 2u)) && c->latched == SGAD_OK) {
+        c->latched = SGAD_EDATA;
+        c->err = "non-finite depth, offset or radius in a keyframe";
+    }
+    if ((st.overflow || (st.sticky & 1u)) && c->latched == SGAD_OK) {
+        c->latched = SGAD_ERANGE;
+        c->err = "instance list overflow";
+    }
+}
+
+// Read device-side conditions of finished forwards without blocking.
+void poll(sgad_ctx* c, bool block) {
+    if (c->track.status_pending) {
+        bool done = block ? hipEventSynchronize(c->track.ev_status) == hipSuccess
+                          : hipEventQuery(c->track.ev_status) == hipSuccess;
+        if (done) {
+            c->track.status_pending = false;
+            latch_status(c, *c->track.status_h);
+            if (c->track.status_h->sticky & 1u) c->track.sized = false;
+        }
+    }
+    for (sgad_saved* s : c->slots) {
+        if (!s->status_pending) continue;
+        if (block) (void)hipEventSynchronize(s->ev_status);
+        else if (hipEventQuery(s->ev_status) != hipSuccess) continue;
+        s->status_pending = false;
+        const DevStatus st = *s->status_h;
+        if ((st.nonfinite || (st.sticky & 2u)) && c->latched == SGAD_OK) {
+            c->latched = SGAD_EDATA;
+            c->err = "non-finite depth, offset or radius in a keyframe";
+        }
+        if (st.overflow || (st.sticky & 1u)) {
+            if (c->latched == SGAD_OK) {
+                c->latched = SGAD_ERANGE;
+                c->err = "instance list overflow (outputs of that forward are NaN); capacity grows on the next call";
+            }
+            s->sized = false;
+        } else if (st.total > s->capacity - s->capacity / 8) {
+            s->sized = false;  // re-size on the next forward before it can overflow
+        }
+    }
+}
+
+bool finite_pose(const sgad_pose& p) {
+    for (float v : p.R)
+        if (!std::isfinite(v)) return false;
+    for (float v : p.t)
+        if (!std::isfinite(v)) return false;
+    return true;
+}
+
+bool cam_ok(const sgad_cam& c) {
+    return c.H > 0 && c.W > 0 && c.H < 32768 && c.W < 32768 && std::isfinite(c.fx) && std::isfinite(c.fy) &&
+           std::isfinite(c.cx) && std::isfinite(c.cy) && c.fx != 0.f && c.fy != 0.f;
+}
+
+// T_rel = T_view T_kf^-1 in FP64 with the operation order of the binning contract.
+#pragma clang fp contract(off)
+void relative_pose(const sgad_pose& v, const sgad_pose& f, PairConst& pc) {
+    double Rv[9], Rf[9], tv[3], tf[3];
+    for (int i = 0; i < 9; ++i) {
+        Rv[i] = (double)v.R[i];
+        Rf[i] = (double)f.R[i];
+    }
+    for (int i = 0; i < 3; ++i) {
+        tv[i] = (double)v.t[i];
+        tf[i] = (double)f.t[i];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double a = Rv[i * 3 + 0] * Rf[j * 3 + 0];
+            double b = Rv[i * 3 + 1] * Rf[j * 3 + 1];
+            double c = Rv[i * 3 + 2] * Rf[j * 3 + 2];
+            double ab = a + b;
+            pc.R[i * 3 + j] = ab + c;
+        }
+    for (int i = 0; i < 3; ++i) {
+        double a = pc.R[i * 3 + 0] * tf[0];
+        double b = pc.R[i * 3 + 1] * tf[1];
+        double c = pc.R[i * 3 + 2] * tf[2];
+        double ab = a + b;
+        double abc = ab + c;
+        pc.t[i] = tv[i] - abc;
+    }
+    for (int i = 0; i < 9; ++i) pc.Rf[i] = (float)pc.R[i];
+    for (int i = 0; i < 3; ++i) pc.tf[i] = (float)pc.t[i];
+}
+
+sgad_saved* acquire(sgad_ctx* c) {
+    for (sgad_saved* s : c->slots)
+        if (!s->in_use) {
+            s->in_use = true;
+            return s;
+        }
+    sgad_saved* s = new sgad_saved();
+    if (hipEventCreateWithFlags(&s->ev_up, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_up_grad, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_status, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&s->status_h, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+        delete s;
+        return nullptr;
+    }
+    std::memset(s->status_h, 0, sizeof(DevStatus));
+    s->in_use = true;
+    c->slots.push_back(s);
+    return s;
+}
+
+void free_slot(sgad_saved* s) {
+    for (DevBuf* b : {&s->params, &s->pre, &s->tiles, &s->keys, &s->pix, &s->pose_part, &s->status, &s->gradptrs})
+        if (b->p) (void)hipFree(b->p);
+    for (PinBuf* b : {&s->up, &s->up_grad})
+        if (b->p) (void)hipHostFree(b->p);
+    if (s->status_h) (void)hipHostFree(s->status_h);
+    if (s->ev_up) (void)hipEventDestroy(s->ev_up);
+    if (s->ev_up_grad) (void)hipEventDestroy(s->ev_up_grad);
+    if (s->ev_status) (void)hipEventDestroy(s->ev_status);
+    delete s;
+}
+
+bool valid_tile(int w, int h) {
+    return (w == 8 && h == 8) || (w == 16 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 8);
+}
+
+}  // namespace
+
+extern "C" {
+
+sgad_status sgad_create(int device, sgad_ctx** out) {
+    if (!out) return SGAD_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SGAD_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return SGAD_EHIP;
+    sgad_ctx* c = new sgad_ctx();
+    c->device = device;
+    *out = c;
+    return SGAD_OK;
+}
+
+void sgad_destroy(sgad_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (sgad_saved* s : c->slots) free_slot(s);
+    if (c->scratch.p) (void)hipFree(c->scratch.p);
+    {
+        auto& T = c->track;
+        for (DevBuf* b : {&T.params, &T.pre, &T.tiles, &T.keys, &T.part, &T.status, &T.trace})
+            if (b->p) (void)hipFree(b->p);
+        if (T.exec) (void)hipGraphExecDestroy(T.exec);
+        if (T.graph) (void)hipGraphDestroy(T.graph);
+        if (T.cap) (void)hipStreamDestroy(T.cap);
+        if (T.status_h) (void)hipHostFree(T.status_h);
+        if (T.ev_status) (void)hipEventDestroy(T.ev_status);
+    }
+    for (auto& pr : c->timer.pool) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    delete c;
+}
+
+const char* sgad_last_error(const sgad_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+sgad_status sgad_sync(sgad_ctx* c) {
+    if (!c) return SGAD_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceSynchronize());
+    poll(c, true);
+    sgad_status s = c->latched;
+    c->latched = SGAD_OK;
+    return s;
+}
+
+sgad_status sgad_set_tile(sgad_ctx* c, int w, int h) {
+    if (!c) return SGAD_EINVAL;
+    if (!(w == 0 && h == 0) && !valid_tile(w, h)) return fail(c, SGAD_EINVAL, "unsupported tile shape");
+    c->tile_w = w;
+    c->tile_h = h;
+    return SGAD_OK;
+}
+
+sgad_status sgad_get_tile(const sgad_ctx* c, int* w, int* h) {
+    if (!c || !w || !h) return SGAD_EINVAL;
+    *w = c->last_tw;
+    *h = c->last_th;
+    return SGAD_OK;
+}
+
+sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_views, const sgad_cam* vcam,
+                            const sgad_pose* vpose, int n_jobs, const sgad_job* jobs, float* out_rgb,
+                            float* out_depth, float* out_alpha, int32_t* out_count, sgad_saved** saved,
+                            void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!saved) return fail(c, SGAD_EINVAL, "saved is null");
+    *saved = nullptr;
+    if (n_kf < 1 || n_kf > kMaxKf || !kf) return fail(c, SGAD_EINVAL, "n_kf must be in [1, 64]");
+    if (n_views < 1 || !vcam || !vpose) return fail(c, SGAD_EINVAL, "need at least one view");
+    if (n_jobs < 1 || !jobs) return fail(c, SGAD_EINVAL, "need at least one job");
+    if (!out_rgb || !out_depth || !out_alpha) return fail(c, SGAD_EINVAL, "null output");
+    const sgad_cam& k0 = kf[0].cam;
+    for (int f = 0; f < n_kf; ++f) {
+        const sgad_keyframe& k = kf[f];
+        if (!cam_ok(k.cam)) return fail(c, SGAD_EINVAL, "bad keyframe camera");
+        if (k.cam.H != k0.H || k.cam.W != k0.W) return fail(c, SGAD_EINVAL, "keyframes must share H x W");
+        if (!k.depth || !k.offset || !k.radius || !k.opacity || (!k.rgb && !k.sigma))
+            return fail(c, SGAD_EINVAL, "null keyframe plane");
+        if (!finite_pose(k.T_cw)) return fail(c, SGAD_EINVAL, "non-finite keyframe pose");
+    }
+    for (int v = 0; v < n_views; ++v) {
+        if (!cam_ok(vcam[v])) return fail(c, SGAD_EINVAL, "bad view camera");
+        if (vcam[v].H != vcam[0].H || vcam[v].W != vcam[0].W) return fail(c, SGAD_EINVAL, "views must share H x W");
+        if (!finite_pose(vpose[v])) return fail(c, SGAD_EINVAL, "non-finite view pose");
+    }
+    int n_pairs = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        if (jobs[j].view < 0 || jobs[j].view >= n_views) return fail(c, SGAD_EINVAL, "job view out of range");
+        const uint64_t m = (uint64_t)jobs[j].kf_mask_lo | ((uint64_t)jobs[j].kf_mask_hi << 32);
+        if (n_kf < 64 && (m >> n_kf) != 0) return fail(c, SGAD_EINVAL, "job mask names a missing keyframe");
+        n_pairs += __builtin_popcountll(m);
+    }
+    if (n_pairs == 0) return fail(c, SGAD_EINVAL, "jobs render no keyframe");
+    const int64_t N = (int64_t)k0.H * k0.W;
+    if ((int64_t)n_kf * N >= (1ll << 32) || (int64_t)n_pairs * N >= (1ll << 31))
+        return fail(c, SGAD_ERANGE, "too many Gaussians for one call");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    poll(c, false);
+
+    int TW = c->tile_w, TH = c->tile_h;
+    if (TW == 0) {
+        TW = 16;
+        TH = 16;
+    }
+    sgad_saved* S = acquire(c);
+    if (!S) return fail(c, SGAD_ENOMEM, "cannot allocate a saved slot");
+    Geometry& G = S->G;
+    G.n_kf = n_kf;
+    G.n_jobs = n_jobs;
+    G.n_pairs = n_pairs;
+    G.Hk = k0.H;
+    G.Wk = k0.W;
+    G.N = (int)N;
+    G.Hv = vcam[0].H;
+    G.Wv = vcam[0].W;
+    G.P = G.Hv * G.Wv;
+    G.TW = TW;
+    G.TH = TH;
+    G.ntx = (G.Wv + TW - 1) / TW;
+    G.nty = (G.Hv + TH - 1) / TH;
+    G.ntiles = G.ntx * G.nty;
+    S->stream = s;
+    c->last_tw = TW;
+    c->last_th = TH;
+
+    // parameter block: pairs | kf pointers | pair_of
+    const size_t o_pairs = 0;
+    const size_t o_kfs = align256(o_pairs + sizeof(PairConst) * n_pairs);
+    const size_t o_pof = align256(o_kfs + sizeof(KfPtrs) * n_kf);
+    const size_t up_bytes = align256(o_pof + sizeof(int32_t) * n_jobs * n_kf);
+    if (S->up_pending) {
+        HIPCHK(c, hipEventSynchronize(S->ev_up));
+        S->up_pending = false;
+    }
+    if (ensure_pin(S->up, up_bytes) != hipSuccess) return fail(c, SGAD_ENOMEM, "pinned alloc");
+    HIPCHK(c, ensure(S->params, up_bytes, s));
+    char* up = (char*)S->up.p;
+    PairConst* pairs = (PairConst*)(up + o_pairs);
+    KfPtrs* kps = (KfPtrs*)(up + o_kfs);
+    int32_t* pof = (int32_t*)(up + o_pof);
+    int p = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        const uint64_t m = (uint64_t)jobs[j].kf_mask_lo | ((uint64_t)jobs[j].kf_mask_hi << 32);
+        const sgad_cam& vc = vcam[jobs[j].view];
+        for (int f = 0; f < n_kf; ++f) {
+            pof[j * n_kf + f] = -1;
+            if (!((m >> f) & 1ull)) continue;
+            PairConst& pc = pairs[p];
+            relative_pose(vpose[jobs[j].view], kf[f].T_cw, pc);
+            pc.kfx = (double)kf[f].cam.fx;
+            pc.kfy = (double)kf[f].cam.fy;
+            pc.kcx = (double)kf[f].cam.cx;
+            pc.kcy = (double)kf[f].cam.cy;
+            pc.vfx = (double)vc.fx;
+            pc.vfy = (double)vc.fy;
+            pc.vcx = (double)vc.cx;
+            pc.vcy = (double)vc.cy;
+            pc.job = j;
+            pc.kf = f;
+            pof[j * n_kf + f] = p;
+            ++p;
+        }
+    }
+    for (int f = 0; f < n_kf; ++f)
+        kps[f] = KfPtrs{kf[f].depth, kf[f].offset, kf[f].radius, kf[f].opacity, kf[f].rgb, kf[f].sigma};
+    HIPCHK(c, hipMemcpyAsync(S->params.p, up, up_bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipEventRecord(S->ev_up, s));
+    S->up_pending = true;
+
+    // workspace
+    const size_t NP = (size_t)n_pairs * N;
+    const size_t M = (size_t)n_jobs * G.ntiles;
+    const size_t PJ = (size_t)n_jobs * G.P;
+    HIPCHK(c, ensure(S->pre, NP * 32, s));
+    HIPCHK(c, ensure(S->tiles, (3 * M + 1) * 4 + 256, s));
+    HIPCHK(c, ensure(S->pix, PJ * 8, s));
+    HIPCHK(c, ensure(S->pose_part, M * 6 * 4, s));
+    HIPCHK(c, ensure(S->status, sizeof(DevStatus), s));
+    if (!S->sized && S->capacity == 0) {
+        // first use: a generous guess that is corrected after the count pass
+        const size_t guess = NP * 3 + 65536;
+        HIPCHK(c, ensure(S->keys, guess * 8, s));
+        S->capacity = (uint32_t)std::min<size_t>(guess, 0xffffffffu);
+    }
+
+    RenderBufs& B = S->B;
+    char* pb = (char*)S->params.p;
+    B.pairs = (const PairConst*)(pb + o_pairs);
+    B.kfs = (const KfPtrs*)(pb + o_kfs);
+    B.pair_of = (const int32_t*)(pb + o_pof);
+    char* pp = (char*)S->pre.p;
+    B.pre.dx = (float*)(pp + 0 * NP * 4);
+    B.pre.dy = (float*)(pp + 1 * NP * 4);
+    B.pre.ca = (float*)(pp + 2 * NP * 4);
+    B.pre.cb = (float*)(pp + 3 * NP * 4);
+    B.pre.cc = (float*)(pp + 4 * NP * 4);
+    B.pre.z = (float*)(pp + 5 * NP * 4);
+    B.pre.rx = (uint32_t*)(pp + 6 * NP * 4);
+    B.pre.ry = (uint32_t*)(pp + 7 * NP * 4);
+    uint32_t* tb = (uint32_t*)S->tiles.p;
+    B.tile_count = tb;
+    B.tile_fill = tb + M;
+    B.tile_start = tb + 2 * M;
+    B.keys = (uint64_t*)S->keys.p;
+    B.capacity = S->capacity;
+    B.Tfinal = (float*)S->pix.p;
+    B.last = (uint32_t*)((char*)S->pix.p + PJ * 4);
+    B.status = (DevStatus*)S->status.p;
+
+    {
+        TimeScope ts(c, "zero", s);
+        launch_zero_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, s);
+        launch_zero_u32(B.tile_count, (int64_t)M, s);
+    }
+    {
+        TimeScope ts(c, "preprocess", s);
+        launch_preprocess(G, B, s);
+    }
+    {
+        TimeScope ts(c, "scan", s);
+        launch_scan(G, B, s);
+    }
+    if (!S->sized) {
+        // size the instance buffer from the exact count (one host wait)
+        HIPCHK(c, hipMemcpyAsync(S->status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        const uint32_t total = S->status_h->total;
+        if ((size_t)total + (size_t)total / 4 > S->capacity || S->capacity == 0) {
+            const size_t cap = std::min<size_t>((size_t)total + total / 4 + 65536, 0xffffffffu);
+            HIPCHK(c, ensure(S->keys, cap * 8, s));
+            S->capacity = (uint32_t)cap;
+            B.keys = (uint64_t*)S->keys.p;
+            B.capacity = S->capacity;
+            launch_scan(G, B, s);
+        }
+        S->sized = true;
+    }
+    {
+        TimeScope ts(c, "scatter", s);
+        launch_scatter(G, B, s);
+    }
+    {
+        TimeScope ts(c, "sort", s);
+        launch_sort(G, B, s);
+    }
+    {
+        TimeScope ts(c, "composite_fwd", s);
+        if (!launch_fwd(G, B, out_rgb, out_depth, out_alpha, out_count, s))
+            return fail(c, SGAD_EINVAL, "unsupported tile shape");
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(S->status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipEventRecord(S->ev_status, s));
+    S->status_pending = true;
+    *saved = S;
+    return SGAD_OK;
+}
+
+sgad_status sgad_render_bwd(sgad_ctx* c, sgad_saved* S, const float* g_rgb, const float* g_depth,
+                            const float* g_alpha, const sgad_kf_grads* grads, float* d_pose, uint32_t learn_lo,
+                            uint32_t learn_hi, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!S || !S->in_use) return fail(c, SGAD_EINVAL, "invalid saved handle");
+    if (!g_rgb) return fail(c, SGAD_EINVAL, "g_rgb is null");
+    const Geometry& G = S->G;
+    const uint64_t learn = (uint64_t)learn_lo | ((uint64_t)learn_hi << 32);
+    for (int f = 0; f < G.n_kf; ++f) {
+        if (!((learn >> f) & 1ull)) continue;
+        if (!grads || !grads[f].d_rgb || !grads[f].d_opacity || !grads[f].d_radius || !grads[f].d_offset)
+            return fail(c, SGAD_EINVAL, "null gradient output for a learnable keyframe");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    poll(c, false);
+    const size_t gb = align256(sizeof(KfGradPtrs) * G.n_kf);
+    if (S->up_grad_pending) {
+        HIPCHK(c, hipEventSynchronize(S->ev_up_grad));
+        S->up_grad_pending = false;
+    }
+    if (ensure_pin(S->up_grad, gb) != hipSuccess) return fail(c, SGAD_ENOMEM, "pinned alloc");
+    HIPCHK(c, ensure(S->gradptrs, gb, s));
+    KfGradPtrs* gp = (KfGradPtrs*)S->up_grad.p;
+    for (int f = 0; f < G.n_kf; ++f) {
+        if (grads && ((learn >> f) & 1ull))
+            gp[f] = KfGradPtrs{grads[f].d_rgb, grads[f].d_opacity, grads[f].d_radius, grads[f].d_offset};
+        else
+            gp[f] = KfGradPtrs{nullptr, nullptr, nullptr, nullptr};
+    }
+    HIPCHK(c, hipMemcpyAsync(S->gradptrs.p, gp, gb, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipEventRecord(S->ev_up_grad, s));
+    S->up_grad_pending = true;
+    {
+        TimeScope ts(c, "composite_bwd", s);
+        if (!launch_bwd(G, S->B, g_rgb, g_depth, g_alpha, (const KfGradPtrs*)S->gradptrs.p, learn_lo, learn_hi,
+                        (float*)S->pose_part.p, d_pose, s))
+            return fail(c, SGAD_EINVAL, "unsupported tile shape");
+    }
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_timing_enable(sgad_ctx* c, int enable) {
+    if (!c) return SGAD_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    timer_collect(c);
+    c->timer.names.clear();
+    c->timer.ms.clear();
+    c->timer.count.clear();
+    c->timer.on = enable != 0;
+    return SGAD_OK;
+}
+
+sgad_status sgad_timing_report(sgad_ctx* c, char* buf, size_t cap) {
+    if (!c || !buf || cap == 0) return SGAD_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    timer_collect(c);
+    std::string out;
+    char line[256];
+    for (size_t k = 0; k < c->timer.names.size(); ++k) {
+        snprintf(line, sizeof(line), "%s %ld %.6f\n", c->timer.names[k].c_str(), c->timer.count[k], c->timer.ms[k]);
+        out += line;
+    }
+    if (out.size() + 1 > cap) return fail(c, SGAD_ERANGE, "timing report buffer too small");
+    std::memcpy(buf, out.c_str(), out.size() + 1);
+    return SGAD_OK;
+}
+
+sgad_status sgad_l1_loss(sgad_ctx* c, int n_jobs, int H, int W, const float* rgb, const float* depth,
+                         const float* t_rgb, const float* t_depth, float w_rgb, float w_depth, float* g_rgb,
+                         float* g_depth, double* loss, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (n_jobs < 1 || H < 1 || W < 1) return fail(c, SGAD_EINVAL, "bad sizes");
+    if (!rgb || !depth || !t_rgb || !t_depth || !g_rgb || !g_depth || !loss)
+        return fail(c, SGAD_EINVAL, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, ensure(c->scratch, (size_t)n_jobs * 4, s));
+    uint32_t* cnt = (uint32_t*)c->scratch.p;
+    TimeScope ts(c, "l1_loss", s);
+    launch_zero_u32(cnt, n_jobs, s);
+    launch_zero_u32((uint32_t*)loss, 2 * (int64_t)n_jobs, s);
+    launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, g_rgb, g_depth, loss, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_adam_step(sgad_ctx* c, int n_groups, const sgad_adam_group* groups, int step, float beta1,
+                           float beta2, float eps, int zero_grad, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (n_groups < 1 || n_groups > kMaxAdamGroups || !groups) return fail(c, SGAD_ERANGE, "1..32 groups");
+    if (step < 1) return fail(c, SGAD_EINVAL, "step counts from 1");
+    AdamGroups A{};
+    A.n = n_groups;
+    A.off[0] = 0;
+    for (int g = 0; g < n_groups; ++g) {
+        const sgad_adam_group& G = groups[g];
+        if (!G.param || !G.grad || !G.m || !G.v || G.n < 0) return fail(c, SGAD_EINVAL, "bad adam group");
+        A.p[g] = G.param;
+        A.g[g] = G.grad;
+        A.m[g] = G.m;
+        A.v[g] = G.v;
+        A.lr[g] = G.lr;
+        A.lo[g] = G.lo;
+        A.hi[g] = G.hi;
+        A.off[g + 1] = A.off[g] + G.n;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+    TimeScope ts(c, "adam", s);
+    launch_adam(A, beta1, beta2, eps, c1, c2, zero_grad, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_saved_release(sgad_ctx* c, sgad_saved* S) {
+    if (!c || !S) return SGAD_EINVAL;
+    for (sgad_saved* x : c->slots)
+        if (x == S) {
+            S->in_use = false;
+            return SGAD_OK;
+        }
+    return fail(c, SGAD_EINVAL, "handle does not belong to this context");
+}
+
+sgad_status sgad_saved_instances(sgad_ctx* c, const sgad_saved* S, int job, uint32_t* tile_ranges,
+                                 uint64_t* keys, size_t cap, size_t* n_keys, int* n_tiles) {
+    if (!c || !S || !S->in_use || !n_keys || !n_tiles) return SGAD_EINVAL;
+    const Geometry& G = S->G;
+    if (job < 0 || job >= G.n_jobs) return fail(c, SGAD_EINVAL, "job out of range");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(S->stream));
+    DevStatus st;
+    HIPCHK(c, hipMemcpy(&st, S->B.status, sizeof(st), hipMemcpyDeviceToHost));
+    if (st.overflow) return fail(c, SGAD_ERANGE, "instance list overflowed");
+    std::vector<uint32_t> start(G.ntiles + 1);
+    HIPCHK(c, hipMemcpy(start.data(), S->B.tile_start + (size_t)job * G.ntiles, (G.ntiles + 1) * 4,
+                        hipMemcpyDeviceToHost));
+    const size_t n = start[G.ntiles] - start[0];
+    *n_keys = n;
+    *n_tiles = G.ntiles;
+    if (tile_ranges)
+        for (int t = 0; t < G.ntiles; ++t) {
+            tile_ranges[2 * t] = start[t] - start[0];
+            tile_ranges[2 * t + 1] = start[t + 1] - start[0];
+        }
+    if (keys) {
+        if (cap < n) return fail(c, SGAD_ERANGE, "key buffer too small");
+        HIPCHK(c, hipMemcpy(keys, S->B.keys + start[0], n * 8, hipMemcpyDeviceToHost));
+    }
+    return SGAD_OK;
+}
+
+sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam* vcam, const float* obs_depth,
+                          double* pose, int iters, double* trace, uint32_t flags, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!geo || !vcam || !obs_depth || !pose) return fail(c, SGAD_EINVAL, "null argument");
+    if (iters < 1 || iters > 1000) return fail(c, SGAD_ERANGE, "iters must be in [1, 1000]");
+    if (!cam_ok(geo->cam) || !cam_ok(*vcam)) return fail(c, SGAD_EINVAL, "bad camera");
+    if (!geo->depth || !geo->offset || !geo->radius || !geo->opacity || !geo->sigma)
+        return fail(c, SGAD_EINVAL, "geometry keyframe needs depth, offset, radius, opacity and sigma");
+    if (!finite_pose(geo->T_cw)) return fail(c, SGAD_EINVAL, "non-finite keyframe pose");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    poll(c, false);
+    auto& T = c->track;
+    int TW = c->tile_w ? c->tile_w : 16, TH = c->tile_h ? c->tile_h : 16;
+    Geometry& G = T.G;
+    const int64_t N = (int64_t)geo->cam.H * geo->cam.W;
+    const bool same_shape = T.sized && G.Hk == geo->cam.H && G.Wk == geo->cam.W && G.Hv == vcam->H &&
+                            G.Wv == vcam->W && G.TW == TW && G.TH == TH;
+    G.n_kf = 1;
+    G.n_jobs = 1;
+    G.n_pairs = 1;
+    G.Hk = geo->cam.H;
+    G.Wk = geo->cam.W;
+    G.N = (int)N;
+    G.Hv = vcam->H;
+    G.Wv = vcam->W;
+    G.P = G.Hv * G.Wv;
+    G.TW = TW;
+    G.TH = TH;
+    G.ntx = (G.Wv + TW - 1) / TW;
+    G.nty = (G.Hv + TH - 1) / TH;
+    G.ntiles = G.ntx * G.nty;
+    const size_t M = (size_t)G.ntiles;
+    if (!T.status_h) {
+        HIPCHK(c, hipHostMalloc((void**)&T.status_h, sizeof(DevStatus), hipHostMallocDefault));
+        HIPCHK(c, hipEventCreateWithFlags(&T.ev_status, hipEventDisableTiming));
+        HIPCHK(c, hipStreamCreateWithFlags(&T.cap, hipStreamNonBlocking));
+    }
+    if (T.status_pending) {
+        HIPCHK(c, hipEventSynchronize(T.ev_status));
+        T.status_pending = false;
+        latch_status(c, *T.status_h);
+    }
+    HIPCHK(c, ensure(T.params, 1024, s));
+    HIPCHK(c, ensure(T.pre, (size_t)N * 32, s));
+    HIPCHK(c, ensure(T.tiles, (3 * M + 1) * 4 + 256, s));
+    HIPCHK(c, ensure(T.part, M * 32 * 4, s));
+    HIPCHK(c, ensure(T.status, sizeof(DevStatus), s));
+    HIPCHK(c, ensure(T.trace, (size_t)iters * 40 * 8, s));
+    double* tr = trace ? trace : (double*)T.trace.p;
+    RenderBufs& B = T.B;
+    char* pb = (char*)T.params.p;
+    B.pairs = (const PairConst*)pb;
+    B.kfs = (const KfPtrs*)(pb + 512);
+    B.pair_of = (const int32_t*)(pb + 768);
+    char* pp = (char*)T.pre.p;
+    B.pre.dx = (float*)(pp + 0 * N * 4);
+    B.pre.dy = (float*)(pp + 1 * N * 4);
+    B.pre.ca = (float*)(pp + 2 * N * 4);
+    B.pre.cb = (float*)(pp + 3 * N * 4);
+    B.pre.cc = (float*)(pp + 4 * N * 4);
+    B.pre.z = (float*)(pp + 5 * N * 4);
+    B.pre.rx = (uint32_t*)(pp + 6 * N * 4);
+    B.pre.ry = (uint32_t*)(pp + 7 * N * 4);
+    uint32_t* tb = (uint32_t*)T.tiles.p;
+    B.tile_count = tb;
+    B.tile_fill = tb + M;
+    B.tile_start = tb + 2 * M;
+    B.status = (DevStatus*)T.status.p;
+    B.Tfinal = nullptr;
+    B.last = nullptr;
+    // constant tables: keyframe pointers and the single pair index
+    {
+        KfPtrs kp{geo->depth, geo->offset, geo->radius, geo->opacity, nullptr, geo->sigma};
+        int32_t zero = 0;
+        HIPCHK(c, hipMemcpyAsync((char*)T.params.p + 512, &kp, sizeof(kp), hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync((char*)T.params.p + 768, &zero, 4, hipMemcpyHostToDevice, s));
+    }
+    PairConst* pair_dev = (PairConst*)T.params.p;
+    if (!same_shape || !T.sized) {
+        // sizing pass at the starting pose (one host wait)
+        B.keys = nullptr;
+        B.capacity = 0;
+        launch_track_pair(pose, geo->T_cw, geo->cam, *vcam, pair_dev, s);
+        launch_zero_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, s);
+        launch_zero_u32(B.tile_count, (int64_t)M, s);
+        launch_preprocess(G, B, s);
+        launch_scan(G, B, s);
+        HIPCHK(c, hipMemcpyAsync(T.status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        const size_t cap = std::min<size_t>((size_t)T.status_h->total * 3 / 2 + 65536, 0xffffffffu);
+        if (cap > T.capacity) {
+            HIPCHK(c, ensure(T.keys, cap * 8, s));
+            T.capacity = (uint32_t)cap;
+        }
+        T.sized = true;
+    }
+    B.keys = (uint64_t*)T.keys.p;
+    B.capacity = T.capacity;
+    const void* key[8] = {geo->depth, geo->offset, geo->radius, geo->opacity, geo->sigma, obs_depth, pose, tr};
+    auto enqueue = [&](hipStream_t q) -> bool {
+        launch_zero_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, q);
+        for (int it = 0; it < iters; ++it) {
+            launch_track_pair(pose, geo->T_cw, geo->cam, *vcam, pair_dev, q);
+            launch_zero_u32((uint32_t*)B.status, 4, q);   // keeps the sticky word
+            launch_zero_u32(B.tile_count, (int64_t)M, q);
+            launch_preprocess(G, B, q);
+            launch_scan(G, B, q);
+            launch_scatter(G, B, q);
+            launch_sort(G, B, q);
+            if (!launch_track(G, B, obs_depth, (float*)T.part.p, q)) return false;
+            launch_track_solve((const float*)T.part.p, G.ntiles, pose, tr, it, B.status, q);
+        }
+        return true;
+    };
+    if (flags & 1u) {
+        bool reuse = T.exec && T.key_iters == iters && T.key_tw == TW && T.key_th == TH &&
+                     std::memcmp(T.key, key, sizeof(key)) == 0 && std::memcmp(&T.kc, &geo->cam, sizeof(sgad_cam)) == 0 &&
+                     std::memcmp(&T.vc, vcam, sizeof(sgad_cam)) == 0 &&
+                     std::memcmp(&T.kpose, &geo->T_cw, sizeof(sgad_pose)) == 0 && T.B.capacity == B.capacity;
+        if (!reuse) {
+            if (T.exec) (void)hipGraphExecDestroy(T.exec);
+            if (T.graph) (void)hipGraphDestroy(T.graph);
+            T.exec = nullptr;
+            T.graph = nullptr;
+            // the capture stream must see the tables written above
+            HIPCHK(c, hipStreamSynchronize(s));
+            HIPCHK(c, hipStreamBeginCapture(T.cap, hipStreamCaptureModeThreadLocal));
+            const bool ok = enqueue(T.cap);
+            hipGraph_t g = nullptr;
+            HIPCHK(c, hipStreamEndCapture(T.cap, &g));
+            if (!ok) {
+                (void)hipGraphDestroy(g);
+                return fail(c, SGAD_EINVAL, "unsupported tile shape");
+            }
+            T.graph = g;
+            HIPCHK(c, hipGraphInstantiate(&T.exec, g, nullptr, nullptr, 0));
+            std::memcpy(T.key, key, sizeof(key));
+            T.key_iters = iters;
+            T.key_tw = TW;
+            T.key_th = TH;
+            T.kc = geo->cam;
+            T.vc = *vcam;
+            T.kpose = geo->T_cw;
+        }
+        TimeScope ts(c, "track_graph", s);
+        HIPCHK(c, hipGraphLaunch(T.exec, s));
+    } else {
+        TimeScope ts(c, "track_loop", s);
+        if (!enqueue(s)) return fail(c, SGAD_EINVAL, "unsupported tile shape");
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(T.status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipEventRecord(T.ev_status, s));
+    T.status_pending = true;
+    return SGAD_OK;
+}
+
+}  // extern "C"

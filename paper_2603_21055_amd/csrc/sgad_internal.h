@@ -1,0 +1,103 @@
+// Internal structures shared by the host API and the HIP kernels of libsgad.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sgad.h"
+
+namespace sgad {
+
+// Splatting constants (see the conventions in sgad.h).
+constexpr double kLowpass = 0.3;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr double kZNear = 0.2;
+constexpr float kQCut = 9.0f;
+constexpr int kMaxKf = 64;
+constexpr int kMaxAdamGroups = 32;
+
+// Relative transform and intrinsics of one (job, keyframe) pair.
+struct PairConst {
+    double R[9];   // R_rel = R_view R_kf^T (FP64, fixed operation order)
+    double t[3];   // t_rel = t_view - R_rel t_kf
+    double kfx, kfy, kcx, kcy;  // keyframe intrinsics
+    double vfx, vfy, vcx, vcy;  // view intrinsics
+    float Rf[9], tf[3];         // the same transform rounded to float
+    int32_t job, kf;
+};
+
+struct KfPtrs {
+    const float* depth;
+    const float* offset;
+    const float* radius;
+    const float* opacity;
+    const float* rgb;
+    const float* sigma;
+};
+
+struct KfGradPtrs {
+    float* d_rgb;
+    float* d_opacity;
+    float* d_radius;
+    float* d_offset;
+};
+
+// Device-side status latched by kernels.
+struct DevStatus {
+    uint32_t total;      // instances after the count pass (all jobs)
+    uint32_t overflow;   // total > capacity
+    uint32_t nonfinite;  // a non-finite input was seen
+    uint32_t queue;      // work-queue counter of persistent kernels
+    uint32_t sticky;     // bit 0: an overflow, bit 1: a non-finite input, since the call began
+};
+
+// Preprocessed per (pair, Gaussian) data, SoA of length n_pairs * N.
+struct Preproc {
+    float* dx;     // m.x - u   (view pixels)
+    float* dy;     // m.y - v
+    float* ca;     // conic
+    float* cb;
+    float* cc;
+    float* z;      // view-space z (float)
+    uint32_t* rx;  // tile x0 | x1 << 16
+    uint32_t* ry;  // tile y0 | y1 << 16
+};
+
+struct Geometry {
+    int n_kf, n_jobs, n_pairs;
+    int Hk, Wk, N;        // keyframe size, N = Hk * Wk
+    int Hv, Wv, P;        // view size
+    int TW, TH, ntx, nty, ntiles;
+};
+
+struct RenderBufs {
+    const PairConst* pairs;   // [n_pairs]
+    const KfPtrs* kfs;        // [n_kf]
+    const int32_t* pair_of;   // [n_jobs * n_kf] -> pair index or -1
+    Preproc pre;
+    uint32_t* tile_count;     // [n_jobs * ntiles]
+    uint32_t* tile_start;     // [n_jobs * ntiles + 1]
+    uint32_t* tile_fill;      // [n_jobs * ntiles]
+    uint64_t* keys;           // [capacity]
+    uint32_t capacity;
+    float* Tfinal;            // [n_jobs * P]
+    uint32_t* last;           // [n_jobs * P]
+    DevStatus* status;
+};
+
+// Multi-tensor Adam: group g owns elements [off[g], off[g+1]) of the flat range.
+struct AdamGroups {
+    int n;
+    float* p[kMaxAdamGroups];
+    float* g[kMaxAdamGroups];
+    float* m[kMaxAdamGroups];
+    float* v[kMaxAdamGroups];
+    int64_t off[kMaxAdamGroups + 1];
+    float lr[kMaxAdamGroups];
+    float lo[kMaxAdamGroups];
+    float hi[kMaxAdamGroups];
+};
+
+}  // namespace sgad

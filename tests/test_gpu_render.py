@@ -1,0 +1,181 @@
+"""GPU parity of the splat forward/adjoint (through the C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import splat
+from paper_2603_21055_amd import synth
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+TILES = [(16, 16), (8, 8), (16, 8), (32, 8)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2603_21055_amd import sgad
+    assert torch.cuda.is_available()
+    c = sgad.Context(0)
+    yield c
+    c.close()
+
+
+def _upstream(seed, nj, Hh, W):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=(nj, 3, Hh, W)) / (Hh * W), rng.normal(size=(nj, Hh, W)) / (Hh * W),
+            rng.normal(size=(nj, Hh, W)) / (Hh * W))
+
+
+def _run_case(ctx, sc, jobs, tile, learnable, seed=0, check_grads=True):
+    import torch
+    print(f"case tile={tile} jobs={jobs} size={sc['views'][0]['cam']['W']}x{sc['views'][0]['cam']['H']}",
+          flush=True)
+    ctx.set_tile(*tile)
+    kfs_d = H.upload(sc["kfs"], ctx.device)
+    saved, out = H.gpu_render(ctx, kfs_d, sc["views"], jobs)
+    orc = [splat.render_job(sc["kfs"], sc["views"][v], ids) for v, ids in jobs]
+    torch.cuda.synchronize()
+    H.assert_forward_parity(out, orc)
+    if check_grads:
+        Hh, W = sc["views"][0]["cam"]["H"], sc["views"][0]["cam"]["W"]
+        gr, gd, ga = _upstream(seed, len(jobs), Hh, W)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(ctx.device)
+        grads, d_pose = H.gpu_backward(ctx, saved, kfs_d, t(gr), t(gd), t(ga), len(jobs), learnable)
+        torch.cuda.synchronize()
+        b = splat.render_backward(sc["kfs"], sc["views"], jobs, orc,
+                                  [g.astype(np.float32).astype(np.float64) for g in gr],
+                                  [g.astype(np.float32).astype(np.float64) for g in gd],
+                                  [g.astype(np.float32).astype(np.float64) for g in ga], learnable=set(learnable))
+        H.assert_grad_parity(grads, d_pose, b, orc, set(learnable))
+    ctx.release(saved)
+    ctx.sync()
+    return out
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_c1_forward_backward_parity(ctx, tile):
+    sc = synth.c1_scene(0)
+    _run_case(ctx, sc, [(1, [0])], tile, learnable=[0])
+
+
+def test_c1_identity_view(ctx):
+    sc = synth.c1_scene(0)
+    _run_case(ctx, sc, [(0, [0])], (16, 16), learnable=[0])
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_two_keyframes_two_views_ragged(ctx, tile):
+    # 37x21 spans several tiles with ragged edges in both directions
+    sc = synth.small_scene(21, 37, 21, n_kf=2, n_views=2, offset_amp=0.03, max_trans=0.05, max_rot=3)
+    jobs = [(0, [0, 1]), (1, [0, 1]), (1, [1])]
+    _run_case(ctx, sc, jobs, tile, learnable=[0, 1])
+
+
+def test_neighbour_keyframe_is_fixed(ctx):
+    sc = synth.small_scene(22, 48, 32, n_kf=2, n_views=1, offset_amp=0.03)
+    _run_case(ctx, sc, [(0, [0, 1])], (16, 16), learnable=[1])
+
+
+def test_medium_frame_parity(ctx):
+    sc = synth.small_scene(23, 160, 120, n_kf=1, n_views=1)
+    _run_case(ctx, sc, [(0, [0])], (16, 16), learnable=[0])
+
+
+def test_tile_shape_does_not_change_forward(ctx):
+    import torch
+    sc = synth.small_scene(24, 100, 75, n_kf=2, n_views=1, offset_amp=0.03, max_trans=0.05, max_rot=3)
+    kfs_d = H.upload(sc["kfs"], ctx.device)
+    outs = []
+    for tile in TILES:
+        ctx.set_tile(*tile)
+        saved, out = H.gpu_render(ctx, kfs_d, sc["views"], [(0, [0, 1])])
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu().numpy() for k, v in out.items()})
+        ctx.release(saved)
+    for o in outs[1:]:
+        for k in ("rgb", "depth", "alpha", "count"):
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
+def test_forward_is_deterministic(ctx):
+    import torch
+    sc = synth.small_scene(25, 64, 48, n_kf=2, n_views=1, offset_amp=0.03)
+    kfs_d = H.upload(sc["kfs"], ctx.device)
+    ctx.set_tile(16, 16)
+    res = []
+    for _ in range(3):
+        saved, out = H.gpu_render(ctx, kfs_d, sc["views"], [(0, [0, 1])])
+        torch.cuda.synchronize()
+        res.append({k: v.cpu().numpy() for k, v in out.items()})
+        ctx.release(saved)
+    for r in res[1:]:
+        for k in r:
+            assert np.array_equal(r[k], res[0][k])
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_binning_and_sort_bit_exact(ctx, tile):
+    import torch
+    sc = synth.small_scene(26, 45, 29, n_kf=2, n_views=2, offset_amp=0.03, max_trans=0.05, max_rot=3)
+    kfs_d = H.upload(sc["kfs"], ctx.device)
+    ctx.set_tile(*tile)
+    jobs = [(0, [0, 1]), (1, [1])]
+    saved, _ = H.gpu_render(ctx, kfs_d, sc["views"], jobs)
+    torch.cuda.synchronize()
+    for j, (v, ids) in enumerate(jobs):
+        ranges, keys = ctx.instances(saved, j)
+        g = splat.gather_job(sc["kfs"], sc["views"][v], ids)
+        b = splat.bin_and_sort(g, 45, 29, *tile)
+        assert np.array_equal(ranges.astype(np.int64), b["ranges"]), "tile ranges differ"
+        assert np.array_equal((keys >> np.uint64(32)).astype(np.uint32), b["zbits"]), "depth keys differ"
+        assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.int64), b["gid"]), "gids differ"
+    ctx.release(saved)
+
+
+def test_c2_full_frame_parity(ctx):
+    sc = synth.c2_scene(10)
+    _run_case(ctx, sc, [(0, [0])], (16, 16), learnable=[0])
+
+
+def test_everything_culled_renders_empty(ctx):
+    import torch
+    sc = synth.small_scene(27, 32, 24)
+    view = dict(sc["views"][0])
+    view["t"] = np.array([0.0, 0.0, -50.0], np.float32)   # scene far behind the camera
+    kfs_d = H.upload(sc["kfs"], ctx.device)
+    saved, out = H.gpu_render(ctx, kfs_d, [view], [(0, [0])])
+    torch.cuda.synchronize()
+    assert float(out["alpha"].abs().max()) == 0.0 and int(out["count"].max()) == 0
+    ctx.release(saved)
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    import torch
+    from paper_2603_21055_amd import sgad
+    sc = synth.small_scene(28, 16, 12)
+    kfs_d = H.upload(sc["kfs"], ctx.device)
+    with pytest.raises(sgad.SgadError) as e:
+        H.gpu_render(ctx, kfs_d, sc["views"], [(3, [0])])     # view index out of range
+    assert e.value.status == sgad.EINVAL
+    bad = dict(sc["views"][0])
+    bad["t"] = np.array([np.nan, 0, 0], np.float32)
+    with pytest.raises(sgad.SgadError) as e:
+        H.gpu_render(ctx, kfs_d, [bad], [(0, [0])])
+    assert e.value.status == sgad.EINVAL
+    with pytest.raises(sgad.SgadError):
+        ctx.set_tile(12, 12)
+
+
+def test_nonfinite_depth_is_latched(ctx):
+    import torch
+    from paper_2603_21055_amd import sgad
+    sc = synth.small_scene(29, 16, 12)
+    kfs_d = H.upload(sc["kfs"], ctx.device)
+    kfs_d[0]["depth"][3, 4] = float("nan")
+    saved, _ = H.gpu_render(ctx, kfs_d, sc["views"], [(0, [0])])
+    with pytest.raises(sgad.SgadError) as e:
+        ctx.sync()
+    assert e.value.status == sgad.EDATA
+    ctx.release(saved)
+    ctx.sync()   # cleared

@@ -1,0 +1,148 @@
+"""GPU parity of per-pixel depth-distribution Gauss-Newton tracking against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import se3, track
+from paper_2603_21055_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2603_21055_amd import sgad
+    assert torch.cuda.is_available()
+    c = sgad.Context(0)
+    c.set_tile(16, 16)
+    yield c
+    c.close()
+
+
+def _pose_vec(R, t):
+    return np.concatenate([np.asarray(R, np.float64).ravel(), np.asarray(t, np.float64).ravel()])
+
+
+def _pose_err(p, R, t):
+    Rg = p[:9].reshape(3, 3)
+    tg = p[9:]
+    dT = np.eye(4)
+    dT[:3, :3] = Rg @ np.asarray(R, np.float64).T
+    dT[:3, 3] = tg - dT[:3, :3] @ np.asarray(t, np.float64)
+    e = se3.log(dT)
+    return np.linalg.norm(e[:3]), np.degrees(np.linalg.norm(e[3:]))
+
+
+@pytest.fixture(scope="module")
+def small():
+    sc = synth.c4_tracking(31, W=160, H=90)
+    lin = track.linearise(sc["geo"], sc["cam"], sc["gt"]["R"].astype(np.float64),
+                          sc["gt"]["t"].astype(np.float64), np.ones((90, 160)))
+    sc["obs_model"] = np.where(lin["valid"], lin["mu"], 0.0).reshape(90, 160).astype(np.float32)
+    return sc
+
+
+def _run(ctx, sc, obs, iters, graph):
+    import torch
+    from paper_2603_21055_amd import sgad
+    dev = ctx.device
+    geo = sgad.to_device(sc["geo"], dev)
+    pose = torch.from_numpy(_pose_vec(sc["init"]["R"], sc["init"]["t"])).to(dev)
+    trace = torch.zeros((iters, 40), dtype=torch.float64, device=dev)
+    o = torch.from_numpy(np.ascontiguousarray(obs, np.float32)).to(dev)
+    ctx.track_gn(geo, sc["cam"], o, pose, iters=iters, trace=trace, graph=graph)
+    torch.cuda.synchronize()
+    ctx.sync()
+    return pose.cpu().numpy(), trace.cpu().numpy()
+
+
+def _unpack_H(rec):
+    H = np.zeros((6, 6))
+    q = 0
+    for i in range(6):
+        for j in range(i, 6):
+            H[i, j] = H[j, i] = rec[q]
+            q += 1
+    return H
+
+
+def test_first_iteration_normal_equations_match_oracle(ctx, small):
+    print("track small first iteration", flush=True)
+    pose, tr = _run(ctx, small, small["obs_model"], 1, graph=False)
+    lin = track.linearise(small["geo"], small["cam"], small["init"]["R"].astype(np.float64),
+                          small["init"]["t"].astype(np.float64), small["obs_model"].astype(np.float64))
+    H = _unpack_H(tr[0])
+    assert np.linalg.norm(H - lin["H"]) <= 1e-3 * np.linalg.norm(lin["H"])
+    assert np.linalg.norm(tr[0, 21:27] - lin["g"]) <= 1e-3 * np.linalg.norm(lin["g"])
+    assert abs(tr[0, 27] - lin["loglik"]) <= 1e-4 * abs(lin["loglik"]) + 1e-3 * lin["n_valid"]
+    assert abs(tr[0, 28] - lin["n_valid"]) <= max(3, int(lin["flags"].sum()))
+    dxi, _ = track.solve(lin["H"], lin["g"])
+    assert np.linalg.norm(tr[0, 30:36] - dxi) <= 1e-3 * np.linalg.norm(dxi)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_gn_recovers_model_pose(ctx, small, graph):
+    print(f"track small recover graph={graph}", flush=True)
+    pose, tr = _run(ctx, small, small["obs_model"], 30, graph=graph)
+    et, er = _pose_err(pose, small["gt"]["R"], small["gt"]["t"])
+    assert et < 2e-5 and er < 2e-3, (et, er)
+    orc = track.track_gn(small["geo"], small["cam"], small["init"]["R"], small["init"]["t"],
+                         small["obs_model"].astype(np.float64), iters=30)
+    ot, orr = _pose_err(pose, orc["R"], orc["t"])
+    assert ot < 2e-5 and orr < 2e-3
+
+
+def test_graph_replays_match_eager(ctx, small):
+    print("track graph replay", flush=True)
+    import torch
+    eager, tr_e = _run(ctx, small, small["obs_model"], 8, graph=False)
+    from paper_2603_21055_amd import sgad
+    dev = ctx.device
+    geo = sgad.to_device(small["geo"], dev)
+    pose = torch.zeros(12, dtype=torch.float64, device=dev)
+    trace = torch.zeros((8, 40), dtype=torch.float64, device=dev)
+    o = torch.from_numpy(small["obs_model"]).to(dev)
+    init = torch.from_numpy(_pose_vec(small["init"]["R"], small["init"]["t"])).to(dev)
+    for rep in range(3):
+        pose.copy_(init)
+        ctx.track_gn(geo, small["cam"], o, pose, iters=8, trace=trace, graph=True)
+        torch.cuda.synchronize()
+        scratch = torch.randn(1000, device=dev).sum().item()   # eager work between replays
+        assert np.isfinite(scratch)
+        assert np.array_equal(pose.cpu().numpy(), eager), rep
+        assert np.array_equal(trace.cpu().numpy(), tr_e), rep
+
+
+def test_single_plane_takes_damped_steps(ctx):
+    import torch
+    from paper_2603_21055_amd import sgad
+    cam = dict(H=30, W=40, fx=37.5, fy=37.5, cx=20.0, cy=15.0)
+    geo = synth.keyframe_from_frame(cam, np.eye(3), np.zeros(3), np.full((30, 40), 2.0, np.float32), None,
+                                    np.full((30, 40), 0.9, np.float32),
+                                    sigma=np.full((30, 40), 0.01, np.float32))
+    sc = dict(geo=geo, cam=cam, init=dict(R=np.eye(3), t=np.zeros(3)))
+    pose, tr = _run(ctx, sc, np.full((30, 40), 2.01, np.float32), 3, graph=False)
+    assert np.isfinite(pose).all() and np.isfinite(tr).all()
+    # depth-only alignment to a plane 1 cm further away: t_z -> +0.01
+    assert abs(pose[11] - 0.01) < 1e-3
+
+
+def test_c4_full_size_first_iteration(ctx):
+    print("track C4 1200x680 first iteration (oracle ~1 min)", flush=True)
+    sc = synth.c4_tracking(30)
+    pose, tr = _run(ctx, sc, sc["obs_depth"], 1, graph=False)
+    lin = track.linearise(sc["geo"], sc["cam"], sc["init"]["R"].astype(np.float64),
+                          sc["init"]["t"].astype(np.float64), sc["obs_depth"].astype(np.float64))
+    H = _unpack_H(tr[0])
+    assert np.linalg.norm(H - lin["H"]) <= 1e-3 * np.linalg.norm(lin["H"])
+    assert np.linalg.norm(tr[0, 21:27] - lin["g"]) <= 1e-3 * np.linalg.norm(lin["g"])
+
+
+def test_c4_full_size_converges(ctx):
+    print("track C4 1200x680 30 iterations", flush=True)
+    sc = synth.c4_tracking(30)
+    pose, tr = _run(ctx, sc, sc["obs_depth"], 30, graph=True)
+    et, er = _pose_err(pose, sc["gt"]["R"], sc["gt"]["t"])
+    # analytic box depth vs the splatted model: converges close to the truth
+    assert et < 5e-3 and er < 0.2, (et, er)
+    assert tr[-1, 27] > tr[0, 27]
