@@ -382,10 +382,56 @@ def pair_grads(g, P, comp, g_col, g_dep, g_alp):
         g_a=g_q * dx * dx, g_b=g_q * 2.0 * dx * dy, g_c=g_q * dy * dy,
         g_o=g_o, g_col=gc * w[:, None], g_z=gd * w, galpha=galpha,
     )
+    # the same terms with every product expanded to absolute values: bounds
+    # the rounding error of any evaluation order (tolerances, not the value)
+    aal = (np.abs(gc) * (np.abs(col) * Ti[:, None] + np.abs(S[:, :C]) * inv[:, None])).sum(1) \
+        + np.abs(gd) * (np.abs(z) * Ti + np.abs(S[:, C]) * inv) + np.abs(ga) * Tf * inv
+    aq = np.where(unclamped, 0.5 * a * aal, 0.0)
+    out.update(
+        a_mx=aq * 2.0 * (np.abs(A * dx) + np.abs(B * dy)),
+        a_my=aq * 2.0 * (np.abs(B * dx) + np.abs(Cc * dy)),
+        a_a=aq * dx * dx, a_b=aq * 2.0 * np.abs(dx * dy), a_c=aq * dy * dy,
+        a_o=np.where(unclamped, aal * P["G"], 0.0), a_col=np.abs(gc) * w[:, None], a_z=np.abs(gd) * w,
+    )
     for k in list(out):
         v = out[k]
         out[k] = np.where(con[:, None], v, 0.0) if v.ndim == 2 else np.where(con, v, 0.0)
     return out
+
+
+def geom_to_X_abs(g, idx, fx, fy, a_mx, a_my, a_a, a_b, a_c, a_z):
+    """``geom_to_X`` with every factor replaced by its absolute value and every
+    difference by a sum: a bound on the magnitudes the chain rule combines."""
+    x, y, z = np.abs(g["x"][idx]), np.abs(g["y"][idx]), g["z"][idx]
+    r = np.abs(g["r"][idx])
+    s00, s01, s11 = g["s00"][idx], g["s01"][idx], g["s11"][idx]
+    n = len(idx)
+    det = s00 * s11 - s01 * s01
+    Q = np.empty((n, 2, 2))
+    Q[:, 0, 0] = s11 / det
+    Q[:, 0, 1] = Q[:, 1, 0] = np.abs(s01) / det
+    Q[:, 1, 1] = s00 / det
+    Gm = np.empty((n, 2, 2))
+    Gm[:, 0, 0] = a_a
+    Gm[:, 0, 1] = Gm[:, 1, 0] = 0.5 * a_b
+    Gm[:, 1, 1] = a_c
+    GS = np.einsum("nij,njk,nkl->nil", Q, Gm, Q)
+    a00, a01, a11 = GS[:, 0, 0], 2.0 * GS[:, 0, 1], GS[:, 1, 1]
+    iz = 1.0 / z
+    K00 = fx * fx * (iz * iz + x * x * iz ** 4)
+    K01 = fx * fy * x * y * iz ** 4
+    K11 = fy * fy * (iz * iz + y * y * iz ** 4)
+    a_r = 2.0 * r * (a00 * K00 + a01 * K01 + a11 * K11)
+    r2 = r * r
+    ax = r2 * (a00 * 2.0 * fx * fx * x * iz ** 4 + a01 * fx * fy * y * iz ** 4)
+    ay = r2 * (a01 * fx * fy * x * iz ** 4 + a11 * 2.0 * fy * fy * y * iz ** 4)
+    az = r2 * (a00 * fx * fx * (2.0 * iz ** 3 + 4.0 * x * x * iz ** 5)
+               + a01 * 4.0 * fx * fy * x * y * iz ** 5
+               + a11 * fy * fy * (2.0 * iz ** 3 + 4.0 * y * y * iz ** 5))
+    ax = ax + a_mx * fx * iz
+    ay = ay + a_my * fy * iz
+    az = az + a_mx * fx * x * iz * iz + a_my * fy * y * iz * iz + a_z
+    return np.stack([ax, ay, az], 1), a_r
 
 
 def geom_to_X(g, idx, fx, fy, g_mx, g_my, g_a, g_b, g_c, g_z):
@@ -452,24 +498,20 @@ def backward_job(kfs, view, fwd, g_rgb, g_depth, g_alpha):
 
     G = {k: acc(pg[k]) for k in ("g_mx", "g_my", "g_a", "g_b", "g_c", "g_o", "g_z")}
     G["g_col"] = np.stack([acc(pg["g_col"][:, c]) for c in range(C)], 1)
-    A = {k: acc(np.abs(pg[k])) for k in ("g_mx", "g_my", "g_a", "g_b", "g_c", "g_o", "g_z")}
-    A["g_col"] = np.stack([acc(np.abs(pg["g_col"][:, c])) for c in range(C)], 1)
+    A = {"g_" + k[2:]: acc(pg[k]) for k in ("a_mx", "a_my", "a_a", "a_b", "a_c", "a_o", "a_z")}
+    A["g_col"] = np.stack([acc(pg["a_col"][:, c]) for c in range(C)], 1)
 
     idx = np.nonzero(g["valid"])[0]
     gX = np.zeros((M, 3))
     g_r = np.zeros(M)
     gX[idx], g_r[idx] = geom_to_X(g, idx, fx, fy, G["g_mx"][idx], G["g_my"][idx], G["g_a"][idx],
                                   G["g_b"][idx], G["g_c"][idx], G["g_z"][idx])
-    # absolute bound: push |terms| through the same linear maps with |coefficients|
+    # absolute bound: the absolute terms through the chain with |factors|
     aX = np.zeros((M, 3))
     a_r = np.zeros(M)
     if len(idx):
-        for key in ("g_mx", "g_my", "g_a", "g_b", "g_c", "g_z"):
-            args = {k: np.zeros(len(idx)) for k in ("g_mx", "g_my", "g_a", "g_b", "g_c", "g_z")}
-            args[key] = A[key][idx]
-            vX, vr = geom_to_X(g, idx, fx, fy, **args)
-            aX[idx] += np.abs(vX)
-            a_r[idx] += np.abs(vr)
+        aX[idx], a_r[idx] = geom_to_X_abs(g, idx, fx, fy, A["g_mx"][idx], A["g_my"][idx], A["g_a"][idx],
+                                          A["g_b"][idx], A["g_c"][idx], A["g_z"][idx])
     # X = R_rel (d * ray) + t_rel: dL/dd = (R^T gX) . ray, then |D + delta|
     ray = np.stack([g["xn"], g["yn"], np.ones(M)], 1)
     Rs = []
