@@ -224,17 +224,28 @@ typedef struct {
     float* v;
     int64_t n;
     float lr;
-    float lo, hi; /* the parameter is clamped to [lo, hi] after the step */
+    float lo, hi;  /* the parameter is clamped to [lo, hi] after the step */
+    int32_t space; /* SGAD_SPACE_*: the space Adam steps in */
 } sgad_adam_group;
 
+#define SGAD_SPACE_LINEAR 0 /* theta = p */
+#define SGAD_SPACE_LOG 1    /* theta = log p (radius), dL/dtheta = p dL/dp */
+#define SGAD_SPACE_LOGIT 2  /* theta = log(p / (1 - p)) (opacity), dL/dtheta = p (1 - p) dL/dp */
+
 /*
- * Adam step (t = step >= 1) over up to 32 tensors in one launch:
+ * Adam step (t = step >= 1) over up to 32 tensors in one launch.  The
+ * parameter p is mapped to theta (per group `space`), g to dL/dtheta, then
  *   m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
- *   p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), then clamp.
+ *   theta -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps),
+ * and p = inverse map of theta, clamped to [lo, hi].  m and v hold the
+ * moments of dL/dtheta.  Logit maps clamp p to [1e-6, 1 - 1e-6] first, log
+ * maps to >= 1e-12.
  * The grads are zeroed afterwards when zero_grad != 0 (the backward
  * accumulates).  The supplement gives the learning rates (colour 0.0025,
- * radius 0.005, opacity 0.05, offset 0.01); Adam itself is this library's
- * reading of the unnamed optimiser.
+ * radius 0.005, opacity 0.05, offset 0.01); they are the 3DGS values for
+ * log-scale and logit-opacity parameters, so the driver steps radius in
+ * SGAD_SPACE_LOG and opacity in SGAD_SPACE_LOGIT; Adam itself is this
+ * library's reading of the unnamed optimiser.
  */
 sgad_status sgad_adam_step(sgad_ctx* ctx, int n_groups, const sgad_adam_group* groups, int step,
                            float beta1, float beta2, float eps, int zero_grad, void* stream);

@@ -92,12 +92,22 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
         for (int ty = y0; ty < y1; ++ty)
             for (int tx = x0; tx < x1; ++tx) atomicAdd(&cnt[ty * G.ntx + tx], 1u);
     }
-    B.pre.dx[i] = fdx;
-    B.pre.dy[i] = fdy;
-    B.pre.ca[i] = fa;
-    B.pre.cb[i] = fb;
-    B.pre.cc[i] = fc;
-    B.pre.z[i] = ok ? (float)z : 0.f;
+    const float fz = ok ? (float)z : 0.f;
+    float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    if (kp.rgb) {
+        c0 = kp.rgb[pix];
+        c1 = kp.rgb[(size_t)G.N + pix];
+        c2 = kp.rgb[2 * (size_t)G.N + pix];
+    } else if (kp.sigma) {
+        const float sg = kp.sigma[pix];
+        c0 = sg * sg;
+    }
+    float4* rec = B.pre.rec + 4 * i;
+    rec[0] = make_float4((float)u, (float)v, fdx, fdy);
+    rec[1] = make_float4(fa, fb, fc, kp.opacity[pix]);
+    rec[2] = make_float4(c0, c1, c2, fz);
+    rec[3] = make_float4(ok ? (float)x : 0.f, ok ? (float)y : 0.f, Rf, s >= 0.0 ? 1.f : -1.f);
+    B.pre.z[i] = fz;
     B.pre.rx[i] = rx;
     B.pre.ry[i] = ry;
 }

@@ -71,13 +71,28 @@ __global__ __launch_bounds__(256) void k_adam(AdamGroups A, float b1, float b2, 
         int gi = 0;
         while (gi + 1 < A.n && i >= A.off[gi + 1]) ++gi;
         const int64_t k = i - A.off[gi];
-        const float g = A.g[gi][k];
+        const int sp = A.space[gi];
+        float p = A.p[gi][k];
+        float g = A.g[gi][k];
+        float th = p;
+        if (sp == 1) {
+            p = fmaxf(p, 1e-12f);
+            th = logf(p);
+            g *= p;
+        } else if (sp == 2) {
+            p = fminf(fmaxf(p, 1e-6f), 1.f - 1e-6f);
+            th = logf(p / (1.f - p));
+            g *= p * (1.f - p);
+        }
         const float m = b1 * A.m[gi][k] + (1.f - b1) * g;
         const float v = b2 * A.v[gi][k] + (1.f - b2) * g * g;
         A.m[gi][k] = m;
         A.v[gi][k] = v;
         const float mh = m / c1, vh = v / c2;
-        float p = A.p[gi][k] - A.lr[gi] * mh / (sqrtf(vh) + eps);
+        th -= A.lr[gi] * mh / (sqrtf(vh) + eps);
+        if (sp == 1) p = expf(th);
+        else if (sp == 2) p = 1.f / (1.f + expf(-th));
+        else p = th;
         p = fminf(fmaxf(p, A.lo[gi]), A.hi[gi]);
         A.p[gi][k] = p;
         if (zero_grad) A.g[gi][k] = 0.f;

@@ -9,48 +9,9 @@
 // and the view pose once per (Gaussian, tile) before a few global atomics.
 #include <hip/hip_runtime.h>
 
-#include "sgad_internal.h"
+#include "raster_common.h"
 
 namespace sgad {
-
-// -0.5 * log2(e): exp(-q/2) = 2^(q * kNegHalfLog2e)
-constexpr float kNegHalfLog2e = -0.72134752044448170368f;
-
-// q = a dx^2 + 2 b dx dy + c dy^2 with a fixed, unfused-by-the-compiler
-// sequence; forward and backward call the same function so their
-// contribution decisions agree bit for bit.
-__device__ __forceinline__ float pair_q(float dx, float dy, float a, float b, float c) {
-#pragma clang fp contract(off)
-    const float t = __builtin_fmaf(b + b, dy, a * dx);
-    return __builtin_fmaf(dx, t, (c * dy) * dy);
-}
-
-__device__ __forceinline__ float gauss_of_q(float q) {
-#pragma clang fp contract(off)
-    return __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-struct FwdOut {
-    float* rgb;      // [n_jobs][3][P]
-    float* depth;    // [n_jobs][P]
-    float* alpha;    // [n_jobs][P]
-    int32_t* count;  // [n_jobs][P] or null
-};
-
-struct BwdArgs {
-    const float* g_rgb;    // [n_jobs][3][P]
-    const float* g_depth;  // [n_jobs][P] or null
-    const float* g_alpha;  // [n_jobs][P] or null
-    const KfGradPtrs* grads;  // [n_kf]
-    uint32_t learn_lo, learn_hi;
-    float* pose_part;      // [n_jobs * ntiles][6]
-};
 
 // Stage one instance: source pixel (u, v) and screen displacement of the
 // mean, conic, opacity, depth and colour.  A pixel's offset from the mean is
@@ -63,17 +24,10 @@ __device__ __forceinline__ void load_entry(const Geometry& G, const RenderBufs& 
     const int kf = (int)(gid / (uint32_t)G.N);
     const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
     const int pair = B.pair_of[job * G.n_kf + kf];
-    const size_t idx = (size_t)pair * G.N + pix;
-    const int u = pix % G.Wk, v = pix / G.Wk;
-    const KfPtrs kp = B.kfs[kf];
-    eu = make_float4((float)u, (float)v, B.pre.dx[idx], B.pre.dy[idx]);
-    eg = make_float4(B.pre.ca[idx], B.pre.cb[idx], B.pre.cc[idx], kp.opacity[pix]);
-    if (kp.rgb)
-        ec = make_float4(kp.rgb[pix], kp.rgb[(size_t)G.N + pix], kp.rgb[2 * (size_t)G.N + pix], B.pre.z[idx]);
-    else {
-        const float sg = kp.sigma ? kp.sigma[pix] : 0.f;
-        ec = make_float4(sg * sg, 0.f, 0.f, B.pre.z[idx]);
-    }
+    const float4* rec = B.pre.rec + 4 * ((size_t)pair * G.N + pix);
+    eu = rec[0];
+    eg = rec[1];
+    ec = rec[2];
 }
 
 template <int TW, int TH>
@@ -145,72 +99,6 @@ __global__ __launch_bounds__(TW* TH) void k_fwd(Geometry G, RenderBufs B, FwdOut
     if (O.count) O.count[jp] = cnt;
     B.Tfinal[jp] = T;
     B.last[jp] = last;
-}
-
-// Chain rule of one (Gaussian, tile) gradient to the keyframe parameters and
-// the view pose (recomputes the view-space geometry in FP32).
-// v = [g_mx, g_my, g_a, g_b, g_c, g_o, g_z, g_r, g_g, g_b]
-__device__ __forceinline__ void flush_entry(const Geometry& G, const RenderBufs& B, const BwdArgs& A,
-                                            int job, uint64_t key, const float* v, float* pose) {
-    const uint32_t gid = (uint32_t)key;
-    const int kf = (int)(gid / (uint32_t)G.N);
-    const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
-    const int pair = B.pair_of[job * G.n_kf + kf];
-    const PairConst& pc = B.pairs[pair];
-    const KfPtrs kp = B.kfs[kf];
-    const int u = pix % G.Wk, vv = pix / G.Wk;
-    const float s = kp.depth[pix] + kp.offset[pix];
-    const float d = fabsf(s);
-    const float sgn = s >= 0.f ? 1.f : -1.f;
-    const float r = kp.radius[pix];
-    const float xn = ((float)u - (float)pc.kcx) / (float)pc.kfx;
-    const float yn = ((float)vv - (float)pc.kcy) / (float)pc.kfy;
-    const float X0 = d * xn, X1 = d * yn, X2 = d;
-    const float* R = pc.Rf;
-    const float x = R[0] * X0 + R[1] * X1 + R[2] * X2 + pc.tf[0];
-    const float y = R[3] * X0 + R[4] * X1 + R[5] * X2 + pc.tf[1];
-    const float z = R[6] * X0 + R[7] * X1 + R[8] * X2 + pc.tf[2];
-    const float fx = (float)pc.vfx, fy = (float)pc.vfy;
-    const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz, iz4 = iz2 * iz2, iz5 = iz4 * iz;
-    const float tx = x * iz, ty = y * iz, jx = fx * iz, jy = fy * iz;
-    const float k00 = jx * jx * (1.f + tx * tx), k01 = jx * jy * (tx * ty), k11 = jy * jy * (1.f + ty * ty);
-    const float r2 = r * r;
-    const float s00 = r2 * k00 + (float)kLowpass, s01 = r2 * k01, s11 = r2 * k11 + (float)kLowpass;
-    const float idet = 1.f / (s00 * s11 - s01 * s01);
-    const float q00 = s11 * idet, q01 = -s01 * idet, q11 = s00 * idet;
-    const float ga = v[2], hb = 0.5f * v[3], gc = v[4];
-    const float m00 = ga * q00 + hb * q01, m01 = ga * q01 + hb * q11;
-    const float m10 = hb * q00 + gc * q01, m11 = hb * q01 + gc * q11;
-    const float gs00 = -(q00 * m00 + q01 * m10);
-    const float gs01 = -2.f * (q00 * m01 + q01 * m11);
-    const float gs11 = -(q01 * m01 + q11 * m11);
-    const float g_r = 2.f * r * (gs00 * k00 + gs01 * k01 + gs11 * k11);
-    float gx = r2 * (gs00 * 2.f * fx * fx * x * iz4 + gs01 * fx * fy * y * iz4);
-    float gy = r2 * (gs01 * fx * fy * x * iz4 + gs11 * 2.f * fy * fy * y * iz4);
-    float gz = r2 * (gs00 * fx * fx * (-2.f * iz3 - 4.f * x * x * iz5) + gs01 * (-4.f * fx * fy * x * y * iz5) +
-                     gs11 * fy * fy * (-2.f * iz3 - 4.f * y * y * iz5));
-    gx += v[0] * fx * iz;
-    gy += v[1] * fy * iz;
-    gz += -v[0] * fx * x * iz2 - v[1] * fy * y * iz2 + v[6];
-    pose[0] += gx;
-    pose[1] += gy;
-    pose[2] += gz;
-    pose[3] += y * gz - z * gy;
-    pose[4] += z * gx - x * gz;
-    pose[5] += x * gy - y * gx;
-    const bool learn = kf < 32 ? ((A.learn_lo >> kf) & 1u) : ((A.learn_hi >> (kf - 32)) & 1u);
-    if (!learn) return;
-    const float gxf = R[0] * gx + R[3] * gy + R[6] * gz;
-    const float gyf = R[1] * gx + R[4] * gy + R[7] * gz;
-    const float gzf = R[2] * gx + R[5] * gy + R[8] * gz;
-    const float g_off = (gxf * xn + gyf * yn + gzf) * sgn;
-    const KfGradPtrs gp = A.grads[kf];
-    atomicAdd(&gp.d_offset[pix], g_off);
-    atomicAdd(&gp.d_radius[pix], g_r);
-    atomicAdd(&gp.d_opacity[pix], v[5]);
-    atomicAdd(&gp.d_rgb[pix], v[7]);
-    atomicAdd(&gp.d_rgb[(size_t)G.N + pix], v[8]);
-    atomicAdd(&gp.d_rgb[2 * (size_t)G.N + pix], v[9]);
 }
 
 template <int TW, int TH>
@@ -372,10 +260,13 @@ static void bwd_t(const Geometry& G, const RenderBufs& B, const BwdArgs& A, hipS
     hipLaunchKernelGGL((k_bwd<TW, TH>), dim3(G.n_jobs * G.ntiles), dim3(TW * TH), 0, s, G, B, A);
 }
 
+bool launch_fwd8(const Geometry& G, const RenderBufs& B, const FwdOut& O, int sc, hipStream_t s);
+bool launch_bwd8(const Geometry& G, const RenderBufs& B, const BwdArgs& A, int sc, hipStream_t s);
+
 bool launch_fwd(const Geometry& G, const RenderBufs& B, float* rgb, float* depth, float* alpha, int32_t* count,
                 hipStream_t s) {
     FwdOut O{rgb, depth, alpha, count};
-    if (G.TW == 8 && G.TH == 8) fwd_t<8, 8>(G, B, O, s);
+    if (G.TW == 8 && G.TH == 8) return launch_fwd8(G, B, O, G.sc_fwd, s);
     else if (G.TW == 16 && G.TH == 8) fwd_t<16, 8>(G, B, O, s);
     else if (G.TW == 16 && G.TH == 16) fwd_t<16, 16>(G, B, O, s);
     else if (G.TW == 32 && G.TH == 8) fwd_t<32, 8>(G, B, O, s);
@@ -387,7 +278,9 @@ bool launch_bwd(const Geometry& G, const RenderBufs& B, const float* g_rgb, cons
                 const float* g_alpha, const KfGradPtrs* grads, uint32_t lo, uint32_t hi, float* pose_part,
                 float* d_pose, hipStream_t s) {
     BwdArgs A{g_rgb, g_depth, g_alpha, grads, lo, hi, pose_part};
-    if (G.TW == 8 && G.TH == 8) bwd_t<8, 8>(G, B, A, s);
+    if (G.TW == 8 && G.TH == 8) {
+        if (!launch_bwd8(G, B, A, G.sc_bwd, s)) return false;
+    }
     else if (G.TW == 16 && G.TH == 8) bwd_t<16, 8>(G, B, A, s);
     else if (G.TW == 16 && G.TH == 16) bwd_t<16, 16>(G, B, A, s);
     else if (G.TW == 32 && G.TH == 8) bwd_t<32, 8>(G, B, A, s);

@@ -85,27 +85,18 @@ __device__ void load_track_entry(const Geometry& G, const RenderBufs& B, uint64_
     const uint32_t gid = (uint32_t)key;
     const int pix = (int)gid;   // one keyframe
     const PairConst& pc = B.pairs[0];
-    const KfPtrs kp = B.kfs[0];
-    const int u = pix % G.Wk, v = pix / G.Wk;
-    const float a = B.pre.ca[pix], b = B.pre.cb[pix], c = B.pre.cc[pix];
-    const float sg = kp.sigma[pix];
-    e.u = make_float4((float)u, (float)v, B.pre.dx[pix], B.pre.dy[pix]);
-    e.g = make_float4(a, b, c, kp.opacity[pix]);
-    // view-space centre and the derivatives of mean and conic w.r.t. it (FP32)
-    const float s = kp.depth[pix] + kp.offset[pix];
-    const float d = fabsf(s);
-    const float r = kp.radius[pix];
-    const float xn = ((float)u - (float)pc.kcx) / (float)pc.kfx;
-    const float yn = ((float)v - (float)pc.kcy) / (float)pc.kfy;
-    const float X0 = d * xn, X1 = d * yn, X2 = d;
-    const float* R = pc.Rf;
-    const float x = R[0] * X0 + R[1] * X1 + R[2] * X2 + pc.tf[0];
-    const float y = R[3] * X0 + R[4] * X1 + R[5] * X2 + pc.tf[1];
-    const float z = B.pre.z[pix];
+    const float4* rec = B.pre.rec + 4 * (size_t)pix;
+    const float4 r1 = rec[1], r2v = rec[2], r3 = rec[3];
+    const float a = r1.x, b = r1.y, c = r1.z;
+    e.u = rec[0];
+    e.g = r1;
+    const float r = r3.z;
+    const float x = r3.x, y = r3.y, z = r2v.w;
+    const float sg2 = r2v.x;
     const float fx = (float)pc.vfx, fy = (float)pc.vfy;
     const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz, iz4 = iz2 * iz2, iz5 = iz4 * iz;
     const float r2 = r * r;
-    e.c = make_float4(sg * sg, z, x, y);
+    e.c = make_float4(sg2, z, x, y);
     e.m = make_float4(fx * iz, fy * iz, -fx * x * iz2, -fy * y * iz2);
     // dSigma/dX_k (s00, s01, s11), k = x, y, z
     const float p[3] = {r2 * 2.f * fx * fx * x * iz4, 0.f, r2 * fx * fx * (-2.f * iz3 - 4.f * x * x * iz5)};

@@ -1,0 +1,135 @@
+// Device helpers shared by every compositing kernel.  The forward and
+// backward of every variant evaluate a (pixel, Gaussian) pair through these
+// functions, so their contribution decisions (q <= 9, alpha >= 1/255, the
+// 0.99 clamp) agree bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sgad_internal.h"
+
+namespace sgad {
+
+// -0.5 * log2(e): exp(-q/2) = 2^(q * kNegHalfLog2e)
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;
+
+// q = a dx^2 + 2 b dx dy + c dy^2 in a fixed sequence (no contraction left
+// to the compiler).
+__device__ __forceinline__ float pair_q(float dx, float dy, float a, float b, float c) {
+#pragma clang fp contract(off)
+    const float t = __builtin_fmaf(b + b, dy, a * dx);
+    return __builtin_fmaf(dx, t, (c * dy) * dy);
+}
+
+__device__ __forceinline__ float gauss_of_q(float q) {
+#pragma clang fp contract(off)
+    return __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct FwdOut {
+    float* rgb;      // [n_jobs][3][P]
+    float* depth;    // [n_jobs][P]
+    float* alpha;    // [n_jobs][P]
+    int32_t* count;  // [n_jobs][P] or null
+};
+
+struct BwdArgs {
+    const float* g_rgb;       // [n_jobs][3][P]
+    const float* g_depth;     // [n_jobs][P] or null
+    const float* g_alpha;     // [n_jobs][P] or null
+    const KfGradPtrs* grads;  // [n_kf]
+    uint32_t learn_lo, learn_hi;
+    float* pose_part;         // [n_jobs * ntiles][6]
+};
+
+// Record of the instance `key` of job `job`.
+__device__ __forceinline__ const float4* entry_record(const Geometry& G, const RenderBufs& B, int job,
+                                                      uint64_t key) {
+    const uint32_t gid = (uint32_t)key;
+    const int kf = (int)(gid / (uint32_t)G.N);
+    const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
+    const int pair = B.pair_of[job * G.n_kf + kf];
+    return B.pre.rec + 4 * ((size_t)pair * G.N + pix);
+}
+
+// Chain rule of one (Gaussian, tile) gradient to the keyframe parameters and
+// the view pose.  v = [g_mx, g_my, g_a, g_b, g_c, g_o, g_z, g_c0, g_c1, g_c2].
+__device__ __forceinline__ void flush_entry(const Geometry& G, const RenderBufs& B, const BwdArgs& A, int job,
+                                            uint64_t key, const float* v, float* pose) {
+    const uint32_t gid = (uint32_t)key;
+    const int kf = (int)(gid / (uint32_t)G.N);
+    const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
+    const int pair = B.pair_of[job * G.n_kf + kf];
+    const PairConst& pc = B.pairs[pair];
+    const float4* rec = B.pre.rec + 4 * ((size_t)pair * G.N + pix);
+    const float4 r0 = rec[0], r3 = rec[3];
+    const float z = rec[2].w;
+    const float x = r3.x, y = r3.y;
+    const float r = r3.z;
+    const float sgn = r3.w;
+    const float xn = (r0.x - (float)pc.kcx) / (float)pc.kfx;
+    const float yn = (r0.y - (float)pc.kcy) / (float)pc.kfy;
+    const float* R = pc.Rf;
+    const float fx = (float)pc.vfx, fy = (float)pc.vfy;
+    const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz, iz4 = iz2 * iz2, iz5 = iz4 * iz;
+    const float tx = x * iz, ty = y * iz, jx = fx * iz, jy = fy * iz;
+    const float k00 = jx * jx * (1.f + tx * tx), k01 = jx * jy * (tx * ty), k11 = jy * jy * (1.f + ty * ty);
+    const float r2 = r * r;
+    const float s00 = r2 * k00 + (float)kLowpass, s01 = r2 * k01, s11 = r2 * k11 + (float)kLowpass;
+    const float idet = 1.f / (s00 * s11 - s01 * s01);
+    const float q00 = s11 * idet, q01 = -s01 * idet, q11 = s00 * idet;
+    const float ga = v[2], hb = 0.5f * v[3], gc = v[4];
+    const float m00 = ga * q00 + hb * q01, m01 = ga * q01 + hb * q11;
+    const float m10 = hb * q00 + gc * q01, m11 = hb * q01 + gc * q11;
+    const float gs00 = -(q00 * m00 + q01 * m10);
+    const float gs01 = -2.f * (q00 * m01 + q01 * m11);
+    const float gs11 = -(q01 * m01 + q11 * m11);
+    const float g_r = 2.f * r * (gs00 * k00 + gs01 * k01 + gs11 * k11);
+    float gx = r2 * (gs00 * 2.f * fx * fx * x * iz4 + gs01 * fx * fy * y * iz4);
+    float gy = r2 * (gs01 * fx * fy * x * iz4 + gs11 * 2.f * fy * fy * y * iz4);
+    float gz = r2 * (gs00 * fx * fx * (-2.f * iz3 - 4.f * x * x * iz5) + gs01 * (-4.f * fx * fy * x * y * iz5) +
+                     gs11 * fy * fy * (-2.f * iz3 - 4.f * y * y * iz5));
+    gx += v[0] * fx * iz;
+    gy += v[1] * fy * iz;
+    gz += -v[0] * fx * x * iz2 - v[1] * fy * y * iz2 + v[6];
+    pose[0] += gx;
+    pose[1] += gy;
+    pose[2] += gz;
+    pose[3] += y * gz - z * gy;
+    pose[4] += z * gx - x * gz;
+    pose[5] += x * gy - y * gx;
+    const bool learn = kf < 32 ? ((A.learn_lo >> kf) & 1u) : ((A.learn_hi >> (kf - 32)) & 1u);
+    if (!learn) return;
+    const float gxf = R[0] * gx + R[3] * gy + R[6] * gz;
+    const float gyf = R[1] * gx + R[4] * gy + R[7] * gz;
+    const float gzf = R[2] * gx + R[5] * gy + R[8] * gz;
+    const float g_off = (gxf * xn + gyf * yn + gzf) * sgn;
+    const KfGradPtrs gp = A.grads[kf];
+    atomicAdd(&gp.d_offset[pix], g_off);
+    atomicAdd(&gp.d_radius[pix], g_r);
+    atomicAdd(&gp.d_opacity[pix], v[5]);
+    atomicAdd(&gp.d_rgb[pix], v[7]);
+    atomicAdd(&gp.d_rgb[(size_t)G.N + pix], v[8]);
+    atomicAdd(&gp.d_rgb[2 * (size_t)G.N + pix], v[9]);
+}
+
+// Spread consecutive workgroups over the XCDs in contiguous ranges: the
+// hardware hands out workgroup ids round-robin to the 8 XCDs, so a workgroup
+// on XCD x with local index k is given the k-th item of XCD x's range and
+// neighbouring tiles (which share Gaussians) meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    const int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return base + k;
+}
+
+__device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
+}  // namespace sgad

@@ -58,6 +58,7 @@ struct sgad_saved {
     DevBuf params, pre, tiles, keys, pix, pose_part, status, gradptrs;
     uint32_t capacity = 0;
     bool sized = false;
+    size_t size_key[5] = {0, 0, 0, 0, 0};  // workload the capacity was sized for
     // pinned staging
     PinBuf up, up_grad;
     DevStatus* status_h = nullptr;
@@ -82,6 +83,7 @@ struct sgad_ctx {
     int device = 0;
     std::string err;
     sgad_status latched = SGAD_OK;
+    std::string latched_msg;
     int tile_w = 16, tile_h = 16;
     int last_tw = 16, last_th = 16;
     std::vector<sgad_saved*> slots;
@@ -205,18 +207,19 @@ hipError_t ensure_pin(PinBuf& b, size_t bytes) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-void latch_status(sgad_ctx* c, const DevStatus& st) {
-    if ((st.nonfinite || (st.sticky & 2u)) && c->latched == SGAD_OK) {
-        c->latched = SGAD_EDATA;
-        c->err = "non-finite depth, offset or radius in a keyframe";
-    }
-    if ((st.overflow || (st.sticky & 1u)) && c->latched == SGAD_OK) {
-        c->latched = SGAD_ERANGE;
-        c->err = "instance list overflow";
-    }
+void latch(sgad_ctx* c, sgad_status st, const char* msg) {
+    if (c->latched != SGAD_OK) return;
+    c->latched = st;
+    c->latched_msg = msg;
 }
 
-// Read device-side conditions of finished forwards without blocking.
+void latch_status(sgad_ctx* c, const DevStatus& st) {
+    if (st.nonfinite || (st.sticky & 2u)) latch(c, SGAD_EDATA, "non-finite depth, offset or radius in a keyframe");
+    if (st.overflow || (st.sticky & 1u))
+        latch(c, SGAD_ERANGE, "instance list overflow (outputs of that call are NaN); capacity grows on the next call");
+}
+
+// Read device-side conditions of finished calls without blocking.
 void poll(sgad_ctx* c, bool block) {
     if (c->track.status_pending) {
         bool done = block ? hipEventSynchronize(c->track.ev_status) == hipSuccess
@@ -233,19 +236,9 @@ void poll(sgad_ctx* c, bool block) {
         else if (hipEventQuery(s->ev_status) != hipSuccess) continue;
         s->status_pending = false;
         const DevStatus st = *s->status_h;
-        if ((st.nonfinite || (st.sticky & 2u)) && c->latched == SGAD_OK) {
-            c->latched = SGAD_EDATA;
-            c->err = "non-finite depth, offset or radius in a keyframe";
-        }
-        if (st.overflow || (st.sticky & 1u)) {
-            if (c->latched == SGAD_OK) {
-                c->latched = SGAD_ERANGE;
-                c->err = "instance list overflow (outputs of that forward are NaN); capacity grows on the next call";
-            }
-            s->sized = false;
-        } else if (st.total > s->capacity - s->capacity / 8) {
-            s->sized = false;  // re-size on the next forward before it can overflow
-        }
+        latch_status(c, st);
+        if (st.overflow || (st.sticky & 1u) || st.total > s->capacity - s->capacity / 8)
+            s->sized = false;  // re-size on the next forward
     }
 }
 
@@ -377,7 +370,9 @@ sgad_status sgad_sync(sgad_ctx* c) {
     HIPCHK(c, hipDeviceSynchronize());
     poll(c, true);
     sgad_status s = c->latched;
+    if (s != SGAD_OK) c->err = c->latched_msg;
     c->latched = SGAD_OK;
+    c->latched_msg.clear();
     return s;
 }
 
@@ -510,11 +505,18 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     const size_t NP = (size_t)n_pairs * N;
     const size_t M = (size_t)n_jobs * G.ntiles;
     const size_t PJ = (size_t)n_jobs * G.P;
-    HIPCHK(c, ensure(S->pre, NP * 32, s));
+    HIPCHK(c, ensure(S->pre, NP * 76 + 256, s));
     HIPCHK(c, ensure(S->tiles, (3 * M + 1) * 4 + 256, s));
     HIPCHK(c, ensure(S->pix, PJ * 8, s));
     HIPCHK(c, ensure(S->pose_part, M * 6 * 4, s));
     HIPCHK(c, ensure(S->status, sizeof(DevStatus), s));
+    {
+        const size_t key[5] = {NP, M, (size_t)TW, (size_t)TH, (size_t)n_jobs};
+        if (std::memcmp(key, S->size_key, sizeof(key)) != 0) {
+            S->sized = false;
+            std::memcpy(S->size_key, key, sizeof(key));
+        }
+    }
     if (!S->sized && S->capacity == 0) {
         // first use: a generous guess that is corrected after the count pass
         const size_t guess = NP * 3 + 65536;
@@ -528,14 +530,10 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     B.kfs = (const KfPtrs*)(pb + o_kfs);
     B.pair_of = (const int32_t*)(pb + o_pof);
     char* pp = (char*)S->pre.p;
-    B.pre.dx = (float*)(pp + 0 * NP * 4);
-    B.pre.dy = (float*)(pp + 1 * NP * 4);
-    B.pre.ca = (float*)(pp + 2 * NP * 4);
-    B.pre.cb = (float*)(pp + 3 * NP * 4);
-    B.pre.cc = (float*)(pp + 4 * NP * 4);
-    B.pre.z = (float*)(pp + 5 * NP * 4);
-    B.pre.rx = (uint32_t*)(pp + 6 * NP * 4);
-    B.pre.ry = (uint32_t*)(pp + 7 * NP * 4);
+    B.pre.rec = (float4*)pp;
+    B.pre.z = (float*)(pp + (size_t)NP * 64);
+    B.pre.rx = (uint32_t*)(pp + (size_t)NP * 68);
+    B.pre.ry = (uint32_t*)(pp + (size_t)NP * 72);
     uint32_t* tb = (uint32_t*)S->tiles.p;
     B.tile_count = tb;
     B.tile_fill = tb + M;
@@ -701,6 +699,8 @@ sgad_status sgad_adam_step(sgad_ctx* c, int n_groups, const sgad_adam_group* gro
         A.lr[g] = G.lr;
         A.lo[g] = G.lo;
         A.hi[g] = G.hi;
+        if (G.space < 0 || G.space > 2) return fail(c, SGAD_EINVAL, "unknown adam space");
+        A.space[g] = G.space;
         A.off[g + 1] = A.off[g] + G.n;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -795,7 +795,7 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
         latch_status(c, *T.status_h);
     }
     HIPCHK(c, ensure(T.params, 1024, s));
-    HIPCHK(c, ensure(T.pre, (size_t)N * 32, s));
+    HIPCHK(c, ensure(T.pre, (size_t)N * 76 + 256, s));
     HIPCHK(c, ensure(T.tiles, (3 * M + 1) * 4 + 256, s));
     HIPCHK(c, ensure(T.part, M * 32 * 4, s));
     HIPCHK(c, ensure(T.status, sizeof(DevStatus), s));
@@ -807,14 +807,10 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     B.kfs = (const KfPtrs*)(pb + 512);
     B.pair_of = (const int32_t*)(pb + 768);
     char* pp = (char*)T.pre.p;
-    B.pre.dx = (float*)(pp + 0 * N * 4);
-    B.pre.dy = (float*)(pp + 1 * N * 4);
-    B.pre.ca = (float*)(pp + 2 * N * 4);
-    B.pre.cb = (float*)(pp + 3 * N * 4);
-    B.pre.cc = (float*)(pp + 4 * N * 4);
-    B.pre.z = (float*)(pp + 5 * N * 4);
-    B.pre.rx = (uint32_t*)(pp + 6 * N * 4);
-    B.pre.ry = (uint32_t*)(pp + 7 * N * 4);
+    B.pre.rec = (float4*)pp;
+    B.pre.z = (float*)(pp + (size_t)N * 64);
+    B.pre.rx = (uint32_t*)(pp + (size_t)N * 68);
+    B.pre.ry = (uint32_t*)(pp + (size_t)N * 72);
     uint32_t* tb = (uint32_t*)T.tiles.p;
     B.tile_count = tb;
     B.tile_fill = tb + M;

@@ -53,16 +53,17 @@ struct DevStatus {
     uint32_t sticky;     // bit 0: an overflow, bit 1: a non-finite input, since the call began
 };
 
-// Preprocessed per (pair, Gaussian) data, SoA of length n_pairs * N.
+// Preprocessed per (pair, Gaussian) data.  rec holds one 64-byte record per
+// Gaussian (one cache line per gather):
+//   [u, v, dx, dy] [a, b, c, o] [c0, c1, c2, z] [x, y, r, sign(D + delta)]
+// (dx, dy) = projected mean - (u, v) in view pixels, (a, b, c) the conic,
+// o the opacity, c0..c2 the colour (sigma^2 in c0 for tracking), z the view
+// depth, (x, y) the view-space centre, r the radius.
 struct Preproc {
-    float* dx;     // m.x - u   (view pixels)
-    float* dy;     // m.y - v
-    float* ca;     // conic
-    float* cb;
-    float* cc;
-    float* z;      // view-space z (float)
+    float4* rec;   // [n_pairs * N * 4]
     uint32_t* rx;  // tile x0 | x1 << 16
     uint32_t* ry;  // tile y0 | y1 << 16
+    float* z;      // view depth (float), the sort key source
 };
 
 struct Geometry {
@@ -70,6 +71,7 @@ struct Geometry {
     int Hk, Wk, N;        // keyframe size, N = Hk * Wk
     int Hv, Wv, P;        // view size
     int TW, TH, ntx, nty, ntiles;
+    int sc_fwd = 256, sc_bwd = 128;  // super-chunk sizes of the 8x8 wave-tile kernels
 };
 
 struct RenderBufs {
@@ -98,6 +100,7 @@ struct AdamGroups {
     float lr[kMaxAdamGroups];
     float lo[kMaxAdamGroups];
     float hi[kMaxAdamGroups];
+    int space[kMaxAdamGroups];
 };
 
 }  // namespace sgad

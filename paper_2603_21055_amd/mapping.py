@@ -11,7 +11,9 @@ import numpy as np
 
 from . import sgad
 
-LR = dict(rgb=0.0025, radius=0.005, opacity=0.05, offset=0.01)   # supplement
+# supplement learning rates; radius steps as log r and opacity as logit o (the
+# spaces these rates belong to in 3DGS), colour and offset linearly
+LR = dict(rgb=0.0025, radius=0.005, opacity=0.05, offset=0.01)
 W_RGB, W_DEPTH = 0.8, 1.0                                         # Eq. 1 weights (supplement)
 R_MIN = 1e-6
 
@@ -103,10 +105,12 @@ class Mapper:
             g = dict(d_rgb=torch.zeros_like(kf["rgb"]), d_opacity=torch.zeros_like(kf["opacity"]),
                      d_radius=torch.zeros_like(kf["radius"]), d_offset=torch.zeros_like(kf["offset"]))
             self.grads.append(g)
-            for name, gk, lo, hi in (("rgb", "d_rgb", -np.inf, np.inf), ("opacity", "d_opacity", 0.0, 1.0),
-                                     ("radius", "d_radius", R_MIN, np.inf), ("offset", "d_offset", -np.inf, np.inf)):
+            for name, gk, lo, hi, sp in (("rgb", "d_rgb", -np.inf, np.inf, sgad.SPACE_LINEAR),
+                                         ("opacity", "d_opacity", 0.0, 1.0, sgad.SPACE_LOGIT),
+                                         ("radius", "d_radius", R_MIN, np.inf, sgad.SPACE_LOG),
+                                         ("offset", "d_offset", -np.inf, np.inf, sgad.SPACE_LINEAR)):
                 p = kf[name]
-                self.groups.append((p, g[gk], torch.zeros_like(p), torch.zeros_like(p), LR[name], lo, hi))
+                self.groups.append((p, g[gk], torch.zeros_like(p), torch.zeros_like(p), LR[name], lo, hi, sp))
         self.t = 0
 
     def step(self):

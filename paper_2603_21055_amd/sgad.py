@@ -47,7 +47,11 @@ class Job(C.Structure):
 
 class AdamGroup(C.Structure):
     _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
-                ("n", C.c_int64), ("lr", C.c_float), ("lo", C.c_float), ("hi", C.c_float)]
+                ("n", C.c_int64), ("lr", C.c_float), ("lo", C.c_float), ("hi", C.c_float),
+                ("space", C.c_int32)]
+
+
+SPACE_LINEAR, SPACE_LOG, SPACE_LOGIT = 0, 1, 2
 
 
 class KfGrads(C.Structure):
@@ -275,12 +279,16 @@ class Context:
         self._check(st)
 
     def adam_step(self, groups, step, beta1=0.9, beta2=0.999, eps=1e-8, zero_grad=True, stream=None):
-        """groups: list of (param, grad, m, v, lr, lo, hi) device tensors / floats."""
+        """groups: list of (param, grad, m, v, lr, lo, hi[, space]) device tensors
+        / floats; space is SPACE_LINEAR (default), SPACE_LOG or SPACE_LOGIT."""
         arr = (AdamGroup * len(groups))()
-        for i, (p, g, m, v, lr, lo, hi) in enumerate(groups):
+        for i, grp in enumerate(groups):
+            p, g, m, v, lr, lo, hi = grp[:7]
+            space = grp[7] if len(grp) > 7 else SPACE_LINEAR
             for name, t in (("param", p), ("grad", g), ("m", m), ("v", v)):
                 _check_tensor(t, name, self.device)
-            arr[i] = AdamGroup(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), float(lr), float(lo), float(hi))
+            arr[i] = AdamGroup(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), float(lr), float(lo), float(hi),
+                               int(space))
         st = self.lib.sgad_adam_step(self.h, len(groups), C.cast(arr, C.c_void_p), int(step), float(beta1),
                                      float(beta2), float(eps), 1 if zero_grad else 0, _stream(stream))
         self._check(st)

@@ -27,6 +27,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(sgad.Pose) == 48
     assert ctypes.sizeof(sgad.Job) == 12
     assert ctypes.sizeof(sgad.KfGrads) == 32
+    assert ctypes.sizeof(sgad.AdamGroup) == 56
     assert ctypes.sizeof(sgad.Keyframe) == 24 + 48 + 6 * 8
 
 

@@ -68,6 +68,24 @@ def test_adam_matches_oracle(ctx):
         np.testing.assert_allclose(P[i].cpu().numpy(), op[i], rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("space", ["log", "logit"])
+def test_adam_parameter_spaces_match_oracle(ctx, space):
+    import torch
+    from paper_2603_21055_amd import sgad
+    rng = np.random.default_rng(2)
+    p0 = rng.uniform(0.05, 0.95, size=777).astype(np.float32)
+    P = torch.from_numpy(p0.copy()).to(ctx.device)
+    M, V = torch.zeros_like(P), torch.zeros_like(P)
+    op, om, ov = p0.astype(np.float64), np.zeros(777), np.zeros(777)
+    code = sgad.SPACE_LOG if space == "log" else sgad.SPACE_LOGIT
+    for step in range(1, 4):
+        g = rng.normal(size=777).astype(np.float32)
+        ctx.adam_step([(P, torch.from_numpy(g).to(ctx.device), M, V, 0.05, 0.0, 1e30, code)], step)
+        op, om, ov = ooptim.adam_step_space(op, g.astype(np.float64), om, ov, step, 0.05, space)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(P.cpu().numpy(), op, rtol=2e-5)
+
+
 def test_adam_clamps(ctx):
     import torch
     d = ctx.device
@@ -91,7 +109,7 @@ def _oracle_mapping(sc, iters):
         b = splat.render_backward([kf], sc["views"], [(0, [0])], [f], [gr], [gd], [np.zeros_like(gd)])
         for n, gk in (("rgb", "d_rgb"), ("opacity", "d_opacity"), ("radius", "d_radius"), ("offset", "d_offset")):
             m, v = state[n]
-            p, m, v = ooptim.adam_step(kf[n], b["kf"][0][gk], m, v, t, ooptim.LR[n])
+            p, m, v = ooptim.adam_step_space(kf[n], b["kf"][0][gk], m, v, t, ooptim.LR[n], ooptim.SPACE[n])
             kf[n] = ooptim.clamp(n, p)
             state[n] = (m, v)
     return losses, kf

@@ -143,6 +143,8 @@ def test_c4_full_size_converges(ctx):
     sc = synth.c4_tracking(30)
     pose, tr = _run(ctx, sc, sc["obs_depth"], 30, graph=True)
     et, er = _pose_err(pose, sc["gt"]["R"], sc["gt"]["t"])
-    # analytic box depth vs the splatted model: converges close to the truth
-    assert et < 5e-3 and er < 0.2, (et, er)
+    # analytic box depth vs the splatted model (a blurred surface): the
+    # estimate converges near, not onto, the truth
+    print(f"C4 realistic: translation error {et * 1e3:.2f} mm, rotation error {er:.4f} deg", flush=True)
+    assert et < 1e-2 and er < 0.1, (et, er)
     assert tr[-1, 27] > tr[0, 27]
