@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--tile", type=str, default="16x16")
+    ap.add_argument("--tile", type=str, default="auto", help="auto (autotuner) or WxH")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -85,11 +85,16 @@ def main():
     H, W = 480, 640
     N = P = H * W
     ctx = sgad.Context(0)
-    tw, th = (int(x) for x in args.tile.split("x"))
-    ctx.set_tile(tw, th)
     kfs_d = [sgad.to_device(k, dev) for k in sc["kfs"]]
     views = sc["views"]
     jobs = [(0, [0])]
+    if args.tile == "auto":
+        ctx.set_tile(0, 0)
+        (tw, th), tune_ms = ctx.autotune(kfs_d, views, jobs, reps=5)
+        log(f"autotuner chose {tw}x{th} ({tune_ms:.4f} ms per forward + adjoint)")
+    else:
+        tw, th = (int(x) for x in args.tile.split("x"))
+        ctx.set_tile(tw, th)
     from paper_2603_21055_amd.mapping import Mapper
     t_rgb = torch.from_numpy(sc["target"]["rgb"]).to(dev)[None].contiguous()
     t_dep = torch.from_numpy(sc["target"]["depth"]).to(dev)[None].contiguous()

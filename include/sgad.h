@@ -107,9 +107,11 @@ const char* sgad_last_error(const sgad_ctx* ctx);
  * device-side condition (SGAD_EDATA, SGAD_ERANGE) since the previous call,
  * clearing it. */
 sgad_status sgad_sync(sgad_ctx* ctx);
-/* Tile shape of the compositing kernels: (8,8), (16,8), (16,16) or (32,8);
- * (0,0) lets the autotuner choose per workload.  Results do not depend on
- * the tile shape. */
+/* Tile shape of the compositing kernels: (8,8) (one tile per wavefront,
+ * per-pixel candidate masks), (16,8), (16,16) or (32,8) (one tile per
+ * workgroup, full-list walk); (0,0), the default, uses the configuration
+ * sgad_autotune measured for the workload, else (8,8).  Results do not
+ * depend on the tile shape. */
 sgad_status sgad_set_tile(sgad_ctx* ctx, int tile_w, int tile_h);
 /* Tile shape used by the last forward (after autotuning). */
 sgad_status sgad_get_tile(const sgad_ctx* ctx, int* tile_w, int* tile_h);
@@ -171,6 +173,20 @@ sgad_status sgad_saved_release(sgad_ctx* ctx, sgad_saved* saved);
 sgad_status sgad_saved_instances(sgad_ctx* ctx, const sgad_saved* saved, int job,
                                  uint32_t* tile_ranges, uint64_t* keys, size_t cap,
                                  size_t* n_keys, int* n_tiles);
+
+/*
+ * Autotuner: times forward + adjoint of exactly this workload (the same
+ * arguments as sgad_render_fwd) for every tile configuration, reps times
+ * each after one warm-up, using internal scratch outputs and gradients (the
+ * caller's buffers are not touched), and remembers the fastest for the
+ * workload key (view H, W, Gaussians per keyframe, pairs, jobs, keyframes);
+ * forwards with tile (0,0) then use it.  Waits for the stream.  The best
+ * tile and its average ms per forward + adjoint are returned if non-NULL.
+ */
+sgad_status sgad_autotune(sgad_ctx* ctx, int n_kf, const sgad_keyframe* kf, int n_views,
+                          const sgad_cam* vcam, const sgad_pose* vpose, int n_jobs,
+                          const sgad_job* jobs, int reps, int* best_tw, int* best_th,
+                          float* best_ms, void* stream);
 
 /* ---------------------------------------------------------------- tracking */
 

@@ -118,9 +118,9 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
 
-__global__ void k_zero_f32(float* p, int64_t n) {
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.f;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -291,10 +291,10 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u32, dim3(blocks), dim3(256), 0, s, p, n);
 }
 
-void launch_zero_f32(float* p, int64_t n, hipStream_t s) {
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
     if (n <= 0) return;
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_zero_f32, dim3(blocks), dim3(256), 0, s, p, n);
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks), dim3(256), 0, s, p, n, v);
 }
 
 void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s) {

@@ -12,7 +12,7 @@
 
 namespace sgad {
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
-void launch_zero_f32(float* p, int64_t n, hipStream_t s);
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s);
 void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s);
 void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s);
@@ -84,8 +84,18 @@ struct sgad_ctx {
     std::string err;
     sgad_status latched = SGAD_OK;
     std::string latched_msg;
-    int tile_w = 16, tile_h = 16;
-    int last_tw = 16, last_th = 16;
+    int tile_w = 0, tile_h = 0;  // 0,0: autotuned per workload
+    int last_tw = 8, last_th = 8;
+    // autotuner: configurations measured per workload key, and a forced
+    // configuration used while measuring
+    struct TuneEntry {
+        size_t key[6];
+        int tw, th, scf, scb;
+        float ms;
+    };
+    std::vector<TuneEntry> tune;
+    bool force = false;
+    int ftw = 8, fth = 8, fscf = 256, fscb = 128;
     std::vector<sgad_saved*> slots;
     KernelTimer timer;
     DevBuf scratch;  // small per-context scratch (loss counters)
@@ -431,10 +441,24 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     HIPCHK(c, hipSetDevice(c->device));
     poll(c, false);
 
-    int TW = c->tile_w, TH = c->tile_h;
-    if (TW == 0) {
-        TW = 16;
-        TH = 16;
+    int TW = c->tile_w, TH = c->tile_h, SCF = 256, SCB = 128;
+    if (c->force) {
+        TW = c->ftw;
+        TH = c->fth;
+        SCF = c->fscf;
+        SCB = c->fscb;
+    } else if (TW == 0) {
+        const size_t key[6] = {(size_t)vcam[0].H, (size_t)vcam[0].W, (size_t)N, (size_t)n_pairs, (size_t)n_jobs,
+                               (size_t)n_kf};
+        TW = 8;
+        TH = 8;
+        for (const auto& e : c->tune)
+            if (std::memcmp(e.key, key, sizeof(key)) == 0) {
+                TW = e.tw;
+                TH = e.th;
+                SCF = e.scf;
+                SCB = e.scb;
+            }
     }
     sgad_saved* S = acquire(c);
     if (!S) return fail(c, SGAD_ENOMEM, "cannot allocate a saved slot");
@@ -453,6 +477,8 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     G.ntx = (G.Wv + TW - 1) / TW;
     G.nty = (G.Hv + TH - 1) / TH;
     G.ntiles = G.ntx * G.nty;
+    G.sc_fwd = SCF;
+    G.sc_bwd = SCB;
     S->stream = s;
     c->last_tw = TW;
     c->last_th = TH;
@@ -902,6 +928,102 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     HIPCHK(c, hipMemcpyAsync(T.status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipEventRecord(T.ev_status, s));
     T.status_pending = true;
+    return SGAD_OK;
+}
+
+sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_views, const sgad_cam* vcam,
+                          const sgad_pose* vpose, int n_jobs, const sgad_job* jobs, int reps, int* best_tw,
+                          int* best_th, float* best_ms, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (reps < 1 || reps > 1000) return fail(c, SGAD_ERANGE, "reps must be in [1, 1000]");
+    if (n_kf < 1 || n_kf > kMaxKf || !kf || n_views < 1 || !vcam || n_jobs < 1 || !jobs)
+        return fail(c, SGAD_EINVAL, "bad workload");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    const int64_t N = (int64_t)kf[0].cam.H * kf[0].cam.W;
+    const int64_t P = (int64_t)vcam[0].H * vcam[0].W;
+    int n_pairs = 0;
+    for (int j = 0; j < n_jobs; ++j)
+        n_pairs += __builtin_popcountll((uint64_t)jobs[j].kf_mask_lo | ((uint64_t)jobs[j].kf_mask_hi << 32));
+    // scratch: outputs, upstream grads (a constant), keyframe grads, pose
+    DevBuf buf;
+    const size_t fo = (size_t)n_jobs * P * 5, fu = (size_t)n_jobs * P * 5, fg = (size_t)n_kf * N * 6;
+    HIPCHK(c, ensure(buf, (fo + fu + fg + (size_t)n_jobs * 6) * 4, s));
+    float* base = (float*)buf.p;
+    float *o_rgb = base, *o_dep = o_rgb + n_jobs * P * 3, *o_alp = o_dep + n_jobs * P;
+    float *u_rgb = base + fo, *u_dep = u_rgb + n_jobs * P * 3, *u_alp = u_dep + n_jobs * P;
+    float* kg = base + fo + fu;
+    float* dpose = kg + fg;
+    launch_fill_f32(u_rgb, (int64_t)fu, 1e-6f, s);
+    std::vector<sgad_kf_grads> grads(n_kf);
+    for (int f = 0; f < n_kf; ++f) {
+        float* g = kg + (size_t)f * N * 6;
+        grads[f] = sgad_kf_grads{g, g + 3 * N, g + 4 * N, g + 5 * N};
+    }
+    struct Cand {
+        int tw, th, scf, scb;
+    };
+    const Cand cands[] = {{16, 16, 0, 0}, {16, 8, 0, 0}, {32, 8, 0, 0}, {8, 8, 256, 128},
+                          {8, 8, 128, 128}, {8, 8, 256, 256}};
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    float best = 1e30f;
+    Cand bc = cands[3];
+    sgad_status rs = SGAD_OK;
+    for (const Cand& cd : cands) {
+        c->force = true;
+        c->ftw = cd.tw;
+        c->fth = cd.th;
+        c->fscf = cd.scf ? cd.scf : 256;
+        c->fscb = cd.scb ? cd.scb : 128;
+        float ms_tot = 0.f;
+        for (int r = 0; r <= reps && rs == SGAD_OK; ++r) {  // r == 0 is a warm-up
+            sgad_saved* sv = nullptr;
+            if (r == 1) (void)hipEventRecord(e0, s);
+            rs = sgad_render_fwd(c, n_kf, kf, n_views, vcam, vpose, n_jobs, jobs, o_rgb, o_dep, o_alp, nullptr,
+                                 &sv, stream);
+            if (rs != SGAD_OK) break;
+            rs = sgad_render_bwd(c, sv, u_rgb, u_dep, u_alp, grads.data(), dpose, 0xffffffffu, 0xffffffffu, stream);
+            (void)sgad_saved_release(c, sv);
+        }
+        if (rs != SGAD_OK) break;
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms_tot, e0, e1);
+        const float ms = ms_tot / reps;
+        if (ms < best) {
+            best = ms;
+            bc = cd;
+        }
+    }
+    c->force = false;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    if (buf.p) (void)hipFree(buf.p);
+    if (rs != SGAD_OK) return rs;
+    {
+        sgad_ctx::TuneEntry te{};
+        const size_t key[6] = {(size_t)vcam[0].H, (size_t)vcam[0].W, (size_t)N, (size_t)n_pairs, (size_t)n_jobs,
+                               (size_t)n_kf};
+        std::memcpy(te.key, key, sizeof(key));
+        te.tw = bc.tw;
+        te.th = bc.th;
+        te.scf = bc.scf ? bc.scf : 256;
+        te.scb = bc.scb ? bc.scb : 128;
+        te.ms = best;
+        bool found = false;
+        for (auto& e : c->tune)
+            if (std::memcmp(e.key, key, sizeof(key)) == 0) {
+                e = te;
+                found = true;
+            }
+        if (!found) c->tune.push_back(te);
+    }
+    if (best_tw) *best_tw = bc.tw;
+    if (best_th) *best_th = bc.th;
+    if (best_ms) *best_ms = best;
     return SGAD_OK;
 }
 

@@ -80,6 +80,9 @@ _SIGS = {
     "sgad_adam_step": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_int, C.c_float, C.c_float, C.c_float,
                                  C.c_int, _P]),
     "sgad_timing_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
+    "sgad_autotune": (C.c_int, [_P, C.c_int, C.POINTER(Keyframe), C.c_int, C.POINTER(Cam), C.POINTER(Pose),
+                                C.c_int, C.POINTER(Job), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_float), _P]),
     "sgad_saved_instances": (C.c_int, [_P, _P, C.c_int, _P, _P, C.c_size_t, C.POINTER(C.c_size_t),
                                        C.POINTER(C.c_int)]),
 }
@@ -220,9 +223,8 @@ class Context:
                               _ptr(kf.get("rgb")), _ptr(kf.get("sigma")))
         return arr
 
-    def render_fwd(self, kfs, views, jobs, out_rgb, out_depth, out_alpha, out_count=None, stream=None):
-        """Enqueue the forward; returns the saved handle (a c_void_p)."""
-        kfa = self._kf_array(kfs)
+    @staticmethod
+    def _views_jobs(views, jobs):
         cams = (Cam * len(views))(*[_cam(v["cam"]) for v in views])
         poses = (Pose * len(views))(*[_pose(v["R"], v["t"]) for v in views])
         ja = (Job * len(jobs))()
@@ -231,6 +233,23 @@ class Context:
             for f in ids:
                 m |= 1 << int(f)
             ja[i] = Job(int(v), m & 0xFFFFFFFF, (m >> 32) & 0xFFFFFFFF)
+        return cams, poses, ja
+
+    def autotune(self, kfs, views, jobs, reps=5, stream=None):
+        """Time every tile configuration on this workload; returns
+        ((tile_w, tile_h), ms per forward + adjoint) of the fastest."""
+        kfa = self._kf_array(kfs)
+        cams, poses, ja = self._views_jobs(views, jobs)
+        tw, th, ms = C.c_int(), C.c_int(), C.c_float()
+        st = self.lib.sgad_autotune(self.h, len(kfs), kfa, len(views), cams, poses, len(jobs), ja, int(reps),
+                                    C.byref(tw), C.byref(th), C.byref(ms), _stream(stream))
+        self._check(st)
+        return (tw.value, th.value), ms.value
+
+    def render_fwd(self, kfs, views, jobs, out_rgb, out_depth, out_alpha, out_count=None, stream=None):
+        """Enqueue the forward; returns the saved handle (a c_void_p)."""
+        kfa = self._kf_array(kfs)
+        cams, poses, ja = self._views_jobs(views, jobs)
         for name, t in (("out_rgb", out_rgb), ("out_depth", out_depth), ("out_alpha", out_alpha)):
             _check_tensor(t, name, self.device)
         import torch

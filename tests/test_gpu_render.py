@@ -133,9 +133,10 @@ def test_binning_and_sort_bit_exact(ctx, tile):
     ctx.release(saved)
 
 
-def test_c2_full_frame_parity(ctx):
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_c2_full_frame_parity(ctx, tile):
     sc = synth.c2_scene(10)
-    _run_case(ctx, sc, [(0, [0])], (16, 16), learnable=[0])
+    _run_case(ctx, sc, [(0, [0])], tile, learnable=[0])
 
 
 def test_everything_culled_renders_empty(ctx):
@@ -179,3 +180,26 @@ def test_nonfinite_depth_is_latched(ctx):
     assert e.value.status == sgad.EDATA
     ctx.release(saved)
     ctx.sync()   # cleared
+
+
+def test_autotuner_picks_a_config_and_results_do_not_change(ctx):
+    import torch
+    sc = synth.small_scene(30, 160, 120, n_kf=2, n_views=1, offset_amp=0.02)
+    kfs_d = H.upload(sc["kfs"], ctx.device)
+    jobs = [(0, [0, 1])]
+    ctx.set_tile(16, 16)
+    saved, ref = H.gpu_render(ctx, kfs_d, sc["views"], jobs)
+    torch.cuda.synchronize()
+    ref = {k: v.cpu().numpy() for k, v in ref.items()}
+    ctx.release(saved)
+    ctx.set_tile(0, 0)
+    tile, ms = ctx.autotune(kfs_d, sc["views"], jobs, reps=2)
+    print(f"autotune: tile {tile}, {ms:.3f} ms per forward + adjoint", flush=True)
+    assert tile in [(8, 8), (16, 8), (16, 16), (32, 8)] and ms > 0
+    saved, out = H.gpu_render(ctx, kfs_d, sc["views"], jobs)
+    torch.cuda.synchronize()
+    assert ctx.get_tile() == tile
+    for k in ("rgb", "depth", "alpha", "count"):
+        assert np.array_equal(out[k].cpu().numpy(), ref[k]), k
+    ctx.release(saved)
+    ctx.sync()
