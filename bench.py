@@ -62,6 +62,88 @@ def cpu_baseline():
                 sample=f"one full 640x480 frame fwd+bwd (C2 scene seed 10), {dt:.1f} s on 1 thread")
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_window(args):
+    """8 keyframes x 8 views, every view renders all keyframes, all learnable."""
+    import numpy as np
+    import torch
+
+    from paper_2603_21055_amd import sgad, synth
+    from paper_2603_21055_amd.mapping import Mapper
+    log("building 8-keyframe window")
+    dev = torch.device("cuda", 0)
+    sc = synth.c3_window(20)
+    ctx = sgad.Context(0)
+    kfs = [sgad.to_device(k, dev) for k in sc["kfs"]]
+    jobs = [(v, list(range(8))) for v in range(8)]
+    t_rgb = torch.from_numpy(np.stack([t["rgb"] for t in sc["targets"]])).to(dev)
+    t_dep = torch.from_numpy(np.stack([t["depth"] for t in sc["targets"]])).to(dev)
+    ctx.set_tile(0, 0)
+    (tw, th), tms = ctx.autotune(kfs, sc["views"], jobs, reps=2)
+    log(f"autotuner chose {tw}x{th} ({tms:.3f} ms per forward + adjoint)")
+    m = Mapper(ctx, kfs, sc["views"], jobs, list(range(8)), t_rgb, t_dep)
+    steps = max(1, min(args.steps, 50))
+    sec = _timed(m.step, steps, min(args.warmup, 5))
+    ctx.sync()
+    N, P = 8 * 640 * 480, 640 * 480
+    algo = 80 * N + 8 * 52 * P
+    print(json.dumps(dict(metric="batched mapping window iterations/s (8 keyframes x 8 views, 640x480)",
+                          value=1.0 / sec, unit="iterations/s", ms_per_step=sec * 1e3, steps=steps,
+                          hbm_frac=algo / sec / HBM_PEAK, tile=[tw, th], dtype="f32", data="synthetic")),
+          flush=True)
+
+
+def bench_tracking(args):
+    """30 Gauss-Newton iterations at 1200x680 in one hipGraph launch."""
+    import numpy as np
+    import torch
+
+    from paper_2603_21055_amd import sgad, synth
+    log("building 1200x680 tracking scene")
+    dev = torch.device("cuda", 0)
+    sc = synth.c4_tracking(30)
+    ctx = sgad.Context(0)
+    geo = sgad.to_device(sc["geo"], dev)
+    obs = torch.from_numpy(sc["obs_depth"]).to(dev)
+    init = torch.from_numpy(np.concatenate([sc["init"]["R"].ravel(), sc["init"]["t"]]).astype(np.float64)).to(dev)
+    pose = init.clone()
+    trace = torch.zeros((30, 40), dtype=torch.float64, device=dev)
+
+    def run():
+        pose.copy_(init)
+        ctx.track_gn(geo, sc["cam"], obs, pose, iters=30, trace=trace, graph=True)
+
+    steps = max(1, min(args.steps, 20))
+    sec = _timed(run, steps, min(args.warmup, 3))
+    ctx.sync()
+    print(json.dumps(dict(metric="tracking Gauss-Newton iterations/s (1200x680, 30 per graph launch)",
+                          value=30.0 / sec, unit="iterations/s", ms_per_graph=sec * 1e3, steps=steps,
+                          dtype="f32 (FP64 solve)", data="synthetic")), flush=True)
+
+
+def bench_copy(args):
+    """A plain 1 GiB device-to-device copy, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters (bytes per copy are known exactly)."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    sec = _timed(lambda: b.copy_(a), max(1, min(args.steps, 20)), 2)
+    print(json.dumps(dict(metric="device copy GB/s", value=2 * 4 * n / sec / 1e9, unit="GB/s",
+                          bytes_read_per_copy=4 * n, bytes_written_per_copy=4 * n)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,11 +151,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=str, default="auto", help="auto (autotuner) or WxH")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "copy"], default="c2",
+                    help="c2: the headline 640x480 frame; c3: 8-keyframe x 8-view window; "
+                         "c4: 1200x680 tracking; copy: plain device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path (--gpus 1).",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload != "c2":
+        return {"c3": bench_window, "c4": bench_tracking, "copy": bench_copy}[args.workload](args)
 
     import numpy as np
     import torch

@@ -266,6 +266,43 @@ typedef struct {
 sgad_status sgad_adam_step(sgad_ctx* ctx, int n_groups, const sgad_adam_group* groups, int step,
                            float beta1, float beta2, float eps, int zero_grad, void* stream);
 
+/* ---------------------------------------------------------------- conv net */
+/*
+ * Learned offset warm start (this library's addition; the paper starts the
+ * offsets at zero, Sec. 3.2): delta0 = Net(R, G, B, D / 5 m), six 3x3 'same'
+ * convolutions 4 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 with ReLU after the first
+ * five.  Activations are bf16 NHWC ([H][W][C]); weights [9][cout][cin]
+ * (tap = 3 ky + kx, taps reading x[y + ky - 1][x + kx - 1]); products run on
+ * BF16 MFMA with FP32 accumulation.  Supported layers: (cin, cout) = (4, 32),
+ * (32, 32), (32, 1).  All pointers are device pointers.
+ */
+#define SGAD_CONV_RELU_BF16 0  /* y = relu(conv + bias), bf16 [H][W][cout] */
+#define SGAD_CONV_LINEAR_F32 1 /* y = conv + bias, f32 [H][W] (cout == 1) */
+
+/* bf16 copy of FP32 weights [9][cout][cin] and, if wt_bf16 is non-NULL, the
+ * transposed tap-flipped copy wt[8 - t][ci][co] the input gradient uses. */
+sgad_status sgad_conv_weights(sgad_ctx* ctx, int cin, int cout, const float* w, uint16_t* w_bf16,
+                              uint16_t* wt_bf16, void* stream);
+/* Forward of one layer (mode SGAD_CONV_*); y is written. */
+sgad_status sgad_conv3x3_fwd(sgad_ctx* ctx, int H, int W, int cin, int cout, int mode, const uint16_t* x,
+                             const uint16_t* w_bf16, const float* bias, void* y, void* stream);
+/* Input gradient of a layer whose input passed a ReLU: dx = (conv^T dy) * [mask > 0],
+ * dy bf16 [H][W][cout] (gradient of the layer's pre-activation), mask = the
+ * layer's input activations bf16 [H][W][cin], dx bf16 [H][W][cin] written
+ * (the gradient of the previous layer's pre-activation). */
+sgad_status sgad_conv3x3_dgrad(sgad_ctx* ctx, int H, int W, int cin, int cout, const uint16_t* dy,
+                               const uint16_t* wt_bf16, const uint16_t* mask, uint16_t* dx, void* stream);
+/* Weight and bias gradients, ACCUMULATED into FP32 dw [9][cout][cin], db [cout]. */
+sgad_status sgad_conv3x3_wgrad(sgad_ctx* ctx, int H, int W, int cin, int cout, const uint16_t* x,
+                               const uint16_t* dy, float* dw, float* db, void* stream);
+/* Network input (R, G, B, D / 5 m) as bf16 [H][W][4] from planar rgb [3][H][W] and depth [H][W]. */
+sgad_status sgad_net_input(sgad_ctx* ctx, int H, int W, const float* rgb, const float* depth, uint16_t* x0,
+                           void* stream);
+/* Training loss mean |pred - target| over n values (device double, written)
+ * and its gradient as bf16 (n values, written). */
+sgad_status sgad_offset_l1(sgad_ctx* ctx, int n, const float* pred, const float* target, uint16_t* grad,
+                           double* loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

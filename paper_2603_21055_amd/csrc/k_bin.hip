@@ -9,6 +9,42 @@
 namespace sgad {
 
 // ---------------------------------------------------------------------------
+// Wave-aggregated counter increments.  Each lane names at most one counter
+// (t < 0: none); lanes naming the same counter are served by one atomic from
+// their lowest lane, and each learns its rank among them.  Neighbouring
+// Gaussians overlap the same tiles, so a wave issues a handful of atomics
+// instead of one per lane.  Returns the pre-increment value plus the rank
+// (only meaningful for lanes with t >= 0).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_agg_add(uint32_t* ctr, int64_t t, bool need_pos) {
+    const int lane = threadIdx.x & 63;
+    uint64_t active = __ballot(t >= 0);
+    uint32_t pos = 0;
+    while (active) {
+        const int leader = __ffsll((long long)active) - 1;
+        const int64_t tgt = __shfl(t, leader, 64);
+        const uint64_t peers = __ballot(t == tgt) & active;
+        uint32_t base = 0;
+        if (lane == leader) {
+            if (need_pos) base = atomicAdd(&ctr[tgt], (uint32_t)__popcll(peers));
+            else atomicAdd(&ctr[tgt], (uint32_t)__popcll(peers));
+        }
+        if (need_pos) {
+            base = __shfl(base, leader, 64);
+            if ((peers >> lane) & 1ull) pos = base + (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+        }
+        active &= ~peers;
+    }
+    return pos;
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
 // Preprocess one (pair, Gaussian): back-project at |D + delta|, move into the
 // view, project, form the dilated screen covariance, its conic and the tile
 // rectangle; count the tiles.  Every FP64 operation is written in the order
@@ -17,9 +53,10 @@ namespace sgad {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
 #pragma clang fp contract(off)
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)G.n_pairs * G.N;
-    if (i >= total) return;
+    const bool live = i0 < total;
+    const int64_t i = live ? i0 : total - 1;   // idle lanes shadow the last Gaussian, write nothing
     const int pair = (int)(i / G.N);
     const int pix = (int)(i - (int64_t)pair * G.N);
     const PairConst& pc = B.pairs[pair];
@@ -30,7 +67,7 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
     const float Of = kp.offset[pix];
     const float Rf = kp.radius[pix];
     bool ok = isfinite(Df) && isfinite(Of) && isfinite(Rf);
-    if (!ok) {
+    if (!ok && live) {
         atomicOr(&B.status->nonfinite, 1u);
         atomicOr(&B.status->sticky, 2u);
     }
@@ -44,9 +81,10 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
     const double x = ((R[0] * X0 + R[1] * X1) + R[2] * X2) + pc.t[0];
     const double y = ((R[3] * X0 + R[4] * X1) + R[5] * X2) + pc.t[1];
     const double z = ((R[6] * X0 + R[7] * X1) + R[8] * X2) + pc.t[2];
-    ok = ok && (z >= kZNear);
+    ok = ok && (z >= kZNear) && live;
 
     uint32_t rx = 0, ry = 0;
+    int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
     float fdx = 0.f, fdy = 0.f, fa = 0.f, fb = 0.f, fc = 0.f;
     if (ok) {
         const double tx = x / z;
@@ -77,8 +115,10 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
         ay0 = fmax(ay0, 0.0);
         ax1 = fmin(ax1, (double)G.ntx);
         ay1 = fmin(ay1, (double)G.nty);
-        int x0 = (int)fmin(ax0, (double)G.ntx), x1 = (int)fmax(ax1, 0.0);
-        int y0 = (int)fmin(ay0, (double)G.nty), y1 = (int)fmax(ay1, 0.0);
+        x0 = (int)fmin(ax0, (double)G.ntx);
+        x1 = (int)fmax(ax1, 0.0);
+        y0 = (int)fmin(ay0, (double)G.nty);
+        y1 = (int)fmax(ay1, 0.0);
         if (x1 < x0) x1 = x0;
         if (y1 < y0) y1 = y0;
         rx = (uint32_t)x0 | ((uint32_t)x1 << 16);
@@ -88,10 +128,19 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
         fa = (float)ca;
         fb = (float)cb;
         fc = (float)cc;
-        uint32_t* cnt = B.tile_count + (size_t)pc.job * G.ntiles;
-        for (int ty = y0; ty < y1; ++ty)
-            for (int tx = x0; tx < x1; ++tx) atomicAdd(&cnt[ty * G.ntx + tx], 1u);
     }
+    {
+        // count the overlapped tiles, one wave-aggregated round per rectangle cell
+        const int w = x1 - x0, n = ok ? w * (y1 - y0) : 0;
+        const int nmax = wave_max_int(n);
+        const int64_t base = (int64_t)pc.job * G.ntiles;
+        for (int k = 0; k < nmax; ++k) {
+            int64_t t = -1;
+            if (k < n) t = base + (int64_t)(y0 + k / w) * G.ntx + (x0 + k % w);
+            wave_agg_add(B.tile_count, t, false);
+        }
+    }
+    if (!live) return;
     const float fz = ok ? (float)z : 0.f;
     float c0 = 0.f, c1 = 0.f, c2 = 0.f;
     if (kp.rgb) {
@@ -168,7 +217,6 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ coun
         start[M] = tot;
         st->total = tot;
         st->overflow = tot > capacity ? 1u : 0u;
-        if (tot > capacity) st->sticky |= 1u;
         st->queue = 0u;
     }
 }
@@ -181,22 +229,38 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ coun
 __global__ __launch_bounds__(256) void k_scatter(Geometry G, RenderBufs B) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)G.n_pairs * G.N;
-    if (i >= total) return;
-    const uint32_t rx = B.pre.rx[i], ry = B.pre.ry[i];
-    const int x0 = rx & 0xffff, x1 = rx >> 16, y0 = ry & 0xffff, y1 = ry >> 16;
-    if (x0 >= x1 || y0 >= y1) return;
-    const int pair = (int)(i / G.N);
-    const int pix = (int)(i - (int64_t)pair * G.N);
-    const PairConst& pc = B.pairs[pair];
-    const uint32_t gid = (uint32_t)pc.kf * (uint32_t)G.N + (uint32_t)pix;
-    const uint64_t key = ((uint64_t)__float_as_uint(B.pre.z[i]) << 32) | gid;
-    const size_t base = (size_t)pc.job * G.ntiles;
-    for (int ty = y0; ty < y1; ++ty)
-        for (int tx = x0; tx < x1; ++tx) {
-            const size_t t = base + ty * G.ntx + tx;
-            const uint32_t pos = B.tile_start[t] + atomicAdd(&B.tile_fill[t], 1u);
+    int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+    uint64_t key = 0;
+    int64_t base = 0;
+    if (i < total) {
+        const uint32_t rx = B.pre.rx[i], ry = B.pre.ry[i];
+        x0 = rx & 0xffff;
+        x1 = rx >> 16;
+        y0 = ry & 0xffff;
+        y1 = ry >> 16;
+        const int pair = (int)(i / G.N);
+        const int pix = (int)(i - (int64_t)pair * G.N);
+        const PairConst& pc = B.pairs[pair];
+        const uint32_t gid = (uint32_t)pc.kf * (uint32_t)G.N + (uint32_t)pix;
+        key = ((uint64_t)__float_as_uint(B.pre.z[i]) << 32) | gid;
+        base = (int64_t)pc.job * G.ntiles;
+    }
+    const int w = x1 - x0;
+    const int n = (x0 < x1 && y0 < y1) ? w * (y1 - y0) : 0;
+    const int nmax = wave_max_int(n);
+    bool dropped = false;
+    for (int k = 0; k < nmax; ++k) {
+        int64_t t = -1;
+        if (k < n) t = base + (int64_t)(y0 + k / w) * G.ntx + (x0 + k % w);
+        const uint32_t r = wave_agg_add(B.tile_fill, t, true);
+        if (t >= 0) {
+            const uint32_t pos = B.tile_start[t] + r;
             if (pos < B.capacity) B.keys[pos] = key;
+            else dropped = true;
         }
+    }
+    // an instance that did not fit is the overflow the caller must hear of
+    if (__ballot(dropped) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&B.status->sticky, 1u);
 }
 
 // ---------------------------------------------------------------------------

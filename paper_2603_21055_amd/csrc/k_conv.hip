@@ -1,0 +1,311 @@
+// BF16 3x3 convolutions on MFMA (gfx950 v_mfma_f32_16x16x32_bf16) for the
+// offset warm-start net: forward with fused bias + ReLU, input gradient with
+// the ReLU mask of the layer input fused, weight and bias gradients.
+//
+// Activations are NHWC bf16 ([H][W][C], C in {1, 4, 32}); weights are
+// [9][Cout][Cin] bf16 (tap-major).  Every product accumulates in FP32.
+//
+// Implicit GEMM per 16x16 output tile and tap: C[co][pixel] += W[co][ci] *
+// X[ci][pixel + tap offset].  Operand layouts of the 16x16x32 MFMA: lane l
+// holds A[l % 16][8 (l / 16) .. +8], B[8 (l / 16) .. +8][l % 16] and
+// C[4 (l / 16) .. +4][l % 16].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sgad_internal.h"
+
+namespace sgad {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPS = 40;  // LDS pixel stride (bf16 elements) of the input tile
+
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (__bf16)0.f;
+    return v;
+}
+
+// MODE 0: y = relu(conv + bias) as bf16 [H][W][COUT]
+// MODE 1: y = conv + bias as f32 [H][W] (COUT == 1)
+// MODE 2: y = conv * [mask > 0] as bf16 [H][W][COUT] (input gradient through a ReLU)
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv(int H, int W, const __bf16* __restrict__ x,
+                                              const __bf16* __restrict__ w, const float* __restrict__ bias,
+                                              const __bf16* __restrict__ mask, void* __restrict__ yout) {
+    constexpr int MB = (COUT + 15) / 16;
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[18 * 18 * kPS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
+    for (int i = tid; i < 324 * 4; i += 256) {
+        const int pix = i >> 2, ch = i & 3;
+        const int ty = pix / 18, tx = pix - ty * 18;
+        const int gy = y0 + ty - 1, gx = x0 + tx - 1;
+        bf16x8 v = zero8();
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            const size_t base = ((size_t)gy * W + gx) * CIN;
+            if (CIN == 32) {
+                v = *(const bf16x8*)(x + base + ch * 8);
+            } else if (ch == 0) {
+#pragma unroll
+                for (int c = 0; c < CIN; ++c) v[c] = x[base + c];
+            }
+        }
+        *(bf16x8*)(s_x + pix * kPS + ch * 8) = v;
+    }
+    bf16x8 A[9][MB];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int co = mb * 16 + r16;
+            bf16x8 v = zero8();
+            if (co < COUT) {
+                const __bf16* src = w + ((size_t)t * COUT + co) * CIN;
+                if (CIN == 32) {
+                    v = *(const bf16x8*)(src + g * 8);
+                } else if (g == 0) {
+#pragma unroll
+                    for (int c = 0; c < CIN; ++c) v[c] = src[c];
+                }
+            }
+            A[t][mb] = v;
+        }
+    __syncthreads();
+    f32x4 acc[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ky = t / 3, kx = t - ky * 3;
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            const int ry = wave * 4 + nb + ky, rx = r16 + kx;
+            const bf16x8 B = *(const bf16x8*)(s_x + (ry * 18 + rx) * kPS + g * 8);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[t][mb], B, acc[mb][nb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int py = y0 + wave * 4 + nb, px = x0 + r16;
+        if (py >= H || px >= W) continue;
+        const size_t p = (size_t)py * W + px;
+        if (MODE == 1) {
+            if (g == 0) ((float*)yout)[p] = acc[0][nb][0] + bias[0];
+            continue;
+        }
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int co0 = mb * 16 + 4 * g;
+            if (co0 >= COUT) continue;
+            bf16x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v = acc[mb][nb][e];
+                if (MODE == 0) v = fmaxf(v + bias[co0 + e], 0.f);
+                else if ((float)mask[p * COUT + co0 + e] <= 0.f) v = 0.f;
+                o[e] = (__bf16)v;
+            }
+            *(bf16x4*)((__bf16*)yout + p * COUT + co0) = o;
+        }
+    }
+}
+
+// Weight and bias gradients: dw[t][co][ci] += sum_p dy[p][co] x[p + off(t)][ci],
+// db[co] += sum_p dy[p][co].  Each workgroup walks 16x16 tiles and keeps its
+// partial sums in registers (wave w owns taps w, w + 4, w + 8), then adds
+// them to the FP32 outputs with atomics once.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __restrict__ x,
+                                               const __bf16* __restrict__ dy, float* dw, float* db) {
+    constexpr int MB = (COUT + 15) / 16, NB = (CIN + 15) / 16;
+    constexpr int DS = 264;  // [co][pixel] row stride
+    __shared__ __attribute__((aligned(16))) __bf16 s_dy[32 * DS];
+    __shared__ __bf16 s_x[32 * 18 * 24];
+    __shared__ float s_db[8][32];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int ntx = (W + 15) / 16, nty = (H + 15) / 16, ntiles = ntx * nty;
+    f32x4 acc[3][MB][NB];
+#pragma unroll
+    for (int k3 = 0; k3 < 3; ++k3)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[k3][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dbp = 0.f;
+    const int bco = tid & 31, bgrp = tid >> 5;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int x0 = (tile % ntx) * 16, y0 = (tile / ntx) * 16;
+        __syncthreads();
+        for (int i = tid; i < 256 * 32; i += 256) {
+            const int p = i >> 5, co = i & 31;
+            const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
+            __bf16 v = (__bf16)0.f;
+            if (co < COUT && gy < H && gx < W) v = dy[((size_t)gy * W + gx) * COUT + co];
+            s_dy[co * DS + p] = v;
+        }
+        for (int i = tid; i < 324 * 32; i += 256) {
+            const int pix = i >> 5, ci = i & 31;
+            const int ty = pix / 18, tx = pix - ty * 18;
+            const int gy = y0 + ty - 1, gx = x0 + tx - 1;
+            __bf16 v = (__bf16)0.f;
+            if (ci < CIN && gy >= 0 && gy < H && gx >= 0 && gx < W) v = x[((size_t)gy * W + gx) * CIN + ci];
+            s_x[(ci * 18 + ty) * 24 + tx] = v;
+        }
+        __syncthreads();
+        if (bco < COUT)
+            for (int j = 0; j < 32; ++j) dbp += (float)s_dy[bco * DS + bgrp * 32 + j];
+#pragma unroll
+        for (int k3 = 0; k3 < 3; ++k3) {
+            const int t = wave + 4 * k3;
+            if (t >= 9) continue;
+            const int ky = t / 3, kx = t - ky * 3;
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const int row = 2 * ks + (g >> 1), col = (g & 1) * 8;
+                bf16x8 Am[MB];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    Am[mb] = *(const bf16x8*)(s_dy + (mb * 16 + r16) * DS + 32 * ks + 8 * g);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int ci = nb * 16 + r16;
+                    bf16x8 Bv;
+                    const __bf16* src = s_x + (ci * 18 + row + ky) * 24 + col + kx;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) Bv[j] = src[j];
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+                        acc[k3][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am[mb], Bv, acc[k3][mb][nb], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k3 = 0; k3 < 3; ++k3) {
+        const int t = wave + 4 * k3;
+        if (t >= 9) continue;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int co = mb * 16 + 4 * g + e, ci = nb * 16 + r16;
+                    if (co < COUT && ci < CIN) atomicAdd(&dw[((size_t)t * COUT + co) * CIN + ci], acc[k3][mb][nb][e]);
+                }
+    }
+    s_db[bgrp][bco] = dbp;
+    __syncthreads();
+    if (tid < COUT) {
+        float s = 0.f;
+        for (int k = 0; k < 8; ++k) s += s_db[k][tid];
+        atomicAdd(&db[tid], s);
+    }
+}
+
+// FP32 master weights [9][cout][cin] -> bf16 copy and the transposed,
+// tap-flipped bf16 copy used by the input gradient: wt[t][ci][co] = w[8-t][co][ci].
+__global__ void k_conv_weights(int cin, int cout, const float* w, __bf16* wb, __bf16* wt) {
+    const int n = 9 * cin * cout;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int t = i / (cin * cout), rem = i - t * cin * cout;
+        const int co = rem / cin, ci = rem - co * cin;
+        const __bf16 v = (__bf16)w[i];
+        wb[i] = v;
+        if (wt) wt[((size_t)(8 - t) * cin + ci) * cout + co] = v;
+    }
+}
+
+// Network input: (R, G, B, D / 5 m) as bf16 [H][W][4].
+__global__ void k_net_input(int H, int W, const float* rgb, const float* depth, __bf16* x0) {
+    const int P = H * W;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        bf16x4 v;
+        v[0] = (__bf16)rgb[p];
+        v[1] = (__bf16)rgb[P + p];
+        v[2] = (__bf16)rgb[2 * P + p];
+        v[3] = (__bf16)(depth[p] / 5.f);
+        *(bf16x4*)(x0 + (size_t)p * 4) = v;
+    }
+}
+
+// L1 training loss mean|pred - target| and its gradient (bf16, one channel).
+__global__ void k_offset_l1(int n, const float* pred, const float* target, __bf16* grad, double* loss) {
+    double acc = 0.0;
+    const float inv = 1.f / (float)n;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float e = pred[i] - target[i];
+        acc += (double)fabsf(e);
+        grad[i] = (__bf16)(e > 0.f ? inv : (e < 0.f ? -inv : 0.f));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(loss, acc / (double)n);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers (return false for an unsupported channel configuration)
+// ---------------------------------------------------------------------------
+bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* bias,
+                     const void* mask, void* y, hipStream_t s) {
+    const dim3 grid((W + 15) / 16, (H + 15) / 16), blk(256);
+    const __bf16* xb = (const __bf16*)x;
+    const __bf16* wb = (const __bf16*)w;
+    const __bf16* mb = (const __bf16*)mask;
+    if (mode == 0 && cin == 4 && cout == 32)
+        hipLaunchKernelGGL((k_conv<4, 32, 0>), grid, blk, 0, s, H, W, xb, wb, bias, mb, y);
+    else if (mode == 0 && cin == 32 && cout == 32)
+        hipLaunchKernelGGL((k_conv<32, 32, 0>), grid, blk, 0, s, H, W, xb, wb, bias, mb, y);
+    else if (mode == 1 && cin == 32 && cout == 1)
+        hipLaunchKernelGGL((k_conv<32, 1, 1>), grid, blk, 0, s, H, W, xb, wb, bias, mb, y);
+    else if (mode == 2 && cin == 32 && cout == 32)
+        hipLaunchKernelGGL((k_conv<32, 32, 2>), grid, blk, 0, s, H, W, xb, wb, bias, mb, y);
+    else if (mode == 2 && cin == 1 && cout == 32)
+        hipLaunchKernelGGL((k_conv<1, 32, 2>), grid, blk, 0, s, H, W, xb, wb, bias, mb, y);
+    else
+        return false;
+    return true;
+}
+
+bool launch_conv_wgrad(int H, int W, int cin, int cout, const void* x, const void* dy, float* dw, float* db,
+                       hipStream_t s) {
+    const int ntiles = ((W + 15) / 16) * ((H + 15) / 16);
+    const dim3 grid(std::min(ntiles, 256)), blk(256);
+    const __bf16* xb = (const __bf16*)x;
+    const __bf16* db16 = (const __bf16*)dy;
+    if (cin == 4 && cout == 32) hipLaunchKernelGGL((k_wgrad<4, 32>), grid, blk, 0, s, H, W, xb, db16, dw, db);
+    else if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_wgrad<32, 32>), grid, blk, 0, s, H, W, xb, db16, dw, db);
+    else if (cin == 32 && cout == 1) hipLaunchKernelGGL((k_wgrad<32, 1>), grid, blk, 0, s, H, W, xb, db16, dw, db);
+    else return false;
+    return true;
+}
+
+void launch_conv_weights(int cin, int cout, const float* w, void* wb, void* wt, hipStream_t s) {
+    const int n = 9 * cin * cout;
+    hipLaunchKernelGGL(k_conv_weights, dim3((n + 255) / 256), dim3(256), 0, s, cin, cout, w, (__bf16*)wb,
+                       (__bf16*)wt);
+}
+
+void launch_net_input(int H, int W, const float* rgb, const float* depth, void* x0, hipStream_t s) {
+    const int P = H * W;
+    hipLaunchKernelGGL(k_net_input, dim3(std::min(4096, (P + 255) / 256)), dim3(256), 0, s, H, W, rgb, depth,
+                       (__bf16*)x0);
+}
+
+void launch_offset_l1(int n, const float* pred, const float* target, void* grad, double* loss, hipStream_t s) {
+    hipLaunchKernelGGL(k_offset_l1, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, s, n, pred, target,
+                       (__bf16*)grad, loss);
+}
+
+}  // namespace sgad

@@ -29,7 +29,13 @@ __global__ __launch_bounds__(256) void k_count_valid(const float* __restrict__ t
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x)
         c += t_depth[(size_t)job * P + i] > 0.f ? 1u : 0u;
     c = wave_sum_u(c);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&count[job], c);
+    __shared__ uint32_t s_c[4];
+    if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+        if (t) atomicAdd(&count[job], t);
+    }
 }
 
 // Loss value and upstream grads:
@@ -58,7 +64,10 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const
         g_dep[jp] = signf(e) * inv_dep;
     }
     acc = wave_sum_d(acc);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&loss[job], acc);
+    __shared__ double s_a[4];
+    if ((threadIdx.x & 63) == 0) s_a[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&loss[job], s_a[0] + s_a[1] + s_a[2] + s_a[3]);
 }
 
 // Multi-tensor Adam: group g owns elements [off[g], off[g+1]) of the flat range.
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamGroups A, float b1, float b2, 
 void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const float* t_rgb, const float* t_dep,
                float w_rgb, float w_dep, uint32_t* count, float* g_rgb, float* g_dep, double* loss,
                hipStream_t s) {
-    const int bx = std::min(1024, (P + 255) / 256);
+    const int bx = std::min(128, (P + 255) / 256);
     hipLaunchKernelGGL(k_count_valid, dim3(bx, n_jobs), dim3(256), 0, s, t_dep, P, count);
     hipLaunchKernelGGL(k_l1, dim3(bx, n_jobs), dim3(256), 0, s, rgb, dep, t_rgb, t_dep, P, w_rgb, w_dep, count,
                        g_rgb, g_dep, loss);

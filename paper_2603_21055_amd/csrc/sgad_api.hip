@@ -27,6 +27,13 @@ void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const floa
                hipStream_t s);
 void launch_adam(const AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
                  hipStream_t s);
+bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* bias,
+                     const void* mask, void* y, hipStream_t s);
+bool launch_conv_wgrad(int H, int W, int cin, int cout, const void* x, const void* dy, float* dw, float* db,
+                       hipStream_t s);
+void launch_conv_weights(int cin, int cout, const float* w, void* wb, void* wt, hipStream_t s);
+void launch_net_input(int H, int W, const float* rgb, const float* depth, void* x0, hipStream_t s);
+void launch_offset_l1(int n, const float* pred, const float* target, void* grad, double* loss, hipStream_t s);
 void launch_track_pair(const double* pose, const sgad_pose& kf_pose, const sgad_cam& kc, const sgad_cam& vc,
                        PairConst* out, hipStream_t s);
 bool launch_track(const Geometry& G, const RenderBufs& B, const float* obs, float* part, hipStream_t s);
@@ -1024,6 +1031,84 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
     if (best_tw) *best_tw = bc.tw;
     if (best_th) *best_th = bc.th;
     if (best_ms) *best_ms = best;
+    return SGAD_OK;
+}
+
+// ---------------------------------------------------------------- conv net
+static bool conv_dims_ok(int H, int W) { return H > 0 && W > 0 && H < 65536 && W < 65536; }
+
+sgad_status sgad_conv_weights(sgad_ctx* c, int cin, int cout, const float* w, uint16_t* w_bf16, uint16_t* wt_bf16,
+                              void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (cin < 1 || cout < 1 || cin > 32 || cout > 32 || !w || !w_bf16) return fail(c, SGAD_EINVAL, "bad weights");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    TimeScope ts(c, "conv_weights", s);
+    launch_conv_weights(cin, cout, w, w_bf16, wt_bf16, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_conv3x3_fwd(sgad_ctx* c, int H, int W, int cin, int cout, int mode, const uint16_t* x,
+                             const uint16_t* w_bf16, const float* bias, void* y, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!conv_dims_ok(H, W) || !x || !w_bf16 || !bias || !y) return fail(c, SGAD_EINVAL, "bad conv arguments");
+    if (mode != SGAD_CONV_RELU_BF16 && mode != SGAD_CONV_LINEAR_F32) return fail(c, SGAD_EINVAL, "bad conv mode");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    TimeScope ts(c, "conv_fwd", s);
+    if (!launch_conv_fwd(H, W, cin, cout, mode, x, w_bf16, bias, nullptr, y, s))
+        return fail(c, SGAD_EINVAL, "unsupported (cin, cout, mode)");
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_conv3x3_dgrad(sgad_ctx* c, int H, int W, int cin, int cout, const uint16_t* dy,
+                               const uint16_t* wt_bf16, const uint16_t* mask, uint16_t* dx, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!conv_dims_ok(H, W) || !dy || !wt_bf16 || !mask || !dx) return fail(c, SGAD_EINVAL, "bad dgrad arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    TimeScope ts(c, "conv_dgrad", s);
+    // the input gradient is a convolution from cout to cin channels
+    if (!launch_conv_fwd(H, W, cout, cin, 2, dy, wt_bf16, nullptr, mask, dx, s))
+        return fail(c, SGAD_EINVAL, "unsupported (cin, cout)");
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_conv3x3_wgrad(sgad_ctx* c, int H, int W, int cin, int cout, const uint16_t* x, const uint16_t* dy,
+                               float* dw, float* db, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!conv_dims_ok(H, W) || !x || !dy || !dw || !db) return fail(c, SGAD_EINVAL, "bad wgrad arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    TimeScope ts(c, "conv_wgrad", s);
+    if (!launch_conv_wgrad(H, W, cin, cout, x, dy, dw, db, s)) return fail(c, SGAD_EINVAL, "unsupported (cin, cout)");
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_net_input(sgad_ctx* c, int H, int W, const float* rgb, const float* depth, uint16_t* x0,
+                           void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!conv_dims_ok(H, W) || !rgb || !depth || !x0) return fail(c, SGAD_EINVAL, "bad input arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    launch_net_input(H, W, rgb, depth, x0, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_offset_l1(sgad_ctx* c, int n, const float* pred, const float* target, uint16_t* grad,
+                           double* loss, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (n < 1 || !pred || !target || !grad || !loss) return fail(c, SGAD_EINVAL, "bad loss arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    launch_zero_u32((uint32_t*)loss, 2, s);
+    launch_offset_l1(n, pred, target, grad, loss, s);
+    HIPCHK(c, hipGetLastError());
     return SGAD_OK;
 }
 

@@ -80,6 +80,12 @@ _SIGS = {
     "sgad_adam_step": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_int, C.c_float, C.c_float, C.c_float,
                                  C.c_int, _P]),
     "sgad_timing_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
+    "sgad_conv_weights": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
+    "sgad_conv3x3_fwd": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, _P]),
+    "sgad_conv3x3_dgrad": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, _P]),
+    "sgad_conv3x3_wgrad": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, _P]),
+    "sgad_net_input": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
+    "sgad_offset_l1": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
     "sgad_autotune": (C.c_int, [_P, C.c_int, C.POINTER(Keyframe), C.c_int, C.POINTER(Cam), C.POINTER(Pose),
                                 C.c_int, C.POINTER(Job), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                 C.POINTER(C.c_float), _P]),
@@ -324,6 +330,34 @@ class Context:
         st = self.lib.sgad_track_gn(self.h, kfa, C.byref(cam), _ptr(obs_depth), _ptr(pose), int(iters),
                                     _ptr(trace), 1 if graph else 0, _stream(stream))
         self._check(st)
+
+    # -------------------------------------------------------------- conv net
+    def conv_weights(self, cin, cout, w, w_bf16, wt_bf16=None, stream=None):
+        import torch
+        _check_tensor(w, "w", self.device)
+        _check_tensor(w_bf16, "w_bf16", self.device, torch.bfloat16)
+        _check_tensor(wt_bf16, "wt_bf16", self.device, torch.bfloat16)
+        self._check(self.lib.sgad_conv_weights(self.h, cin, cout, _ptr(w), _ptr(w_bf16), _ptr(wt_bf16),
+                                               _stream(stream)))
+
+    def conv_fwd(self, H, W, cin, cout, mode, x, w_bf16, bias, y, stream=None):
+        self._check(self.lib.sgad_conv3x3_fwd(self.h, H, W, cin, cout, mode, _ptr(x), _ptr(w_bf16), _ptr(bias),
+                                              _ptr(y), _stream(stream)))
+
+    def conv_dgrad(self, H, W, cin, cout, dy, wt_bf16, mask, dx, stream=None):
+        self._check(self.lib.sgad_conv3x3_dgrad(self.h, H, W, cin, cout, _ptr(dy), _ptr(wt_bf16), _ptr(mask),
+                                                _ptr(dx), _stream(stream)))
+
+    def conv_wgrad(self, H, W, cin, cout, x, dy, dw, db, stream=None):
+        self._check(self.lib.sgad_conv3x3_wgrad(self.h, H, W, cin, cout, _ptr(x), _ptr(dy), _ptr(dw), _ptr(db),
+                                                _stream(stream)))
+
+    def net_input(self, H, W, rgb, depth, x0, stream=None):
+        self._check(self.lib.sgad_net_input(self.h, H, W, _ptr(rgb), _ptr(depth), _ptr(x0), _stream(stream)))
+
+    def offset_l1(self, pred, target, grad, loss, stream=None):
+        self._check(self.lib.sgad_offset_l1(self.h, pred.numel(), _ptr(pred), _ptr(target), _ptr(grad),
+                                            _ptr(loss), _stream(stream)))
 
     def release(self, saved):
         self._check(self.lib.sgad_saved_release(self.h, saved))

@@ -1,0 +1,180 @@
+"""Learned offset warm start: data from the method's own converged offsets,
+training of the BF16 conv net, and the warm-vs-plain mapping comparison.
+
+Training frames are 160x120 crops at the 640x480 focal length (fx = 600, so
+one pixel covers the same angle as in the evaluation frames) of random box
+rooms seen from random orientations; the keyframe depth carries N(0, 1 cm)
+noise.  The target offsets are what plain mapping converges to: a fixed
+number of mapping iterations of the keyframe (offsets from zero) against
+noise-free ray-cast renders at its own view and two neighbours perturbed by
+up to 2 cm / 1 degree.  The network sees (R, G, B, noisy D / 5 m).
+
+Evaluation: an 8-keyframe 640x480 window with the same depth noise, every
+view rendering all keyframes; plain mapping starts from zero offsets, warm
+mapping from the network's prediction; reported are the plain loss after
+`plain_iters` iterations and the first iteration at which the warm run's loss
+is at or below it.
+"""
+from __future__ import annotations
+
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import sgad, synth
+from .mapping import Mapper
+from .offsetnet import OffsetNet
+
+DEPTH_NOISE = 0.01
+
+
+def _rand_rot(rng, max_deg):
+    from scipy.spatial.transform import Rotation
+    v = rng.normal(size=3)
+    v /= np.linalg.norm(v)
+    return Rotation.from_rotvec(v * np.deg2rad(rng.uniform(0, max_deg))).as_matrix()
+
+
+def training_frame(seed: int, W: int = 160, H: int = 120, f: float = 600.0) -> dict:
+    """One training frame (CPU, numpy): noisy keyframe and three targets."""
+    rng = np.random.default_rng(seed)
+    room = synth.make_room(rng)
+    cam = dict(H=H, W=W, fx=f, fy=f, cx=W / 2.0, cy=H / 2.0)
+    R, t = synth.pose_from_c2w(_rand_rot(rng, 60.0), rng.uniform(-0.3, 0.3, size=3))
+    depth, rgb = room.raycast(cam, R, t)
+    noisy = (depth + rng.normal(0.0, DEPTH_NOISE, size=depth.shape)).astype(np.float32)
+    kf = synth.keyframe_from_frame(cam, R, t, noisy, rgb,
+                                   rng.uniform(0.5, 1.0, size=(H, W)).astype(np.float32))
+    views, targets = [dict(cam=dict(cam), R=R, t=t)], [dict(rgb=rgb, depth=depth)]
+    for _ in range(2):
+        Rv, tv = synth.perturb_pose(R, t, rng, 0.02, 1.0)
+        d, c = room.raycast(cam, Rv, tv)
+        views.append(dict(cam=dict(cam), R=Rv, t=tv))
+        targets.append(dict(rgb=c, depth=d))
+    return dict(kf=kf, views=views, targets=targets)
+
+
+def _gen(args):
+    return training_frame(*args)
+
+
+def make_frames(seeds, workers: int = 8):
+    if workers <= 1:
+        return [training_frame(s) for s in seeds]
+    from multiprocessing import Pool
+    with Pool(workers) as p:
+        return p.map(_gen, [(s,) for s in seeds])
+
+
+def converged_offsets(ctx, frame, iters: int = 200):
+    """Run plain mapping on one frame and return (rgb, noisy depth, offsets)."""
+    import torch
+    dev = ctx.device
+    kf = sgad.to_device(frame["kf"], dev)
+    t_rgb = torch.from_numpy(np.stack([t["rgb"] for t in frame["targets"]])).to(dev)
+    t_dep = torch.from_numpy(np.stack([t["depth"] for t in frame["targets"]])).to(dev)
+    jobs = [(v, [0]) for v in range(len(frame["views"]))]
+    m = Mapper(ctx, [kf], frame["views"], jobs, [0], t_rgb, t_dep)
+    for _ in range(iters):
+        m.step()
+    return kf["rgb"], kf["depth"], kf["offset"].clone()
+
+
+def train(ctx, data, epochs: int = 20, batch: int = 8, lr: float = 1e-3, seed: int = 0, log=None):
+    net = OffsetNet(ctx, seed=seed)
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        order = rng.permutation(len(data))
+        losses = []
+        for b0 in range(0, len(data), batch):
+            losses.append(net.train_step([data[i] for i in order[b0:b0 + batch]], lr=lr))
+        ep_loss = float(np.mean([l.mean().item() for l in losses]))
+        hist.append(ep_loss)
+        if log:
+            log(f"epoch {ep}: L1 {ep_loss * 1e3:.3f} mm")
+    return net, hist
+
+
+def eval_window(seed: int = 3000, W: int = 640, H: int = 480, n: int = 8) -> dict:
+    """8-keyframe window with noisy keyframe depth (CPU, numpy)."""
+    sc = synth.c3_window(seed, W=W, H=H, n=n)
+    rng = np.random.default_rng(seed + 1)
+    for kf in sc["kfs"]:
+        kf["depth"] = (kf["depth"] + rng.normal(0.0, DEPTH_NOISE, size=kf["depth"].shape)).astype(np.float32)
+        kf["radius"] = (kf["depth"] / np.float32(kf["cam"]["fx"])).astype(np.float32)
+        kf["offset"] = np.zeros_like(kf["depth"])
+    return sc
+
+
+def mapping_curve(ctx, sc, net, iters: int):
+    """Loss after each of `iters` mapping iterations of the whole window; the
+    offsets start at zero (net None) or at the network's prediction."""
+    import torch
+    dev = ctx.device
+    kfs = [sgad.to_device(k, dev) for k in sc["kfs"]]
+    if net is not None:
+        for k in kfs:
+            k["offset"].copy_(net.forward(k["rgb"], k["depth"]))
+    n = len(kfs)
+    t_rgb = torch.from_numpy(np.stack([t["rgb"] for t in sc["targets"]])).to(dev)
+    t_dep = torch.from_numpy(np.stack([t["depth"] for t in sc["targets"]])).to(dev)
+    jobs = [(v, list(range(n))) for v in range(n)]
+    m = Mapper(ctx, kfs, sc["views"], jobs, list(range(n)), t_rgb, t_dep)
+    curve = torch.zeros(iters, dtype=torch.float64, device=dev)
+    for i in range(iters):
+        m.step()
+        curve[i] = m.loss.sum()
+    torch.cuda.synchronize()
+    return curve.cpu().numpy()
+
+
+def experiment(ctx, n_frames=2000, epochs=20, batch=8, map_iters=200, plain_iters=50, workers=8, log=print,
+               eval_seed=3000, eval_size=(640, 480)):
+    t0 = time.time()
+    log(f"generating {n_frames} training frames")
+    frames = make_frames(range(1000, 1000 + n_frames), workers)
+    log(f"converging offsets ({map_iters} mapping iterations per frame)")
+    data = []
+    for i, fr in enumerate(frames):
+        rgb, dep, off = converged_offsets(ctx, fr, map_iters)
+        data.append((rgb, dep, off))
+        if i % 200 == 199:
+            log(f"  {i + 1} frames")
+    log("training")
+    net, hist = train(ctx, data, epochs=epochs, batch=batch, log=log)
+    log("evaluating")
+    sc = eval_window(eval_seed, W=eval_size[0], H=eval_size[1])
+    plain = mapping_curve(ctx, sc, None, plain_iters)
+    warm = mapping_curve(ctx, sc, net, plain_iters)
+    target = plain[-1]
+    hit = np.nonzero(warm <= target)[0]
+    warm_iters = int(hit[0]) + 1 if len(hit) else None
+    return dict(plain_iters=plain_iters, plain_final_loss=float(target), warm_iters_to_plain_loss=warm_iters,
+                warm_final_loss=float(warm[-1]), plain_curve=plain.tolist(), warm_curve=warm.tolist(),
+                train_loss=hist, n_frames=n_frames, epochs=epochs, seconds=time.time() - t0)
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--frames", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--map-iters", type=int, default=200)
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--out", type=str, default=None)
+    a = ap.parse_args()
+    ctx = sgad.Context(0)
+    res = experiment(ctx, a.frames, a.epochs, map_iters=a.map_iters, workers=a.workers,
+                     log=lambda m: print(m, file=sys.stderr, flush=True))
+    s = json.dumps({k: v for k, v in res.items() if not k.endswith("curve")})
+    print(s, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f)
+
+
+if __name__ == "__main__":
+    main()

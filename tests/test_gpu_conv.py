@@ -1,0 +1,172 @@
+"""GPU parity of the BF16-MFMA conv net against the FP64 oracle that emulates
+its BF16 roundings (tolerances: one bf16 step elementwise where the output
+is rounded to bf16; 1e-2 normwise for network outputs and gradients, whose
+inputs went through several bf16 roundings that FP32 vs FP64 accumulation
+can tip to the neighbouring bf16 value)."""
+import numpy as np
+import pytest
+
+from oracle import conv as oconv
+
+pytestmark = pytest.mark.gpu
+
+BF16_STEP = 2.0 ** -8   # relative spacing bound of bf16 (7 stored mantissa bits)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2603_21055_amd import sgad
+    assert torch.cuda.is_available()
+    c = sgad.Context(0)
+    yield c
+    c.close()
+
+
+def _bf(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev).to(torch.bfloat16)
+
+
+def _np(t):
+    import torch
+    return t.to(torch.float32).cpu().numpy().astype(np.float64)
+
+
+def _layer_weights(ctx, cin, cout, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    w = rng.normal(size=(3, 3, cout, cin)).astype(np.float32) * np.float32(np.sqrt(2.0 / (9 * cin)))
+    b = rng.normal(size=cout).astype(np.float32) * np.float32(0.1)
+    w9 = torch.from_numpy(np.ascontiguousarray(w.reshape(9, cout, cin))).to(ctx.device)
+    w16 = torch.empty((9, cout, cin), dtype=torch.bfloat16, device=ctx.device)
+    wt16 = torch.empty((9, cin, cout), dtype=torch.bfloat16, device=ctx.device)
+    ctx.conv_weights(cin, cout, w9, w16, wt16)
+    return w, b, w16, wt16
+
+
+@pytest.mark.parametrize("cin,cout", [(4, 32), (32, 32), (32, 1)])
+def test_single_layer_forward(ctx, cin, cout):
+    import torch
+    print(f"conv fwd {cin}->{cout}", flush=True)
+    H, W = 37, 45      # several 16x16 tiles with ragged edges
+    rng = np.random.default_rng(cin * 100 + cout)
+    x = rng.normal(size=(H, W, cin)).astype(np.float32)
+    w, b, w16, _ = _layer_weights(ctx, cin, cout, 1)
+    xb = _bf(x, ctx.device)
+    bt = torch.from_numpy(b).to(ctx.device)
+    if cout == 1:
+        y = torch.empty((H, W), dtype=torch.float32, device=ctx.device)
+        ctx.conv_fwd(H, W, cin, cout, 1, xb, w16, bt, y)
+        torch.cuda.synchronize()
+        ref = oconv.conv3x3(oconv.bf16(x), oconv.bf16(w), b.astype(np.float64))[..., 0]
+        got = y.cpu().numpy().astype(np.float64)
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    else:
+        y = torch.empty((H, W, cout), dtype=torch.bfloat16, device=ctx.device)
+        ctx.conv_fwd(H, W, cin, cout, 0, xb, w16, bt, y)
+        torch.cuda.synchronize()
+        pre = oconv.conv3x3(oconv.bf16(x), oconv.bf16(w), b.astype(np.float64))
+        ref = oconv.bf16(np.maximum(pre, 0.0))
+        # FP32 accumulation can move a pre-activation by ~1e-6 of its absolute
+        # terms: across the ReLU kink or a bf16 rounding boundary
+        absterms = oconv.conv3x3(np.abs(oconv.bf16(x)), np.abs(oconv.bf16(w)), np.abs(b.astype(np.float64)))
+        got = _np(y)
+        assert np.all(np.abs(got - ref) <= BF16_STEP * np.abs(ref) + 1e-6 * absterms)
+        assert (got == ref).mean() > 0.99
+
+
+@pytest.mark.parametrize("cin,cout", [(32, 32), (32, 1)])
+def test_single_layer_input_gradient(ctx, cin, cout):
+    import torch
+    print(f"conv dgrad {cin}->{cout}", flush=True)
+    H, W = 33, 40
+    rng = np.random.default_rng(7 + cout)
+    dy = rng.normal(size=(H, W, cout)).astype(np.float32)
+    mask = np.maximum(rng.normal(size=(H, W, cin)), 0.0).astype(np.float32)
+    w, b, w16, wt16 = _layer_weights(ctx, cin, cout, 2)
+    dx = torch.empty((H, W, cin), dtype=torch.bfloat16, device=ctx.device)
+    ctx.conv_dgrad(H, W, cin, cout, _bf(dy, ctx.device), wt16, _bf(mask, ctx.device), dx)
+    torch.cuda.synchronize()
+    ref = oconv.bf16(oconv.conv3x3_input_grad(oconv.bf16(dy), oconv.bf16(w)) * (oconv.bf16(mask) > 0))
+    absterms = oconv.conv3x3_input_grad(np.abs(oconv.bf16(dy)), np.abs(oconv.bf16(w)))
+    got = _np(dx)
+    assert np.all(np.abs(got - ref) <= BF16_STEP * np.abs(ref) + 1e-6 * absterms)
+
+
+@pytest.mark.parametrize("cin,cout", [(4, 32), (32, 32), (32, 1)])
+def test_single_layer_weight_gradient(ctx, cin, cout):
+    import torch
+    print(f"conv wgrad {cin}->{cout}", flush=True)
+    H, W = 50, 70
+    rng = np.random.default_rng(11 + cin + cout)
+    x = rng.normal(size=(H, W, cin)).astype(np.float32)
+    dy = rng.normal(size=(H, W, cout)).astype(np.float32)
+    dw = torch.zeros((9, cout, cin), dtype=torch.float32, device=ctx.device)
+    db = torch.zeros(cout, dtype=torch.float32, device=ctx.device)
+    ctx.conv_wgrad(H, W, cin, cout, _bf(x, ctx.device), _bf(dy, ctx.device), dw, db)
+    torch.cuda.synchronize()
+    ref = oconv.conv3x3_weight_grad(oconv.bf16(dy), oconv.bf16(x))
+    got = dw.cpu().numpy().reshape(3, 3, cout, cin)
+    assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    np.testing.assert_allclose(db.cpu().numpy(), oconv.bf16(dy).sum((0, 1)), rtol=1e-5, atol=1e-3)
+
+
+def test_network_forward_and_gradients(ctx):
+    import torch
+    from paper_2603_21055_amd.offsetnet import OffsetNet, init_params
+    from paper_2603_21055_amd import synth
+    print("offset net fwd/bwd 96x72", flush=True)
+    sc = synth.small_scene(50, 96, 72)
+    kf = sc["kfs"][0]
+    params = init_params(3)
+    rng = np.random.default_rng(4)
+    params = [(w, (rng.normal(size=b.shape) * 0.05).astype(np.float32)) for w, b in params]
+    net = OffsetNet(ctx, params)
+    dev = ctx.device
+    rgb = torch.from_numpy(kf["rgb"]).to(dev)
+    dep = torch.from_numpy(kf["depth"]).to(dev)
+    delta = net.forward(rgb, dep)
+    target = torch.from_numpy(rng.normal(size=(72, 96)).astype(np.float32) * 0.01).to(dev)
+    g = torch.empty((72, 96), dtype=torch.bfloat16, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctx.offset_l1(delta, target, g, loss)
+    net.backward(g)
+    torch.cuda.synchronize()
+    x0 = oconv.net_input(kf["rgb"], kf["depth"])
+    d0, acts, _ = oconv.forward(params, x0)
+    got = delta.cpu().numpy()
+    assert np.linalg.norm(got - d0) <= 1e-2 * np.linalg.norm(d0)
+    L, gd = oconv.l1(got, target.cpu().numpy())      # same sign pattern as the GPU's
+    assert abs(loss.item() - L) <= 1e-6 * L
+    grads = oconv.backward(params, acts, gd)
+    for l in range(6):
+        gw = net.dw[l].cpu().numpy().reshape(grads[l][0].shape)
+        e = np.linalg.norm(gw - grads[l][0]) / np.linalg.norm(grads[l][0])
+        print(f"layer {l}: weight-grad rel err {e:.2e}", flush=True)
+        assert e <= 1e-2
+        gb = net.db[l].cpu().numpy()
+        assert np.linalg.norm(gb - grads[l][1]) <= 1e-2 * np.linalg.norm(grads[l][1]) + 1e-6
+
+
+def test_training_reduces_loss(ctx):
+    import torch
+    from paper_2603_21055_amd.offsetnet import OffsetNet
+    from paper_2603_21055_amd import synth
+    print("offset net training", flush=True)
+    dev = ctx.device
+    batch = []
+    for s in range(4):
+        sc = synth.small_scene(60 + s, 64, 48)
+        kf = sc["kfs"][0]
+        rng = np.random.default_rng(s)
+        noise = rng.normal(size=kf["depth"].shape).astype(np.float32) * 0.01
+        # learnable target: the offset that undoes a known depth perturbation
+        batch.append((torch.from_numpy(kf["rgb"]).to(dev), torch.from_numpy(kf["depth"] + noise).to(dev),
+                      torch.from_numpy(-noise).to(dev)))
+    net = OffsetNet(ctx, seed=0)
+    first = net.train_step(batch).mean().item()
+    for _ in range(60):
+        last = net.train_step(batch)
+    torch.cuda.synchronize()
+    assert last.mean().item() < first
