@@ -10,7 +10,7 @@ from oracle import conv as oconv
 
 pytestmark = pytest.mark.gpu
 
-BF16_STEP = 2.0 ** -8   # relative spacing bound of bf16 (7 stored mantissa bits)
+BF16_STEP = 2.0 ** -7   # bf16 keeps 8 significant bits: neighbours are at most 2^-7 |x| apart
 
 
 @pytest.fixture(scope="module")
@@ -68,11 +68,13 @@ def test_single_layer_forward(ctx, cin, cout):
         torch.cuda.synchronize()
         pre = oconv.conv3x3(oconv.bf16(x), oconv.bf16(w), b.astype(np.float64))
         ref = oconv.bf16(np.maximum(pre, 0.0))
-        # FP32 accumulation can move a pre-activation by ~1e-6 of its absolute
-        # terms: across the ReLU kink or a bf16 rounding boundary
+        # FP32 accumulation of K = 9 cin products moves a pre-activation by up
+        # to K * 2^-24 of its absolute terms: across the ReLU kink or a bf16
+        # rounding boundary
         absterms = oconv.conv3x3(np.abs(oconv.bf16(x)), np.abs(oconv.bf16(w)), np.abs(b.astype(np.float64)))
         got = _np(y)
-        assert np.all(np.abs(got - ref) <= BF16_STEP * np.abs(ref) + 1e-6 * absterms)
+        viol = np.abs(got - ref) - (BF16_STEP * np.abs(ref) + 9 * cin * 2.0 ** -24 * absterms)
+        assert viol.max() <= 0, (float(viol.max()), int((viol > 0).sum()))
         assert (got == ref).mean() > 0.99
 
 
@@ -91,7 +93,8 @@ def test_single_layer_input_gradient(ctx, cin, cout):
     ref = oconv.bf16(oconv.conv3x3_input_grad(oconv.bf16(dy), oconv.bf16(w)) * (oconv.bf16(mask) > 0))
     absterms = oconv.conv3x3_input_grad(np.abs(oconv.bf16(dy)), np.abs(oconv.bf16(w)))
     got = _np(dx)
-    assert np.all(np.abs(got - ref) <= BF16_STEP * np.abs(ref) + 1e-6 * absterms)
+    viol = np.abs(got - ref) - (BF16_STEP * np.abs(ref) + 9 * cout * 2.0 ** -24 * absterms)
+    assert viol.max() <= 0, (float(viol.max()), int((viol > 0).sum()))
 
 
 @pytest.mark.parametrize("cin,cout", [(4, 32), (32, 32), (32, 1)])
