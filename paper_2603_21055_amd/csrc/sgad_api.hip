@@ -102,7 +102,7 @@ struct sgad_ctx {
     };
     std::vector<TuneEntry> tune;
     bool force = false;
-    int ftw = 8, fth = 8, fscf = 256, fscb = 128;
+    int ftw = 8, fth = 8, fscf = 256, fscb = 32;
     std::vector<sgad_saved*> slots;
     KernelTimer timer;
     DevBuf scratch;  // small per-context scratch (loss counters)
@@ -448,7 +448,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     HIPCHK(c, hipSetDevice(c->device));
     poll(c, false);
 
-    int TW = c->tile_w, TH = c->tile_h, SCF = 256, SCB = 128;
+    int TW = c->tile_w, TH = c->tile_h, SCF = 256, SCB = 32;
     if (c->force) {
         TW = c->ftw;
         TH = c->fth;
@@ -970,8 +970,8 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
     struct Cand {
         int tw, th, scf, scb;
     };
-    const Cand cands[] = {{16, 16, 0, 0}, {16, 8, 0, 0}, {32, 8, 0, 0}, {8, 8, 256, 128},
-                          {8, 8, 128, 128}, {8, 8, 256, 256}};
+    const Cand cands[] = {{16, 16, 0, 0}, {16, 8, 0, 0}, {32, 8, 0, 0}, {8, 8, 256, 32},
+                          {8, 8, 128, 32}, {8, 8, 256, 16}};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -983,7 +983,7 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
         c->ftw = cd.tw;
         c->fth = cd.th;
         c->fscf = cd.scf ? cd.scf : 256;
-        c->fscb = cd.scb ? cd.scb : 128;
+        c->fscb = cd.scb ? cd.scb : 32;
         float ms_tot = 0.f;
         for (int r = 0; r <= reps && rs == SGAD_OK; ++r) {  // r == 0 is a warm-up
             sgad_saved* sv = nullptr;
@@ -1018,7 +1018,7 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
         te.tw = bc.tw;
         te.th = bc.th;
         te.scf = bc.scf ? bc.scf : 256;
-        te.scb = bc.scb ? bc.scb : 128;
+        te.scb = bc.scb ? bc.scb : 32;
         te.ms = best;
         bool found = false;
         for (auto& e : c->tune)

@@ -71,7 +71,7 @@ struct Geometry {
     int Hk, Wk, N;        // keyframe size, N = Hk * Wk
     int Hv, Wv, P;        // view size
     int TW, TH, ntx, nty, ntiles;
-    int sc_fwd = 256, sc_bwd = 128;  // super-chunk sizes of the 8x8 wave-tile kernels
+    int sc_fwd = 256, sc_bwd = 32;  // forward super-chunk / backward sub-chunk of the 8x8 kernels
 };
 
 struct RenderBufs {
