@@ -34,6 +34,34 @@ FLOPS_PER_PAIR = {"composite_fwd": 26, "composite_bwd": 60}
 BYTES_BY_KERNEL = {  # algorithmic bytes per Gaussian / per pixel of each kernel
     "composite_fwd": (28, 24), "composite_bwd": (52, 28), "preprocess": (16, 0),
 }
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch, one counter per run) on this workload, scaled by what the same
+# counters read for a plain 1 GiB device copy: FETCH_SIZE reports 0.5 GiB for
+# the copy's 1 GiB of reads (x2.0), WRITE_SIZE the exact 1 GiB (x1.0).  An
+# entry holds only for the kernel sources it was taken on (sha256 of the files
+# in KERNEL_SOURCES); after any change the traffic is reported as null.
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+KERNEL_SOURCES = {
+    "composite_bwd": ("k_raster8.hip", "raster_common.h", "sgad_internal.h"),
+    "composite_fwd": ("k_raster8.hip", "raster_common.h", "sgad_internal.h"),
+}
+PMC = {}   # kernel -> dict(fetch_kib=..., write_kib=..., sha=...)
+
+
+def sources_sha(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, ()):
+        with open(os.path.join(ROOT, "paper_2603_21055_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel):
+    e = PMC.get(kernel)
+    if e is None or e["sha"] != sources_sha(kernel):
+        return None
+    return (e["fetch_kib"] * FETCH_SCALE + e["write_kib"] * WRITE_SCALE) * 1024.0
 
 
 def log(msg):
@@ -151,10 +179,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=str, default="auto", help="auto (autotuner) or WxH")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--print-sha", action="store_true", help="print the kernel-source hashes and exit")
+    ap.add_argument("--graph", action="store_true", help="time replays of a captured graph of one step")
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "copy"], default="c2",
                     help="c2: the headline 640x480 frame; c3: 8-keyframe x 8-view window; "
                          "c4: 1200x680 tracking; copy: plain device copy (counter calibration)")
     args = ap.parse_args()
+    if args.print_sha:
+        print(json.dumps({k: sources_sha(k) for k in KERNEL_SOURCES}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path (--gpus 1).",
               file=sys.stderr)
@@ -188,15 +221,34 @@ def main():
     mapper = Mapper(ctx, kfs_d, views, jobs, [0], t_rgb, t_dep, with_count=True)
     step = mapper.step
 
+    # warmup: W eager steps (the first sizes the workspace); the second half
+    # runs with every kernel timed, for the per-kernel breakdown
     log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
+    half = max(1, args.warmup // 2)
+    for _ in range(half):
         step()
     torch.cuda.synchronize()
     ctx.sync()
+    ctx.timing(True)
+    for _ in range(max(1, args.warmup - half)):
+        step()
+    torch.cuda.synchronize()
+    warm = {k: v[1] / v[0] for k, v in ctx.timing_report().items()}
+    ctx.timing(False)
+    ctx.sync()
     pairs = int(mapper.cnt.sum().item())
     loss0 = mapper.loss_value()
-    log(f"timed {args.steps} steps")
+    dom = max(warm, key=warm.get)
+    # timed region: events bracket only the dominant kernel
+    ctx.timing_only(dom)
     ctx.timing(True)
+    if args.graph:
+        step()                    # re-sizes the workspace if the warmup outgrew it
+        torch.cuda.synchronize()
+        mapper.capture()          # (the timing events become graph nodes)
+        step = mapper.replay
+        ctx.timing(True)
+    log(f"timed {args.steps} steps ({'graph replays' if args.graph else 'eager calls'}; timing {dom})")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -205,23 +257,25 @@ def main():
     t1 = time.perf_counter()
     rep = ctx.timing_report()
     ctx.timing(False)
+    ctx.timing_only(None)
     ctx.sync()
+    if args.graph:
+        mapper.release_graph()
     ms = (t1 - t0) * 1e3 / args.steps
     fps = 1e3 / ms
-    kern = {k: v[1] / v[0] for k, v in rep.items()}       # average ms per launch
-    log("kernel avg ms: " + ", ".join(f"{k}={v:.4f}" for k, v in sorted(kern.items(), key=lambda x: -x[1])))
-    dom = max(kern, key=kern.get)
+    kern = {k: v[1] / v[0] for k, v in rep.items()}       # average ms per launch, timed region
+    log("warmup kernel avg ms: " + ", ".join(f"{k}={v:.4f}" for k, v in sorted(warm.items(), key=lambda x: -x[1])))
     t_dom = kern[dom] * 1e-3
     if dom in FLOPS_PER_PAIR:
         achieved = pairs * FLOPS_PER_PAIR[dom] / t_dom
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=FP32_VECTOR_PEAK / 1e12, unit="TFLOP/s",
-                    frac=achieved / FP32_VECTOR_PEAK, traffic=None, kernel=dom,
+                    frac=achieved / FP32_VECTOR_PEAK, traffic=traffic_bytes(dom), kernel=dom,
                     kernel_ms=kern[dom], pairs_per_launch=pairs, flops_per_pair=FLOPS_PER_PAIR[dom])
     else:
         bg, bp = BYTES_BY_KERNEL.get(dom, (0, 0))
         achieved = (bg * N + bp * P) / t_dom
         roof = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                    frac=achieved / HBM_PEAK, traffic=None, kernel=dom, kernel_ms=kern[dom])
+                    frac=achieved / HBM_PEAK, traffic=traffic_bytes(dom), kernel=dom, kernel_ms=kern[dom])
     algo_bytes = BYTES_PER_GAUSSIAN * N + BYTES_PER_PIXEL * P
     out = dict(
         metric="fwd+bwd splat frames/s at 640x480 (%HBM roofline); mapping iters to loss, warm vs plain",
@@ -229,10 +283,11 @@ def main():
         higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload="one 640x480 keyframe (307,200 pixel-aligned Gaussians) splatted into one "
                              "view perturbed <=2 cm / 1 deg; step = forward, L1 loss, adjoint, Adam",
-                    frame=[W, H], gaussians=N, tile=[tw, th]),
+                    frame=[W, H], gaussians=N, tile=[tw, th],
+                    launch="one captured graph per step" if args.graph else "eager calls"),
         hbm_frac=algo_bytes / (ms * 1e-3) / HBM_PEAK,
         roofline=roof,
-        kernels_ms=kern,
+        kernels_ms=warm,          # per launch, from the warmup steps with every kernel timed
         loss_after_warmup=loss0, loss_final=mapper.loss_value(),
     )
     if not args.no_cpu_baseline:

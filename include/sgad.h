@@ -56,6 +56,7 @@ typedef enum {
 
 typedef struct sgad_ctx sgad_ctx;
 typedef struct sgad_saved sgad_saved;
+typedef struct sgad_graph sgad_graph;
 
 /* Pinhole camera: image H x W, focal lengths and principal point in pixels. */
 typedef struct {
@@ -120,6 +121,10 @@ sgad_status sgad_get_tile(const sgad_ctx* ctx, int* tile_w, int* tile_h);
  * bracketed by hipEvents recorded on its launch stream.  Enabling or
  * disabling resets the accumulators. */
 sgad_status sgad_timing_enable(sgad_ctx* ctx, int enable);
+/* Restrict timing to the kernel called `name` (as in the report; NULL or ""
+ * times every kernel).  Fewer events per call keep the host cost of timing
+ * small.  The name is copied. */
+sgad_status sgad_timing_only(sgad_ctx* ctx, const char* name);
 /* Waits for the recorded events and writes one line per kernel name,
  * "<name> <launches> <total_ms>\n", into buf (capacity cap bytes, NUL
  * terminated); SGAD_ERANGE if it does not fit. */
@@ -164,6 +169,37 @@ sgad_status sgad_render_bwd(sgad_ctx* ctx, sgad_saved* saved,
 
 /* Return a saved handle to the context. */
 sgad_status sgad_saved_release(sgad_ctx* ctx, sgad_saved* saved);
+
+/*
+ * Graph capture of a sequence of library calls (e.g. one mapping iteration:
+ * sgad_render_fwd, sgad_l1_loss, sgad_render_bwd, sgad_saved_release,
+ * sgad_adam_step) so that it can be replayed with one launch per iteration.
+ *
+ * sgad_graph_begin waits for `stream` and the device, then records every
+ * library call made from this thread until sgad_graph_end; the recorded calls
+ * do not run at record time and ignore their stream argument.  A recorded
+ * call must find its workspace already sized by an earlier eager call of the
+ * same workload (else SGAD_EINVAL); sgad_sync, sgad_autotune, sgad_track_gn,
+ * sgad_saved_instances and the timing calls return SGAD_EINVAL while a
+ * capture is open.  Device pointers and the values of the call arguments are
+ * frozen into the graph, except that each recorded sgad_adam_step advances
+ * its step count by one per launch (the first launch uses the `step` given
+ * at record time).  Kernels timed while sgad_timing_enable is on at record
+ * time are timed on every launch.
+ *
+ * sgad_graph_end instantiates the graph (*out is owned by the caller; free it
+ * with sgad_graph_destroy before sgad_destroy).  The saved slots it recorded
+ * belong to the graph until it is destroyed and are never reused or resized:
+ * if a replayed forward overflows its instance list, its outputs are NaN,
+ * SGAD_ERANGE is latched, and the graph must be destroyed and captured
+ * again.  sgad_graph_launch enqueues one replay on `stream` (plus the
+ * read-back of the replayed forwards' status); sgad_graph_destroy waits for
+ * the device.
+ */
+sgad_status sgad_graph_begin(sgad_ctx* ctx, void* stream);
+sgad_status sgad_graph_end(sgad_ctx* ctx, sgad_graph** out);
+sgad_status sgad_graph_launch(sgad_ctx* ctx, sgad_graph* graph, void* stream);
+sgad_status sgad_graph_destroy(sgad_ctx* ctx, sgad_graph* graph);
 
 /*
  * Debug export of job `job`'s sorted instance list (waits for the stream).

@@ -13,29 +13,50 @@ namespace sgad {
 // (t < 0: none); lanes naming the same counter are served by one atomic from
 // their lowest lane, and each learns its rank among them.  Neighbouring
 // Gaussians overlap the same tiles, so a wave issues a handful of atomics
-// instead of one per lane.  Returns the pre-increment value plus the rank
-// (only meaningful for lanes with t >= 0).
+// instead of one per lane.  The target is read with a scalar lane read and the
+// atomics' return values are collected after the loop, so the loop does not
+// wait on memory.  Returns the pre-increment value plus the rank (only
+// meaningful for lanes with t >= 0 when need_pos).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t wave_agg_add(uint32_t* ctr, int64_t t, bool need_pos) {
     const int lane = threadIdx.x & 63;
+    const int t_lo = (int)(uint32_t)(uint64_t)t, t_hi = (int)(uint32_t)((uint64_t)t >> 32);
     uint64_t active = __ballot(t >= 0);
-    uint32_t pos = 0;
+    uint32_t ret = 0, rank = 0;
+    int leader_of_mine = 0;
     while (active) {
-        const int leader = __ffsll((long long)active) - 1;
-        const int64_t tgt = __shfl(t, leader, 64);
+        const int leader = (int)__builtin_ctzll(active);
+        const int64_t tgt = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(t_hi, leader) << 32) |
+                                      (uint32_t)__builtin_amdgcn_readlane(t_lo, leader));
         const uint64_t peers = __ballot(t == tgt) & active;
-        uint32_t base = 0;
         if (lane == leader) {
-            if (need_pos) base = atomicAdd(&ctr[tgt], (uint32_t)__popcll(peers));
+            if (need_pos) ret = atomicAdd(&ctr[tgt], (uint32_t)__popcll(peers));
             else atomicAdd(&ctr[tgt], (uint32_t)__popcll(peers));
         }
-        if (need_pos) {
-            base = __shfl(base, leader, 64);
-            if ((peers >> lane) & 1ull) pos = base + (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+        if ((peers >> lane) & 1ull) {
+            leader_of_mine = leader;
+            rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
         }
         active &= ~peers;
     }
-    return pos;
+    if (!need_pos) return 0u;
+    return (uint32_t)__shfl((int)ret, leader_of_mine, 64) + rank;
+}
+
+// Gaussian of this thread: each wavefront takes an 8x8 patch of one keyframe,
+// so its Gaussians overlap few distinct tiles per counting round.
+// `live` is false for lanes past the keyframe edge or the last pair.
+__device__ __forceinline__ int64_t patch_index(const Geometry& G, bool& live) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int pw = (G.Wk + 7) >> 3, ph = (G.Hk + 7) >> 3;
+    const int64_t per_pair = (int64_t)pw * ph;
+    const int64_t pair = wave / per_pair;
+    const int64_t patch = wave - pair * per_pair;
+    const int u = (int)(patch % pw) * 8 + (lane & 7);
+    const int v = (int)(patch / pw) * 8 + (lane >> 3);
+    live = pair < G.n_pairs && u < G.Wk && v < G.Hk;
+    return pair * G.N + (int64_t)v * G.Wk + u;
 }
 
 __device__ __forceinline__ int wave_max_int(int v) {
@@ -53,9 +74,9 @@ __device__ __forceinline__ int wave_max_int(int v) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
 #pragma clang fp contract(off)
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)G.n_pairs * G.N;
-    const bool live = i0 < total;
+    bool live;
+    const int64_t i0 = patch_index(G, live);
     const int64_t i = live ? i0 : total - 1;   // idle lanes shadow the last Gaussian, write nothing
     const int pair = (int)(i / G.N);
     const int pix = (int)(i - (int64_t)pair * G.N);
@@ -227,12 +248,12 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ coun
 // by the sort, so the atomic slot order does not matter.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_scatter(Geometry G, RenderBufs B) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)G.n_pairs * G.N;
+    bool live;
+    const int64_t i = patch_index(G, live);
     int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
     uint64_t key = 0;
     int64_t base = 0;
-    if (i < total) {
+    if (live) {
         const uint32_t rx = B.pre.rx[i], ry = B.pre.ry[i];
         x0 = rx & 0xffff;
         x1 = rx >> 16;
@@ -264,13 +285,88 @@ __global__ __launch_bounds__(256) void k_scatter(Geometry G, RenderBufs B) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-segment ascending sort of 64-bit keys.  Bitonic network in which every
-// comparator is ascending (the first step of each merge compares mirrored
-// positions), so positions past the segment end behave as +inf without
-// being stored.  Segments up to kSortLds keys are sorted in LDS; longer ones
-// in place in global memory by the same block.
+// Per-segment ascending sort of 64-bit keys, one wavefront per segment.
+// Segments up to 1024 keys are sorted in registers: K = 1..16 keys per lane,
+// key i = lane * K + r in register r, padded with all-ones keys to 64 K.  The
+// bitonic network takes every comparator ascending (the first step of each
+// merge pairs mirrored positions), so exchanges inside a lane are register
+// swaps and exchanges across lanes are one xor shuffle per key half.  Longer
+// segments are sorted by the same network in LDS (up to kSortLds keys) or in
+// place in global memory with virtual +inf padding.
 // ---------------------------------------------------------------------------
 constexpr int kSortLds = 4096;
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const int lo = __shfl_xor((int)(uint32_t)v, m, 64);
+    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <int K>
+__device__ __forceinline__ void sort_in_lane(uint64_t (&x)[K], int j) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int p = r ^ j;
+        if (p > r) {
+            const uint64_t a = x[r], b = x[p];
+            x[r] = a < b ? a : b;
+            x[p] = a < b ? b : a;
+        }
+    }
+}
+
+template <int K>
+__device__ void wave_sort_segment(uint64_t* g, int n, int lane) {
+    uint64_t x[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int i = lane * K + r;
+        x[r] = i < n ? g[i] : ~0ull;
+    }
+#pragma unroll
+    for (int k = 2; k <= 64 * K; k <<= 1) {
+        if (k <= K) {
+            // mirror step inside the lane: r <-> r ^ (k - 1)
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const int p = r ^ (k - 1);
+                if (p > r) {
+                    const uint64_t a = x[r], b = x[p];
+                    x[r] = a < b ? a : b;
+                    x[p] = a < b ? b : a;
+                }
+            }
+        } else {
+            // mirror step across lanes: (lane, r) <-> (lane ^ (k / K - 1), K - 1 - r)
+            const int lm = k / K - 1;
+            const bool lower = (lane & (k / (2 * K))) == 0;
+            uint64_t y[K];
+#pragma unroll
+            for (int r = 0; r < K; ++r) y[r] = shfl_xor_u64(x[K - 1 - r], lm);
+#pragma unroll
+            for (int r = 0; r < K; ++r) x[r] = lower ? (x[r] < y[r] ? x[r] : y[r]) : (x[r] < y[r] ? y[r] : x[r]);
+        }
+#pragma unroll
+        for (int j = k >> 2; j >= 1; j >>= 1) {
+            if (j < K) {
+                sort_in_lane<K>(x, j);
+            } else {
+                const int lm = j / K;
+                const bool lower = (lane & lm) == 0;
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    const uint64_t y = shfl_xor_u64(x[r], lm);
+                    x[r] = lower ? (x[r] < y ? x[r] : y) : (x[r] < y ? y : x[r]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int i = lane * K + r;
+        if (i < n) g[i] = x[r];
+    }
+}
 
 __device__ inline void cmpswap_lds(uint64_t* s, int a, int b) {
     uint64_t x = s[a], y = s[b];
@@ -280,18 +376,33 @@ __device__ inline void cmpswap_lds(uint64_t* s, int a, int b) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_sort(Geometry G, RenderBufs B) {
+__global__ __launch_bounds__(64) void k_sort(Geometry G, RenderBufs B) {
+    const int seg = blockIdx.x;
+    if (B.status->overflow) return;
+    const uint32_t st = B.tile_start[seg];
+    const int n = (int)(B.tile_start[seg + 1] - st);
+    uint64_t* g = B.keys + st;
+    const int tid = threadIdx.x;
+    if (n <= 1) return;
+    if (n <= 64) wave_sort_segment<1>(g, n, tid);
+    else if (n <= 128) wave_sort_segment<2>(g, n, tid);
+    else if (n <= 256) wave_sort_segment<4>(g, n, tid);
+    else if (n <= 512) wave_sort_segment<8>(g, n, tid);
+    else if (n <= 1024) wave_sort_segment<16>(g, n, tid);
+}
+
+// Segments longer than 1024 keys (every other segment returns at once).
+__global__ __launch_bounds__(256) void k_sort_long(Geometry G, RenderBufs B) {
     __shared__ uint64_t s[kSortLds];
     const int seg = blockIdx.x;
     if (B.status->overflow) return;
     const uint32_t st = B.tile_start[seg];
-    const uint32_t en = B.tile_start[seg + 1];
-    const int n = (int)(en - st);
-    if (n <= 1) return;
+    const int n = (int)(B.tile_start[seg + 1] - st);
+    if (n <= 1024) return;
     uint64_t* g = B.keys + st;
+    const int tid = threadIdx.x;
     int np2 = 1;
     while (np2 < n) np2 <<= 1;
-    const int tid = threadIdx.x;
     if (np2 <= kSortLds) {
         for (int k = tid; k < np2; k += blockDim.x) s[k] = k < n ? g[k] : ~0ull;
         __syncthreads();
@@ -361,9 +472,13 @@ void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_f32, dim3(blocks), dim3(256), 0, s, p, n, v);
 }
 
+static int64_t patch_blocks(const Geometry& G) {
+    const int64_t threads = (int64_t)G.n_pairs * ((G.Wk + 7) >> 3) * ((G.Hk + 7) >> 3) * 64;
+    return (threads + 255) / 256;
+}
+
 void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s) {
-    const int64_t n = (int64_t)G.n_pairs * G.N;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, B);
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)patch_blocks(G)), dim3(256), 0, s, G, B);
 }
 
 void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s) {
@@ -373,13 +488,13 @@ void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s) {
 }
 
 void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s) {
-    const int64_t n = (int64_t)G.n_pairs * G.N;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, B);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)patch_blocks(G)), dim3(256), 0, s, G, B);
 }
 
 void launch_sort(const Geometry& G, const RenderBufs& B, hipStream_t s) {
     const int M = G.n_jobs * G.ntiles;
-    hipLaunchKernelGGL(k_sort, dim3(M), dim3(256), 0, s, G, B);
+    hipLaunchKernelGGL(k_sort, dim3(M), dim3(64), 0, s, G, B);
+    hipLaunchKernelGGL(k_sort_long, dim3(M), dim3(256), 0, s, G, B);
 }
 
 }  // namespace sgad

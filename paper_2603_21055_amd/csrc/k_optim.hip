@@ -72,8 +72,23 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const
 
 // Multi-tensor Adam: group g owns elements [off[g], off[g+1]) of the flat range.
 
+// Step counter of a replayed Adam: t += 1 and the bias corrections
+// 1 - beta^t, so every replay of a captured step takes the next t.
+// state = [t (int bits), c1, c2, unused].
+__global__ void k_adam_tick(float* state, float b1, float b2) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int t = __float_as_int(state[0]) + 1;
+    state[0] = __int_as_float(t);
+    state[1] = (float)(1.0 - pow((double)b1, (double)t));
+    state[2] = (float)(1.0 - pow((double)b2, (double)t));
+}
+
 __global__ __launch_bounds__(256) void k_adam(AdamGroups A, float b1, float b2, float eps, float c1, float c2,
-                                              int zero_grad) {
+                                              int zero_grad, const float* cdev) {
+    if (cdev) {
+        c1 = cdev[1];
+        c2 = cdev[2];
+    }
     const int64_t total = A.off[A.n];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -117,12 +132,16 @@ void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const floa
                        g_rgb, g_dep, loss);
 }
 
+// cdev null: bias corrections c1, c2 as given; else advance the device
+// counter cdev and take them from it.
 void launch_adam(const AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
-                 hipStream_t s) {
+                 float* cdev, hipStream_t s) {
     const int64_t total = A.off[A.n];
     if (total <= 0) return;
+    if (cdev) hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(64), 0, s, cdev, b1, b2);
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, s, A, b1, b2, eps, c1, c2, zero_grad);
+    hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, s, A, b1, b2, eps, c1, c2, zero_grad,
+                       (const float*)cdev);
 }
 
 }  // namespace sgad

@@ -1,42 +1,65 @@
-// Wave-tile compositing: one 8x8 tile per wavefront, one lane per pixel, four
-// independent tiles per workgroup (no workgroup barriers).
+// Wave-tile compositing: one 8x8 tile per wavefront (one wavefront per
+// workgroup, no barriers), one lane per pixel.
 //
-// The tile's sorted instance list is taken in super-chunks of SC entries.
-// For each 64-entry chunk every lane stages one entry in LDS and computes the
-// pixel rectangle that bounds the entry's 3-sigma ellipse inside the tile;
-// sixteen wave ballots turn those rectangles into 8 column masks and 8 row
-// masks, and pixel (c, r) takes the chunk's candidates as col[c] & row[r].
-// Each lane then walks only its own candidates, in list order (forward) or
-// reverse list order (backward), so a pixel evaluates ~47 pairs instead of
-// the whole list.  The rectangle is a superset of every pair with q <= 9 as
-// evaluated in FP32, so the contributor sets and their order are exactly
-// those of the full-list walk.
+// The tile's sorted instance list is taken in chunks of 64 entries.  For each
+// chunk every lane publishes one entry in LDS and computes the pixel rectangle
+// that bounds the entry's 3-sigma ellipse inside the tile; sixteen wave ballots
+// turn those rectangles into 8 column masks and 8 row masks, and pixel (c, r)
+// takes the chunk's candidates as col[c] & row[r].  Each lane then walks only
+// its own candidates, in list order (forward) or reverse list order
+// (backward), so a pixel evaluates ~47 pairs instead of the whole list.  The
+// rectangle is a superset of every pair with q <= 9 as evaluated in FP32, so
+// the contributor sets and their order are exactly those of the full-list
+// walk.
 //
-// Backward: see k_bwd8 (a pixel-parallel walk that stores per-pair terms and an
-// entry-parallel sum over pixels, with no atomics inside the tile).
+// Latency hiding: the records of the next chunk are gathered from HBM into
+// registers while the current chunk is walked (keys two chunks ahead, records
+// one chunk ahead), and the walks take two candidates per round, whose
+// evaluations (LDS reads, q, exp, alpha) are independent of each other.
 #include <hip/hip_runtime.h>
 
 #include "raster_common.h"
 
 namespace sgad {
 
-constexpr int kWaves = 4;
-
 __device__ __forceinline__ uint64_t low_bits(int k) { return k >= 64 ? ~0ull : ((1ull << k) - 1ull); }
 
-// Stage chunk `ch` of a super-chunk and publish its coverage masks.
-__device__ __forceinline__ void stage_chunk(const Geometry& G, const RenderBufs& B, int job, uint32_t base, int n,
-                                            int ch, int lane, float fx0, float fy0, float4 (*se)[3],
-                                            uint64_t* sm) {
-    const int e = ch * 64 + lane;
-    const bool valid = e < n;
+// One lane's share of a chunk, gathered from HBM: its entry's key and record.
+struct ChunkRegs {
+    uint64_t key;
+    float4 r0, r1, r2, r3;
+};
+
+// Key of entry `e` of the list starting at `base` (0 when e >= n).
+__device__ __forceinline__ uint64_t fetch_key(const RenderBufs& B, uint32_t base, int e, int n) {
+    return e < n ? B.keys[base + (uint32_t)e] : 0ull;
+}
+
+// Record of `key` (pair looked up in the job's pair table `pof`).  WITH_R3
+// also fetches [x, y, r, sign], which only the backward needs.
+template <bool WITH_R3>
+__device__ __forceinline__ void fetch_record(const Geometry& G, const RenderBufs& B, const int* pof, bool valid,
+                                             ChunkRegs& c) {
+    if (!valid) return;
+    const uint32_t gid = (uint32_t)c.key;
+    const int kf = (int)(gid / (uint32_t)G.N);
+    const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
+    const float4* rec = B.pre.rec + 4 * ((size_t)pof[kf] * G.N + pix);
+    c.r0 = rec[0];
+    c.r1 = rec[1];
+    c.r2 = rec[2];
+    if (WITH_R3) c.r3 = rec[3];
+}
+
+// Publish a chunk in LDS (records and coverage masks).
+__device__ __forceinline__ void publish_chunk(const ChunkRegs& c, bool valid, int lane, float fx0, float fy0,
+                                              float4 (*se)[3], uint64_t* sm) {
     int x0 = 8, x1 = -1, y0 = 8, y1 = -1;
     if (valid) {
-        const float4* rec = entry_record(G, B, job, B.keys[base + e]);
-        const float4 eu = rec[0], eg = rec[1], ec = rec[2];
-        se[e][0] = eu;
-        se[e][1] = eg;
-        se[e][2] = ec;
+        const float4 eu = c.r0, eg = c.r1;
+        se[lane][0] = eu;
+        se[lane][1] = eg;
+        se[lane][2] = c.r2;
         const float mx = (eu.x - fx0) + eu.z, my = (eu.y - fy0) + eu.w;
         const float det = eg.x * eg.z - eg.y * eg.y;
         const float ex = 3.f * sqrtf(eg.z / det) + 1e-3f;
@@ -50,77 +73,115 @@ __device__ __forceinline__ void stage_chunk(const Geometry& G, const RenderBufs&
     for (int k = 0; k < 8; ++k) {
         const uint64_t cm = __ballot(valid && x0 <= k && k <= x1);
         const uint64_t rm = __ballot(valid && y0 <= k && k <= y1);
-        if (lane == k) sm[ch * 16 + k] = cm;
-        if (lane == 8 + k) sm[ch * 16 + 8 + k] = rm;
+        if (lane == k) sm[k] = cm;
+        if (lane == 8 + k) sm[8 + k] = rm;
     }
 }
 
-template <int SC>
-__global__ __launch_bounds__(256) void k_fwd8(Geometry G, RenderBufs B, FwdOut O) {
-    constexpr int NCH = SC / 64;
-    __shared__ float4 s_e[kWaves][SC][3];
-    __shared__ uint64_t s_m[kWaves][NCH * 16];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave;
+// Tile coordinates of a work item and its pair table in LDS.
+struct TileItem {
+    int job, tx, ty;
+};
+
+__device__ __forceinline__ TileItem tile_item(const Geometry& G, const RenderBufs& B, int item, int lane,
+                                              int* pof) {
+    TileItem t;
+    t.job = item / G.ntiles;
+    const int tile = item - t.job * G.ntiles;
+    t.tx = tile % G.ntx;
+    t.ty = tile / G.ntx;
+    pof[lane] = lane < G.n_kf ? B.pair_of[t.job * G.n_kf + lane] : -1;
+    return t;
+}
+
+__global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O) {
+    __shared__ float4 s_e[64][3];
+    __shared__ uint64_t s_m[16];
+    __shared__ int s_pof[64];
+    const int lane = threadIdx.x;
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
     if (item >= G.n_jobs * G.ntiles) return;
-    const int job = item / G.ntiles;
-    const int tile = item - job * G.ntiles;
-    const int tx = tile % G.ntx, ty = tile / G.ntx;
+    const TileItem ti = tile_item(G, B, item, lane, s_pof);
+    const int job = ti.job;
     const int lx = lane & 7, ly = lane >> 3;
-    const int px = tx * 8 + lx, py = ty * 8 + ly;
+    const int px = ti.tx * 8 + lx, py = ti.ty * 8 + ly;
     const bool inside = px < G.Wv && py < G.Hv;
     const bool ovf = B.status->overflow != 0u;
     const uint32_t st = B.tile_start[item];
-    const uint32_t en = ovf ? st : B.tile_start[item + 1];
+    const int len = ovf ? 0 : (int)(B.tile_start[item + 1] - st);
     const float fpx = (float)px, fpy = (float)py;
-    const float fx0 = (float)(tx * 8), fy0 = (float)(ty * 8);
-    float4 (*se)[3] = s_e[wave];
-    uint64_t* sm = s_m[wave];
+    const float fx0 = (float)(ti.tx * 8), fy0 = (float)(ti.ty * 8);
     float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;
     int cnt = 0;
     uint32_t last = 0;
     bool done = !inside;
-    for (uint32_t sc0 = st; sc0 < en; sc0 += SC) {
-        const int n = (int)min((uint32_t)SC, en - sc0);
-        const int nch = (n + 63) >> 6;
-        for (int ch = 0; ch < nch; ++ch) stage_chunk(G, B, job, sc0, n, ch, lane, fx0, fy0, se, sm);
+    lds_fence();
+    ChunkRegs cur{}, nxt{};
+    cur.key = fetch_key(B, st, lane, len);
+    fetch_record<false>(G, B, s_pof, lane < len, cur);
+    nxt.key = fetch_key(B, st + 64u, lane, len - 64);
+    for (int c0 = 0; c0 < len; c0 += 64) {
+        const int n = min(64, len - c0);
+        publish_chunk(cur, lane < n, lane, fx0, fy0, s_e, s_m);
         lds_fence();
+        // gather ahead: records of the next chunk, keys of the one after
+        fetch_record<false>(G, B, s_pof, lane < len - c0 - 64, nxt);
+        const uint64_t key2 = fetch_key(B, st + (uint32_t)(c0 + 128), lane, len - c0 - 128);
         if (!done) {
-            int ch = 0;
-            uint64_t m = sm[lx] & sm[8 + ly];
-            while (true) {
-                while (m == 0ull && ch + 1 < nch) {
-                    ++ch;
-                    m = sm[ch * 16 + lx] & sm[ch * 16 + 8 + ly];
-                }
-                if (m == 0ull) break;
-                const int e = ch * 64 + __builtin_ctzll(m);
+            uint64_t m = s_m[lx] & s_m[8 + ly];
+            // two candidates per round: their q, alpha evaluations are independent
+            while (m != 0ull) {
+                const int b0 = (int)__builtin_ctzll(m);
                 m &= m - 1ull;
-                const float4 eu = se[e][0];
-                const float dx = (fpx - eu.x) - eu.z, dy = (fpy - eu.y) - eu.w;
-                const float4 eg = se[e][1];
-                const float q = pair_q(dx, dy, eg.x, eg.y, eg.z);
-                if (!(q <= kQCut)) continue;
-                const float alpha = fminf(kAlphaMax, eg.w * gauss_of_q(q));
-                if (alpha < kAlphaMin) continue;
-                const float test = T * (1.f - alpha);
-                if (test < kTMin) {
-                    done = true;
-                    break;
+                const bool two = m != 0ull;
+                const int b1 = two ? (int)__builtin_ctzll(m) : b0;
+                if (two) m &= m - 1ull;
+                const float4 eu0 = s_e[b0][0], eg0 = s_e[b0][1];
+                const float4 eu1 = s_e[b1][0], eg1 = s_e[b1][1];
+                const float dx0 = (fpx - eu0.x) - eu0.z, dy0 = (fpy - eu0.y) - eu0.w;
+                const float dx1 = (fpx - eu1.x) - eu1.z, dy1 = (fpy - eu1.y) - eu1.w;
+                const float q0 = pair_q(dx0, dy0, eg0.x, eg0.y, eg0.z);
+                const float q1 = pair_q(dx1, dy1, eg1.x, eg1.y, eg1.z);
+                const float al0 = fminf(kAlphaMax, eg0.w * gauss_of_q(q0));
+                const float al1 = fminf(kAlphaMax, eg1.w * gauss_of_q(q1));
+                if (q0 <= kQCut && al0 >= kAlphaMin) {
+                    const float test = T * (1.f - al0);
+                    if (test < kTMin) {
+                        done = true;
+                        break;
+                    }
+                    const float w = al0 * T;
+                    const float4 c = s_e[b0][2];
+                    cr += w * c.x;
+                    cg += w * c.y;
+                    cb += w * c.z;
+                    dd += w * c.w;
+                    T = test;
+                    ++cnt;
+                    last = (uint32_t)(c0 + b0 + 1);
                 }
-                const float w = alpha * T;
-                const float4 c = se[e][2];
-                cr += w * c.x;
-                cg += w * c.y;
-                cb += w * c.z;
-                dd += w * c.w;
-                T = test;
-                ++cnt;
-                last = sc0 - st + (uint32_t)e + 1u;
+                if (two && q1 <= kQCut && al1 >= kAlphaMin) {
+                    const float test = T * (1.f - al1);
+                    if (test < kTMin) {
+                        done = true;
+                        break;
+                    }
+                    const float w = al1 * T;
+                    const float4 c = s_e[b1][2];
+                    cr += w * c.x;
+                    cg += w * c.y;
+                    cb += w * c.z;
+                    dd += w * c.w;
+                    T = test;
+                    ++cnt;
+                    last = (uint32_t)(c0 + b1 + 1);
+                }
             }
         }
-        lds_fence();
         if (__ballot(!done) == 0ull) break;
+        cur = nxt;
+        nxt.key = key2;
+        lds_fence();
     }
     if (!inside) return;
     const size_t pix = (size_t)py * G.Wv + px;
@@ -141,7 +202,7 @@ __global__ __launch_bounds__(256) void k_fwd8(Geometry G, RenderBufs B, FwdOut O
     B.last[jp] = last;
 }
 
-// Backward of one 8x8 tile per wavefront (one wavefront per workgroup).
+// Backward of one 8x8 tile per wavefront.
 //
 // The tile's list is taken in 64-entry chunks from the back, each chunk in
 // sub-chunks of SUB entries from the back, in two phases per sub-chunk:
@@ -153,7 +214,8 @@ __global__ __launch_bounds__(256) void k_fwd8(Geometry G, RenderBufs B, FwdOut O
 //    clears what it read.
 // The per-entry sums are gq-weighted moments of (dx, dy) and gradient-weighted
 // sums of w; the conic enters after the sum.  No LDS location is written by two
-// lanes at once, and the in-tile summation order is fixed.
+// lanes at once, and the in-tile summation order is fixed.  After a chunk, lane
+// e applies the chain rule of entry e from the record it gathered.
 template <int SUB>
 __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A) {
     constexpr int NS = 64 / SUB;        // sub-chunks per chunk = pixel groups in phase B
@@ -161,15 +223,15 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     __shared__ float4 s_e[64][3];
     __shared__ uint64_t s_m[16];
     __shared__ float4 s_pc[65];
+    __shared__ int s_pof[64];
     __shared__ __align__(16) float s_M[65 * LS];   // row 64 stays zero: the idle pixel of phase B
     const int lane = threadIdx.x;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     if (item >= G.n_jobs * G.ntiles) return;
-    const int job = item / G.ntiles;
-    const int tile = item - job * G.ntiles;
-    const int tx = tile % G.ntx, ty = tile / G.ntx;
+    const TileItem ti = tile_item(G, B, item, lane, s_pof);
+    const int job = ti.job;
     const int lx = lane & 7, ly = lane >> 3;
-    const int px = tx * 8 + lx, py = ty * 8 + ly;
+    const int px = ti.tx * 8 + lx, py = ti.ty * 8 + ly;
     const bool inside = px < G.Wv && py < G.Hv;
     const bool ovf = B.status->overflow != 0u;
     const uint32_t st = B.tile_start[item];
@@ -197,14 +259,26 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     for (int o = 32; o >= 1; o >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, o, 64));
     const float Tf = T;
     const float fpx = (float)px, fpy = (float)py;
-    const float fx0 = (float)(tx * 8), fy0 = (float)(ty * 8);
+    const float fx0 = (float)(ti.tx * 8), fy0 = (float)(ti.ty * 8);
     const int sub = lane & (SUB - 1), grp = lane / SUB;
     float S0 = 0.f, S1 = 0.f, S2 = 0.f, SD = 0.f;
     float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int c0 = maxlast > 0 ? ((maxlast - 1) & ~63) : -1; c0 >= 0; c0 -= 64) {
+    lds_fence();
+    // chunks c0 = top, top - 64, ..., 0; every chunk below the top one is full
+    const int top = maxlast > 0 ? ((maxlast - 1) & ~63) : -1;
+    ChunkRegs cur{}, nxt{};
+    if (top >= 0) {
+        cur.key = fetch_key(B, st + (uint32_t)top, lane, maxlast - top);
+        fetch_record<true>(G, B, s_pof, lane < maxlast - top, cur);
+        if (top >= 64) nxt.key = B.keys[st + (uint32_t)(top - 64 + lane)];
+    }
+    for (int c0 = top; c0 >= 0; c0 -= 64) {
         const int n = min(64, maxlast - c0);
-        stage_chunk(G, B, job, st + (uint32_t)c0, n, 0, lane, fx0, fy0, s_e, s_m);
+        publish_chunk(cur, lane < n, lane, fx0, fy0, s_e, s_m);
         lds_fence();
+        // gather ahead: records of the next chunk, keys of the one after
+        if (c0 >= 64) fetch_record<true>(G, B, s_pof, true, nxt);
+        const uint64_t key2 = c0 >= 128 ? B.keys[st + (uint32_t)(c0 - 128 + lane)] : 0ull;
         const uint64_t mine = s_m[lx] & s_m[8 + ly];
         const int lim = min(n, last - c0);   // this pixel's entries are e < lim
         float r[10];
@@ -212,25 +286,13 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
         for (int k = 0; k < 10; ++k) r[k] = 0.f;
 #pragma unroll
         for (int s = NS - 1; s >= 0; --s) {
-            // phase A: reverse walk of this pixel's candidates in the sub-chunk
+            // phase A: reverse walk of this pixel's candidates in the sub-chunk,
+            // two candidates per round (their q, alpha evaluations are independent)
             const int cut = lim - s * SUB;
-            uint64_t m = cut <= 0 ? 0ull : ((mine >> (s * SUB)) & low_bits(min(cut, SUB)));
+            uint32_t m = cut <= 0 ? 0u : (uint32_t)((mine >> (s * SUB)) & low_bits(min(cut, SUB)));
             bool wrote = false;
-            while (m != 0ull) {
-                const int bit = 63 - __builtin_clzll(m);
-                m &= ~(1ull << bit);
-                const int e = s * SUB + bit;
-                const float4 eu = s_e[e][0];
-                const float dx = (fpx - eu.x) - eu.z, dy = (fpy - eu.y) - eu.w;
-                const float4 eg = s_e[e][1];
-                const float q = pair_q(dx, dy, eg.x, eg.y, eg.z);
-                if (!(q <= kQCut)) continue;
-                const float Gv = gauss_of_q(q);
-                const float raw = eg.w * Gv;
-                const float alpha = fminf(kAlphaMax, raw);
-                if (alpha < kAlphaMin) continue;
-                const float4 c = s_e[e][2];
-                const float inv = 1.f / (1.f - alpha);
+            auto contribute = [&](float alpha, float raw, float4 c, int bit) {
+                const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
                 T = T * inv;
                 const float w = alpha * T;
                 const float gal = gC0 * (c.x * T - S0 * inv) + gC1 * (c.y * T - S1 * inv) +
@@ -242,40 +304,71 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 const float gq = raw < kAlphaMax ? -0.5f * alpha * gal : 0.f;
                 *(float2*)&s_M[lane * LS + 2 * bit] = make_float2(w, gq);
                 wrote = true;
+            };
+            while (m != 0u) {
+                const int b0 = 31 - (int)__builtin_clz(m);
+                m &= ~(1u << b0);
+                const bool two = m != 0u;
+                const int b1 = two ? 31 - (int)__builtin_clz(m) : b0;
+                m &= ~(1u << b1);
+                const float4* r0 = s_e[s * SUB + b0];
+                const float4* r1 = s_e[s * SUB + b1];
+                const float4 eu0 = r0[0], eg0 = r0[1], ec0 = r0[2];
+                const float4 eu1 = r1[0], eg1 = r1[1], ec1 = r1[2];
+                const float dx0 = (fpx - eu0.x) - eu0.z, dy0 = (fpy - eu0.y) - eu0.w;
+                const float dx1 = (fpx - eu1.x) - eu1.z, dy1 = (fpy - eu1.y) - eu1.w;
+                const float q0 = pair_q(dx0, dy0, eg0.x, eg0.y, eg0.z);
+                const float q1 = pair_q(dx1, dy1, eg1.x, eg1.y, eg1.z);
+                const float raw0 = eg0.w * gauss_of_q(q0);
+                const float raw1 = eg1.w * gauss_of_q(q1);
+                const float al0 = fminf(kAlphaMax, raw0), al1 = fminf(kAlphaMax, raw1);
+                if (q0 <= kQCut && al0 >= kAlphaMin) contribute(al0, raw0, ec0, b0);
+                if (two && q1 <= kQCut && al1 >= kAlphaMin) contribute(al1, raw1, ec1, b1);
             }
             const uint64_t pm0 = __ballot(wrote);
             lds_fence();
-            // phase B: lane = entry s * SUB + sub, pixel group grp
-            const float4 eu = s_e[s * SUB + sub][0];
+            // phase B: lane = entry s * SUB + sub, pixel group grp, two pixels per round
+            const float4 eu0 = s_e[s * SUB + sub][0];
             float a[10];
 #pragma unroll
             for (int k = 0; k < 10; ++k) a[k] = 0.f;
             uint64_t pm = pm0;
             while (pm != 0ull) {
-                int p = 64;
+                int pp[2] = {64, 64};
 #pragma unroll
-                for (int g = 0; g < NS; ++g) {
-                    const int pg = pm != 0ull ? (int)__builtin_ctzll(pm) : 64;
-                    pm &= pm - 1ull;
-                    p = g == grp ? pg : p;
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int g = 0; g < NS; ++g) {
+                        const int pg = pm != 0ull ? (int)__builtin_ctzll(pm) : 64;
+                        pm &= pm - 1ull;
+                        pp[h] = g == grp ? pg : pp[h];
+                    }
+                float2 mv[2];
+                float4 gv[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    float2* cell = (float2*)&s_M[pp[h] * LS + 2 * sub];
+                    mv[h] = *cell;
+                    gv[h] = s_pc[pp[h]];
+                    *cell = make_float2(0.f, 0.f);
                 }
-                float2* cell = (float2*)&s_M[p * LS + 2 * sub];
-                const float2 mv = *cell;
-                *cell = make_float2(0.f, 0.f);
-                const float4 g = s_pc[p];
-                const float dx = ((float)(tx * 8 + (p & 7)) - eu.x) - eu.z;
-                const float dy = ((float)(ty * 8 + (p >> 3)) - eu.y) - eu.w;
-                a[0] += g.x * mv.x;
-                a[1] += g.y * mv.x;
-                a[2] += g.z * mv.x;
-                a[3] += g.w * mv.x;
-                a[4] += mv.y;
-                const float u = mv.y * dx, v = mv.y * dy;
-                a[5] += u;
-                a[6] += v;
-                a[7] += u * dx;
-                a[8] += u * dy;
-                a[9] += v * dy;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int p = pp[h];
+                    const float dx = ((float)(ti.tx * 8 + (p & 7)) - eu0.x) - eu0.z;
+                    const float dy = ((float)(ti.ty * 8 + (p >> 3)) - eu0.y) - eu0.w;
+                    a[0] += gv[h].x * mv[h].x;
+                    a[1] += gv[h].y * mv[h].x;
+                    a[2] += gv[h].z * mv[h].x;
+                    a[3] += gv[h].w * mv[h].x;
+                    a[4] += mv[h].y;
+                    const float u = mv[h].y * dx, v = mv[h].y * dy;
+                    a[5] += u;
+                    a[6] += v;
+                    a[7] += u * dx;
+                    a[8] += u * dy;
+                    a[9] += v * dy;
+                }
             }
 #pragma unroll
             for (int o = SUB; o < 64; o <<= 1)
@@ -292,7 +385,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
 #pragma unroll
             for (int k = 0; k < 10; ++k) any |= r[k] != 0.f;
             if (any) {
-                const float4 eg = s_e[lane][1];
+                const float4 eg = cur.r1;
                 float v[10];
                 v[0] = -2.f * (eg.x * r[5] + eg.y * r[6]);
                 v[1] = -2.f * (eg.y * r[5] + eg.z * r[6]);
@@ -304,9 +397,14 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 v[7] = r[0];
                 v[8] = r[1];
                 v[9] = r[2];
-                flush_entry(G, B, A, job, B.keys[st + (uint32_t)c0 + (uint32_t)lane], v, pose);
+                const uint32_t gid = (uint32_t)cur.key;
+                const int kf = (int)(gid / (uint32_t)G.N);
+                const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
+                chain_rule(G, A, B.pairs[s_pof[kf]], kf, pix, cur.r0.x, cur.r0.y, cur.r2.w, cur.r3, v, pose);
             }
         }
+        cur = nxt;
+        nxt.key = key2;
         lds_fence();
     }
 #pragma unroll
@@ -316,24 +414,15 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     }
 }
 
-template <int SC>
-static void fwd8_t(const Geometry& G, const RenderBufs& B, const FwdOut& O, hipStream_t s) {
-    const int items = G.n_jobs * G.ntiles;
-    hipLaunchKernelGGL((k_fwd8<SC>), dim3((items + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, s, G, B, O);
+bool launch_fwd8(const Geometry& G, const RenderBufs& B, const FwdOut& O, hipStream_t s) {
+    if (G.TW != 8 || G.TH != 8) return false;
+    hipLaunchKernelGGL(k_fwd8, dim3(G.n_jobs * G.ntiles), dim3(64), 0, s, G, B, O);
+    return true;
 }
 
 template <int SUB>
 static void bwd8_t(const Geometry& G, const RenderBufs& B, const BwdArgs& A, hipStream_t s) {
-    const int items = G.n_jobs * G.ntiles;
-    hipLaunchKernelGGL((k_bwd8<SUB>), dim3(items), dim3(64), 0, s, G, B, A);
-}
-
-bool launch_fwd8(const Geometry& G, const RenderBufs& B, const FwdOut& O, int sc, hipStream_t s) {
-    if (G.TW != 8 || G.TH != 8) return false;
-    if (sc == 256) fwd8_t<256>(G, B, O, s);
-    else if (sc == 128) fwd8_t<128>(G, B, O, s);
-    else return false;
-    return true;
+    hipLaunchKernelGGL((k_bwd8<SUB>), dim3(G.n_jobs * G.ntiles), dim3(64), 0, s, G, B, A);
 }
 
 bool launch_bwd8(const Geometry& G, const RenderBufs& B, const BwdArgs& A, int sub, hipStream_t s) {

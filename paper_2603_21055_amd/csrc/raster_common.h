@@ -59,22 +59,17 @@ __device__ __forceinline__ const float4* entry_record(const Geometry& G, const R
 }
 
 // Chain rule of one (Gaussian, tile) gradient to the keyframe parameters and
-// the view pose.  v = [g_mx, g_my, g_a, g_b, g_c, g_o, g_z, g_c0, g_c1, g_c2].
-__device__ __forceinline__ void flush_entry(const Geometry& G, const RenderBufs& B, const BwdArgs& A, int job,
-                                            uint64_t key, const float* v, float* pose) {
-    const uint32_t gid = (uint32_t)key;
-    const int kf = (int)(gid / (uint32_t)G.N);
-    const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
-    const int pair = B.pair_of[job * G.n_kf + kf];
-    const PairConst& pc = B.pairs[pair];
-    const float4* rec = B.pre.rec + 4 * ((size_t)pair * G.N + pix);
-    const float4 r0 = rec[0], r3 = rec[3];
-    const float z = rec[2].w;
+// the view pose.  v = [g_mx, g_my, g_a, g_b, g_c, g_o, g_z, g_c0, g_c1, g_c2];
+// (u, v) the keyframe pixel, z the view depth and r3 = [x, y, r, sign] of the
+// Gaussian's record.
+__device__ __forceinline__ void chain_rule(const Geometry& G, const BwdArgs& A, const PairConst& pc, int kf,
+                                           int pix, float ku, float kv, float z, float4 r3, const float* v,
+                                           float* pose) {
     const float x = r3.x, y = r3.y;
     const float r = r3.z;
     const float sgn = r3.w;
-    const float xn = (r0.x - (float)pc.kcx) / (float)pc.kfx;
-    const float yn = (r0.y - (float)pc.kcy) / (float)pc.kfy;
+    const float xn = (ku - (float)pc.kcx) / (float)pc.kfx;
+    const float yn = (kv - (float)pc.kcy) / (float)pc.kfy;
     const float* R = pc.Rf;
     const float fx = (float)pc.vfx, fy = (float)pc.vfy;
     const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz, iz4 = iz2 * iz2, iz5 = iz4 * iz;
@@ -117,6 +112,18 @@ __device__ __forceinline__ void flush_entry(const Geometry& G, const RenderBufs&
     atomicAdd(&gp.d_rgb[pix], v[7]);
     atomicAdd(&gp.d_rgb[(size_t)G.N + pix], v[8]);
     atomicAdd(&gp.d_rgb[2 * (size_t)G.N + pix], v[9]);
+}
+
+// The same, reading the record of the instance `key` of job `job`.
+__device__ __forceinline__ void flush_entry(const Geometry& G, const RenderBufs& B, const BwdArgs& A, int job,
+                                            uint64_t key, const float* v, float* pose) {
+    const uint32_t gid = (uint32_t)key;
+    const int kf = (int)(gid / (uint32_t)G.N);
+    const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
+    const int pair = B.pair_of[job * G.n_kf + kf];
+    const float4* rec = B.pre.rec + 4 * ((size_t)pair * G.N + pix);
+    const float4 r0 = rec[0];
+    chain_rule(G, A, B.pairs[pair], kf, pix, r0.x, r0.y, rec[2].w, rec[3], v, pose);
 }
 
 // Spread consecutive workgroups over the XCDs in contiguous ranges: the

@@ -26,7 +26,7 @@ void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const floa
                float w_rgb, float w_dep, uint32_t* count, float* g_rgb, float* g_dep, double* loss,
                hipStream_t s);
 void launch_adam(const AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
-                 hipStream_t s);
+                 float* cdev, hipStream_t s);
 bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* bias,
                      const void* mask, void* y, hipStream_t s);
 bool launch_conv_wgrad(int H, int W, int cin, int cout, const void* x, const void* dy, float* dw, float* db,
@@ -59,6 +59,7 @@ struct PinBuf {
 
 struct sgad_saved {
     bool in_use = false;
+    const sgad_graph* owner = nullptr;  // captured into this graph: never reused or resized
     Geometry G{};
     hipStream_t stream = nullptr;
     // device buffers (grow-only)
@@ -68,16 +69,31 @@ struct sgad_saved {
     size_t size_key[5] = {0, 0, 0, 0, 0};  // workload the capacity was sized for
     // pinned staging
     PinBuf up, up_grad;
+    // host copies of what the device parameter blocks hold: an unchanged
+    // block (every iteration of a mapping loop) is not uploaded again
+    std::vector<char> stage, last_up, stage_grad, last_up_grad;
     DevStatus* status_h = nullptr;
     hipEvent_t ev_up = nullptr, ev_up_grad = nullptr, ev_status = nullptr;
     bool up_pending = false, up_grad_pending = false, status_pending = false;
     RenderBufs B{};
 };
 
+// A captured sequence of library calls and what it holds on to.
+struct sgad_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<sgad_saved*> slots;
+    DevBuf adam;
+    // per timed kernel: its two event-record nodes (events swapped per launch)
+    std::vector<std::pair<std::string, std::pair<hipGraphNode_t, hipGraphNode_t>>> timed;
+    std::vector<hipEvent_t> events;  // the events the nodes were captured with
+};
+
 // Optional per-kernel timing: a pair of hipEvents recorded on the launch
 // stream around every library kernel, accumulated per kernel name.
 struct KernelTimer {
     bool on = false;
+    std::string only;  // time only this kernel name (empty: all)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
     size_t used = 0;
     std::vector<std::pair<std::string, size_t>> pending;  // name, pool index
@@ -97,14 +113,24 @@ struct sgad_ctx {
     // configuration used while measuring
     struct TuneEntry {
         size_t key[6];
-        int tw, th, scf, scb;
+        int tw, th, scb;
         float ms;
     };
     std::vector<TuneEntry> tune;
     bool force = false;
-    int ftw = 8, fth = 8, fscf = 256, fscb = 32;
+    int ftw = 8, fth = 8, fscb = 16;
     std::vector<sgad_saved*> slots;
     KernelTimer timer;
+    // stream capture of library calls into a graph (sgad_graph_begin/end)
+    struct Capture {
+        bool on = false;
+        hipStream_t cap = nullptr;    // private non-blocking stream the calls are recorded on
+        DevBuf adam;                  // Adam step counters of the graph being built
+        int n_adam = 0;
+        int adam_t0[kMaxGraphAdam] = {};
+        std::vector<sgad_saved*> slots;
+        std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> timed;
+    } capture;
     DevBuf scratch;  // small per-context scratch (loss counters)
     struct Track {
         bool sized = false;
@@ -128,14 +154,53 @@ struct sgad_ctx {
 
 namespace {
 
+// Append an event-record node to the graph being captured on `s` and make it
+// the stream's capture dependency (explicit node, so it does not rely on
+// external event records in stream capture).
+hipError_t capture_event_node(hipStream_t s, hipEvent_t ev) {
+    hipStreamCaptureStatus st;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    hipError_t e = hipStreamGetCaptureInfo_v2(s, &st, &id, &g, &deps, &nd);
+    if (e != hipSuccess) return e;
+    if (st != hipStreamCaptureStatusActive || !g) return hipErrorIllegalState;
+    hipGraphNode_t n = nullptr;
+    e = hipGraphAddEventRecordNode(&n, g, deps, nd, ev);
+    if (e != hipSuccess) return e;
+    return hipStreamUpdateCaptureDependencies(s, &n, 1, hipStreamSetCaptureDependencies);
+}
+
 // RAII scope that brackets one launch with timing events when enabled.
 struct TimeScope {
     sgad_ctx* c;
     size_t idx = (size_t)-1;
     hipStream_t s;
+    bool cap = false;
+    hipEvent_t ca = nullptr, cb = nullptr;
     TimeScope(sgad_ctx* ctx, const char* name, hipStream_t stream) : c(ctx), s(stream) {
         KernelTimer& t = c->timer;
         if (!t.on) return;
+        if (!t.only.empty() && t.only != name) return;
+        if (c->capture.on) {
+            // recorded as event nodes of the graph; sgad_graph_launch gives
+            // them fresh events on every launch
+            if (hipEventCreate(&ca) != hipSuccess) return;
+            if (hipEventCreate(&cb) != hipSuccess) {
+                (void)hipEventDestroy(ca);
+                ca = nullptr;
+                return;
+            }
+            if (capture_event_node(s, ca) != hipSuccess) {
+                (void)hipEventDestroy(ca);
+                (void)hipEventDestroy(cb);
+                return;
+            }
+            cap = true;
+            c->capture.timed.push_back({name, {ca, cb}});
+            return;
+        }
         if (t.used == t.pool.size()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return;
@@ -150,9 +215,29 @@ struct TimeScope {
         t.pending.emplace_back(name, idx);
     }
     ~TimeScope() {
+        if (cap) (void)capture_event_node(s, cb);
         if (idx != (size_t)-1) (void)hipEventRecord(c->timer.pool[idx].second, s);
     }
 };
+
+// A fresh timing event pair from the pool, queued for timer_collect.
+bool timer_pair(sgad_ctx* c, const std::string& name, hipEvent_t* a, hipEvent_t* b) {
+    KernelTimer& t = c->timer;
+    if (t.used == t.pool.size()) {
+        hipEvent_t x, y;
+        if (hipEventCreate(&x) != hipSuccess) return false;
+        if (hipEventCreate(&y) != hipSuccess) {
+            (void)hipEventDestroy(x);
+            return false;
+        }
+        t.pool.emplace_back(x, y);
+    }
+    const size_t idx = t.used++;
+    *a = t.pool[idx].first;
+    *b = t.pool[idx].second;
+    t.pending.emplace_back(name, idx);
+    return true;
+}
 
 void timer_collect(sgad_ctx* c) {
     KernelTimer& t = c->timer;
@@ -208,6 +293,18 @@ hipError_t ensure(DevBuf& b, size_t bytes, hipStream_t s) {
     return hipSuccess;
 }
 
+// ensure() that refuses to allocate while calls are being captured (a
+// captured call must find its workspace sized by an earlier eager call).
+hipError_t ensure_c(sgad_ctx* c, DevBuf& b, size_t bytes, hipStream_t s) {
+    if (c->capture.on) return b.bytes >= (bytes ? bytes : 256) ? hipSuccess : hipErrorNotSupported;
+    return ensure(b, bytes, s);
+}
+
+// The stream a call enqueues on: the caller's, or the capture stream.
+hipStream_t pick_stream(const sgad_ctx* c, void* stream) {
+    return c->capture.on ? c->capture.cap : (hipStream_t)stream;
+}
+
 hipError_t ensure_pin(PinBuf& b, size_t bytes) {
     if (b.bytes >= bytes) return hipSuccess;
     if (b.p) {
@@ -238,6 +335,7 @@ void latch_status(sgad_ctx* c, const DevStatus& st) {
 
 // Read device-side conditions of finished calls without blocking.
 void poll(sgad_ctx* c, bool block) {
+    if (c->capture.on) return;   // no queries while calls are being recorded
     if (c->track.status_pending) {
         bool done = block ? hipEventSynchronize(c->track.ev_status) == hipSuccess
                           : hipEventQuery(c->track.ev_status) == hipSuccess;
@@ -306,7 +404,7 @@ void relative_pose(const sgad_pose& v, const sgad_pose& f, PairConst& pc) {
 
 sgad_saved* acquire(sgad_ctx* c) {
     for (sgad_saved* s : c->slots)
-        if (!s->in_use) {
+        if (!s->in_use && !s->owner) {
             s->in_use = true;
             return s;
         }
@@ -322,6 +420,16 @@ sgad_saved* acquire(sgad_ctx* c) {
     s->in_use = true;
     c->slots.push_back(s);
     return s;
+}
+
+// While capturing: a free slot already sized for this workload key.
+sgad_saved* acquire_sized(sgad_ctx* c, const size_t* key) {
+    for (sgad_saved* s : c->slots)
+        if (!s->in_use && !s->owner && s->sized && std::memcmp(s->size_key, key, 5 * sizeof(size_t)) == 0) {
+            s->in_use = true;
+            return s;
+        }
+    return nullptr;
 }
 
 void free_slot(sgad_saved* s) {
@@ -359,6 +467,14 @@ sgad_status sgad_create(int device, sgad_ctx** out) {
 void sgad_destroy(sgad_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    if (c->capture.on) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(c->capture.cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        c->capture.on = false;
+    }
+    if (c->capture.cap) (void)hipStreamDestroy(c->capture.cap);
+    if (c->capture.adam.p) (void)hipFree(c->capture.adam.p);
     (void)hipDeviceSynchronize();
     for (sgad_saved* s : c->slots) free_slot(s);
     if (c->scratch.p) (void)hipFree(c->scratch.p);
@@ -383,6 +499,7 @@ const char* sgad_last_error(const sgad_ctx* c) { return c ? c->err.c_str() : "nu
 
 sgad_status sgad_sync(sgad_ctx* c) {
     if (!c) return SGAD_EINVAL;
+    if (c->capture.on) return fail(c, SGAD_EINVAL, "not allowed while capturing a graph");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipDeviceSynchronize());
     poll(c, true);
@@ -444,15 +561,15 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     const int64_t N = (int64_t)k0.H * k0.W;
     if ((int64_t)n_kf * N >= (1ll << 32) || (int64_t)n_pairs * N >= (1ll << 31))
         return fail(c, SGAD_ERANGE, "too many Gaussians for one call");
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
     HIPCHK(c, hipSetDevice(c->device));
     poll(c, false);
+    const bool cap = c->capture.on;
 
-    int TW = c->tile_w, TH = c->tile_h, SCF = 256, SCB = 32;
+    int TW = c->tile_w, TH = c->tile_h, SCB = 16;
     if (c->force) {
         TW = c->ftw;
         TH = c->fth;
-        SCF = c->fscf;
         SCB = c->fscb;
     } else if (TW == 0) {
         const size_t key[6] = {(size_t)vcam[0].H, (size_t)vcam[0].W, (size_t)N, (size_t)n_pairs, (size_t)n_jobs,
@@ -463,12 +580,23 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
             if (std::memcmp(e.key, key, sizeof(key)) == 0) {
                 TW = e.tw;
                 TH = e.th;
-                SCF = e.scf;
                 SCB = e.scb;
             }
     }
-    sgad_saved* S = acquire(c);
+    const size_t NP = (size_t)n_pairs * N;
+    const size_t M = (size_t)n_jobs * (size_t)((vcam[0].W + TW - 1) / TW) * (size_t)((vcam[0].H + TH - 1) / TH);
+    const size_t size_key[5] = {NP, M, (size_t)TW, (size_t)TH, (size_t)n_jobs};
+    sgad_saved* S = cap ? acquire_sized(c, size_key) : acquire(c);
+    if (!S && cap) {
+        std::string why = "capturing a forward needs an earlier eager call of the same workload (slots:";
+        for (sgad_saved* x : c->slots)
+            why += std::string(" [") + (x->in_use ? "in use " : "") + (x->owner ? "graph " : "") +
+                   (x->sized ? "" : "unsized ") +
+                   (std::memcmp(x->size_key, size_key, sizeof(size_key)) ? "other-workload" : "same-workload") + "]";
+        return fail(c, SGAD_EINVAL, why + ")");
+    }
     if (!S) return fail(c, SGAD_ENOMEM, "cannot allocate a saved slot");
+    if (cap) c->capture.slots.push_back(S);
     Geometry& G = S->G;
     G.n_kf = n_kf;
     G.n_jobs = n_jobs;
@@ -484,7 +612,6 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     G.ntx = (G.Wv + TW - 1) / TW;
     G.nty = (G.Hv + TH - 1) / TH;
     G.ntiles = G.ntx * G.nty;
-    G.sc_fwd = SCF;
     G.sc_bwd = SCB;
     S->stream = s;
     c->last_tw = TW;
@@ -495,13 +622,8 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     const size_t o_kfs = align256(o_pairs + sizeof(PairConst) * n_pairs);
     const size_t o_pof = align256(o_kfs + sizeof(KfPtrs) * n_kf);
     const size_t up_bytes = align256(o_pof + sizeof(int32_t) * n_jobs * n_kf);
-    if (S->up_pending) {
-        HIPCHK(c, hipEventSynchronize(S->ev_up));
-        S->up_pending = false;
-    }
-    if (ensure_pin(S->up, up_bytes) != hipSuccess) return fail(c, SGAD_ENOMEM, "pinned alloc");
-    HIPCHK(c, ensure(S->params, up_bytes, s));
-    char* up = (char*)S->up.p;
+    S->stage.assign(up_bytes, 0);
+    char* up = S->stage.data();
     PairConst* pairs = (PairConst*)(up + o_pairs);
     KfPtrs* kps = (KfPtrs*)(up + o_kfs);
     int32_t* pof = (int32_t*)(up + o_pof);
@@ -530,25 +652,35 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     }
     for (int f = 0; f < n_kf; ++f)
         kps[f] = KfPtrs{kf[f].depth, kf[f].offset, kf[f].radius, kf[f].opacity, kf[f].rgb, kf[f].sigma};
-    HIPCHK(c, hipMemcpyAsync(S->params.p, up, up_bytes, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipEventRecord(S->ev_up, s));
-    S->up_pending = true;
+    if (S->stage != S->last_up || S->params.bytes < up_bytes) {
+        if (S->up_pending) {
+            // the pinned staging buffer is rewritten: wait for its last upload
+            // (while capturing nothing is in flight: capture began after a sync)
+            if (!cap) HIPCHK(c, hipEventSynchronize(S->ev_up));
+            S->up_pending = false;
+        }
+        if (cap && S->up.bytes < up_bytes) return fail(c, SGAD_EINVAL, "capture would resize the staging buffer");
+        if (ensure_pin(S->up, up_bytes) != hipSuccess) return fail(c, SGAD_ENOMEM, "pinned alloc");
+        HIPCHK(c, ensure_c(c, S->params, up_bytes, s));
+        std::memcpy(S->up.p, up, up_bytes);
+        HIPCHK(c, hipMemcpyAsync(S->params.p, S->up.p, up_bytes, hipMemcpyHostToDevice, s));
+        if (!cap) {
+            HIPCHK(c, hipEventRecord(S->ev_up, s));
+            S->up_pending = true;
+        }
+        S->last_up = S->stage;
+    }
 
     // workspace
-    const size_t NP = (size_t)n_pairs * N;
-    const size_t M = (size_t)n_jobs * G.ntiles;
     const size_t PJ = (size_t)n_jobs * G.P;
-    HIPCHK(c, ensure(S->pre, NP * 76 + 256, s));
-    HIPCHK(c, ensure(S->tiles, (3 * M + 1) * 4 + 256, s));
-    HIPCHK(c, ensure(S->pix, PJ * 8, s));
-    HIPCHK(c, ensure(S->pose_part, M * 6 * 4, s));
-    HIPCHK(c, ensure(S->status, sizeof(DevStatus), s));
-    {
-        const size_t key[5] = {NP, M, (size_t)TW, (size_t)TH, (size_t)n_jobs};
-        if (std::memcmp(key, S->size_key, sizeof(key)) != 0) {
-            S->sized = false;
-            std::memcpy(S->size_key, key, sizeof(key));
-        }
+    HIPCHK(c, ensure_c(c, S->pre, NP * 76 + 256, s));
+    HIPCHK(c, ensure_c(c, S->tiles, (3 * M + 1) * 4 + 256, s));
+    HIPCHK(c, ensure_c(c, S->pix, PJ * 8, s));
+    HIPCHK(c, ensure_c(c, S->pose_part, M * 6 * 4, s));
+    HIPCHK(c, ensure_c(c, S->status, sizeof(DevStatus), s));
+    if (std::memcmp(size_key, S->size_key, sizeof(size_key)) != 0) {
+        S->sized = false;
+        std::memcpy(S->size_key, size_key, sizeof(size_key));
     }
     if (!S->sized && S->capacity == 0) {
         // first use: a generous guess that is corrected after the count pass
@@ -619,9 +751,12 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
             return fail(c, SGAD_EINVAL, "unsupported tile shape");
     }
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(S->status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipEventRecord(S->ev_status, s));
-    S->status_pending = true;
+    if (!cap) {
+        // (a captured forward's status is read back after each graph launch)
+        HIPCHK(c, hipMemcpyAsync(S->status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipEventRecord(S->ev_status, s));
+        S->status_pending = true;
+    }
     *saved = S;
     return SGAD_OK;
 }
@@ -639,26 +774,36 @@ sgad_status sgad_render_bwd(sgad_ctx* c, sgad_saved* S, const float* g_rgb, cons
         if (!grads || !grads[f].d_rgb || !grads[f].d_opacity || !grads[f].d_radius || !grads[f].d_offset)
             return fail(c, SGAD_EINVAL, "null gradient output for a learnable keyframe");
     }
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
+    const bool cap = c->capture.on;
     HIPCHK(c, hipSetDevice(c->device));
     poll(c, false);
     const size_t gb = align256(sizeof(KfGradPtrs) * G.n_kf);
-    if (S->up_grad_pending) {
-        HIPCHK(c, hipEventSynchronize(S->ev_up_grad));
-        S->up_grad_pending = false;
-    }
-    if (ensure_pin(S->up_grad, gb) != hipSuccess) return fail(c, SGAD_ENOMEM, "pinned alloc");
-    HIPCHK(c, ensure(S->gradptrs, gb, s));
-    KfGradPtrs* gp = (KfGradPtrs*)S->up_grad.p;
+    S->stage_grad.assign(gb, 0);
+    KfGradPtrs* gp = (KfGradPtrs*)S->stage_grad.data();
     for (int f = 0; f < G.n_kf; ++f) {
         if (grads && ((learn >> f) & 1ull))
             gp[f] = KfGradPtrs{grads[f].d_rgb, grads[f].d_opacity, grads[f].d_radius, grads[f].d_offset};
         else
             gp[f] = KfGradPtrs{nullptr, nullptr, nullptr, nullptr};
     }
-    HIPCHK(c, hipMemcpyAsync(S->gradptrs.p, gp, gb, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipEventRecord(S->ev_up_grad, s));
-    S->up_grad_pending = true;
+    if (S->stage_grad != S->last_up_grad || S->gradptrs.bytes < gb) {
+        if (S->up_grad_pending) {
+            if (!cap) HIPCHK(c, hipEventSynchronize(S->ev_up_grad));
+            S->up_grad_pending = false;
+        }
+        if (cap && (S->up_grad.bytes < gb || S->gradptrs.bytes < gb))
+            return fail(c, SGAD_EINVAL, "capturing a backward needs an earlier eager call of the same workload");
+        if (ensure_pin(S->up_grad, gb) != hipSuccess) return fail(c, SGAD_ENOMEM, "pinned alloc");
+        HIPCHK(c, ensure_c(c, S->gradptrs, gb, s));
+        std::memcpy(S->up_grad.p, gp, gb);
+        HIPCHK(c, hipMemcpyAsync(S->gradptrs.p, S->up_grad.p, gb, hipMemcpyHostToDevice, s));
+        if (!cap) {
+            HIPCHK(c, hipEventRecord(S->ev_up_grad, s));
+            S->up_grad_pending = true;
+        }
+        S->last_up_grad = S->stage_grad;
+    }
     {
         TimeScope ts(c, "composite_bwd", s);
         if (!launch_bwd(G, S->B, g_rgb, g_depth, g_alpha, (const KfGradPtrs*)S->gradptrs.p, learn_lo, learn_hi,
@@ -671,6 +816,7 @@ sgad_status sgad_render_bwd(sgad_ctx* c, sgad_saved* S, const float* g_rgb, cons
 
 sgad_status sgad_timing_enable(sgad_ctx* c, int enable) {
     if (!c) return SGAD_EINVAL;
+    if (c->capture.on) return fail(c, SGAD_EINVAL, "not allowed while capturing a graph");
     HIPCHK(c, hipSetDevice(c->device));
     timer_collect(c);
     c->timer.names.clear();
@@ -680,8 +826,15 @@ sgad_status sgad_timing_enable(sgad_ctx* c, int enable) {
     return SGAD_OK;
 }
 
+sgad_status sgad_timing_only(sgad_ctx* c, const char* name) {
+    if (!c) return SGAD_EINVAL;
+    c->timer.only = name ? name : "";
+    return SGAD_OK;
+}
+
 sgad_status sgad_timing_report(sgad_ctx* c, char* buf, size_t cap) {
     if (!c || !buf || cap == 0) return SGAD_EINVAL;
+    if (c->capture.on) return fail(c, SGAD_EINVAL, "not allowed while capturing a graph");
     HIPCHK(c, hipSetDevice(c->device));
     timer_collect(c);
     std::string out;
@@ -702,9 +855,9 @@ sgad_status sgad_l1_loss(sgad_ctx* c, int n_jobs, int H, int W, const float* rgb
     if (n_jobs < 1 || H < 1 || W < 1) return fail(c, SGAD_EINVAL, "bad sizes");
     if (!rgb || !depth || !t_rgb || !t_depth || !g_rgb || !g_depth || !loss)
         return fail(c, SGAD_EINVAL, "null pointer");
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, ensure(c->scratch, (size_t)n_jobs * 4, s));
+    HIPCHK(c, ensure_c(c, c->scratch, (size_t)n_jobs * 4, s));
     uint32_t* cnt = (uint32_t*)c->scratch.p;
     TimeScope ts(c, "l1_loss", s);
     launch_zero_u32(cnt, n_jobs, s);
@@ -736,13 +889,157 @@ sgad_status sgad_adam_step(sgad_ctx* c, int n_groups, const sgad_adam_group* gro
         A.space[g] = G.space;
         A.off[g + 1] = A.off[g] + G.n;
     }
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
     HIPCHK(c, hipSetDevice(c->device));
     const float c1 = (float)(1.0 - std::pow((double)beta1, step));
     const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+    float* cdev = nullptr;
+    if (c->capture.on) {
+        // a replayed step must advance t: the graph keeps a device counter
+        // that starts at step - 1 and is incremented by each launch
+        auto& C = c->capture;
+        if (C.n_adam == kMaxGraphAdam) return fail(c, SGAD_ERANGE, "too many Adam calls in one captured graph");
+        C.adam_t0[C.n_adam] = step - 1;
+        cdev = (float*)C.adam.p + 4 * C.n_adam;
+        ++C.n_adam;
+    }
     TimeScope ts(c, "adam", s);
-    launch_adam(A, beta1, beta2, eps, c1, c2, zero_grad, s);
+    launch_adam(A, beta1, beta2, eps, c1, c2, zero_grad, cdev, s);
     HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_graph_begin(sgad_ctx* c, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    auto& C = c->capture;
+    if (C.on) return fail(c, SGAD_EINVAL, "a capture is already open");
+    HIPCHK(c, hipSetDevice(c->device));
+    // nothing of this context may be in flight while its staging buffers are
+    // rewritten by the captured calls
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    HIPCHK(c, hipDeviceSynchronize());
+    poll(c, true);
+    if (!C.cap) HIPCHK(c, hipStreamCreateWithFlags(&C.cap, hipStreamNonBlocking));
+    HIPCHK(c, ensure(C.adam, sizeof(float) * 4 * kMaxGraphAdam, C.cap));
+    C.n_adam = 0;
+    C.slots.clear();
+    C.timed.clear();
+    HIPCHK(c, hipStreamBeginCapture(C.cap, hipStreamCaptureModeThreadLocal));
+    C.on = true;
+    return SGAD_OK;
+}
+
+sgad_status sgad_graph_end(sgad_ctx* c, sgad_graph** out) {
+    if (!c) return SGAD_EINVAL;
+    auto& C = c->capture;
+    if (!C.on) return fail(c, SGAD_EINVAL, "no capture is open");
+    C.on = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(C.cap, &graph);
+    auto drop_timed = [&]() {
+        for (auto& t : C.timed) {
+            (void)hipEventDestroy(t.second.first);
+            (void)hipEventDestroy(t.second.second);
+        }
+        C.timed.clear();
+    };
+    if (e != hipSuccess || !graph || !out) {
+        if (graph) (void)hipGraphDestroy(graph);
+        drop_timed();
+        if (!out) return fail(c, SGAD_EINVAL, "out is null");
+        return fail(c, SGAD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    sgad_graph* g = new sgad_graph();
+    g->graph = graph;
+    // map the timing events to their event-record nodes
+    if (!C.timed.empty()) {
+        size_t n = 0;
+        std::vector<hipGraphNode_t> nodes;
+        if (hipGraphGetNodes(graph, nullptr, &n) == hipSuccess && n > 0) {
+            nodes.resize(n);
+            if (hipGraphGetNodes(graph, nodes.data(), &n) != hipSuccess) nodes.clear();
+        }
+        for (auto& t : C.timed) {
+            hipGraphNode_t na = nullptr, nb = nullptr;
+            for (hipGraphNode_t nd : nodes) {
+                hipGraphNodeType ty;
+                hipEvent_t ev = nullptr;
+                if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeEventRecord) continue;
+                if (hipGraphEventRecordNodeGetEvent(nd, &ev) != hipSuccess) continue;
+                if (ev == t.second.first) na = nd;
+                if (ev == t.second.second) nb = nd;
+            }
+            if (na && nb) g->timed.push_back({t.first, {na, nb}});
+        }
+    }
+    hipError_t ie = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        drop_timed();
+        delete g;
+        return fail(c, SGAD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    // the nodes keep referring to these events until they are swapped
+    for (auto& t : C.timed) {
+        g->events.push_back(t.second.first);
+        g->events.push_back(t.second.second);
+    }
+    C.timed.clear();
+    // the graph owns the Adam counters and the slots it was captured with
+    g->adam = C.adam;
+    C.adam = DevBuf{};
+    if (C.n_adam > 0) {
+        float init[4 * kMaxGraphAdam] = {};
+        for (int k = 0; k < C.n_adam; ++k) {
+            int t0 = C.adam_t0[k];
+            std::memcpy(&init[4 * k], &t0, sizeof(int));
+        }
+        HIPCHK(c, hipMemcpy(g->adam.p, init, sizeof(init), hipMemcpyHostToDevice));
+    }
+    for (sgad_saved* S : C.slots) {
+        S->owner = g;
+        g->slots.push_back(S);
+    }
+    C.slots.clear();
+    *out = g;
+    return SGAD_OK;
+}
+
+sgad_status sgad_graph_launch(sgad_ctx* c, sgad_graph* g, void* stream) {
+    if (!c || !g) return SGAD_EINVAL;
+    if (c->capture.on) return fail(c, SGAD_EINVAL, "not allowed while capturing a graph");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    poll(c, false);
+    if (c->timer.on)
+        for (auto& t : g->timed) {
+            hipEvent_t a, b;
+            if (!timer_pair(c, t.first, &a, &b)) break;
+            HIPCHK(c, hipGraphExecEventRecordNodeSetEvent(g->exec, t.second.first, a));
+            HIPCHK(c, hipGraphExecEventRecordNodeSetEvent(g->exec, t.second.second, b));
+        }
+    HIPCHK(c, hipGraphLaunch(g->exec, s));
+    for (sgad_saved* S : g->slots) {
+        // read back what the replayed forwards found, as an eager forward does
+        if (S->status_pending) continue;
+        HIPCHK(c, hipMemcpyAsync(S->status_h, S->B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipEventRecord(S->ev_status, s));
+        S->status_pending = true;
+    }
+    return SGAD_OK;
+}
+
+sgad_status sgad_graph_destroy(sgad_ctx* c, sgad_graph* g) {
+    if (!c || !g) return SGAD_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceSynchronize());
+    poll(c, true);
+    for (sgad_saved* S : g->slots) S->owner = nullptr;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
+    if (g->adam.p) (void)hipFree(g->adam.p);
+    delete g;
     return SGAD_OK;
 }
 
@@ -759,6 +1056,7 @@ sgad_status sgad_saved_release(sgad_ctx* c, sgad_saved* S) {
 sgad_status sgad_saved_instances(sgad_ctx* c, const sgad_saved* S, int job, uint32_t* tile_ranges,
                                  uint64_t* keys, size_t cap, size_t* n_keys, int* n_tiles) {
     if (!c || !S || !S->in_use || !n_keys || !n_tiles) return SGAD_EINVAL;
+    if (c->capture.on) return fail(c, SGAD_EINVAL, "not allowed while capturing a graph");
     const Geometry& G = S->G;
     if (job < 0 || job >= G.n_jobs) return fail(c, SGAD_EINVAL, "job out of range");
     HIPCHK(c, hipSetDevice(c->device));
@@ -787,6 +1085,7 @@ sgad_status sgad_saved_instances(sgad_ctx* c, const sgad_saved* S, int job, uint
 sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam* vcam, const float* obs_depth,
                           double* pose, int iters, double* trace, uint32_t flags, void* stream) {
     if (!c) return SGAD_EINVAL;
+    if (c->capture.on) return fail(c, SGAD_EINVAL, "not allowed while capturing a graph");
     if (!geo || !vcam || !obs_depth || !pose) return fail(c, SGAD_EINVAL, "null argument");
     if (iters < 1 || iters > 1000) return fail(c, SGAD_ERANGE, "iters must be in [1, 1000]");
     if (!cam_ok(geo->cam) || !cam_ok(*vcam)) return fail(c, SGAD_EINVAL, "bad camera");
@@ -942,6 +1241,7 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
                           const sgad_pose* vpose, int n_jobs, const sgad_job* jobs, int reps, int* best_tw,
                           int* best_th, float* best_ms, void* stream) {
     if (!c) return SGAD_EINVAL;
+    if (c->capture.on) return fail(c, SGAD_EINVAL, "not allowed while capturing a graph");
     if (reps < 1 || reps > 1000) return fail(c, SGAD_ERANGE, "reps must be in [1, 1000]");
     if (n_kf < 1 || n_kf > kMaxKf || !kf || n_views < 1 || !vcam || n_jobs < 1 || !jobs)
         return fail(c, SGAD_EINVAL, "bad workload");
@@ -968,10 +1268,9 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
         grads[f] = sgad_kf_grads{g, g + 3 * N, g + 4 * N, g + 5 * N};
     }
     struct Cand {
-        int tw, th, scf, scb;
+        int tw, th, scb;
     };
-    const Cand cands[] = {{16, 16, 0, 0}, {16, 8, 0, 0}, {32, 8, 0, 0}, {8, 8, 256, 32},
-                          {8, 8, 128, 32}, {8, 8, 256, 16}};
+    const Cand cands[] = {{16, 16, 0}, {16, 8, 0}, {32, 8, 0}, {8, 8, 16}, {8, 8, 32}};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -982,8 +1281,7 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
         c->force = true;
         c->ftw = cd.tw;
         c->fth = cd.th;
-        c->fscf = cd.scf ? cd.scf : 256;
-        c->fscb = cd.scb ? cd.scb : 32;
+        c->fscb = cd.scb ? cd.scb : 16;
         float ms_tot = 0.f;
         for (int r = 0; r <= reps && rs == SGAD_OK; ++r) {  // r == 0 is a warm-up
             sgad_saved* sv = nullptr;
@@ -1017,8 +1315,7 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
         std::memcpy(te.key, key, sizeof(key));
         te.tw = bc.tw;
         te.th = bc.th;
-        te.scf = bc.scf ? bc.scf : 256;
-        te.scb = bc.scb ? bc.scb : 32;
+        te.scb = bc.scb ? bc.scb : 16;
         te.ms = best;
         bool found = false;
         for (auto& e : c->tune)
@@ -1042,7 +1339,7 @@ sgad_status sgad_conv_weights(sgad_ctx* c, int cin, int cout, const float* w, ui
     if (!c) return SGAD_EINVAL;
     if (cin < 1 || cout < 1 || cin > 32 || cout > 32 || !w || !w_bf16) return fail(c, SGAD_EINVAL, "bad weights");
     HIPCHK(c, hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
     TimeScope ts(c, "conv_weights", s);
     launch_conv_weights(cin, cout, w, w_bf16, wt_bf16, s);
     HIPCHK(c, hipGetLastError());
@@ -1055,7 +1352,7 @@ sgad_status sgad_conv3x3_fwd(sgad_ctx* c, int H, int W, int cin, int cout, int m
     if (!conv_dims_ok(H, W) || !x || !w_bf16 || !bias || !y) return fail(c, SGAD_EINVAL, "bad conv arguments");
     if (mode != SGAD_CONV_RELU_BF16 && mode != SGAD_CONV_LINEAR_F32) return fail(c, SGAD_EINVAL, "bad conv mode");
     HIPCHK(c, hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
     TimeScope ts(c, "conv_fwd", s);
     if (!launch_conv_fwd(H, W, cin, cout, mode, x, w_bf16, bias, nullptr, y, s))
         return fail(c, SGAD_EINVAL, "unsupported (cin, cout, mode)");
@@ -1068,7 +1365,7 @@ sgad_status sgad_conv3x3_dgrad(sgad_ctx* c, int H, int W, int cin, int cout, con
     if (!c) return SGAD_EINVAL;
     if (!conv_dims_ok(H, W) || !dy || !wt_bf16 || !mask || !dx) return fail(c, SGAD_EINVAL, "bad dgrad arguments");
     HIPCHK(c, hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
     TimeScope ts(c, "conv_dgrad", s);
     // the input gradient is a convolution from cout to cin channels
     if (!launch_conv_fwd(H, W, cout, cin, 2, dy, wt_bf16, nullptr, mask, dx, s))
@@ -1082,7 +1379,7 @@ sgad_status sgad_conv3x3_wgrad(sgad_ctx* c, int H, int W, int cin, int cout, con
     if (!c) return SGAD_EINVAL;
     if (!conv_dims_ok(H, W) || !x || !dy || !dw || !db) return fail(c, SGAD_EINVAL, "bad wgrad arguments");
     HIPCHK(c, hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
     TimeScope ts(c, "conv_wgrad", s);
     if (!launch_conv_wgrad(H, W, cin, cout, x, dy, dw, db, s)) return fail(c, SGAD_EINVAL, "unsupported (cin, cout)");
     HIPCHK(c, hipGetLastError());
@@ -1094,7 +1391,7 @@ sgad_status sgad_net_input(sgad_ctx* c, int H, int W, const float* rgb, const fl
     if (!c) return SGAD_EINVAL;
     if (!conv_dims_ok(H, W) || !rgb || !depth || !x0) return fail(c, SGAD_EINVAL, "bad input arguments");
     HIPCHK(c, hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
     launch_net_input(H, W, rgb, depth, x0, s);
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
@@ -1105,7 +1402,7 @@ sgad_status sgad_offset_l1(sgad_ctx* c, int n, const float* pred, const float* t
     if (!c) return SGAD_EINVAL;
     if (n < 1 || !pred || !target || !grad || !loss) return fail(c, SGAD_EINVAL, "bad loss arguments");
     HIPCHK(c, hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = pick_stream(c, stream);
     launch_zero_u32((uint32_t*)loss, 2, s);
     launch_offset_l1(n, pred, target, grad, loss, s);
     HIPCHK(c, hipGetLastError());

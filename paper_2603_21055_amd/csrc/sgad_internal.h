@@ -17,6 +17,7 @@ constexpr double kZNear = 0.2;
 constexpr float kQCut = 9.0f;
 constexpr int kMaxKf = 64;
 constexpr int kMaxAdamGroups = 32;
+constexpr int kMaxGraphAdam = 8;   // Adam calls one captured graph may hold
 
 // Relative transform and intrinsics of one (job, keyframe) pair.
 struct PairConst {
@@ -71,7 +72,7 @@ struct Geometry {
     int Hk, Wk, N;        // keyframe size, N = Hk * Wk
     int Hv, Wv, P;        // view size
     int TW, TH, ntx, nty, ntiles;
-    int sc_fwd = 256, sc_bwd = 32;  // forward super-chunk / backward sub-chunk of the 8x8 kernels
+    int sc_bwd = 16;   // backward sub-chunk of the 8x8 kernels (16 or 32 entries)
 };
 
 struct RenderBufs {

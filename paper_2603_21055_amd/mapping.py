@@ -82,7 +82,7 @@ class Mapper:
     views / jobs: as for sgad.Context.render_fwd; targets: per-job device
     tensors t_rgb [n_jobs, 3, H, W], t_depth [n_jobs, H, W]."""
 
-    def __init__(self, ctx, kfs, views, jobs, learnable, t_rgb, t_depth, with_count=False):
+    def __init__(self, ctx, kfs, views, jobs, learnable, t_rgb, t_depth, with_count=False, lr=None):
         import torch
         self.ctx, self.kfs, self.views, self.jobs = ctx, kfs, views, jobs
         self.learn = list(learnable)
@@ -110,8 +110,10 @@ class Mapper:
                                          ("radius", "d_radius", R_MIN, np.inf, sgad.SPACE_LOG),
                                          ("offset", "d_offset", -np.inf, np.inf, sgad.SPACE_LINEAR)):
                 p = kf[name]
-                self.groups.append((p, g[gk], torch.zeros_like(p), torch.zeros_like(p), LR[name], lo, hi, sp))
+                rate = (lr or LR)[name]
+                self.groups.append((p, g[gk], torch.zeros_like(p), torch.zeros_like(p), rate, lo, hi, sp))
         self.t = 0
+        self.graph = None
 
     def step(self):
         """One mapping iteration; returns nothing (loss stays on the device)."""
@@ -123,6 +125,30 @@ class Mapper:
         c.release(saved)
         self.t += 1
         c.adam_step(self.groups, self.t)
+
+    def capture(self):
+        """Record one mapping iteration as a graph (after at least one eager
+        step, which sizes the workspace); later iterations are replay()."""
+        if self.graph is not None:
+            return
+        c = self.ctx
+        c.graph_begin()
+        try:
+            self.step()          # recorded, not run
+        finally:
+            g = c.graph_end()
+        self.t -= 1
+        self.graph = g
+
+    def replay(self):
+        """One mapping iteration by replaying the captured graph."""
+        self.ctx.graph_launch(self.graph)
+        self.t += 1
+
+    def release_graph(self):
+        if self.graph is not None:
+            self.ctx.graph_destroy(self.graph)
+            self.graph = None
 
     def loss_value(self) -> float:
         return float(self.loss.sum().item())

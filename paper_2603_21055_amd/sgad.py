@@ -75,6 +75,7 @@ _SIGS = {
     "sgad_track_gn": (C.c_int, [_P, C.POINTER(Keyframe), C.POINTER(Cam), _P, _P, C.c_int, _P, C.c_uint32,
                                 _P]),
     "sgad_timing_enable": (C.c_int, [_P, C.c_int]),
+    "sgad_timing_only": (C.c_int, [_P, C.c_char_p]),
     "sgad_l1_loss": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, C.c_float, C.c_float, _P, _P,
                                _P, _P]),
     "sgad_adam_step": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_int, C.c_float, C.c_float, C.c_float,
@@ -91,6 +92,10 @@ _SIGS = {
                                 C.POINTER(C.c_float), _P]),
     "sgad_saved_instances": (C.c_int, [_P, _P, C.c_int, _P, _P, C.c_size_t, C.POINTER(C.c_size_t),
                                        C.POINTER(C.c_int)]),
+    "sgad_graph_begin": (C.c_int, [_P, _P]),
+    "sgad_graph_end": (C.c_int, [_P, C.POINTER(_P)]),
+    "sgad_graph_launch": (C.c_int, [_P, _P, _P]),
+    "sgad_graph_destroy": (C.c_int, [_P, _P]),
 }
 
 _lib = None
@@ -178,6 +183,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for g in list(getattr(self, "_graphs", [])):
+                self.lib.sgad_graph_destroy(self.h, g)
             self.lib.sgad_destroy(self.h)
             self.h = None
 
@@ -207,6 +214,10 @@ class Context:
     def timing(self, enable: bool):
         """Enable/disable per-kernel event timing (resets the accumulators)."""
         self._check(self.lib.sgad_timing_enable(self.h, 1 if enable else 0))
+
+    def timing_only(self, name=None):
+        """Time only the kernel `name` (None: every kernel)."""
+        self._check(self.lib.sgad_timing_only(self.h, name.encode() if name else None))
 
     def timing_report(self) -> dict:
         """{kernel name: (launches, total ms)} since timing was enabled."""
@@ -361,6 +372,27 @@ class Context:
 
     def release(self, saved):
         self._check(self.lib.sgad_saved_release(self.h, saved))
+
+    # graph capture of library calls (see sgad_graph_begin in include/sgad.h)
+    def graph_begin(self, stream=None):
+        self._check(self.lib.sgad_graph_begin(self.h, _stream(stream)))
+
+    def graph_end(self):
+        g = C.c_void_p()
+        self._check(self.lib.sgad_graph_end(self.h, C.byref(g)))
+        self.__dict__.setdefault("_graphs", []).append(g)
+        return g
+
+    def graph_launch(self, graph, stream=None):
+        self._check(self.lib.sgad_graph_launch(self.h, graph, _stream(stream)))
+
+    def graph_destroy(self, graph):
+        gs = self.__dict__.get("_graphs", [])
+        for i, g in enumerate(gs):
+            if g.value == graph.value:
+                del gs[i]
+                break
+        self._check(self.lib.sgad_graph_destroy(self.h, graph))
 
     def instances(self, saved, job):
         """Sorted instance list of one job: (tile_ranges [n_tiles, 2], keys)."""

@@ -131,18 +131,19 @@ def mapping_curve(ctx, sc, net, iters: int):
     return curve.cpu().numpy()
 
 
-def experiment(ctx, n_frames=2000, epochs=20, batch=8, map_iters=200, plain_iters=50, workers=8, log=print,
+def experiment(ctx, frames, epochs=20, batch=8, map_iters=200, plain_iters=50, log=print,
                eval_seed=3000, eval_size=(640, 480)):
+    """frames: from make_frames (generated before the device is opened, so the
+    worker processes never inherit a device context)."""
     t0 = time.time()
-    log(f"generating {n_frames} training frames")
-    frames = make_frames(range(1000, 1000 + n_frames), workers)
+    n_frames = len(frames)
     log(f"converging offsets ({map_iters} mapping iterations per frame)")
     data = []
     for i, fr in enumerate(frames):
         rgb, dep, off = converged_offsets(ctx, fr, map_iters)
         data.append((rgb, dep, off))
-        if i % 200 == 199:
-            log(f"  {i + 1} frames")
+        if i % 100 == 99:
+            log(f"  {i + 1} frames ({time.time() - t0:.0f} s)")
     log("training")
     net, hist = train(ctx, data, epochs=epochs, batch=batch, log=log)
     log("evaluating")
@@ -166,9 +167,11 @@ def main():
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--out", type=str, default=None)
     a = ap.parse_args()
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    log(f"generating {a.frames} training frames")
+    frames = make_frames(range(1000, 1000 + a.frames), a.workers)
     ctx = sgad.Context(0)
-    res = experiment(ctx, a.frames, a.epochs, map_iters=a.map_iters, workers=a.workers,
-                     log=lambda m: print(m, file=sys.stderr, flush=True))
+    res = experiment(ctx, frames, a.epochs, map_iters=a.map_iters, log=log)
     s = json.dumps({k: v for k, v in res.items() if not k.endswith("curve")})
     print(s, flush=True)
     if a.out:
