@@ -45,7 +45,12 @@ KERNEL_SOURCES = {
     "composite_bwd": ("k_raster8.hip", "raster_common.h", "sgad_internal.h"),
     "composite_fwd": ("k_raster8.hip", "raster_common.h", "sgad_internal.h"),
 }
-PMC = {}   # kernel -> dict(fetch_kib=..., write_kib=..., sha=...)
+PMC = {    # kernel -> counters per dispatch and the sources they were taken on
+    "composite_bwd": dict(fetch_kib=19205.1, write_kib=84978.3,
+                          sha="95e68584dace6b1d0d6213bd5cbb8e59694415a068352852f22c34be3327ec10"),
+    "composite_fwd": dict(fetch_kib=15593.7, write_kib=9601.0,
+                          sha="95e68584dace6b1d0d6213bd5cbb8e59694415a068352852f22c34be3327ec10"),
+}
 
 
 def sources_sha(kernel):
@@ -172,6 +177,25 @@ def bench_copy(args):
                           bytes_read_per_copy=4 * n, bytes_written_per_copy=4 * n)), flush=True)
 
 
+def warm_frames(n_frames=400):
+    """Training frames of the warm-start comparison (CPU worker processes;
+    made before the GPU is opened)."""
+    from paper_2603_21055_amd import warmstart
+    return warmstart.make_frames(range(1000, 1000 + n_frames), workers=min(8, os.cpu_count() or 1))
+
+
+def warm_start(ctx, log, frames, epochs=20):
+    """Mapping iterations to a loss level, warm (conv-net offsets) vs plain
+    (zero offsets), on an unseen 8-keyframe 640x480 window; the net is trained
+    here on the offsets plain mapping converges to on the given frames."""
+    from paper_2603_21055_amd import warmstart
+    log(f"warm start: {len(frames)} training frames, {epochs} epochs")
+    res = warmstart.experiment(ctx, frames, epochs=epochs, map_iters=150, log=log)
+    keep = ("plain_iters", "plain_first_loss", "warm_first_loss", "plain_final_loss", "warm_final_loss",
+            "warm_iters_to_plain_level", "warm_iters_to_plain_loss", "n_frames", "epochs", "seconds")
+    return {k: res[k] for k in keep}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +205,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--print-sha", action="store_true", help="print the kernel-source hashes and exit")
     ap.add_argument("--graph", action="store_true", help="time replays of a captured graph of one step")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start comparison")
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "copy"], default="c2",
                     help="c2: the headline 640x480 frame; c3: 8-keyframe x 8-view window; "
                          "c4: 1200x680 tracking; copy: plain device copy (counter calibration)")
@@ -195,6 +220,10 @@ def main():
     if args.workload != "c2":
         return {"c3": bench_window, "c4": bench_tracking, "copy": bench_copy}[args.workload](args)
 
+    frames = None
+    if not args.no_warm_start:
+        log("warm-start training frames (CPU)")
+        frames = warm_frames()
     import numpy as np
     import torch
 
@@ -290,6 +319,8 @@ def main():
         kernels_ms=warm,          # per launch, from the warmup steps with every kernel timed
         loss_after_warmup=loss0, loss_final=mapper.loss_value(),
     )
+    if not args.no_warm_start:
+        out["warm_start"] = warm_start(ctx, log, frames)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, ~20 s)")
         out["cpu_baseline"] = cpu_baseline()

@@ -68,8 +68,10 @@ def make_frames(seeds, workers: int = 8):
         return p.map(_gen, [(s,) for s in seeds])
 
 
-def converged_offsets(ctx, frame, iters: int = 200):
-    """Run plain mapping on one frame and return (rgb, noisy depth, offsets)."""
+def converged_offsets(ctx, frame, iters: int = 200, avg: int = 50):
+    """Run plain mapping on one frame and return (rgb, noisy depth, offsets);
+    the offsets are the mean of the last `avg` iterates (Adam keeps moving
+    each parameter by about its learning rate, so single iterates jitter)."""
     import torch
     dev = ctx.device
     kf = sgad.to_device(frame["kf"], dev)
@@ -77,9 +79,12 @@ def converged_offsets(ctx, frame, iters: int = 200):
     t_dep = torch.from_numpy(np.stack([t["depth"] for t in frame["targets"]])).to(dev)
     jobs = [(v, [0]) for v in range(len(frame["views"]))]
     m = Mapper(ctx, [kf], frame["views"], jobs, [0], t_rgb, t_dep)
-    for _ in range(iters):
+    acc = torch.zeros_like(kf["offset"])
+    for i in range(iters):
         m.step()
-    return kf["rgb"], kf["depth"], kf["offset"].clone()
+        if i >= iters - avg:
+            acc += kf["offset"]
+    return kf["rgb"], kf["depth"], acc / float(min(avg, iters))
 
 
 def train(ctx, data, epochs: int = 20, batch: int = 8, lr: float = 1e-3, seed: int = 0, log=None):
@@ -150,10 +155,17 @@ def experiment(ctx, frames, epochs=20, batch=8, map_iters=200, plain_iters=50, l
     sc = eval_window(eval_seed, W=eval_size[0], H=eval_size[1])
     plain = mapping_curve(ctx, sc, None, plain_iters)
     warm = mapping_curve(ctx, sc, net, plain_iters)
+    # iterations the warm start needs to reach the loss plain mapping has after
+    # k iterations, for several k
+    levels = {}
+    for k in (2, 5, 10, 20, plain_iters):
+        hit = np.nonzero(warm <= plain[k - 1])[0]
+        levels[str(k)] = int(hit[0]) + 1 if len(hit) else None
     target = plain[-1]
     hit = np.nonzero(warm <= target)[0]
     warm_iters = int(hit[0]) + 1 if len(hit) else None
     return dict(plain_iters=plain_iters, plain_final_loss=float(target), warm_iters_to_plain_loss=warm_iters,
+                warm_iters_to_plain_level=levels, plain_first_loss=float(plain[0]), warm_first_loss=float(warm[0]),
                 warm_final_loss=float(warm[-1]), plain_curve=plain.tolist(), warm_curve=warm.tolist(),
                 train_loss=hist, n_frames=n_frames, epochs=epochs, seconds=time.time() - t0)
 
