@@ -239,7 +239,7 @@ def main():
     jobs = [(0, [0])]
     if args.tile == "auto":
         ctx.set_tile(0, 0)
-        (tw, th), tune_ms = ctx.autotune(kfs_d, views, jobs, reps=5)
+        (tw, th), tune_ms = ctx.autotune(kfs_d, views, jobs, reps=10)
         log(f"autotuner chose {tw}x{th} ({tune_ms:.4f} ms per forward + adjoint)")
     else:
         tw, th = (int(x) for x in args.tile.split("x"))

@@ -177,6 +177,14 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
     rec[1] = make_float4(fa, fb, fc, kp.opacity[pix]);
     rec[2] = make_float4(c0, c1, c2, fz);
     rec[3] = make_float4(ok ? (float)x : 0.f, ok ? (float)y : 0.f, Rf, s >= 0.0 ? 1.f : -1.f);
+    {
+        // offset direction: the view-space centre moves by R (xn, yn, 1) per
+        // unit of |D + delta|, and |D + delta| by sign(D + delta) per unit of delta
+        const double sg = s >= 0.0 ? 1.0 : -1.0;
+        B.pre.dir[i] = make_float4((float)(sg * ((R[0] * xn + R[1] * yn) + R[2])),
+                                   (float)(sg * ((R[3] * xn + R[4] * yn) + R[5])),
+                                   (float)(sg * ((R[6] * xn + R[7] * yn) + R[8])), 0.f);
+    }
     B.pre.z[i] = fz;
     B.pre.rx[i] = rx;
     B.pre.ry[i] = ry;
@@ -186,6 +194,15 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
 __global__ void k_zero_u32(uint32_t* p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Two arrays zeroed by one launch.
+__global__ void k_zero2_u32(uint32_t* a, int64_t na, uint32_t* b, int64_t nb) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+        if (i < na) a[i] = 0u;
+        else b[i - na] = 0u;
+    }
 }
 
 __global__ void k_fill_f32(float* p, int64_t n, float v) {
@@ -206,8 +223,14 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ coun
     const int chunk = (M + 1023) / 1024;
     const int b = tid * chunk;
     const int e = min(M, b + chunk);
-    uint32_t sum = 0;
-    for (int k = b; k < e; ++k) sum += count[k];
+    uint32_t sum = 0, mx = 0;
+    for (int k = b; k < e; ++k) {
+        sum += count[k];
+        mx = max(mx, count[k]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    __shared__ uint32_t s_max[16];
     // inclusive scan across the wave
     const int lane = tid & 63, wave = tid >> 6;
     uint32_t inc = sum;
@@ -216,6 +239,7 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ coun
         if (lane >= off) inc += o;
     }
     if (lane == 63) s_wave[wave] = inc;
+    if (lane == 0) s_max[wave] = mx;
     __syncthreads();
     if (wave == 0) {
         uint32_t w = lane < 16 ? s_wave[lane] : 0u;
@@ -239,6 +263,9 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ coun
         st->total = tot;
         st->overflow = tot > capacity ? 1u : 0u;
         st->queue = 0u;
+        uint32_t m = 0;
+        for (int w = 0; w < 16; ++w) m = max(m, s_max[w]);
+        st->max_seg = m;
     }
 }
 
@@ -337,14 +364,18 @@ __device__ void wave_sort_segment(uint64_t* g, int n, int lane) {
                 }
             }
         } else {
-            // mirror step across lanes: (lane, r) <-> (lane ^ (k / K - 1), K - 1 - r)
+            // mirror step across lanes: (lane, r) <-> (lane ^ (k / K - 1), K - 1 - r),
+            // taken in register pairs (r, K - 1 - r)
             const int lm = k / K - 1;
             const bool lower = (lane & (k / (2 * K))) == 0;
-            uint64_t y[K];
 #pragma unroll
-            for (int r = 0; r < K; ++r) y[r] = shfl_xor_u64(x[K - 1 - r], lm);
-#pragma unroll
-            for (int r = 0; r < K; ++r) x[r] = lower ? (x[r] < y[r] ? x[r] : y[r]) : (x[r] < y[r] ? y[r] : x[r]);
+            for (int r = 0; r < (K + 1) / 2; ++r) {
+                const int q = K - 1 - r;
+                const uint64_t ya = shfl_xor_u64(x[q], lm);
+                const uint64_t yb = shfl_xor_u64(x[r], lm);
+                x[r] = lower ? (x[r] < ya ? x[r] : ya) : (x[r] < ya ? ya : x[r]);
+                if (q != r) x[q] = lower ? (x[q] < yb ? x[q] : yb) : (x[q] < yb ? yb : x[q]);
+            }
         }
 #pragma unroll
         for (int j = k >> 2; j >= 1; j >>= 1) {
@@ -376,6 +407,8 @@ __device__ inline void cmpswap_lds(uint64_t* s, int a, int b) {
     }
 }
 
+__device__ void sort_global_segment(uint64_t* g, int n);
+
 __global__ __launch_bounds__(64) void k_sort(Geometry G, RenderBufs B) {
     const int seg = blockIdx.x;
     if (B.status->overflow) return;
@@ -389,42 +422,15 @@ __global__ __launch_bounds__(64) void k_sort(Geometry G, RenderBufs B) {
     else if (n <= 256) wave_sort_segment<4>(g, n, tid);
     else if (n <= 512) wave_sort_segment<8>(g, n, tid);
     else if (n <= 1024) wave_sort_segment<16>(g, n, tid);
+    else if (!G.sort_long) sort_global_segment(g, n);   // no long-segment pass follows
 }
 
-// Segments longer than 1024 keys (every other segment returns at once).
-__global__ __launch_bounds__(256) void k_sort_long(Geometry G, RenderBufs B) {
-    __shared__ uint64_t s[kSortLds];
-    const int seg = blockIdx.x;
-    if (B.status->overflow) return;
-    const uint32_t st = B.tile_start[seg];
-    const int n = (int)(B.tile_start[seg + 1] - st);
-    if (n <= 1024) return;
-    uint64_t* g = B.keys + st;
+// Bitonic network in place in global memory with virtual +inf padding, by the
+// threads of one workgroup.
+__device__ void sort_global_segment(uint64_t* g, int n) {
     const int tid = threadIdx.x;
     int np2 = 1;
     while (np2 < n) np2 <<= 1;
-    if (np2 <= kSortLds) {
-        for (int k = tid; k < np2; k += blockDim.x) s[k] = k < n ? g[k] : ~0ull;
-        __syncthreads();
-        for (int k = 2; k <= np2; k <<= 1) {
-            const int h = k >> 1;
-            for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
-                const int blk = p / h, off = p - blk * h;
-                cmpswap_lds(s, blk * k + off, blk * k + k - 1 - off);
-            }
-            __syncthreads();
-            for (int j = k >> 2; j >= 1; j >>= 1) {
-                for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
-                    const int blk = p / j, off = p - blk * j;
-                    const int a = blk * 2 * j + off;
-                    cmpswap_lds(s, a, a + j);
-                }
-                __syncthreads();
-            }
-        }
-        for (int k = tid; k < n; k += blockDim.x) g[k] = s[k];
-        return;
-    }
     // long segment: same network in global memory, virtual +inf padding
     for (int k = 2; k <= np2; k <<= 1) {
         const int h = k >> 1;
@@ -457,6 +463,49 @@ __global__ __launch_bounds__(256) void k_sort_long(Geometry G, RenderBufs B) {
     }
 }
 
+
+__device__ void sort_long_segment(uint64_t* g, int n, uint64_t* s) {
+    const int tid = threadIdx.x;
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    if (np2 <= kSortLds) {
+        for (int k = tid; k < np2; k += blockDim.x) s[k] = k < n ? g[k] : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= np2; k <<= 1) {
+            const int h = k >> 1;
+            for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
+                const int blk = p / h, off = p - blk * h;
+                cmpswap_lds(s, blk * k + off, blk * k + k - 1 - off);
+            }
+            __syncthreads();
+            for (int j = k >> 2; j >= 1; j >>= 1) {
+                for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
+                    const int blk = p / j, off = p - blk * j;
+                    const int a = blk * 2 * j + off;
+                    cmpswap_lds(s, a, a + j);
+                }
+                __syncthreads();
+            }
+        }
+        for (int k = tid; k < n; k += blockDim.x) g[k] = s[k];
+        return;
+    }
+    sort_global_segment(g, n);
+}
+
+// Segments longer than 1024 keys, launched when the previous forward of the
+// workload had one (the scan records the longest segment); one workgroup per
+// segment, LDS up to kSortLds keys.
+__global__ __launch_bounds__(256) void k_sort_long(Geometry G, RenderBufs B) {
+    __shared__ uint64_t s[kSortLds];
+    if (B.status->overflow) return;
+    const int seg = blockIdx.x;
+    const uint32_t st = B.tile_start[seg];
+    const int n = (int)(B.tile_start[seg + 1] - st);
+    if (n <= 1024) return;
+    sort_long_segment(B.keys + st, n, s);
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -464,6 +513,13 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_zero_u32, dim3(blocks), dim3(256), 0, s, p, n);
+}
+
+void launch_zero2_u32(uint32_t* a, int64_t na, uint32_t* b, int64_t nb, hipStream_t s) {
+    const int64_t n = na + nb;
+    if (n <= 0) return;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero2_u32, dim3(blocks), dim3(256), 0, s, a, na, b, nb);
 }
 
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
@@ -494,7 +550,7 @@ void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s) {
 void launch_sort(const Geometry& G, const RenderBufs& B, hipStream_t s) {
     const int M = G.n_jobs * G.ntiles;
     hipLaunchKernelGGL(k_sort, dim3(M), dim3(64), 0, s, G, B);
-    hipLaunchKernelGGL(k_sort_long, dim3(M), dim3(256), 0, s, G, B);
+    if (G.sort_long) hipLaunchKernelGGL(k_sort_long, dim3(M), dim3(256), 0, s, G, B);
 }
 
 }  // namespace sgad

@@ -260,13 +260,13 @@ static void bwd_t(const Geometry& G, const RenderBufs& B, const BwdArgs& A, hipS
     hipLaunchKernelGGL((k_bwd<TW, TH>), dim3(G.n_jobs * G.ntiles), dim3(TW * TH), 0, s, G, B, A);
 }
 
-bool launch_fwd8(const Geometry& G, const RenderBufs& B, const FwdOut& O, hipStream_t s);
+bool launch_fwd8(const Geometry& G, const RenderBufs& B, const FwdOut& O, int sch, hipStream_t s);
 bool launch_bwd8(const Geometry& G, const RenderBufs& B, const BwdArgs& A, int sc, hipStream_t s);
 
 bool launch_fwd(const Geometry& G, const RenderBufs& B, float* rgb, float* depth, float* alpha, int32_t* count,
                 hipStream_t s) {
     FwdOut O{rgb, depth, alpha, count};
-    if (G.TW == 8 && G.TH == 8) return launch_fwd8(G, B, O, s);
+    if (G.TW == 8 && G.TH == 8) return launch_fwd8(G, B, O, G.sc_fwd, s);
     else if (G.TW == 16 && G.TH == 8) fwd_t<16, 8>(G, B, O, s);
     else if (G.TW == 16 && G.TH == 16) fwd_t<16, 16>(G, B, O, s);
     else if (G.TW == 32 && G.TH == 8) fwd_t<32, 8>(G, B, O, s);

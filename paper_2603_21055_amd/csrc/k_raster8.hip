@@ -27,7 +27,7 @@ __device__ __forceinline__ uint64_t low_bits(int k) { return k >= 64 ? ~0ull : (
 // One lane's share of a chunk, gathered from HBM: its entry's key and record.
 struct ChunkRegs {
     uint64_t key;
-    float4 r0, r1, r2, r3;
+    float4 r0, r1, r2, r3, d;
 };
 
 // Key of entry `e` of the list starting at `base` (0 when e >= n).
@@ -36,7 +36,8 @@ __device__ __forceinline__ uint64_t fetch_key(const RenderBufs& B, uint32_t base
 }
 
 // Record of `key` (pair looked up in the job's pair table `pof`).  WITH_R3
-// also fetches [x, y, r, sign], which only the backward needs.
+// also fetches [x, y, r, sign] and the offset direction, which only the
+// backward needs.
 template <bool WITH_R3>
 __device__ __forceinline__ void fetch_record(const Geometry& G, const RenderBufs& B, const int* pof, bool valid,
                                              ChunkRegs& c) {
@@ -44,11 +45,15 @@ __device__ __forceinline__ void fetch_record(const Geometry& G, const RenderBufs
     const uint32_t gid = (uint32_t)c.key;
     const int kf = (int)(gid / (uint32_t)G.N);
     const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
-    const float4* rec = B.pre.rec + 4 * ((size_t)pof[kf] * G.N + pix);
+    const size_t i = (size_t)pof[kf] * G.N + pix;
+    const float4* rec = B.pre.rec + 4 * i;
     c.r0 = rec[0];
     c.r1 = rec[1];
     c.r2 = rec[2];
-    if (WITH_R3) c.r3 = rec[3];
+    if (WITH_R3) {
+        c.r3 = rec[3];
+        c.d = B.pre.dir[i];
+    }
 }
 
 // Publish a chunk in LDS (records and coverage masks).
@@ -115,7 +120,7 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
     int cnt = 0;
     uint32_t last = 0;
     bool done = !inside;
-    lds_fence();
+    wave_lds_sync();
     ChunkRegs cur{}, nxt{};
     cur.key = fetch_key(B, st, lane, len);
     fetch_record<false>(G, B, s_pof, lane < len, cur);
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
     for (int c0 = 0; c0 < len; c0 += 64) {
         const int n = min(64, len - c0);
         publish_chunk(cur, lane < n, lane, fx0, fy0, s_e, s_m);
-        lds_fence();
+        wave_lds_sync();
         // gather ahead: records of the next chunk, keys of the one after
         fetch_record<false>(G, B, s_pof, lane < len - c0 - 64, nxt);
         const uint64_t key2 = fetch_key(B, st + (uint32_t)(c0 + 128), lane, len - c0 - 128);
@@ -181,7 +186,138 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
         if (__ballot(!done) == 0ull) break;
         cur = nxt;
         nxt.key = key2;
-        lds_fence();
+        wave_lds_sync();
+    }
+    if (!inside) return;
+    const size_t pix = (size_t)py * G.Wv + px;
+    const size_t P = (size_t)G.P;
+    const size_t jp = (size_t)job * P + pix;
+    if (ovf) {
+        const float nan = __builtin_nanf("");
+        cr = cg = cb = dd = nan;
+        T = nan;
+    }
+    O.rgb[((size_t)job * 3 + 0) * P + pix] = cr;
+    O.rgb[((size_t)job * 3 + 1) * P + pix] = cg;
+    O.rgb[((size_t)job * 3 + 2) * P + pix] = cb;
+    O.depth[jp] = dd;
+    O.alpha[jp] = 1.f - T;
+    if (O.count) O.count[jp] = cnt;
+    B.Tfinal[jp] = T;
+    B.last[jp] = last;
+}
+
+// Forward over super-chunks of SCH published chunks: each lane walks its
+// candidates across all SCH chunks without waiting at chunk boundaries, so a
+// wave runs the per-super-chunk maximum over lanes instead of the sum of the
+// per-chunk maxima (depth order is spatially correlated: with one
+// 256-entry super-chunk a 640x480 tile needs ~25 rounds instead of ~65).
+template <int SCH>
+__global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O) {
+    constexpr int SPAN = 64 * SCH;
+    __shared__ float4 s_e[SPAN][3];
+    __shared__ uint64_t s_m[SCH][16];
+    __shared__ int s_pof[64];
+    const int lane = threadIdx.x;
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    if (item >= G.n_jobs * G.ntiles) return;
+    const TileItem ti = tile_item(G, B, item, lane, s_pof);
+    const int job = ti.job;
+    const int lx = lane & 7, ly = lane >> 3;
+    const int px = ti.tx * 8 + lx, py = ti.ty * 8 + ly;
+    const bool inside = px < G.Wv && py < G.Hv;
+    const bool ovf = B.status->overflow != 0u;
+    const uint32_t st = B.tile_start[item];
+    const int len = ovf ? 0 : (int)(B.tile_start[item + 1] - st);
+    const float fpx = (float)px, fpy = (float)py;
+    const float fx0 = (float)(ti.tx * 8), fy0 = (float)(ti.ty * 8);
+    float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;
+    int cnt = 0;
+    uint32_t last = 0;
+    bool done = !inside;
+    wave_lds_sync();
+    uint64_t keys[SCH];
+#pragma unroll
+    for (int i = 0; i < SCH; ++i) keys[i] = fetch_key(B, st + (uint32_t)(64 * i), lane, len - 64 * i);
+    for (int c0 = 0; c0 < len; c0 += SPAN) {
+        const int n = min(SPAN, len - c0);
+        const int nch = (n + 63) >> 6;
+        ChunkRegs r[SCH];
+#pragma unroll
+        for (int i = 0; i < SCH; ++i) {
+            r[i].key = keys[i];
+            fetch_record<false>(G, B, s_pof, lane < n - 64 * i, r[i]);
+        }
+        // keys of the next super-chunk while this one is walked
+#pragma unroll
+        for (int i = 0; i < SCH; ++i)
+            keys[i] = fetch_key(B, st + (uint32_t)(c0 + SPAN + 64 * i), lane, len - c0 - SPAN - 64 * i);
+#pragma unroll
+        for (int i = 0; i < SCH; ++i)
+            publish_chunk(r[i], lane < n - 64 * i, lane, fx0, fy0, s_e + 64 * i, s_m[i]);
+        wave_lds_sync();
+        if (!done) {
+            int ch = 0;
+            uint64_t m = s_m[0][lx] & s_m[0][8 + ly];
+            while (true) {
+                while (m == 0ull && ch + 1 < nch) {
+                    ++ch;
+                    m = s_m[ch][lx] & s_m[ch][8 + ly];
+                }
+                if (m == 0ull) break;
+                const int e0 = ch * 64 + (int)__builtin_ctzll(m);
+                m &= m - 1ull;
+                while (m == 0ull && ch + 1 < nch) {
+                    ++ch;
+                    m = s_m[ch][lx] & s_m[ch][8 + ly];
+                }
+                const bool two = m != 0ull;
+                const int e1 = two ? ch * 64 + (int)__builtin_ctzll(m) : e0;
+                if (two) m &= m - 1ull;
+                const float4 eu0 = s_e[e0][0], eg0 = s_e[e0][1];
+                const float4 eu1 = s_e[e1][0], eg1 = s_e[e1][1];
+                const float dx0 = (fpx - eu0.x) - eu0.z, dy0 = (fpy - eu0.y) - eu0.w;
+                const float dx1 = (fpx - eu1.x) - eu1.z, dy1 = (fpy - eu1.y) - eu1.w;
+                const float q0 = pair_q(dx0, dy0, eg0.x, eg0.y, eg0.z);
+                const float q1 = pair_q(dx1, dy1, eg1.x, eg1.y, eg1.z);
+                const float al0 = fminf(kAlphaMax, eg0.w * gauss_of_q(q0));
+                const float al1 = fminf(kAlphaMax, eg1.w * gauss_of_q(q1));
+                if (q0 <= kQCut && al0 >= kAlphaMin) {
+                    const float test = T * (1.f - al0);
+                    if (test < kTMin) {
+                        done = true;
+                        break;
+                    }
+                    const float w = al0 * T;
+                    const float4 c = s_e[e0][2];
+                    cr += w * c.x;
+                    cg += w * c.y;
+                    cb += w * c.z;
+                    dd += w * c.w;
+                    T = test;
+                    ++cnt;
+                    last = (uint32_t)(c0 + e0 + 1);
+                }
+                if (two && q1 <= kQCut && al1 >= kAlphaMin) {
+                    const float test = T * (1.f - al1);
+                    if (test < kTMin) {
+                        done = true;
+                        break;
+                    }
+                    const float w = al1 * T;
+                    const float4 c = s_e[e1][2];
+                    cr += w * c.x;
+                    cg += w * c.y;
+                    cb += w * c.z;
+                    dd += w * c.w;
+                    T = test;
+                    ++cnt;
+                    last = (uint32_t)(c0 + e1 + 1);
+                }
+            }
+        }
+        if (__ballot(!done) == 0ull) break;
+        wave_lds_sync();
     }
     if (!inside) return;
     const size_t pix = (size_t)py * G.Wv + px;
@@ -263,7 +399,16 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     const int sub = lane & (SUB - 1), grp = lane / SUB;
     float S0 = 0.f, S1 = 0.f, S2 = 0.f, SD = 0.f;
     float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    lds_fence();
+    wave_lds_sync();
+    // the view's focal lengths (every pair of a job shares the view)
+    float vfx, vfy;
+    {
+        const uint64_t has = __ballot(lane < G.n_kf && s_pof[lane] >= 0);
+        const int f0 = has != 0ull ? (int)__builtin_ctzll(has) : 0;
+        const PairConst& pc0 = B.pairs[max(0, s_pof[f0])];
+        vfx = (float)pc0.vfx;
+        vfy = (float)pc0.vfy;
+    }
     // chunks c0 = top, top - 64, ..., 0; every chunk below the top one is full
     const int top = maxlast > 0 ? ((maxlast - 1) & ~63) : -1;
     ChunkRegs cur{}, nxt{};
@@ -275,7 +420,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     for (int c0 = top; c0 >= 0; c0 -= 64) {
         const int n = min(64, maxlast - c0);
         publish_chunk(cur, lane < n, lane, fx0, fy0, s_e, s_m);
-        lds_fence();
+        wave_lds_sync();
         // gather ahead: records of the next chunk, keys of the one after
         if (c0 >= 64) fetch_record<true>(G, B, s_pof, true, nxt);
         const uint64_t key2 = c0 >= 128 ? B.keys[st + (uint32_t)(c0 - 128 + lane)] : 0ull;
@@ -326,9 +471,11 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 if (two && q1 <= kQCut && al1 >= kAlphaMin) contribute(al1, raw1, ec1, b1);
             }
             const uint64_t pm0 = __ballot(wrote);
-            lds_fence();
-            // phase B: lane = entry s * SUB + sub, pixel group grp, two pixels per round
+            wave_lds_sync();
+            // phase B: lane = entry s * SUB + sub, pixel group grp, two pixels per
+            // round; (dx, dy) from the tile-local pixel and the entry's mean
             const float4 eu0 = s_e[s * SUB + sub][0];
+            const float mxl = (eu0.x - fx0) + eu0.z, myl = (eu0.y - fy0) + eu0.w;
             float a[10];
 #pragma unroll
             for (int k = 0; k < 10; ++k) a[k] = 0.f;
@@ -354,9 +501,8 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 }
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int p = pp[h];
-                    const float dx = ((float)(ti.tx * 8 + (p & 7)) - eu0.x) - eu0.z;
-                    const float dy = ((float)(ti.ty * 8 + (p >> 3)) - eu0.y) - eu0.w;
+                    const float dx = (float)(pp[h] & 7) - mxl;
+                    const float dy = (float)(pp[h] >> 3) - myl;
                     a[0] += gv[h].x * mv[h].x;
                     a[1] += gv[h].y * mv[h].x;
                     a[2] += gv[h].z * mv[h].x;
@@ -377,7 +523,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
             if (grp == s)
 #pragma unroll
                 for (int k = 0; k < 10; ++k) r[k] = a[k];
-            lds_fence();
+            wave_lds_sync();
         }
         // lane = chunk entry: chain rule to the keyframe parameters and the pose
         if (lane < n) {
@@ -400,12 +546,12 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 const uint32_t gid = (uint32_t)cur.key;
                 const int kf = (int)(gid / (uint32_t)G.N);
                 const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
-                chain_rule(G, A, B.pairs[s_pof[kf]], kf, pix, cur.r0.x, cur.r0.y, cur.r2.w, cur.r3, v, pose);
+                chain_rule(G, A, vfx, vfy, kf, pix, cur.r2.w, cur.r3, cur.d, v, pose);
             }
         }
         cur = nxt;
         nxt.key = key2;
-        lds_fence();
+        wave_lds_sync();
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -414,9 +560,13 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     }
 }
 
-bool launch_fwd8(const Geometry& G, const RenderBufs& B, const FwdOut& O, hipStream_t s) {
+bool launch_fwd8(const Geometry& G, const RenderBufs& B, const FwdOut& O, int sch, hipStream_t s) {
     if (G.TW != 8 || G.TH != 8) return false;
-    hipLaunchKernelGGL(k_fwd8, dim3(G.n_jobs * G.ntiles), dim3(64), 0, s, G, B, O);
+    const dim3 grid(G.n_jobs * G.ntiles), block(64);
+    if (sch == 1) hipLaunchKernelGGL(k_fwd8, grid, block, 0, s, G, B, O);
+    else if (sch == 2) hipLaunchKernelGGL((k_fwd8s<2>), grid, block, 0, s, G, B, O);
+    else if (sch == 4) hipLaunchKernelGGL((k_fwd8s<4>), grid, block, 0, s, G, B, O);
+    else return false;
     return true;
 }
 

@@ -58,20 +58,23 @@ __device__ __forceinline__ const float4* entry_record(const Geometry& G, const R
     return B.pre.rec + 4 * ((size_t)pair * G.N + pix);
 }
 
+// Device-scope float add on global memory, without return.  The pointer is
+// taken as a global address so the atomic counts only against the vector
+// memory counter (a generic-address atomic also holds the LDS counter, which
+// every LDS wait would then wait on).
+__device__ __forceinline__ void global_add(float* p, float v) {
+    using gfloat = __attribute__((address_space(1))) float;
+    __hip_atomic_fetch_add((gfloat*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Chain rule of one (Gaussian, tile) gradient to the keyframe parameters and
 // the view pose.  v = [g_mx, g_my, g_a, g_b, g_c, g_o, g_z, g_c0, g_c1, g_c2];
-// (u, v) the keyframe pixel, z the view depth and r3 = [x, y, r, sign] of the
-// Gaussian's record.
-__device__ __forceinline__ void chain_rule(const Geometry& G, const BwdArgs& A, const PairConst& pc, int kf,
-                                           int pix, float ku, float kv, float z, float4 r3, const float* v,
-                                           float* pose) {
+// (fx, fy) the view's focal lengths, z the view depth, r3 = [x, y, r, sign]
+// and d the offset direction of the Gaussian's preprocessed data.
+__device__ __forceinline__ void chain_rule(const Geometry& G, const BwdArgs& A, float fx, float fy, int kf,
+                                           int pix, float z, float4 r3, float4 d, const float* v, float* pose) {
     const float x = r3.x, y = r3.y;
     const float r = r3.z;
-    const float sgn = r3.w;
-    const float xn = (ku - (float)pc.kcx) / (float)pc.kfx;
-    const float yn = (kv - (float)pc.kcy) / (float)pc.kfy;
-    const float* R = pc.Rf;
-    const float fx = (float)pc.vfx, fy = (float)pc.vfy;
     const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz, iz4 = iz2 * iz2, iz5 = iz4 * iz;
     const float tx = x * iz, ty = y * iz, jx = fx * iz, jy = fy * iz;
     const float k00 = jx * jx * (1.f + tx * tx), k01 = jx * jy * (tx * ty), k11 = jy * jy * (1.f + ty * ty);
@@ -101,17 +104,14 @@ __device__ __forceinline__ void chain_rule(const Geometry& G, const BwdArgs& A, 
     pose[5] += x * gy - y * gx;
     const bool learn = kf < 32 ? ((A.learn_lo >> kf) & 1u) : ((A.learn_hi >> (kf - 32)) & 1u);
     if (!learn) return;
-    const float gxf = R[0] * gx + R[3] * gy + R[6] * gz;
-    const float gyf = R[1] * gx + R[4] * gy + R[7] * gz;
-    const float gzf = R[2] * gx + R[5] * gy + R[8] * gz;
-    const float g_off = (gxf * xn + gyf * yn + gzf) * sgn;
+    const float g_off = gx * d.x + gy * d.y + gz * d.z;
     const KfGradPtrs gp = A.grads[kf];
-    atomicAdd(&gp.d_offset[pix], g_off);
-    atomicAdd(&gp.d_radius[pix], g_r);
-    atomicAdd(&gp.d_opacity[pix], v[5]);
-    atomicAdd(&gp.d_rgb[pix], v[7]);
-    atomicAdd(&gp.d_rgb[(size_t)G.N + pix], v[8]);
-    atomicAdd(&gp.d_rgb[2 * (size_t)G.N + pix], v[9]);
+    global_add(&gp.d_offset[pix], g_off);
+    global_add(&gp.d_radius[pix], g_r);
+    global_add(&gp.d_opacity[pix], v[5]);
+    global_add(&gp.d_rgb[pix], v[7]);
+    global_add(&gp.d_rgb[(size_t)G.N + pix], v[8]);
+    global_add(&gp.d_rgb[2 * (size_t)G.N + pix], v[9]);
 }
 
 // The same, reading the record of the instance `key` of job `job`.
@@ -121,9 +121,10 @@ __device__ __forceinline__ void flush_entry(const Geometry& G, const RenderBufs&
     const int kf = (int)(gid / (uint32_t)G.N);
     const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
     const int pair = B.pair_of[job * G.n_kf + kf];
-    const float4* rec = B.pre.rec + 4 * ((size_t)pair * G.N + pix);
-    const float4 r0 = rec[0];
-    chain_rule(G, A, B.pairs[pair], kf, pix, r0.x, r0.y, rec[2].w, rec[3], v, pose);
+    const size_t i = (size_t)pair * G.N + pix;
+    const float4* rec = B.pre.rec + 4 * i;
+    const PairConst& pc = B.pairs[pair];
+    chain_rule(G, A, (float)pc.vfx, (float)pc.vfy, kf, pix, rec[2].w, rec[3], B.pre.dir[i], v, pose);
 }
 
 // Spread consecutive workgroups over the XCDs in contiguous ranges: the
@@ -137,6 +138,10 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return base + k;
 }
 
-__device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+// Order one wavefront's LDS accesses around this point (workgroups of one
+// wavefront: no other wave shares the LDS data): the compiler may not move
+// memory accesses across it, and the wave waits for its outstanding LDS
+// operations.  Global memory operations are not waited for.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 }  // namespace sgad

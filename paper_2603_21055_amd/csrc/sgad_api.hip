@@ -13,6 +13,7 @@
 namespace sgad {
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+void launch_zero2_u32(uint32_t* a, int64_t na, uint32_t* b, int64_t nb, hipStream_t s);
 void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s);
 void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s);
 void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s);
@@ -65,6 +66,7 @@ struct sgad_saved {
     // device buffers (grow-only)
     DevBuf params, pre, tiles, keys, pix, pose_part, status, gradptrs;
     uint32_t capacity = 0;
+    uint32_t last_max_seg = 0xffffffffu;  // longest segment seen by the last finished forward
     bool sized = false;
     size_t size_key[5] = {0, 0, 0, 0, 0};  // workload the capacity was sized for
     // pinned staging
@@ -113,12 +115,12 @@ struct sgad_ctx {
     // configuration used while measuring
     struct TuneEntry {
         size_t key[6];
-        int tw, th, scb;
+        int tw, th, scf, scb;
         float ms;
     };
     std::vector<TuneEntry> tune;
     bool force = false;
-    int ftw = 8, fth = 8, fscb = 16;
+    int ftw = 8, fth = 8, fscf = 4, fscb = 16;
     std::vector<sgad_saved*> slots;
     KernelTimer timer;
     // stream capture of library calls into a graph (sgad_graph_begin/end)
@@ -352,6 +354,7 @@ void poll(sgad_ctx* c, bool block) {
         s->status_pending = false;
         const DevStatus st = *s->status_h;
         latch_status(c, st);
+        s->last_max_seg = st.max_seg;
         if (st.overflow || (st.sticky & 1u) || st.total > s->capacity - s->capacity / 8)
             s->sized = false;  // re-size on the next forward
     }
@@ -566,10 +569,11 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     poll(c, false);
     const bool cap = c->capture.on;
 
-    int TW = c->tile_w, TH = c->tile_h, SCB = 16;
+    int TW = c->tile_w, TH = c->tile_h, SCF = 4, SCB = 16;
     if (c->force) {
         TW = c->ftw;
         TH = c->fth;
+        SCF = c->fscf;
         SCB = c->fscb;
     } else if (TW == 0) {
         const size_t key[6] = {(size_t)vcam[0].H, (size_t)vcam[0].W, (size_t)N, (size_t)n_pairs, (size_t)n_jobs,
@@ -580,6 +584,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
             if (std::memcmp(e.key, key, sizeof(key)) == 0) {
                 TW = e.tw;
                 TH = e.th;
+                SCF = e.scf;
                 SCB = e.scb;
             }
     }
@@ -612,6 +617,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     G.ntx = (G.Wv + TW - 1) / TW;
     G.nty = (G.Hv + TH - 1) / TH;
     G.ntiles = G.ntx * G.nty;
+    G.sc_fwd = SCF;
     G.sc_bwd = SCB;
     S->stream = s;
     c->last_tw = TW;
@@ -673,15 +679,20 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
 
     // workspace
     const size_t PJ = (size_t)n_jobs * G.P;
-    HIPCHK(c, ensure_c(c, S->pre, NP * 76 + 256, s));
+    HIPCHK(c, ensure_c(c, S->pre, NP * 92 + 256, s));
     HIPCHK(c, ensure_c(c, S->tiles, (3 * M + 1) * 4 + 256, s));
     HIPCHK(c, ensure_c(c, S->pix, PJ * 8, s));
     HIPCHK(c, ensure_c(c, S->pose_part, M * 6 * 4, s));
     HIPCHK(c, ensure_c(c, S->status, sizeof(DevStatus), s));
     if (std::memcmp(size_key, S->size_key, sizeof(size_key)) != 0) {
         S->sized = false;
+        S->last_max_seg = 0xffffffffu;
         std::memcpy(S->size_key, size_key, sizeof(size_key));
     }
+    // the long-segment sort pass only when the last forward of this workload
+    // had a segment over 1024 keys (or is unknown); else the register sort
+    // falls back to a global-memory network for any segment that grew past it
+    G.sort_long = S->last_max_seg > 1024u ? 1 : 0;
     if (!S->sized && S->capacity == 0) {
         // first use: a generous guess that is corrected after the count pass
         const size_t guess = NP * 3 + 65536;
@@ -696,9 +707,10 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     B.pair_of = (const int32_t*)(pb + o_pof);
     char* pp = (char*)S->pre.p;
     B.pre.rec = (float4*)pp;
-    B.pre.z = (float*)(pp + (size_t)NP * 64);
-    B.pre.rx = (uint32_t*)(pp + (size_t)NP * 68);
-    B.pre.ry = (uint32_t*)(pp + (size_t)NP * 72);
+    B.pre.dir = (float4*)(pp + (size_t)NP * 64);
+    B.pre.z = (float*)(pp + (size_t)NP * 80);
+    B.pre.rx = (uint32_t*)(pp + (size_t)NP * 84);
+    B.pre.ry = (uint32_t*)(pp + (size_t)NP * 88);
     uint32_t* tb = (uint32_t*)S->tiles.p;
     B.tile_count = tb;
     B.tile_fill = tb + M;
@@ -711,8 +723,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
 
     {
         TimeScope ts(c, "zero", s);
-        launch_zero_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, s);
-        launch_zero_u32(B.tile_count, (int64_t)M, s);
+        launch_zero2_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, B.tile_count, (int64_t)M, s);
     }
     {
         TimeScope ts(c, "preprocess", s);
@@ -860,8 +871,7 @@ sgad_status sgad_l1_loss(sgad_ctx* c, int n_jobs, int H, int W, const float* rgb
     HIPCHK(c, ensure_c(c, c->scratch, (size_t)n_jobs * 4, s));
     uint32_t* cnt = (uint32_t*)c->scratch.p;
     TimeScope ts(c, "l1_loss", s);
-    launch_zero_u32(cnt, n_jobs, s);
-    launch_zero_u32((uint32_t*)loss, 2 * (int64_t)n_jobs, s);
+    launch_zero2_u32(cnt, n_jobs, (uint32_t*)loss, 2 * (int64_t)n_jobs, s);
     launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, g_rgb, g_depth, loss, s);
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
@@ -1127,7 +1137,7 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
         latch_status(c, *T.status_h);
     }
     HIPCHK(c, ensure(T.params, 1024, s));
-    HIPCHK(c, ensure(T.pre, (size_t)N * 76 + 256, s));
+    HIPCHK(c, ensure(T.pre, (size_t)N * 92 + 256, s));
     HIPCHK(c, ensure(T.tiles, (3 * M + 1) * 4 + 256, s));
     HIPCHK(c, ensure(T.part, M * 32 * 4, s));
     HIPCHK(c, ensure(T.status, sizeof(DevStatus), s));
@@ -1140,9 +1150,10 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     B.pair_of = (const int32_t*)(pb + 768);
     char* pp = (char*)T.pre.p;
     B.pre.rec = (float4*)pp;
-    B.pre.z = (float*)(pp + (size_t)N * 64);
-    B.pre.rx = (uint32_t*)(pp + (size_t)N * 68);
-    B.pre.ry = (uint32_t*)(pp + (size_t)N * 72);
+    B.pre.dir = (float4*)(pp + (size_t)N * 64);
+    B.pre.z = (float*)(pp + (size_t)N * 80);
+    B.pre.rx = (uint32_t*)(pp + (size_t)N * 84);
+    B.pre.ry = (uint32_t*)(pp + (size_t)N * 88);
     uint32_t* tb = (uint32_t*)T.tiles.p;
     B.tile_count = tb;
     B.tile_fill = tb + M;
@@ -1268,9 +1279,10 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
         grads[f] = sgad_kf_grads{g, g + 3 * N, g + 4 * N, g + 5 * N};
     }
     struct Cand {
-        int tw, th, scb;
+        int tw, th, scf, scb;
     };
-    const Cand cands[] = {{16, 16, 0}, {16, 8, 0}, {32, 8, 0}, {8, 8, 16}, {8, 8, 32}};
+    const Cand cands[] = {{16, 16, 0, 0}, {16, 8, 0, 0}, {32, 8, 0, 0}, {8, 8, 4, 16},
+                          {8, 8, 1, 16},  {8, 8, 2, 16}, {8, 8, 4, 32}};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -1281,6 +1293,7 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
         c->force = true;
         c->ftw = cd.tw;
         c->fth = cd.th;
+        c->fscf = cd.scf ? cd.scf : 4;
         c->fscb = cd.scb ? cd.scb : 16;
         float ms_tot = 0.f;
         for (int r = 0; r <= reps && rs == SGAD_OK; ++r) {  // r == 0 is a warm-up
@@ -1315,6 +1328,7 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
         std::memcpy(te.key, key, sizeof(key));
         te.tw = bc.tw;
         te.th = bc.th;
+        te.scf = bc.scf ? bc.scf : 4;
         te.scb = bc.scb ? bc.scb : 16;
         te.ms = best;
         bool found = false;

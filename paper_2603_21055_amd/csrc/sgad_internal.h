@@ -52,6 +52,7 @@ struct DevStatus {
     uint32_t nonfinite;  // a non-finite input was seen
     uint32_t queue;      // work-queue counter of persistent kernels
     uint32_t sticky;     // bit 0: an overflow, bit 1: a non-finite input, since the call began
+    uint32_t max_seg;    // longest (job, tile) instance list of the call
 };
 
 // Preprocessed per (pair, Gaussian) data.  rec holds one 64-byte record per
@@ -62,6 +63,7 @@ struct DevStatus {
 // depth, (x, y) the view-space centre, r the radius.
 struct Preproc {
     float4* rec;   // [n_pairs * N * 4]
+    float4* dir;   // [n_pairs * N]: d(view-space centre)/d(offset) = sign(D + delta) R_rel (xn, yn, 1), 0
     uint32_t* rx;  // tile x0 | x1 << 16
     uint32_t* ry;  // tile y0 | y1 << 16
     float* z;      // view depth (float), the sort key source
@@ -72,6 +74,8 @@ struct Geometry {
     int Hk, Wk, N;        // keyframe size, N = Hk * Wk
     int Hv, Wv, P;        // view size
     int TW, TH, ntx, nty, ntiles;
+    int sc_fwd = 4;    // 64-entry chunks the 8x8 forward publishes at once (1, 2 or 4)
+    int sort_long = 1; // run the long-segment sort pass (else the register sort takes all)
     int sc_bwd = 16;   // backward sub-chunk of the 8x8 kernels (16 or 32 entries)
 };
 

@@ -167,6 +167,31 @@ def test_long_lists_sort_bit_exact(ctx, fac, tile, lo, hi):
     ctx.release(saved)
 
 
+def test_long_lists_sorted_without_the_long_pass(ctx):
+    """The long-segment pass runs only when the previous forward of the same
+    workload had a segment over 1024 keys; a segment that grows past it in
+    between is sorted by the register kernel's global-memory fallback."""
+    import torch
+    print("long lists: fallback sort", flush=True)
+    ctx.set_tile(8, 8)
+    short = _wide_scene(1)      # every list <= 768 keys
+    saved, _ = H.gpu_render(ctx, H.upload(short["kfs"], ctx.device), short["views"], [(0, [0, 1, 2])])
+    ctx.release(saved)
+    ctx.sync()                  # the slot now knows its longest segment
+    sc = _wide_scene(4)         # same sizes, lists of 1242-3325 keys
+    saved, _ = H.gpu_render(ctx, H.upload(sc["kfs"], ctx.device), sc["views"], [(0, [0, 1, 2])])
+    torch.cuda.synchronize()
+    ranges, keys = ctx.instances(saved, 0)
+    g = splat.gather_job(sc["kfs"], sc["views"][0], [0, 1, 2])
+    b = splat.bin_and_sort(g, 48, 32, 8, 8)
+    assert (b["ranges"][:, 1] - b["ranges"][:, 0]).max() > 1024
+    assert np.array_equal(ranges.astype(np.int64), b["ranges"])
+    assert np.array_equal((keys >> np.uint64(32)).astype(np.uint32), b["zbits"])
+    assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.int64), b["gid"])
+    ctx.release(saved)
+    ctx.sync()
+
+
 @pytest.mark.parametrize("fac", [1, 4])
 def test_long_lists_render_parity(ctx, fac):
     """Faint wide Gaussians: hundreds of contributors per pixel, so the walks
