@@ -345,9 +345,9 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
 //  A (lane = pixel): the reverse walk over the pixel's candidates carries the
 //    transmittance and the suffix colour sums and stores, per contributing
 //    pair, w = alpha T and gq = dL/dq into a [pixel][entry] LDS matrix;
-//  B (lane = entry, 64 / SUB pixel groups): every lane sums its entry's pairs
-//    over the pixels of its group that wrote anything in the sub-chunk, and
-//    clears what it read.
+//  B (lane = entry, 64 / SUB lanes per entry): 64-bit ballots turn the
+//    per-pixel contribution masks into per-entry pixel sets, and each lane sums
+//    its entry's pairs over the contributing pixels of its columns.
 // The per-entry sums are gq-weighted moments of (dx, dy) and gradient-weighted
 // sums of w; the conic enters after the sum.  No LDS location is written by two
 // lanes at once, and the in-tile summation order is fixed.  After a chunk, lane
@@ -355,12 +355,12 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
 template <int SUB>
 __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A) {
     constexpr int NS = 64 / SUB;        // sub-chunks per chunk = pixel groups in phase B
-    constexpr int LS = 2 * SUB + 4;     // floats per matrix row: 16-byte rows, rows 4 banks apart
+    constexpr int LS = 2 * SUB + 2;     // floats per matrix row: rows 2 banks apart
     __shared__ float4 s_e[64][3];
     __shared__ uint64_t s_m[16];
-    __shared__ float4 s_pc[65];
+    __shared__ float4 s_pc[64];
     __shared__ int s_pof[64];
-    __shared__ __align__(16) float s_M[65 * LS];   // row 64 stays zero: the idle pixel of phase B
+    __shared__ __align__(16) float s_M[64 * LS];   // [pixel][entry] (w, gq); a cell is read only if written
     const int lane = threadIdx.x;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     if (item >= G.n_jobs * G.ntiles) return;
@@ -386,10 +386,6 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
         if (A.g_alpha) gA = A.g_alpha[jp];
     }
     s_pc[lane] = make_float4(gC0, gC1, gC2, gD);
-    if (lane == 0) s_pc[64] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int k = 0; k < LS; k += 4) *(float4*)&s_M[lane * LS + k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (lane < LS / 4) *(float4*)&s_M[64 * LS + lane * 4] = make_float4(0.f, 0.f, 0.f, 0.f);
     int maxlast = last;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, o, 64));
@@ -435,7 +431,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
             // two candidates per round (their q, alpha evaluations are independent)
             const int cut = lim - s * SUB;
             uint32_t m = cut <= 0 ? 0u : (uint32_t)((mine >> (s * SUB)) & low_bits(min(cut, SUB)));
-            bool wrote = false;
+            uint32_t cmask = 0u;   // entries of the sub-chunk this pixel contributed to
             auto contribute = [&](float alpha, float raw, float4 c, int bit) {
                 const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
                 T = T * inv;
@@ -448,7 +444,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 SD += w * c.w;
                 const float gq = raw < kAlphaMax ? -0.5f * alpha * gal : 0.f;
                 *(float2*)&s_M[lane * LS + 2 * bit] = make_float2(w, gq);
-                wrote = true;
+                cmask |= 1u << bit;
             };
             while (m != 0u) {
                 const int b0 = 31 - (int)__builtin_clz(m);
@@ -470,51 +466,42 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 if (q0 <= kQCut && al0 >= kAlphaMin) contribute(al0, raw0, ec0, b0);
                 if (two && q1 <= kQCut && al1 >= kAlphaMin) contribute(al1, raw1, ec1, b1);
             }
-            const uint64_t pm0 = __ballot(wrote);
-            wave_lds_sync();
-            // phase B: lane = entry s * SUB + sub, pixel group grp, two pixels per
-            // round; (dx, dy) from the tile-local pixel and the entry's mean
+            // transpose the contributions: lane (grp, sub) keeps the pixel set
+            // of entry `sub` (one ballot per entry, selected in registers)
+            uint64_t emask = 0ull;
+#pragma unroll
+            for (int e = 0; e < SUB; ++e) {
+                const uint64_t me = __ballot((cmask >> e) & 1u);
+                emask = sub == e ? me : emask;
+            }
+            // phase B: lane = entry s * SUB + sub; the NS lanes of an entry
+            // split its contributing pixels by column (x mod NS), and each
+            // walks only the cells phase A wrote
             const float4 eu0 = s_e[s * SUB + sub][0];
             const float mxl = (eu0.x - fx0) + eu0.z, myl = (eu0.y - fy0) + eu0.w;
+            constexpr uint64_t kCols = NS == 4 ? 0x1111111111111111ull : (NS == 2 ? 0x5555555555555555ull : ~0ull);
             float a[10];
 #pragma unroll
             for (int k = 0; k < 10; ++k) a[k] = 0.f;
-            uint64_t pm = pm0;
+            uint64_t pm = emask & (kCols << grp);
             while (pm != 0ull) {
-                int pp[2] = {64, 64};
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int g = 0; g < NS; ++g) {
-                        const int pg = pm != 0ull ? (int)__builtin_ctzll(pm) : 64;
-                        pm &= pm - 1ull;
-                        pp[h] = g == grp ? pg : pp[h];
-                    }
-                float2 mv[2];
-                float4 gv[2];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    float2* cell = (float2*)&s_M[pp[h] * LS + 2 * sub];
-                    mv[h] = *cell;
-                    gv[h] = s_pc[pp[h]];
-                    *cell = make_float2(0.f, 0.f);
-                }
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const float dx = (float)(pp[h] & 7) - mxl;
-                    const float dy = (float)(pp[h] >> 3) - myl;
-                    a[0] += gv[h].x * mv[h].x;
-                    a[1] += gv[h].y * mv[h].x;
-                    a[2] += gv[h].z * mv[h].x;
-                    a[3] += gv[h].w * mv[h].x;
-                    a[4] += mv[h].y;
-                    const float u = mv[h].y * dx, v = mv[h].y * dy;
-                    a[5] += u;
-                    a[6] += v;
-                    a[7] += u * dx;
-                    a[8] += u * dy;
-                    a[9] += v * dy;
-                }
+                const int p = (int)__builtin_ctzll(pm);
+                pm &= pm - 1ull;
+                const float2 mv = *(const float2*)&s_M[p * LS + 2 * sub];
+                const float4 gv = s_pc[p];
+                const float dx = (float)(p & 7) - mxl;
+                const float dy = (float)(p >> 3) - myl;
+                a[0] += gv.x * mv.x;
+                a[1] += gv.y * mv.x;
+                a[2] += gv.z * mv.x;
+                a[3] += gv.w * mv.x;
+                a[4] += mv.y;
+                const float u = mv.y * dx, v = mv.y * dy;
+                a[5] += u;
+                a[6] += v;
+                a[7] += u * dx;
+                a[8] += u * dy;
+                a[9] += v * dy;
             }
 #pragma unroll
             for (int o = SUB; o < 64; o <<= 1)
