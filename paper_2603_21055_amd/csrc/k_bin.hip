@@ -216,16 +216,17 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 // work-queue counter.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ count, uint32_t* start,
-                                               uint32_t* fill, int M, uint32_t capacity,
+                                               uint32_t* fill, uint32_t* cstart, int M, uint32_t capacity,
                                                DevStatus* st) {
-    __shared__ uint32_t s_wave[16];
+    __shared__ uint32_t s_wave[16], s_cw[16];
     const int tid = threadIdx.x;
     const int chunk = (M + 1023) / 1024;
     const int b = tid * chunk;
     const int e = min(M, b + chunk);
-    uint32_t sum = 0, mx = 0;
+    uint32_t sum = 0, mx = 0, csum = 0;
     for (int k = b; k < e; ++k) {
         sum += count[k];
+        csum += (count[k] + 63u) >> 6;
         mx = max(mx, count[k]);
     }
 #pragma unroll
@@ -233,33 +234,52 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ coun
     __shared__ uint32_t s_max[16];
     // inclusive scan across the wave
     const int lane = tid & 63, wave = tid >> 6;
-    uint32_t inc = sum;
+    uint32_t inc = sum, cinc = csum;
     for (int off = 1; off < 64; off <<= 1) {
         uint32_t o = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += o;
+        uint32_t co = __shfl_up(cinc, off, 64);
+        if (lane >= off) {
+            inc += o;
+            cinc += co;
+        }
     }
-    if (lane == 63) s_wave[wave] = inc;
+    if (lane == 63) {
+        s_wave[wave] = inc;
+        s_cw[wave] = cinc;
+    }
     if (lane == 0) s_max[wave] = mx;
     __syncthreads();
     if (wave == 0) {
         uint32_t w = lane < 16 ? s_wave[lane] : 0u;
-        uint32_t wi = w;
+        uint32_t cw = lane < 16 ? s_cw[lane] : 0u;
+        uint32_t wi = w, cwi = cw;
         for (int off = 1; off < 16; off <<= 1) {
             uint32_t o = __shfl_up(wi, off, 64);
-            if (lane >= off) wi += o;
+            uint32_t co = __shfl_up(cwi, off, 64);
+            if (lane >= off) {
+                wi += o;
+                cwi += co;
+            }
         }
-        if (lane < 16) s_wave[lane] = wi - w;  // exclusive wave offsets
+        if (lane < 16) {
+            s_wave[lane] = wi - w;  // exclusive wave offsets
+            s_cw[lane] = cwi - cw;
+        }
     }
     __syncthreads();
     uint32_t run = s_wave[wave] + inc - sum;
+    uint32_t crun = s_cw[wave] + cinc - csum;
     for (int k = b; k < e; ++k) {
         start[k] = run;
+        cstart[k] = crun;
         run += count[k];
+        crun += (count[k] + 63u) >> 6;
         fill[k] = 0u;
     }
     if (tid == 1023) {
         const uint32_t tot = s_wave[wave] + inc;
         start[M] = tot;
+        cstart[M] = s_cw[wave] + cinc;
         st->total = tot;
         st->overflow = tot > capacity ? 1u : 0u;
         st->queue = 0u;
@@ -539,8 +559,8 @@ void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s) {
 
 void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s) {
     const int M = G.n_jobs * G.ntiles;
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, B.tile_count, B.tile_start, B.tile_fill, M,
-                       B.capacity, B.status);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, B.tile_count, B.tile_start, B.tile_fill,
+                       B.chunk_start, M, B.capacity, B.status);
 }
 
 void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s) {

@@ -27,7 +27,7 @@ __device__ __forceinline__ uint64_t low_bits(int k) { return k >= 64 ? ~0ull : (
 // One lane's share of a chunk, gathered from HBM: its entry's key and record.
 struct ChunkRegs {
     uint64_t key;
-    float4 r0, r1, r2, r3, d;
+    float4 r0, r1, r2;
 };
 
 // Key of entry `e` of the list starting at `base` (0 when e >= n).
@@ -35,10 +35,7 @@ __device__ __forceinline__ uint64_t fetch_key(const RenderBufs& B, uint32_t base
     return e < n ? B.keys[base + (uint32_t)e] : 0ull;
 }
 
-// Record of `key` (pair looked up in the job's pair table `pof`).  WITH_R3
-// also fetches [x, y, r, sign] and the offset direction, which only the
-// backward needs.
-template <bool WITH_R3>
+// Record of `key` (pair looked up in the job's pair table `pof`).
 __device__ __forceinline__ void fetch_record(const Geometry& G, const RenderBufs& B, const int* pof, bool valid,
                                              ChunkRegs& c) {
     if (!valid) return;
@@ -50,10 +47,6 @@ __device__ __forceinline__ void fetch_record(const Geometry& G, const RenderBufs
     c.r0 = rec[0];
     c.r1 = rec[1];
     c.r2 = rec[2];
-    if (WITH_R3) {
-        c.r3 = rec[3];
-        c.d = B.pre.dir[i];
-    }
 }
 
 // Publish a chunk in LDS (records and coverage masks).
@@ -81,6 +74,24 @@ __device__ __forceinline__ void publish_chunk(const ChunkRegs& c, bool valid, in
         if (lane == k) sm[k] = cm;
         if (lane == 8 + k) sm[8 + k] = rm;
     }
+}
+
+// The backward's gather of one record (separate values rather than a struct,
+// so that everything stays in registers).
+__device__ __forceinline__ void fetch_bwd(const Geometry& G, const RenderBufs& B, const int* pof, bool valid,
+                                          uint64_t key, float4& r0, float4& r1, float4& r2, float4& r3,
+                                          float4& d) {
+    if (!valid) return;
+    const uint32_t gid = (uint32_t)key;
+    const int kf = (int)(gid / (uint32_t)G.N);
+    const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
+    const size_t i = (size_t)pof[kf] * G.N + pix;
+    const float4* rec = B.pre.rec + 4 * i;
+    r0 = rec[0];
+    r1 = rec[1];
+    r2 = rec[2];
+    r3 = rec[3];
+    d = B.pre.dir[i];
 }
 
 // Tile coordinates of a work item and its pair table in LDS.
@@ -114,6 +125,7 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
     const bool ovf = B.status->overflow != 0u;
     const uint32_t st = B.tile_start[item];
     const int len = ovf ? 0 : (int)(B.tile_start[item + 1] - st);
+    const uint32_t cs = B.chunk_start[item];   // this tile's first contributor-mask chunk
     const float fpx = (float)px, fpy = (float)py;
     const float fx0 = (float)(ti.tx * 8), fy0 = (float)(ti.ty * 8);
     float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;
@@ -123,15 +135,16 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
     wave_lds_sync();
     ChunkRegs cur{}, nxt{};
     cur.key = fetch_key(B, st, lane, len);
-    fetch_record<false>(G, B, s_pof, lane < len, cur);
+    fetch_record(G, B, s_pof, lane < len, cur);
     nxt.key = fetch_key(B, st + 64u, lane, len - 64);
     for (int c0 = 0; c0 < len; c0 += 64) {
         const int n = min(64, len - c0);
         publish_chunk(cur, lane < n, lane, fx0, fy0, s_e, s_m);
         wave_lds_sync();
         // gather ahead: records of the next chunk, keys of the one after
-        fetch_record<false>(G, B, s_pof, lane < len - c0 - 64, nxt);
+        fetch_record(G, B, s_pof, lane < len - c0 - 64, nxt);
         const uint64_t key2 = fetch_key(B, st + (uint32_t)(c0 + 128), lane, len - c0 - 128);
+        uint64_t cm = 0ull;   // entries of this chunk the pixel takes
         if (!done) {
             uint64_t m = s_m[lx] & s_m[8 + ly];
             // two candidates per round: their q, alpha evaluations are independent
@@ -164,6 +177,7 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
                     T = test;
                     ++cnt;
                     last = (uint32_t)(c0 + b0 + 1);
+                    cm |= 1ull << b0;
                 }
                 if (two && q1 <= kQCut && al1 >= kAlphaMin) {
                     const float test = T * (1.f - al1);
@@ -180,9 +194,11 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
                     T = test;
                     ++cnt;
                     last = (uint32_t)(c0 + b1 + 1);
+                    cm |= 1ull << b1;
                 }
             }
         }
+        B.cmask[((size_t)cs + (size_t)(c0 >> 6)) * 64 + lane] = cm;
         if (__ballot(!done) == 0ull) break;
         cur = nxt;
         nxt.key = key2;
@@ -229,6 +245,7 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
     const bool ovf = B.status->overflow != 0u;
     const uint32_t st = B.tile_start[item];
     const int len = ovf ? 0 : (int)(B.tile_start[item + 1] - st);
+    const uint32_t cs = B.chunk_start[item];   // this tile's first contributor-mask chunk
     const float fpx = (float)px, fpy = (float)py;
     const float fx0 = (float)(ti.tx * 8), fy0 = (float)(ti.ty * 8);
     float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;
@@ -246,7 +263,7 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
 #pragma unroll
         for (int i = 0; i < SCH; ++i) {
             r[i].key = keys[i];
-            fetch_record<false>(G, B, s_pof, lane < n - 64 * i, r[i]);
+            fetch_record(G, B, s_pof, lane < n - 64 * i, r[i]);
         }
         // keys of the next super-chunk while this one is walked
 #pragma unroll
@@ -256,6 +273,9 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
         for (int i = 0; i < SCH; ++i)
             publish_chunk(r[i], lane < n - 64 * i, lane, fx0, fy0, s_e + 64 * i, s_m[i]);
         wave_lds_sync();
+        uint64_t cm[SCH];
+#pragma unroll
+        for (int i = 0; i < SCH; ++i) cm[i] = 0ull;
         if (!done) {
             int ch = 0;
             uint64_t m = s_m[0][lx] & s_m[0][8 + ly];
@@ -297,6 +317,8 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
                     T = test;
                     ++cnt;
                     last = (uint32_t)(c0 + e0 + 1);
+#pragma unroll
+                    for (int i = 0; i < SCH; ++i) cm[i] |= (e0 >> 6) == i ? 1ull << (e0 & 63) : 0ull;
                 }
                 if (two && q1 <= kQCut && al1 >= kAlphaMin) {
                     const float test = T * (1.f - al1);
@@ -313,9 +335,14 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
                     T = test;
                     ++cnt;
                     last = (uint32_t)(c0 + e1 + 1);
+#pragma unroll
+                    for (int i = 0; i < SCH; ++i) cm[i] |= (e1 >> 6) == i ? 1ull << (e1 & 63) : 0ull;
                 }
             }
         }
+#pragma unroll
+        for (int i = 0; i < SCH; ++i)
+            if (i < nch) B.cmask[((size_t)cs + (size_t)(c0 >> 6) + i) * 64 + lane] = cm[i];
         if (__ballot(!done) == 0ull) break;
         wave_lds_sync();
     }
@@ -357,7 +384,6 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     constexpr int NS = 64 / SUB;        // sub-chunks per chunk = pixel groups in phase B
     constexpr int LS = 2 * SUB + 2;     // floats per matrix row: rows 2 banks apart
     __shared__ float4 s_e[64][3];
-    __shared__ uint64_t s_m[16];
     __shared__ float4 s_pc[64];
     __shared__ int s_pof[64];
     __shared__ __align__(16) float s_M[64 * LS];   // [pixel][entry] (w, gq); a cell is read only if written
@@ -407,28 +433,39 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     }
     // chunks c0 = top, top - 64, ..., 0; every chunk below the top one is full
     const int top = maxlast > 0 ? ((maxlast - 1) & ~63) : -1;
-    ChunkRegs cur{}, nxt{};
+    // current and next chunk: key, record and offset direction of the lane's entry
+    uint64_t ck = 0ull, nk = 0ull;
+    float4 c0r, c1r, c2r, c3r, cdr, n0r, n1r, n2r, n3r, ndr;
+    const uint32_t cs = B.chunk_start[item];   // this tile's first contributor-mask chunk
+    uint64_t mine = 0ull, mine_nxt = 0ull;
     if (top >= 0) {
-        cur.key = fetch_key(B, st + (uint32_t)top, lane, maxlast - top);
-        fetch_record<true>(G, B, s_pof, lane < maxlast - top, cur);
-        if (top >= 64) nxt.key = B.keys[st + (uint32_t)(top - 64 + lane)];
+        ck = fetch_key(B, st + (uint32_t)top, lane, maxlast - top);
+        fetch_bwd(G, B, s_pof, lane < maxlast - top, ck, c0r, c1r, c2r, c3r, cdr);
+        mine = B.cmask[((size_t)cs + (size_t)(top >> 6)) * 64 + lane];
+        if (top >= 64) nk = B.keys[st + (uint32_t)(top - 64 + lane)];
     }
     for (int c0 = top; c0 >= 0; c0 -= 64) {
         const int n = min(64, maxlast - c0);
-        publish_chunk(cur, lane < n, lane, fx0, fy0, s_e, s_m);
+        if (lane < n) {
+            s_e[lane][0] = c0r;
+            s_e[lane][1] = c1r;
+            s_e[lane][2] = c2r;
+        }
         wave_lds_sync();
-        // gather ahead: records of the next chunk, keys of the one after
-        if (c0 >= 64) fetch_record<true>(G, B, s_pof, true, nxt);
+        // gather ahead: records and masks of the next chunk, keys of the one after
+        if (c0 >= 64) {
+            fetch_bwd(G, B, s_pof, true, nk, n0r, n1r, n2r, n3r, ndr);
+            mine_nxt = B.cmask[((size_t)cs + (size_t)((c0 - 64) >> 6)) * 64 + lane];
+        }
         const uint64_t key2 = c0 >= 128 ? B.keys[st + (uint32_t)(c0 - 128 + lane)] : 0ull;
-        const uint64_t mine = s_m[lx] & s_m[8 + ly];
         const int lim = min(n, last - c0);   // this pixel's entries are e < lim
         float r[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) r[k] = 0.f;
 #pragma unroll
         for (int s = NS - 1; s >= 0; --s) {
-            // phase A: reverse walk of this pixel's candidates in the sub-chunk,
-            // two candidates per round (their q, alpha evaluations are independent)
+            // phase A: reverse walk of this pixel's contributors in the sub-chunk
+            // (the forward's decisions), two per round
             const int cut = lim - s * SUB;
             uint32_t m = cut <= 0 ? 0u : (uint32_t)((mine >> (s * SUB)) & low_bits(min(cut, SUB)));
             uint32_t cmask = 0u;   // entries of the sub-chunk this pixel contributed to
@@ -463,8 +500,8 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 const float raw0 = eg0.w * gauss_of_q(q0);
                 const float raw1 = eg1.w * gauss_of_q(q1);
                 const float al0 = fminf(kAlphaMax, raw0), al1 = fminf(kAlphaMax, raw1);
-                if (q0 <= kQCut && al0 >= kAlphaMin) contribute(al0, raw0, ec0, b0);
-                if (two && q1 <= kQCut && al1 >= kAlphaMin) contribute(al1, raw1, ec1, b1);
+                contribute(al0, raw0, ec0, b0);
+                if (two) contribute(al1, raw1, ec1, b1);
             }
             // transpose the contributions: lane (grp, sub) keeps the pixel set
             // of entry `sub` (one ballot per entry, selected in registers)
@@ -518,7 +555,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
 #pragma unroll
             for (int k = 0; k < 10; ++k) any |= r[k] != 0.f;
             if (any) {
-                const float4 eg = cur.r1;
+                const float4 eg = c1r;
                 float v[10];
                 v[0] = -2.f * (eg.x * r[5] + eg.y * r[6]);
                 v[1] = -2.f * (eg.y * r[5] + eg.z * r[6]);
@@ -530,14 +567,20 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 v[7] = r[0];
                 v[8] = r[1];
                 v[9] = r[2];
-                const uint32_t gid = (uint32_t)cur.key;
+                const uint32_t gid = (uint32_t)ck;
                 const int kf = (int)(gid / (uint32_t)G.N);
                 const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
-                chain_rule(G, A, vfx, vfy, kf, pix, cur.r2.w, cur.r3, cur.d, v, pose);
+                chain_rule(G, A, vfx, vfy, kf, pix, c2r.w, c3r, cdr, v, pose);
             }
         }
-        cur = nxt;
-        nxt.key = key2;
+        ck = nk;
+        c0r = n0r;
+        c1r = n1r;
+        c2r = n2r;
+        c3r = n3r;
+        cdr = ndr;
+        nk = key2;
+        mine = mine_nxt;
         wave_lds_sync();
     }
 #pragma unroll

@@ -64,7 +64,7 @@ struct sgad_saved {
     Geometry G{};
     hipStream_t stream = nullptr;
     // device buffers (grow-only)
-    DevBuf params, pre, tiles, keys, pix, pose_part, status, gradptrs;
+    DevBuf params, pre, tiles, keys, pix, pose_part, status, gradptrs, cmask;
     uint32_t capacity = 0;
     uint32_t last_max_seg = 0xffffffffu;  // longest segment seen by the last finished forward
     bool sized = false;
@@ -436,7 +436,8 @@ sgad_saved* acquire_sized(sgad_ctx* c, const size_t* key) {
 }
 
 void free_slot(sgad_saved* s) {
-    for (DevBuf* b : {&s->params, &s->pre, &s->tiles, &s->keys, &s->pix, &s->pose_part, &s->status, &s->gradptrs})
+    for (DevBuf* b : {&s->params, &s->pre, &s->tiles, &s->keys, &s->pix, &s->pose_part, &s->status, &s->gradptrs,
+                      &s->cmask})
         if (b->p) (void)hipFree(b->p);
     for (PinBuf* b : {&s->up, &s->up_grad})
         if (b->p) (void)hipHostFree(b->p);
@@ -680,7 +681,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     // workspace
     const size_t PJ = (size_t)n_jobs * G.P;
     HIPCHK(c, ensure_c(c, S->pre, NP * 92 + 256, s));
-    HIPCHK(c, ensure_c(c, S->tiles, (3 * M + 1) * 4 + 256, s));
+    HIPCHK(c, ensure_c(c, S->tiles, (4 * M + 2) * 4 + 256, s));
     HIPCHK(c, ensure_c(c, S->pix, PJ * 8, s));
     HIPCHK(c, ensure_c(c, S->pose_part, M * 6 * 4, s));
     HIPCHK(c, ensure_c(c, S->status, sizeof(DevStatus), s));
@@ -715,8 +716,10 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     B.tile_count = tb;
     B.tile_fill = tb + M;
     B.tile_start = tb + 2 * M;
+    B.chunk_start = tb + 3 * M + 1;
     B.keys = (uint64_t*)S->keys.p;
     B.capacity = S->capacity;
+    B.cmask = nullptr;
     B.Tfinal = (float*)S->pix.p;
     B.last = (uint32_t*)((char*)S->pix.p + PJ * 4);
     B.status = (DevStatus*)S->status.p;
@@ -748,6 +751,10 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
         }
         S->sized = true;
     }
+    // contributor masks: one u64 per (64-entry chunk, pixel); at most
+    // capacity / 64 + M chunks
+    HIPCHK(c, ensure_c(c, S->cmask, ((size_t)S->capacity / 64 + M + 1) * 64 * 8, s));
+    B.cmask = (uint64_t*)S->cmask.p;
     {
         TimeScope ts(c, "scatter", s);
         launch_scatter(G, B, s);
@@ -1138,7 +1145,7 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     }
     HIPCHK(c, ensure(T.params, 1024, s));
     HIPCHK(c, ensure(T.pre, (size_t)N * 92 + 256, s));
-    HIPCHK(c, ensure(T.tiles, (3 * M + 1) * 4 + 256, s));
+    HIPCHK(c, ensure(T.tiles, (4 * M + 2) * 4 + 256, s));
     HIPCHK(c, ensure(T.part, M * 32 * 4, s));
     HIPCHK(c, ensure(T.status, sizeof(DevStatus), s));
     HIPCHK(c, ensure(T.trace, (size_t)iters * 40 * 8, s));
@@ -1158,6 +1165,8 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     B.tile_count = tb;
     B.tile_fill = tb + M;
     B.tile_start = tb + 2 * M;
+    B.chunk_start = tb + 3 * M + 1;
+    B.cmask = nullptr;
     B.status = (DevStatus*)T.status.p;
     B.Tfinal = nullptr;
     B.last = nullptr;

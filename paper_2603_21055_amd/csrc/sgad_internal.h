@@ -87,7 +87,9 @@ struct RenderBufs {
     uint32_t* tile_count;     // [n_jobs * ntiles]
     uint32_t* tile_start;     // [n_jobs * ntiles + 1]
     uint32_t* tile_fill;      // [n_jobs * ntiles]
+    uint32_t* chunk_start;    // [n_jobs * ntiles + 1]: exclusive scan of ceil(count / 64)
     uint64_t* keys;           // [capacity]
+    uint64_t* cmask;          // [chunks][64]: per 64-entry chunk and pixel, the contributing entries
     uint32_t capacity;
     float* Tfinal;            // [n_jobs * P]
     uint32_t* last;           // [n_jobs * P]
