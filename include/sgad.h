@@ -268,7 +268,9 @@ sgad_status sgad_l1_loss(sgad_ctx* ctx, int n_jobs, int H, int W,
                          float w_rgb, float w_depth, float* g_rgb, float* g_depth, double* loss,
                          void* stream);
 
-/* One parameter tensor for sgad_adam_step (all device pointers, n floats). */
+/* One parameter tensor for sgad_adam_step (all device pointers, n floats;
+ * the pointers may be null when n is 0).  Arrays that start on a 16-byte
+ * boundary are read and written four floats at a time. */
 typedef struct {
     float* param;
     float* grad;

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 
+#include "segsort.h"
 #include "sgad_internal.h"
 
 namespace sgad {
@@ -331,94 +332,6 @@ __global__ __launch_bounds__(256) void k_scatter(Geometry G, RenderBufs B) {
     if (__ballot(dropped) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&B.status->sticky, 1u);
 }
 
-// ---------------------------------------------------------------------------
-// Per-segment ascending sort of 64-bit keys, one wavefront per segment.
-// Segments up to 1024 keys are sorted in registers: K = 1..16 keys per lane,
-// key i = lane * K + r in register r, padded with all-ones keys to 64 K.  The
-// bitonic network takes every comparator ascending (the first step of each
-// merge pairs mirrored positions), so exchanges inside a lane are register
-// swaps and exchanges across lanes are one xor shuffle per key half.  Longer
-// segments are sorted by the same network in LDS (up to kSortLds keys) or in
-// place in global memory with virtual +inf padding.
-// ---------------------------------------------------------------------------
-constexpr int kSortLds = 4096;
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const int lo = __shfl_xor((int)(uint32_t)v, m, 64);
-    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-template <int K>
-__device__ __forceinline__ void sort_in_lane(uint64_t (&x)[K], int j) {
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-        const int p = r ^ j;
-        if (p > r) {
-            const uint64_t a = x[r], b = x[p];
-            x[r] = a < b ? a : b;
-            x[p] = a < b ? b : a;
-        }
-    }
-}
-
-template <int K>
-__device__ void wave_sort_segment(uint64_t* g, int n, int lane) {
-    uint64_t x[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-        const int i = lane * K + r;
-        x[r] = i < n ? g[i] : ~0ull;
-    }
-#pragma unroll
-    for (int k = 2; k <= 64 * K; k <<= 1) {
-        if (k <= K) {
-            // mirror step inside the lane: r <-> r ^ (k - 1)
-#pragma unroll
-            for (int r = 0; r < K; ++r) {
-                const int p = r ^ (k - 1);
-                if (p > r) {
-                    const uint64_t a = x[r], b = x[p];
-                    x[r] = a < b ? a : b;
-                    x[p] = a < b ? b : a;
-                }
-            }
-        } else {
-            // mirror step across lanes: (lane, r) <-> (lane ^ (k / K - 1), K - 1 - r),
-            // taken in register pairs (r, K - 1 - r)
-            const int lm = k / K - 1;
-            const bool lower = (lane & (k / (2 * K))) == 0;
-#pragma unroll
-            for (int r = 0; r < (K + 1) / 2; ++r) {
-                const int q = K - 1 - r;
-                const uint64_t ya = shfl_xor_u64(x[q], lm);
-                const uint64_t yb = shfl_xor_u64(x[r], lm);
-                x[r] = lower ? (x[r] < ya ? x[r] : ya) : (x[r] < ya ? ya : x[r]);
-                if (q != r) x[q] = lower ? (x[q] < yb ? x[q] : yb) : (x[q] < yb ? yb : x[q]);
-            }
-        }
-#pragma unroll
-        for (int j = k >> 2; j >= 1; j >>= 1) {
-            if (j < K) {
-                sort_in_lane<K>(x, j);
-            } else {
-                const int lm = j / K;
-                const bool lower = (lane & lm) == 0;
-#pragma unroll
-                for (int r = 0; r < K; ++r) {
-                    const uint64_t y = shfl_xor_u64(x[r], lm);
-                    x[r] = lower ? (x[r] < y ? x[r] : y) : (x[r] < y ? y : x[r]);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-        const int i = lane * K + r;
-        if (i < n) g[i] = x[r];
-    }
-}
-
 __device__ inline void cmpswap_lds(uint64_t* s, int a, int b) {
     uint64_t x = s[a], y = s[b];
     if (y < x) {
@@ -427,62 +340,14 @@ __device__ inline void cmpswap_lds(uint64_t* s, int a, int b) {
     }
 }
 
-__device__ void sort_global_segment(uint64_t* g, int n);
-
 __global__ __launch_bounds__(64) void k_sort(Geometry G, RenderBufs B) {
     const int seg = blockIdx.x;
     if (B.status->overflow) return;
     const uint32_t st = B.tile_start[seg];
     const int n = (int)(B.tile_start[seg + 1] - st);
     uint64_t* g = B.keys + st;
-    const int tid = threadIdx.x;
-    if (n <= 1) return;
-    if (n <= 64) wave_sort_segment<1>(g, n, tid);
-    else if (n <= 128) wave_sort_segment<2>(g, n, tid);
-    else if (n <= 256) wave_sort_segment<4>(g, n, tid);
-    else if (n <= 512) wave_sort_segment<8>(g, n, tid);
-    else if (n <= 1024) wave_sort_segment<16>(g, n, tid);
-    else if (!G.sort_long) sort_global_segment(g, n);   // no long-segment pass follows
+    sort_segment(g, n, threadIdx.x, G.sort_long != 0);
 }
-
-// Bitonic network in place in global memory with virtual +inf padding, by the
-// threads of one workgroup.
-__device__ void sort_global_segment(uint64_t* g, int n) {
-    const int tid = threadIdx.x;
-    int np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    // long segment: same network in global memory, virtual +inf padding
-    for (int k = 2; k <= np2; k <<= 1) {
-        const int h = k >> 1;
-        for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
-            const int blk = p / h, off = p - blk * h;
-            const int a = blk * k + off, b = blk * k + k - 1 - off;
-            if (b < n) {
-                uint64_t x = g[a], y = g[b];
-                if (y < x) {
-                    g[a] = y;
-                    g[b] = x;
-                }
-            }
-        }
-        __syncthreads();
-        for (int j = k >> 2; j >= 1; j >>= 1) {
-            for (int p = tid; p < (np2 >> 1); p += blockDim.x) {
-                const int blk = p / j, off = p - blk * j;
-                const int a = blk * 2 * j + off, b = a + j;
-                if (b < n) {
-                    uint64_t x = g[a], y = g[b];
-                    if (y < x) {
-                        g[a] = y;
-                        g[b] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
 
 __device__ void sort_long_segment(uint64_t* g, int n, uint64_t* s) {
     const int tid = threadIdx.x;
@@ -567,9 +432,12 @@ void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)patch_blocks(G)), dim3(256), 0, s, G, B);
 }
 
+// With G.fuse_sort the forward sorts the segments of up to 1024 keys itself
+// (and the longer ones when no long pass runs); only the long pass is
+// launched here.
 void launch_sort(const Geometry& G, const RenderBufs& B, hipStream_t s) {
     const int M = G.n_jobs * G.ntiles;
-    hipLaunchKernelGGL(k_sort, dim3(M), dim3(64), 0, s, G, B);
+    if (!G.fuse_sort) hipLaunchKernelGGL(k_sort, dim3(M), dim3(64), 0, s, G, B);
     if (G.sort_long) hipLaunchKernelGGL(k_sort_long, dim3(M), dim3(256), 0, s, G, B);
 }
 

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "raster_common.h"
+#include "segsort.h"
 
 namespace sgad {
 
@@ -126,6 +127,12 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
     const uint32_t st = B.tile_start[item];
     const int len = ovf ? 0 : (int)(B.tile_start[item + 1] - st);
     const uint32_t cs = B.chunk_start[item];   // this tile's first contributor-mask chunk
+    if (G.fuse_sort) {
+        // depth order of this tile's segment; the barrier makes the sorted
+        // keys visible to every lane before the walk reads them
+        sort_segment(B.keys + st, len, lane, G.sort_long != 0);
+        __syncthreads();
+    }
     const float fpx = (float)px, fpy = (float)py;
     const float fx0 = (float)(ti.tx * 8), fy0 = (float)(ti.ty * 8);
     float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;
@@ -246,6 +253,12 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
     const uint32_t st = B.tile_start[item];
     const int len = ovf ? 0 : (int)(B.tile_start[item + 1] - st);
     const uint32_t cs = B.chunk_start[item];   // this tile's first contributor-mask chunk
+    if (G.fuse_sort) {
+        // depth order of this tile's segment; the barrier makes the sorted
+        // keys visible to every lane before the walk reads them
+        sort_segment(B.keys + st, len, lane, G.sort_long != 0);
+        __syncthreads();
+    }
     const float fpx = (float)px, fpy = (float)py;
     const float fx0 = (float)(ti.tx * 8), fy0 = (float)(ti.ty * 8);
     float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;

@@ -26,7 +26,8 @@ bool launch_bwd(const Geometry& G, const RenderBufs& B, const float* g_rgb, cons
 void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const float* t_rgb, const float* t_dep,
                float w_rgb, float w_dep, uint32_t* count, float* g_rgb, float* g_dep, double* loss,
                hipStream_t s);
-void launch_adam(const AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
+int l1_blocks(int P);
+void launch_adam(AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
                  float* cdev, hipStream_t s);
 bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* bias,
                      const void* mask, void* y, hipStream_t s);
@@ -620,6 +621,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     G.ntiles = G.ntx * G.nty;
     G.sc_fwd = SCF;
     G.sc_bwd = SCB;
+    G.fuse_sort = TW == 8 && TH == 8 ? 1 : 0;
     S->stream = s;
     c->last_tw = TW;
     c->last_th = TH;
@@ -875,10 +877,10 @@ sgad_status sgad_l1_loss(sgad_ctx* c, int n_jobs, int H, int W, const float* rgb
         return fail(c, SGAD_EINVAL, "null pointer");
     hipStream_t s = pick_stream(c, stream);
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, ensure_c(c, c->scratch, (size_t)n_jobs * 4, s));
+    if ((int64_t)H * W > INT32_MAX / 2) return fail(c, SGAD_ERANGE, "image too large");
+    HIPCHK(c, ensure_c(c, c->scratch, (size_t)n_jobs * l1_blocks(H * W) * 4, s));
     uint32_t* cnt = (uint32_t*)c->scratch.p;
     TimeScope ts(c, "l1_loss", s);
-    launch_zero2_u32(cnt, n_jobs, (uint32_t*)loss, 2 * (int64_t)n_jobs, s);
     launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, g_rgb, g_depth, loss, s);
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
@@ -894,7 +896,8 @@ sgad_status sgad_adam_step(sgad_ctx* c, int n_groups, const sgad_adam_group* gro
     A.off[0] = 0;
     for (int g = 0; g < n_groups; ++g) {
         const sgad_adam_group& G = groups[g];
-        if (!G.param || !G.grad || !G.m || !G.v || G.n < 0) return fail(c, SGAD_EINVAL, "bad adam group");
+        if (G.n < 0 || (G.n > 0 && (!G.param || !G.grad || !G.m || !G.v)))
+            return fail(c, SGAD_EINVAL, "bad adam group");
         A.p[g] = G.param;
         A.g[g] = G.grad;
         A.m[g] = G.m;
@@ -906,6 +909,7 @@ sgad_status sgad_adam_step(sgad_ctx* c, int n_groups, const sgad_adam_group* gro
         A.space[g] = G.space;
         A.off[g + 1] = A.off[g] + G.n;
     }
+    if (A.off[n_groups] > ((int64_t)1 << 40)) return fail(c, SGAD_ERANGE, "more than 2^40 Adam elements");
     hipStream_t s = pick_stream(c, stream);
     HIPCHK(c, hipSetDevice(c->device));
     const float c1 = (float)(1.0 - std::pow((double)beta1, step));

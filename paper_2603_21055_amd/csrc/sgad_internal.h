@@ -77,6 +77,7 @@ struct Geometry {
     int sc_fwd = 4;    // 64-entry chunks the 8x8 forward publishes at once (1, 2 or 4)
     int sort_long = 1; // run the long-segment sort pass (else the register sort takes all)
     int sc_bwd = 16;   // backward sub-chunk of the 8x8 kernels (16 or 32 entries)
+    int fuse_sort = 0; // the 8x8 forward sorts its own segment (no separate sort launch)
 };
 
 struct RenderBufs {
@@ -108,6 +109,8 @@ struct AdamGroups {
     float lo[kMaxAdamGroups];
     float hi[kMaxAdamGroups];
     int space[kMaxAdamGroups];
+    int boff[kMaxAdamGroups + 1];   // first block of each group (set by the launcher)
+    int vec[kMaxAdamGroups];        // all four arrays 16-byte aligned
 };
 
 }  // namespace sgad

@@ -22,10 +22,14 @@ def ctx():
     c.close()
 
 
-def test_l1_loss_matches_oracle(ctx):
+@pytest.mark.parametrize("H,W", [(37, 53), (48, 64), (120, 160)])
+def test_l1_loss_matches_oracle(ctx, H, W):
+    """Odd pixel counts take the scalar path, multiples of 4 the float4 path;
+    all three span several 1024-pixel blocks with a ragged last block."""
     import torch
-    rng = np.random.default_rng(0)
-    nj, H, W = 2, 37, 53
+    print(f"l1 {H}x{W}", flush=True)
+    rng = np.random.default_rng(H * W)
+    nj = 2
     rgb, trgb = rng.uniform(size=(nj, 3, H, W)), rng.uniform(size=(nj, 3, H, W))
     dep, tdep = rng.uniform(1, 3, size=(nj, H, W)), rng.uniform(1, 3, size=(nj, H, W))
     tdep[:, ::7, ::5] = 0.0
@@ -66,6 +70,31 @@ def test_adam_matches_oracle(ctx):
             assert float(G[i].abs().max()) == 0.0     # grads zeroed after use
     for i in range(3):
         np.testing.assert_allclose(P[i].cpu().numpy(), op[i], rtol=1e-5, atol=1e-6)
+
+
+def test_adam_unaligned_and_empty_groups(ctx):
+    """Groups whose arrays start off a 16-byte boundary take the scalar path;
+    an empty group owns no block."""
+    import torch
+    rng = np.random.default_rng(5)
+    d = ctx.device
+    n = 3001
+    base = [torch.from_numpy(rng.normal(size=n + 1).astype(np.float32)).to(d) for _ in range(2)]
+    P, G = base[0][1:], base[1][1:]                 # 4-byte offset views
+    M, V = torch.zeros(n + 1, device=d)[1:], torch.zeros(n + 1, device=d)[1:]
+    E = torch.zeros(0, device=d)
+    Q = torch.from_numpy(rng.normal(size=2500).astype(np.float32)).to(d)
+    GQ = torch.from_numpy(rng.normal(size=2500).astype(np.float32)).to(d)
+    op, og = P.cpu().numpy().astype(np.float64), G.cpu().numpy().astype(np.float64)
+    oq, ogq = Q.cpu().numpy().astype(np.float64), GQ.cpu().numpy().astype(np.float64)
+    ctx.adam_step([(E, E, E, E, 0.1, -1e30, 1e30), (P, G, M, V, 0.01, -1e30, 1e30),
+                   (Q, GQ, torch.zeros_like(Q), torch.zeros_like(Q), 0.02, -1e30, 1e30)], 1)
+    torch.cuda.synchronize()
+    ep, _, _ = ooptim.adam_step(op, og, np.zeros(n), np.zeros(n), 1, 0.01)
+    eq, _, _ = ooptim.adam_step(oq, ogq, np.zeros(2500), np.zeros(2500), 1, 0.02)
+    np.testing.assert_allclose(P.cpu().numpy(), ep, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(Q.cpu().numpy(), eq, rtol=1e-5, atol=1e-6)
+    assert float(G.abs().max()) == 0.0 and float(GQ.abs().max()) == 0.0
 
 
 @pytest.mark.parametrize("space", ["log", "logit"])
