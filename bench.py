@@ -313,6 +313,7 @@ def main():
         config=dict(workload="one 640x480 keyframe (307,200 pixel-aligned Gaussians) splatted into one "
                              "view perturbed <=2 cm / 1 deg; step = forward, L1 loss, adjoint, Adam",
                     frame=[W, H], gaussians=N, tile=[tw, th],
+                    tile_variant=dict(zip(("fwd_chunks", "bwd_sub"), ctx.get_tile_variant())),
                     launch="one captured graph per step" if args.graph else "eager calls"),
         hbm_frac=algo_bytes / (ms * 1e-3) / HBM_PEAK,
         roofline=roof,

@@ -116,6 +116,11 @@ sgad_status sgad_sync(sgad_ctx* ctx);
 sgad_status sgad_set_tile(sgad_ctx* ctx, int tile_w, int tile_h);
 /* Tile shape used by the last forward (after autotuning). */
 sgad_status sgad_get_tile(const sgad_ctx* ctx, int* tile_w, int* tile_h);
+/* Kernel variant of the last forward's 8x8 wave tiles (after autotuning):
+ * *fwd_chunks = 64-entry chunks the forward publishes at once (1, 2 or 4),
+ * *bwd_sub = entries per adjoint sub-chunk (16 or 32).  Meaningless for the
+ * other tile shapes.  SGAD_EINVAL on a null pointer. */
+sgad_status sgad_get_tile_variant(const sgad_ctx* ctx, int* fwd_chunks, int* bwd_sub);
 
 /* Per-kernel timing (tracing): when enabled, every library kernel is
  * bracketed by hipEvents recorded on its launch stream.  Enabling or

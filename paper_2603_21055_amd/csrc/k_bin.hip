@@ -45,19 +45,29 @@ __device__ __forceinline__ uint32_t wave_agg_add(uint32_t* ctr, int64_t t, bool 
 }
 
 // Gaussian of this thread: each wavefront takes an 8x8 patch of one keyframe,
-// so its Gaussians overlap few distinct tiles per counting round.
-// `live` is false for lanes past the keyframe edge or the last pair.
-__device__ __forceinline__ int64_t patch_index(const Geometry& G, bool& live) {
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+// so its Gaussians overlap few distinct tiles per counting round.  Grid: x =
+// four patches per 256-thread block, y = pair.  `live` is false for lanes
+// past the keyframe edge; they are given pixel 0 of the pair.  (n_pairs * N
+// < 2^31, so 32-bit indices suffice.)
+struct PatchPos {
+    int pair, u, v, pix;
+    bool live;
+};
+
+__device__ __forceinline__ PatchPos patch_pos(const Geometry& G) {
+    PatchPos p;
     const int lane = threadIdx.x & 63;
-    const int pw = (G.Wk + 7) >> 3, ph = (G.Hk + 7) >> 3;
-    const int64_t per_pair = (int64_t)pw * ph;
-    const int64_t pair = wave / per_pair;
-    const int64_t patch = wave - pair * per_pair;
-    const int u = (int)(patch % pw) * 8 + (lane & 7);
-    const int v = (int)(patch / pw) * 8 + (lane >> 3);
-    live = pair < G.n_pairs && u < G.Wk && v < G.Hk;
-    return pair * G.N + (int64_t)v * G.Wk + u;
+    const int patch = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+    const int pw = (G.Wk + 7) >> 3;
+    const int pv = patch / pw;
+    const int pu = patch - pv * pw;
+    const int u = pu * 8 + (lane & 7), v = pv * 8 + (lane >> 3);
+    p.pair = (int)blockIdx.y;
+    p.live = u < G.Wk && v < G.Hk;
+    p.u = p.live ? u : 0;
+    p.v = p.live ? v : 0;
+    p.pix = p.v * G.Wk + p.u;
+    return p;
 }
 
 __device__ __forceinline__ int wave_max_int(int v) {
@@ -75,16 +85,12 @@ __device__ __forceinline__ int wave_max_int(int v) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
 #pragma clang fp contract(off)
-    const int64_t total = (int64_t)G.n_pairs * G.N;
-    bool live;
-    const int64_t i0 = patch_index(G, live);
-    const int64_t i = live ? i0 : total - 1;   // idle lanes shadow the last Gaussian, write nothing
-    const int pair = (int)(i / G.N);
-    const int pix = (int)(i - (int64_t)pair * G.N);
+    const PatchPos pp = patch_pos(G);
+    const bool live = pp.live;   // idle lanes compute pixel 0 and write nothing
+    const int pair = pp.pair, pix = pp.pix, u = pp.u, v = pp.v;
+    const size_t i = (size_t)pair * G.N + pix;
     const PairConst& pc = B.pairs[pair];
     const KfPtrs kp = B.kfs[pc.kf];
-    const int u = pix % G.Wk;
-    const int v = pix / G.Wk;
     const float Df = kp.depth[pix];
     const float Of = kp.offset[pix];
     const float Rf = kp.radius[pix];
@@ -129,10 +135,13 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
         const double hd = 0.5 * (s00 - s11);
         const double lam = 0.5 * (s00 + s11) + sqrt(hd * hd + s01 * s01);
         const double rho = ceil(3.0 * sqrt(lam));
-        double ax0 = floor((mx - rho) / (double)G.TW);
-        double ax1 = floor((mx + rho) / (double)G.TW) + 1.0;
-        double ay0 = floor((my - rho) / (double)G.TH);
-        double ay1 = floor((my + rho) / (double)G.TH) + 1.0;
+        // tile sizes are powers of two: scaling by the reciprocal is the
+        // exact quotient
+        const double itw = 1.0 / (double)G.TW, ith = 1.0 / (double)G.TH;
+        double ax0 = floor((mx - rho) * itw);
+        double ax1 = floor((mx + rho) * itw) + 1.0;
+        double ay0 = floor((my - rho) * ith);
+        double ay1 = floor((my + rho) * ith) + 1.0;
         ax0 = fmax(ax0, 0.0);
         ay0 = fmax(ay0, 0.0);
         ax1 = fmin(ax1, (double)G.ntx);
@@ -296,20 +305,19 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ coun
 // by the sort, so the atomic slot order does not matter.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_scatter(Geometry G, RenderBufs B) {
-    bool live;
-    const int64_t i = patch_index(G, live);
+    const PatchPos pp = patch_pos(G);
+    const size_t i = (size_t)pp.pair * G.N + pp.pix;
     int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
     uint64_t key = 0;
     int64_t base = 0;
-    if (live) {
+    if (pp.live) {
         const uint32_t rx = B.pre.rx[i], ry = B.pre.ry[i];
         x0 = rx & 0xffff;
         x1 = rx >> 16;
         y0 = ry & 0xffff;
         y1 = ry >> 16;
-        const int pair = (int)(i / G.N);
-        const int pix = (int)(i - (int64_t)pair * G.N);
-        const PairConst& pc = B.pairs[pair];
+        const int pix = pp.pix;
+        const PairConst& pc = B.pairs[pp.pair];
         const uint32_t gid = (uint32_t)pc.kf * (uint32_t)G.N + (uint32_t)pix;
         key = ((uint64_t)__float_as_uint(B.pre.z[i]) << 32) | gid;
         base = (int64_t)pc.job * G.ntiles;
@@ -413,13 +421,13 @@ void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_f32, dim3(blocks), dim3(256), 0, s, p, n, v);
 }
 
-static int64_t patch_blocks(const Geometry& G) {
-    const int64_t threads = (int64_t)G.n_pairs * ((G.Wk + 7) >> 3) * ((G.Hk + 7) >> 3) * 64;
-    return (threads + 255) / 256;
+static dim3 patch_grid(const Geometry& G) {
+    const int patches = ((G.Wk + 7) >> 3) * ((G.Hk + 7) >> 3);
+    return dim3((unsigned)((patches + 3) / 4), (unsigned)G.n_pairs);
 }
 
 void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s) {
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)patch_blocks(G)), dim3(256), 0, s, G, B);
+    hipLaunchKernelGGL(k_preprocess, patch_grid(G), dim3(256), 0, s, G, B);
 }
 
 void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s) {
@@ -429,7 +437,7 @@ void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s) {
 }
 
 void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)patch_blocks(G)), dim3(256), 0, s, G, B);
+    hipLaunchKernelGGL(k_scatter, patch_grid(G), dim3(256), 0, s, G, B);
 }
 
 // With G.fuse_sort the forward sorts the segments of up to 1024 keys itself

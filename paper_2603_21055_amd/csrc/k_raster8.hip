@@ -399,7 +399,8 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     __shared__ float4 s_e[64][3];
     __shared__ float4 s_pc[64];
     __shared__ int s_pof[64];
-    __shared__ __align__(16) float s_M[64 * LS];   // [pixel][entry] (w, gq); a cell is read only if written
+    __shared__ __align__(16) float s_M[64 * LS];
+    __shared__ uint64_t s_eb[SUB];                 // pixel set of each sub-chunk entry   // [pixel][entry] (w, gq); a cell is read only if written
     const int lane = threadIdx.x;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     if (item >= G.n_jobs * G.ntiles) return;
@@ -516,24 +517,32 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 contribute(al0, raw0, ec0, b0);
                 if (two) contribute(al1, raw1, ec1, b1);
             }
-            // transpose the contributions: lane (grp, sub) keeps the pixel set
-            // of entry `sub` (one ballot per entry, selected in registers)
-            uint64_t emask = 0ull;
+            // transpose the contributions: lane (grp, sub) takes the pixel set
+            // of entry `sub` (one ballot per entry, published by lane 0)
+            {
+                uint64_t bal[SUB];
 #pragma unroll
-            for (int e = 0; e < SUB; ++e) {
-                const uint64_t me = __ballot((cmask >> e) & 1u);
-                emask = sub == e ? me : emask;
+                for (int e = 0; e < SUB; ++e) bal[e] = __ballot((cmask >> e) & 1u);
+                if (lane == 0)
+#pragma unroll
+                    for (int e = 0; e < SUB; ++e) s_eb[e] = bal[e];
             }
+            wave_lds_sync();
+            const uint64_t emask = s_eb[sub];
             // phase B: lane = entry s * SUB + sub; the NS lanes of an entry
-            // split its contributing pixels by column (x mod NS), and each
-            // walks only the cells phase A wrote
+            // split its contributing pixels by a checkerboard class (NS = 4:
+            // (x mod 2, y mod 2); NS = 2: (x + y) mod 2), which balances
+            // compact footprints better than columns, and each walks only
+            // the cells phase A wrote
             const float4 eu0 = s_e[s * SUB + sub][0];
             const float mxl = (eu0.x - fx0) + eu0.z, myl = (eu0.y - fy0) + eu0.w;
-            constexpr uint64_t kCols = NS == 4 ? 0x1111111111111111ull : (NS == 2 ? 0x5555555555555555ull : ~0ull);
+            const uint64_t cls = NS == 4   ? 0x0055005500550055ull << ((grp & 1) + 8 * (grp >> 1))
+                                 : NS == 2 ? (grp ? ~0xAA55AA55AA55AA55ull : 0xAA55AA55AA55AA55ull)
+                                           : ~0ull;
             float a[10];
 #pragma unroll
             for (int k = 0; k < 10; ++k) a[k] = 0.f;
-            uint64_t pm = emask & (kCols << grp);
+            uint64_t pm = emask & cls;
             while (pm != 0ull) {
                 const int p = (int)__builtin_ctzll(pm);
                 pm &= pm - 1ull;

@@ -111,7 +111,7 @@ struct sgad_ctx {
     sgad_status latched = SGAD_OK;
     std::string latched_msg;
     int tile_w = 0, tile_h = 0;  // 0,0: autotuned per workload
-    int last_tw = 8, last_th = 8;
+    int last_tw = 8, last_th = 8, last_scf = 4, last_scb = 16;
     // autotuner: configurations measured per workload key, and a forced
     // configuration used while measuring
     struct TuneEntry {
@@ -530,6 +530,13 @@ sgad_status sgad_get_tile(const sgad_ctx* c, int* w, int* h) {
     return SGAD_OK;
 }
 
+sgad_status sgad_get_tile_variant(const sgad_ctx* c, int* fwd_chunks, int* bwd_sub) {
+    if (!c || !fwd_chunks || !bwd_sub) return SGAD_EINVAL;
+    *fwd_chunks = c->last_scf;
+    *bwd_sub = c->last_scb;
+    return SGAD_OK;
+}
+
 sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_views, const sgad_cam* vcam,
                             const sgad_pose* vpose, int n_jobs, const sgad_job* jobs, float* out_rgb,
                             float* out_depth, float* out_alpha, int32_t* out_count, sgad_saved** saved,
@@ -564,7 +571,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     }
     if (n_pairs == 0) return fail(c, SGAD_EINVAL, "jobs render no keyframe");
     const int64_t N = (int64_t)k0.H * k0.W;
-    if ((int64_t)n_kf * N >= (1ll << 32) || (int64_t)n_pairs * N >= (1ll << 31))
+    if ((int64_t)n_kf * N >= (1ll << 32) || (int64_t)n_pairs * N >= (1ll << 31) || n_pairs > 65535)
         return fail(c, SGAD_ERANGE, "too many Gaussians for one call");
     hipStream_t s = pick_stream(c, stream);
     HIPCHK(c, hipSetDevice(c->device));
@@ -625,6 +632,8 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     S->stream = s;
     c->last_tw = TW;
     c->last_th = TH;
+    c->last_scf = SCF;
+    c->last_scb = SCB;
 
     // parameter block: pairs | kf pointers | pair_of
     const size_t o_pairs = 0;

@@ -67,6 +67,7 @@ _SIGS = {
     "sgad_sync": (C.c_int, [_P]),
     "sgad_set_tile": (C.c_int, [_P, C.c_int, C.c_int]),
     "sgad_get_tile": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "sgad_get_tile_variant": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "sgad_render_fwd": (C.c_int, [_P, C.c_int, C.POINTER(Keyframe), C.c_int, C.POINTER(Cam),
                                   C.POINTER(Pose), C.c_int, C.POINTER(Job), _P, _P, _P, _P,
                                   C.POINTER(_P), _P]),
@@ -210,6 +211,12 @@ class Context:
         w, h = C.c_int(), C.c_int()
         self._check(self.lib.sgad_get_tile(self.h, C.byref(w), C.byref(h)))
         return w.value, h.value
+
+    def get_tile_variant(self):
+        """(forward chunks per super-chunk, adjoint sub-chunk) of the last 8x8 forward."""
+        f, b = C.c_int(), C.c_int()
+        self._check(self.lib.sgad_get_tile_variant(self.h, C.byref(f), C.byref(b)))
+        return f.value, b.value
 
     def timing(self, enable: bool):
         """Enable/disable per-kernel event timing (resets the accumulators)."""
