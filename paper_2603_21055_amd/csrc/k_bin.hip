@@ -223,11 +223,12 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 // ---------------------------------------------------------------------------
 // Exclusive scan of the per-(job, tile) counts in one 1024-thread block; also
 // publishes the total, the overflow flag, and clears the fill counters and the
-// work-queue counter.
+// work-queue counter (and, with zero_counts, the counts themselves, so that
+// the next call's count pass needs no clearing launch).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ count, uint32_t* start,
-                                               uint32_t* fill, uint32_t* cstart, int M, uint32_t capacity,
-                                               DevStatus* st) {
+__global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ count, uint32_t* start, uint32_t* fill,
+                                               uint32_t* cstart, int M, uint32_t capacity, DevStatus* st,
+                                               int zero_counts) {
     __shared__ uint32_t s_wave[16], s_cw[16];
     const int tid = threadIdx.x;
     const int chunk = (M + 1023) / 1024;
@@ -280,11 +281,13 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ coun
     uint32_t run = s_wave[wave] + inc - sum;
     uint32_t crun = s_cw[wave] + cinc - csum;
     for (int k = b; k < e; ++k) {
+        const uint32_t ck = count[k];
         start[k] = run;
         cstart[k] = crun;
-        run += count[k];
-        crun += (count[k] + 63u) >> 6;
+        run += ck;
+        crun += (ck + 63u) >> 6;
         fill[k] = 0u;
+        if (zero_counts) count[k] = 0u;   // ready for the next count pass
     }
     if (tid == 1023) {
         const uint32_t tot = s_wave[wave] + inc;
@@ -430,10 +433,10 @@ void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s) {
     hipLaunchKernelGGL(k_preprocess, patch_grid(G), dim3(256), 0, s, G, B);
 }
 
-void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s) {
+void launch_scan(const Geometry& G, const RenderBufs& B, bool zero_counts, hipStream_t s) {
     const int M = G.n_jobs * G.ntiles;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, B.tile_count, B.tile_start, B.tile_fill,
-                       B.chunk_start, M, B.capacity, B.status);
+                       B.chunk_start, M, B.capacity, B.status, zero_counts ? 1 : 0);
 }
 
 void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s) {

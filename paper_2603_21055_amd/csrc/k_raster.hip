@@ -34,6 +34,7 @@ template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_fwd(Geometry G, RenderBufs B, FwdOut O) {
     constexpr int NT = TW * TH;
     __shared__ float4 s_u[NT], s_g[NT], s_c[NT];
+    publish_status(B);
     const int item = blockIdx.x;
     const int job = item / G.ntiles;
     const int tile = item - job * G.ntiles;

@@ -116,6 +116,7 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
     __shared__ uint64_t s_m[16];
     __shared__ int s_pof[64];
     const int lane = threadIdx.x;
+    publish_status(B);
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     if (item >= G.n_jobs * G.ntiles) return;
     const TileItem ti = tile_item(G, B, item, lane, s_pof);
@@ -242,6 +243,7 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
     __shared__ uint64_t s_m[SCH][16];
     __shared__ int s_pof[64];
     const int lane = threadIdx.x;
+    publish_status(B);
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     if (item >= G.n_jobs * G.ntiles) return;
     const TileItem ti = tile_item(G, B, item, lane, s_pof);

@@ -6,9 +6,26 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "sgad_internal.h"
 
 namespace sgad {
+
+// First workgroup of a forward: hand the call's status to the host (pinned
+// memory, read after the call's completion event) and clear the flags that
+// the count and scatter passes raise, so that the next call on this slot
+// starts clean.  No kernel of the forward reads those flags.
+__device__ __forceinline__ void publish_status(const RenderBufs& B) {
+    if (B.status_host == nullptr || blockIdx.x != 0) return;
+    constexpr unsigned kWords = sizeof(DevStatus) / 4;
+    const unsigned t = threadIdx.x;
+    if (t < kWords) {
+        uint32_t* st = reinterpret_cast<uint32_t*>(B.status);
+        B.status_host[t] = st[t];
+        if (t == offsetof(DevStatus, nonfinite) / 4 || t == offsetof(DevStatus, sticky) / 4) st[t] = 0u;
+    }
+}
 
 // -0.5 * log2(e): exp(-q/2) = 2^(q * kNegHalfLog2e)
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;

@@ -15,7 +15,7 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 void launch_zero2_u32(uint32_t* a, int64_t na, uint32_t* b, int64_t nb, hipStream_t s);
 void launch_preprocess(const Geometry& G, const RenderBufs& B, hipStream_t s);
-void launch_scan(const Geometry& G, const RenderBufs& B, hipStream_t s);
+void launch_scan(const Geometry& G, const RenderBufs& B, bool zero_counts, hipStream_t s);
 void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s);
 void launch_sort(const Geometry& G, const RenderBufs& B, hipStream_t s);
 bool launch_fwd(const Geometry& G, const RenderBufs& B, float* rgb, float* depth, float* alpha, int32_t* count,
@@ -76,6 +76,9 @@ struct sgad_saved {
     // block (every iteration of a mapping loop) is not uploaded again
     std::vector<char> stage, last_up, stage_grad, last_up_grad;
     DevStatus* status_h = nullptr;
+    uint32_t* status_dev = nullptr;   // status_h as the forward kernel writes it (null: copied instead)
+    int zeroed_M = -1;                // the tile counts [0, M) and the flags are known to be clear
+    void* zeroed_tiles = nullptr;     // ... in this allocation of the tile buffer
     hipEvent_t ev_up = nullptr, ev_up_grad = nullptr, ev_status = nullptr;
     bool up_pending = false, up_grad_pending = false, status_pending = false;
     RenderBufs B{};
@@ -415,12 +418,26 @@ sgad_saved* acquire(sgad_ctx* c) {
     sgad_saved* s = new sgad_saved();
     if (hipEventCreateWithFlags(&s->ev_up, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&s->ev_up_grad, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_status, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void**)&s->status_h, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+        hipEventCreateWithFlags(&s->ev_status, hipEventDisableTiming) != hipSuccess) {
         delete s;
         return nullptr;
     }
+    if (hipHostMalloc((void**)&s->status_h, sizeof(DevStatus), hipHostMallocCoherent | hipHostMallocMapped) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        s->status_h = nullptr;
+        if (hipHostMalloc((void**)&s->status_h, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return nullptr;
+        }
+    }
     std::memset(s->status_h, 0, sizeof(DevStatus));
+    // the forward's first workgroup writes the status straight into it
+    if (hipHostGetDevicePointer((void**)&s->status_dev, s->status_h, 0) != hipSuccess) {
+        s->status_dev = nullptr;
+        (void)hipGetLastError();
+    }
     s->in_use = true;
     c->slots.push_back(s);
     return s;
@@ -734,18 +751,23 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     B.Tfinal = (float*)S->pix.p;
     B.last = (uint32_t*)((char*)S->pix.p + PJ * 4);
     B.status = (DevStatus*)S->status.p;
+    B.status_host = S->status_dev;
 
-    {
+    // Each call's scan clears the counts it read and its forward clears the
+    // flags, so the clearing launch is needed only when the slot's buffers or
+    // tile count changed, or the previous call stopped before its forward.
+    if (!S->status_dev || S->zeroed_M != M || S->tiles.p != S->zeroed_tiles) {
         TimeScope ts(c, "zero", s);
         launch_zero2_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, B.tile_count, (int64_t)M, s);
     }
+    S->zeroed_M = -1;   // until this call's forward is enqueued
     {
         TimeScope ts(c, "preprocess", s);
         launch_preprocess(G, B, s);
     }
     {
         TimeScope ts(c, "scan", s);
-        launch_scan(G, B, s);
+        launch_scan(G, B, S->sized, s);   // the sizing pass keeps the counts for its rescan
     }
     if (!S->sized) {
         // size the instance buffer from the exact count (one host wait)
@@ -758,8 +780,8 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
             S->capacity = (uint32_t)cap;
             B.keys = (uint64_t*)S->keys.p;
             B.capacity = S->capacity;
-            launch_scan(G, B, s);
         }
+        launch_scan(G, B, true, s);   // same offsets; overflow against the new capacity; counts cleared
         S->sized = true;
     }
     // contributor masks: one u64 per (64-entry chunk, pixel); at most
@@ -780,9 +802,12 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
             return fail(c, SGAD_EINVAL, "unsupported tile shape");
     }
     HIPCHK(c, hipGetLastError());
+    S->zeroed_M = M;
+    S->zeroed_tiles = S->tiles.p;
     if (!cap) {
         // (a captured forward's status is read back after each graph launch)
-        HIPCHK(c, hipMemcpyAsync(S->status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        if (!S->status_dev)
+            HIPCHK(c, hipMemcpyAsync(S->status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipEventRecord(S->ev_status, s));
         S->status_pending = true;
     }
@@ -1052,7 +1077,8 @@ sgad_status sgad_graph_launch(sgad_ctx* c, sgad_graph* g, void* stream) {
     for (sgad_saved* S : g->slots) {
         // read back what the replayed forwards found, as an eager forward does
         if (S->status_pending) continue;
-        HIPCHK(c, hipMemcpyAsync(S->status_h, S->B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        if (!S->status_dev)
+            HIPCHK(c, hipMemcpyAsync(S->status_h, S->B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipEventRecord(S->ev_status, s));
         S->status_pending = true;
     }
@@ -1199,7 +1225,7 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
         launch_zero_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, s);
         launch_zero_u32(B.tile_count, (int64_t)M, s);
         launch_preprocess(G, B, s);
-        launch_scan(G, B, s);
+        launch_scan(G, B, false, s);
         HIPCHK(c, hipMemcpyAsync(T.status_h, B.status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
         const size_t cap = std::min<size_t>((size_t)T.status_h->total * 3 / 2 + 65536, 0xffffffffu);
@@ -1219,7 +1245,7 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
             launch_zero_u32((uint32_t*)B.status, 4, q);   // keeps the sticky word
             launch_zero_u32(B.tile_count, (int64_t)M, q);
             launch_preprocess(G, B, q);
-            launch_scan(G, B, q);
+            launch_scan(G, B, false, q);
             launch_scatter(G, B, q);
             launch_sort(G, B, q);
             if (!launch_track(G, B, obs_depth, (float*)T.part.p, q)) return false;

@@ -95,6 +95,7 @@ struct RenderBufs {
     float* Tfinal;            // [n_jobs * P]
     uint32_t* last;           // [n_jobs * P]
     DevStatus* status;
+    uint32_t* status_host;    // device address of the call's pinned host copy of *status, or null
 };
 
 // Multi-tensor Adam: group g owns elements [off[g], off[g+1]) of the flat range.

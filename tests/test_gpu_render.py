@@ -248,6 +248,15 @@ def test_nonfinite_depth_is_latched(ctx):
     assert e.value.status == sgad.EDATA
     ctx.release(saved)
     ctx.sync()   # cleared
+    # the flag belongs to that call: the same slot, with the input repaired,
+    # reports nothing (each forward clears the flags it handed back)
+    kfs_d[0]["depth"][3, 4] = 2.0
+    for tile in ((8, 8), (16, 16), (8, 8)):
+        ctx.set_tile(*tile)
+        saved, _ = H.gpu_render(ctx, kfs_d, sc["views"], [(0, [0])])
+        ctx.release(saved)
+        ctx.sync()
+    ctx.set_tile(0, 0)
 
 
 def test_autotuner_picks_a_config_and_results_do_not_change(ctx):
