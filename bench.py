@@ -42,14 +42,14 @@ BYTES_BY_KERNEL = {  # algorithmic bytes per Gaussian / per pixel of each kernel
 # in KERNEL_SOURCES); after any change the traffic is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = {
-    "composite_bwd": ("k_raster8.hip", "raster_common.h", "sgad_internal.h"),
-    "composite_fwd": ("k_raster8.hip", "raster_common.h", "sgad_internal.h"),
+    "composite_bwd": ("k_raster8.hip", "raster_common.h", "segsort.h", "sgad_internal.h"),
+    "composite_fwd": ("k_raster8.hip", "raster_common.h", "segsort.h", "sgad_internal.h"),
 }
 PMC = {    # kernel -> counters per dispatch and the sources they were taken on
-    "composite_bwd": dict(fetch_kib=19205.1, write_kib=84978.3,
-                          sha="95e68584dace6b1d0d6213bd5cbb8e59694415a068352852f22c34be3327ec10"),
-    "composite_fwd": dict(fetch_kib=15593.7, write_kib=9601.0,
-                          sha="95e68584dace6b1d0d6213bd5cbb8e59694415a068352852f22c34be3327ec10"),
+    "composite_bwd": dict(fetch_kib=26848.5, write_kib=84981.3,
+                          sha="a8519670ce324b43505e9c54dfa041991711d775292873896d165b8a784628aa"),
+    "composite_fwd": dict(fetch_kib=16246.1, write_kib=28953.7,
+                          sha="a8519670ce324b43505e9c54dfa041991711d775292873896d165b8a784628aa"),
 }
 
 
@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=str, default="auto", help="auto (autotuner) or WxH")
+    ap.add_argument("--variant", type=str, default="4,16",
+                    help="8x8 kernel variant with --tile 8x8: forward chunks (1, 2, 4), adjoint sub-chunk (16, 32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--print-sha", action="store_true", help="print the kernel-source hashes and exit")
     ap.add_argument("--graph", action="store_true", help="time replays of a captured graph of one step")
@@ -244,6 +246,7 @@ def main():
     else:
         tw, th = (int(x) for x in args.tile.split("x"))
         ctx.set_tile(tw, th)
+        ctx.set_tile_variant(*(int(x) for x in args.variant.split(",")))
     from paper_2603_21055_amd.mapping import Mapper
     t_rgb = torch.from_numpy(sc["target"]["rgb"]).to(dev)[None].contiguous()
     t_dep = torch.from_numpy(sc["target"]["depth"]).to(dev)[None].contiguous()

@@ -114,6 +114,7 @@ struct sgad_ctx {
     sgad_status latched = SGAD_OK;
     std::string latched_msg;
     int tile_w = 0, tile_h = 0;  // 0,0: autotuned per workload
+    int var_scf = 4, var_scb = 16;  // 8x8 kernel variant when the tile is set by hand
     int last_tw = 8, last_th = 8, last_scf = 4, last_scb = 16;
     // autotuner: configurations measured per workload key, and a forced
     // configuration used while measuring
@@ -540,6 +541,15 @@ sgad_status sgad_set_tile(sgad_ctx* c, int w, int h) {
     return SGAD_OK;
 }
 
+sgad_status sgad_set_tile_variant(sgad_ctx* c, int fwd_chunks, int bwd_sub) {
+    if (!c) return SGAD_EINVAL;
+    if (!(fwd_chunks == 1 || fwd_chunks == 2 || fwd_chunks == 4) || !(bwd_sub == 16 || bwd_sub == 32))
+        return fail(c, SGAD_EINVAL, "unsupported 8x8 kernel variant");
+    c->var_scf = fwd_chunks;
+    c->var_scb = bwd_sub;
+    return SGAD_OK;
+}
+
 sgad_status sgad_get_tile(const sgad_ctx* c, int* w, int* h) {
     if (!c || !w || !h) return SGAD_EINVAL;
     *w = c->last_tw;
@@ -595,7 +605,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     poll(c, false);
     const bool cap = c->capture.on;
 
-    int TW = c->tile_w, TH = c->tile_h, SCF = 4, SCB = 16;
+    int TW = c->tile_w, TH = c->tile_h, SCF = c->var_scf, SCB = c->var_scb;
     if (c->force) {
         TW = c->ftw;
         TH = c->fth;

@@ -68,6 +68,7 @@ _SIGS = {
     "sgad_set_tile": (C.c_int, [_P, C.c_int, C.c_int]),
     "sgad_get_tile": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "sgad_get_tile_variant": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "sgad_set_tile_variant": (C.c_int, [_P, C.c_int, C.c_int]),
     "sgad_render_fwd": (C.c_int, [_P, C.c_int, C.POINTER(Keyframe), C.c_int, C.POINTER(Cam),
                                   C.POINTER(Pose), C.c_int, C.POINTER(Job), _P, _P, _P, _P,
                                   C.POINTER(_P), _P]),
@@ -211,6 +212,10 @@ class Context:
         w, h = C.c_int(), C.c_int()
         self._check(self.lib.sgad_get_tile(self.h, C.byref(w), C.byref(h)))
         return w.value, h.value
+
+    def set_tile_variant(self, fwd_chunks: int, bwd_sub: int):
+        """8x8 kernel variant used when the tile is set to (8, 8) by hand."""
+        self._check(self.lib.sgad_set_tile_variant(self.h, int(fwd_chunks), int(bwd_sub)))
 
     def get_tile_variant(self):
         """(forward chunks per super-chunk, adjoint sub-chunk) of the last 8x8 forward."""
