@@ -10,6 +10,8 @@
 // held fixed.  H = sum J^T J, g = sum J^T r, l = sum(-r^2/2 - ln s - ln(2pi)/2).
 #include <hip/hip_runtime.h>
 
+#include "raster_common.h"
+#include "segsort.h"
 #include "sgad_internal.h"
 
 namespace sgad {
@@ -234,6 +236,185 @@ __global__ __launch_bounds__(TW* TH) void k_track(Geometry G, RenderBufs B, cons
     }
 }
 
+// One pixel's contribution of one entry (front-to-back order): the same
+// operations as the workgroup-tile walk, in the same order.  Returns false
+// when the pixel stops before this entry (T would fall below kTMin).
+struct TrackPix {
+    float T, Dp, Ss, dD[6], dT[6];
+};
+
+__device__ __forceinline__ bool track_step(TrackPix& s, const TrackEntry& e, float fpx, float fpy) {
+    const float4 eu = e.u;
+    const float dx = (fpx - eu.x) - eu.z, dy = (fpy - eu.y) - eu.w;
+    const float4 g = e.g;
+    const float qv = tq(dx, dy, g.x, g.y, g.z);
+    if (!(qv <= kQCut)) return true;
+    const float Gv = __builtin_amdgcn_exp2f(qv * kNegHalfLog2eT);
+    const float raw = g.w * Gv;
+    const float alpha = fminf(kAlphaMax, raw);
+    if (alpha < kAlphaMin) return true;
+    const float om = 1.f - alpha;
+    const float test = s.T * om;
+    if (test < kTMin) return false;
+    const float4 ec = e.c;
+    const float w = alpha * s.T;
+    float da[6];
+    if (raw < kAlphaMax) {
+        const float4 em = e.m, q0 = e.q0, q1 = e.q1, q2 = e.q2;
+        const float gmx = -2.f * (g.x * dx + g.y * dy);
+        const float gmy = -2.f * (g.y * dx + g.z * dy);
+        const float ga = dx * dx, gb = 2.f * dx * dy, gc = dy * dy;
+        const float vx = gmx * em.x + ga * q0.x + gb * q0.w + gc * q1.z;
+        const float vy = gmy * em.y + ga * q0.y + gb * q1.x + gc * q1.w;
+        const float vz = gmx * em.z + gmy * em.w + ga * q0.z + gb * q1.y + gc * q2.x;
+        const float x = ec.z, y = ec.w, z = ec.y;
+        const float h = -0.5f * alpha;
+        da[0] = h * vx;
+        da[1] = h * vy;
+        da[2] = h * vz;
+        da[3] = h * (y * vz - z * vy);
+        da[4] = h * (z * vx - x * vz);
+        da[5] = h * (x * vy - y * vx);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) da[j] = 0.f;
+    }
+    // dz/dxi = (0, 0, 1, y, -x, 0)
+    const float dz[6] = {0.f, 0.f, 1.f, ec.w, -ec.z, 0.f};
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const float dw = da[j] * s.T + alpha * s.dT[j];
+        s.dD[j] += dw * ec.y + w * dz[j];
+        s.dT[j] = s.dT[j] * om - s.T * da[j];
+    }
+    s.Dp += w * ec.y;
+    s.Ss += w * ec.x;
+    s.T = test;
+    return true;
+}
+
+// Per-pixel residual, Jacobian and the 29 normal-equation terms.
+__device__ __forceinline__ void track_terms(const TrackPix& s, float o, float (&vals)[kTrackVals]) {
+#pragma unroll
+    for (int i = 0; i < kTrackVals; ++i) vals[i] = 0.f;
+    const float A = 1.f - s.T;
+    if (A >= kAValid && o > 0.f) {
+        const float mu = s.Dp / A;
+        const float sd = sqrtf(s.Ss / A);
+        const float r = (o - mu) / sd;
+        const float k = -1.f / (A * sd);
+        float J[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) J[j] = k * (s.dD[j] + mu * s.dT[j]);  // dA = -dT
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i; j < 6; ++j) vals[q++] = J[i] * J[j];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) vals[21 + i] = J[i] * r;
+        vals[27] = -0.5f * r * r - logf(sd) - 0.91893853320467274178f;
+        vals[28] = 1.f;
+    }
+}
+
+// 8x8 wave tiles, four per 256-thread workgroup (one partial record per
+// workgroup).  Each wave sorts its tile's segment (segments over 1024 keys
+// were sorted by the long pass), then per 64-entry chunk publishes the
+// derived entries and 16 ballots of their pixel rectangles (3-sigma bounds
+// of the q <= 9 ellipse), and each lane walks only its own candidates: the
+// entries it skips have q > 9 at its pixel, so every pixel performs the same
+// operations in the same order as in the workgroup-tile kernel.
+__global__ __launch_bounds__(256) void k_track8(Geometry G, RenderBufs B, const float* __restrict__ obs,
+                                                float* part) {
+    __shared__ TrackEntry s_e[4][64];
+    __shared__ uint64_t s_m[4][16];
+    __shared__ float s_red[4][kTrackVals];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = blk * 4 + wave;
+    const bool tile_ok = item < G.ntiles;
+    const int tx = tile_ok ? item % G.ntx : 0, ty = tile_ok ? item / G.ntx : 0;
+    const int lx = lane & 7, ly = lane >> 3;
+    const int px = tx * 8 + lx, py = ty * 8 + ly;
+    const bool inside = tile_ok && px < G.Wv && py < G.Hv;
+    const bool ovf = B.status->overflow != 0u;
+    const uint32_t st = tile_ok ? B.tile_start[item] : 0u;
+    const int len = (ovf || !tile_ok) ? 0 : (int)(B.tile_start[item + 1] - st);
+    if (G.fuse_sort) sort_segment(B.keys + st, len, lane, true);
+    __syncthreads();   // sorted keys visible to every lane
+    const float fpx = (float)px, fpy = (float)py;
+    const float fx0 = (float)(tx * 8), fy0 = (float)(ty * 8);
+    TrackPix s;
+    s.T = 1.f;
+    s.Dp = 0.f;
+    s.Ss = 0.f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        s.dD[j] = 0.f;
+        s.dT[j] = 0.f;
+    }
+    bool done = !inside;
+    TrackEntry* se = s_e[wave];
+    uint64_t* sm = s_m[wave];
+    uint64_t key = lane < len ? B.keys[st + lane] : 0ull;
+    for (int c0 = 0; c0 < len; c0 += 64) {
+        const int n = min(64, len - c0);
+        int x0 = 8, x1 = -1, y0 = 8, y1 = -1;
+        if (lane < n) {
+            TrackEntry e;
+            load_track_entry(G, B, key, e);
+            se[lane] = e;
+            const float mx = (e.u.x - fx0) + e.u.z, my = (e.u.y - fy0) + e.u.w;
+            const float det = e.g.x * e.g.z - e.g.y * e.g.y;
+            const float ex = 3.f * sqrtf(e.g.z / det) + 1e-3f;
+            const float ey = 3.f * sqrtf(e.g.x / det) + 1e-3f;
+            x0 = max(0, (int)ceilf(mx - ex));
+            x1 = min(7, (int)floorf(mx + ex));
+            y0 = max(0, (int)ceilf(my - ey));
+            y1 = min(7, (int)floorf(my + ey));
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint64_t cm = __ballot(lane < n && x0 <= k && k <= x1);
+            const uint64_t rm = __ballot(lane < n && y0 <= k && k <= y1);
+            if (lane == k) sm[k] = cm;
+            if (lane == 8 + k) sm[8 + k] = rm;
+        }
+        wave_lds_sync();   // (this wave's own LDS region)
+        // the next chunk's key while this one is walked
+        key = lane < len - c0 - 64 ? B.keys[st + (uint32_t)(c0 + 64 + lane)] : 0ull;
+        if (!done) {
+            uint64_t m = sm[lx] & sm[8 + ly];
+            while (m != 0ull) {
+                const int b = (int)__builtin_ctzll(m);
+                m &= m - 1ull;
+                if (!track_step(s, se[b], fpx, fpy)) {
+                    done = true;
+                    break;
+                }
+            }
+        }
+        if (__ballot(!done) == 0ull) break;
+        wave_lds_sync();   // walk reads done before the next publish
+    }
+    float vals[kTrackVals];
+    track_terms(s, inside ? obs[(size_t)py * G.Wv + px] : 0.f, vals);
+#pragma unroll
+    for (int i = 0; i < kTrackVals; ++i) {
+        const float sv = twave_sum(vals[i]);
+        if (lane == 0) s_red[wave][i] = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x < kTrackVals) {
+        const int t = threadIdx.x;
+        part[(size_t)blk * 32 + t] = (s_red[0][t] + s_red[1][t]) + (s_red[2][t] + s_red[3][t]);
+    }
+}
+
+// Partial records k_track / k_track8 write (one per tile, or per four tiles).
+int track_parts(const Geometry& G) { return (G.TW == 8 && G.TH == 8) ? (G.ntiles + 3) / 4 : G.ntiles; }
+
 // FP64 sum of the tile partials, damped Cholesky solve, Exp(dxi) * pose.
 __device__ bool chol6(const double* A, double* L) {
     for (int i = 0; i < 6; ++i)
@@ -365,7 +546,7 @@ bool launch_track(const Geometry& G, const RenderBufs& B, const float* obs, floa
     if (G.TW == 16 && G.TH == 16)
         hipLaunchKernelGGL((k_track<16, 16>), dim3(G.ntiles), dim3(256), 0, s, G, B, obs, part);
     else if (G.TW == 8 && G.TH == 8)
-        hipLaunchKernelGGL((k_track<8, 8>), dim3(G.ntiles), dim3(64), 0, s, G, B, obs, part);
+        hipLaunchKernelGGL(k_track8, dim3(track_parts(G)), dim3(256), 0, s, G, B, obs, part);
     else if (G.TW == 16 && G.TH == 8)
         hipLaunchKernelGGL((k_track<16, 8>), dim3(G.ntiles), dim3(128), 0, s, G, B, obs, part);
     else if (G.TW == 32 && G.TH == 8)

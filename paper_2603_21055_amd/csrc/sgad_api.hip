@@ -39,6 +39,7 @@ void launch_offset_l1(int n, const float* pred, const float* target, void* grad,
 void launch_track_pair(const double* pose, const sgad_pose& kf_pose, const sgad_cam& kc, const sgad_cam& vc,
                        PairConst* out, hipStream_t s);
 bool launch_track(const Geometry& G, const RenderBufs& B, const float* obs, float* part, hipStream_t s);
+int track_parts(const Geometry& G);
 void launch_track_solve(const float* part, int nitems, double* pose, double* trace, int it, const DevStatus* st,
                         hipStream_t s);
 }  // namespace sgad
@@ -1162,7 +1163,7 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     HIPCHK(c, hipSetDevice(c->device));
     poll(c, false);
     auto& T = c->track;
-    int TW = c->tile_w ? c->tile_w : 16, TH = c->tile_h ? c->tile_h : 16;
+    int TW = c->tile_w ? c->tile_w : 8, TH = c->tile_h ? c->tile_h : 8;
     Geometry& G = T.G;
     const int64_t N = (int64_t)geo->cam.H * geo->cam.W;
     const bool same_shape = T.sized && G.Hk == geo->cam.H && G.Wk == geo->cam.W && G.Hv == vcam->H &&
@@ -1181,6 +1182,7 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     G.ntx = (G.Wv + TW - 1) / TW;
     G.nty = (G.Hv + TH - 1) / TH;
     G.ntiles = G.ntx * G.nty;
+    G.fuse_sort = TW == 8 && TH == 8 ? 1 : 0;   // the wave-tile kernel sorts its own segments
     const size_t M = (size_t)G.ntiles;
     if (!T.status_h) {
         HIPCHK(c, hipHostMalloc((void**)&T.status_h, sizeof(DevStatus), hipHostMallocDefault));
@@ -1248,18 +1250,18 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     B.keys = (uint64_t*)T.keys.p;
     B.capacity = T.capacity;
     const void* key[8] = {geo->depth, geo->offset, geo->radius, geo->opacity, geo->sigma, obs_depth, pose, tr};
+    // Each iteration's scan clears the counts it read and rewrites total,
+    // overflow and queue; a non-finite flag, once raised, stays for the call.
     auto enqueue = [&](hipStream_t q) -> bool {
-        launch_zero_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, q);
+        launch_zero2_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, B.tile_count, (int64_t)M, q);
         for (int it = 0; it < iters; ++it) {
             launch_track_pair(pose, geo->T_cw, geo->cam, *vcam, pair_dev, q);
-            launch_zero_u32((uint32_t*)B.status, 4, q);   // keeps the sticky word
-            launch_zero_u32(B.tile_count, (int64_t)M, q);
             launch_preprocess(G, B, q);
-            launch_scan(G, B, false, q);
+            launch_scan(G, B, true, q);
             launch_scatter(G, B, q);
             launch_sort(G, B, q);
             if (!launch_track(G, B, obs_depth, (float*)T.part.p, q)) return false;
-            launch_track_solve((const float*)T.part.p, G.ntiles, pose, tr, it, B.status, q);
+            launch_track_solve((const float*)T.part.p, track_parts(G), pose, tr, it, B.status, q);
         }
         return true;
     };

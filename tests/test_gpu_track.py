@@ -8,13 +8,15 @@ from paper_2603_21055_amd import synth
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[(16, 16), (8, 8)], ids=["wg16x16", "wave8x8"])
+def ctx(request):
+    """Workgroup tiles (full-list walk) and 8x8 wave tiles (candidate walk,
+    in-kernel segment sort)."""
     import torch
     from paper_2603_21055_amd import sgad
     assert torch.cuda.is_available()
     c = sgad.Context(0)
-    c.set_tile(16, 16)
+    c.set_tile(*request.param)
     yield c
     c.close()
 
@@ -127,20 +129,27 @@ def test_single_plane_takes_damped_steps(ctx):
     assert abs(pose[11] - 0.01) < 1e-3
 
 
-def test_c4_full_size_first_iteration(ctx):
-    print("track C4 1200x680 first iteration (oracle ~1 min)", flush=True)
+@pytest.fixture(scope="module")
+def c4():
+    print("C4 1200x680 scene and oracle linearisation (~1 min)", flush=True)
     sc = synth.c4_tracking(30)
-    pose, tr = _run(ctx, sc, sc["obs_depth"], 1, graph=False)
     lin = track.linearise(sc["geo"], sc["cam"], sc["init"]["R"].astype(np.float64),
                           sc["init"]["t"].astype(np.float64), sc["obs_depth"].astype(np.float64))
+    return sc, lin
+
+
+def test_c4_full_size_first_iteration(ctx, c4):
+    print("track C4 1200x680 first iteration", flush=True)
+    sc, lin = c4
+    pose, tr = _run(ctx, sc, sc["obs_depth"], 1, graph=False)
     H = _unpack_H(tr[0])
     assert np.linalg.norm(H - lin["H"]) <= 1e-3 * np.linalg.norm(lin["H"])
     assert np.linalg.norm(tr[0, 21:27] - lin["g"]) <= 1e-3 * np.linalg.norm(lin["g"])
 
 
-def test_c4_full_size_converges(ctx):
+def test_c4_full_size_converges(ctx, c4):
     print("track C4 1200x680 30 iterations", flush=True)
-    sc = synth.c4_tracking(30)
+    sc, _ = c4
     pose, tr = _run(ctx, sc, sc["obs_depth"], 30, graph=True)
     et, er = _pose_err(pose, sc["gt"]["R"], sc["gt"]["t"])
     # analytic box depth vs the splatted model (a blurred surface): the
