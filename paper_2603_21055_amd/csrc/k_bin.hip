@@ -221,80 +221,178 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of the per-(job, tile) counts in one 1024-thread block; also
-// publishes the total, the overflow flag, and clears the fill counters and the
-// work-queue counter (and, with zero_counts, the counts themselves, so that
-// the next call's count pass needs no clearing launch).
+// Exclusive scan of the per-(job, tile) counts (and of their 64-entry chunk
+// counts) in one 1024-thread block.  Up to 6144 elements: one pass, thread t
+// owning ceil(M / 1024) consecutive elements, all loaded before use.  More:
+// rounds of 4096 elements, thread t owning elements 4t..4t+3 of a round (a
+// wave's accesses cover one contiguous 1 KB span), the counts of up to
+// kScanPre rounds loaded up front.  Also publishes the total, the overflow flag and the
+// longest segment, and clears the fill counters and the work-queue counter
+// (and, with zero_counts, the counts themselves, so that the next call's
+// count pass needs no clearing launch).
 // ---------------------------------------------------------------------------
+constexpr int kScanIt = 4;
+constexpr int kScanPre = 4;
+constexpr int kScanRound = 1024 * kScanIt;
+constexpr int kScanSmall = 6;   // up to 6144 elements: one pass, <= 6 per thread
+
 __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ count, uint32_t* start, uint32_t* fill,
                                                uint32_t* cstart, int M, uint32_t capacity, DevStatus* st,
                                                int zero_counts) {
-    __shared__ uint32_t s_wave[16], s_cw[16];
-    const int tid = threadIdx.x;
-    const int chunk = (M + 1023) / 1024;
-    const int b = tid * chunk;
-    const int e = min(M, b + chunk);
-    uint32_t sum = 0, mx = 0, csum = 0;
-    for (int k = b; k < e; ++k) {
-        sum += count[k];
-        csum += (count[k] + 63u) >> 6;
-        mx = max(mx, count[k]);
+    __shared__ uint32_t s_w[16], s_cw[16], s_max[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (M <= 1024 * kScanSmall) {
+        // one pass: thread t owns [t * per, t * per + per)
+        const int per = (M + 1023) / 1024;
+        const int b = tid * per;
+        uint32_t c[kScanSmall];
+#pragma unroll
+        for (int j = 0; j < kScanSmall; ++j) c[j] = (j < per && b + j < M) ? count[b + j] : 0u;
+        uint32_t sum = 0, csum = 0, mx = 0;
+#pragma unroll
+        for (int j = 0; j < kScanSmall; ++j) {
+            sum += c[j];
+            csum += (c[j] + 63u) >> 6;
+            mx = max(mx, c[j]);
+        }
+        uint32_t inc = sum, cinc = csum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64), co = __shfl_up(cinc, off, 64);
+            if (lane >= off) {
+                inc += o;
+                cinc += co;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+        if (lane == 63) {
+            s_w[wave] = inc;
+            s_cw[wave] = cinc;
+        }
+        if (lane == 0) s_max[wave] = mx;
+        __syncthreads();
+        const uint32_t a0 = lane < 16 ? s_w[lane] : 0u, ca0 = lane < 16 ? s_cw[lane] : 0u;
+        uint32_t a = a0, ca = ca0;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t o = __shfl_up(a, off, 64), co = __shfl_up(ca, off, 64);
+            if (lane >= off) {
+                a += o;
+                ca += co;
+            }
+        }
+        uint32_t run = (uint32_t)__shfl((int)(a - a0), wave, 64) + inc - sum;
+        uint32_t crun = (uint32_t)__shfl((int)(ca - ca0), wave, 64) + cinc - csum;
+#pragma unroll
+        for (int j = 0; j < kScanSmall; ++j) {
+            const int i = b + j;
+            if (j < per && i < M) {
+                start[i] = run;
+                cstart[i] = crun;
+                fill[i] = 0u;
+                if (zero_counts) count[i] = 0u;   // ready for the next count pass
+            }
+            run += c[j];
+            crun += (c[j] + 63u) >> 6;
+        }
+        const uint32_t tot = (uint32_t)__shfl((int)a, 15, 64), ctot = (uint32_t)__shfl((int)ca, 15, 64);
+        if (tid == 0) {
+            start[M] = tot;
+            cstart[M] = ctot;
+            st->total = tot;
+            st->overflow = tot > capacity ? 1u : 0u;
+            st->queue = 0u;
+            uint32_t m = 0;
+            for (int w = 0; w < 16; ++w) m = max(m, s_max[w]);
+            st->max_seg = m;
+        }
+        return;
+    }
+    const int rounds = (M + kScanRound - 1) / kScanRound;
+    uint32_t pre[kScanPre][kScanIt];
+#pragma unroll
+    for (int r = 0; r < kScanPre; ++r)
+#pragma unroll
+        for (int j = 0; j < kScanIt; ++j) {
+            const int i = r * kScanRound + kScanIt * tid + j;
+            pre[r][j] = (r < rounds && i < M) ? count[i] : 0u;
+        }
+    uint32_t carry = 0, ccarry = 0, mx = 0;
+    for (int r = 0; r < rounds; ++r) {
+        const int i0 = r * kScanRound + kScanIt * tid;
+        uint32_t c[kScanIt];
+#pragma unroll
+        for (int j = 0; j < kScanIt; ++j) {
+            c[j] = 0u;
+#pragma unroll
+            for (int k = 0; k < kScanPre; ++k)
+                if (k == r) c[j] = pre[k][j];
+            if (r >= kScanPre && i0 + j < M) c[j] = count[i0 + j];
+        }
+        uint32_t cc[kScanIt], sum = 0, csum = 0;
+#pragma unroll
+        for (int j = 0; j < kScanIt; ++j) {
+            cc[j] = (c[j] + 63u) >> 6;
+            sum += c[j];
+            csum += cc[j];
+            mx = max(mx, c[j]);
+        }
+        // inclusive scan of the per-thread sums across the wave
+        uint32_t inc = sum, cinc = csum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64), co = __shfl_up(cinc, off, 64);
+            if (lane >= off) {
+                inc += o;
+                cinc += co;
+            }
+        }
+        if (lane == 63) {
+            s_w[wave] = inc;
+            s_cw[wave] = cinc;
+        }
+        __syncthreads();
+        // every wave scans the 16 wave totals itself (lanes 0-15)
+        const uint32_t a0 = lane < 16 ? s_w[lane] : 0u, ca0 = lane < 16 ? s_cw[lane] : 0u;
+        uint32_t a = a0, ca = ca0;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t o = __shfl_up(a, off, 64), co = __shfl_up(ca, off, 64);
+            if (lane >= off) {
+                a += o;
+                ca += co;
+            }
+        }
+        const uint32_t tot = (uint32_t)__shfl((int)a, 15, 64), ctot = (uint32_t)__shfl((int)ca, 15, 64);
+        const uint32_t wo = (uint32_t)__shfl((int)(a - a0), wave, 64);     // exclusive wave offsets
+        const uint32_t cwo = (uint32_t)__shfl((int)(ca - ca0), wave, 64);
+        uint32_t run = carry + wo + inc - sum, crun = ccarry + cwo + cinc - csum;
+#pragma unroll
+        for (int j = 0; j < kScanIt; ++j) {
+            const int i = i0 + j;
+            if (i < M) {
+                start[i] = run;
+                cstart[i] = crun;
+                fill[i] = 0u;
+                if (zero_counts) count[i] = 0u;   // ready for the next count pass
+            }
+            run += c[j];
+            crun += cc[j];
+        }
+        carry += tot;
+        ccarry += ctot;
+        __syncthreads();   // s_w is rewritten by the next round
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
-    __shared__ uint32_t s_max[16];
-    // inclusive scan across the wave
-    const int lane = tid & 63, wave = tid >> 6;
-    uint32_t inc = sum, cinc = csum;
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t o = __shfl_up(inc, off, 64);
-        uint32_t co = __shfl_up(cinc, off, 64);
-        if (lane >= off) {
-            inc += o;
-            cinc += co;
-        }
-    }
-    if (lane == 63) {
-        s_wave[wave] = inc;
-        s_cw[wave] = cinc;
-    }
     if (lane == 0) s_max[wave] = mx;
     __syncthreads();
-    if (wave == 0) {
-        uint32_t w = lane < 16 ? s_wave[lane] : 0u;
-        uint32_t cw = lane < 16 ? s_cw[lane] : 0u;
-        uint32_t wi = w, cwi = cw;
-        for (int off = 1; off < 16; off <<= 1) {
-            uint32_t o = __shfl_up(wi, off, 64);
-            uint32_t co = __shfl_up(cwi, off, 64);
-            if (lane >= off) {
-                wi += o;
-                cwi += co;
-            }
-        }
-        if (lane < 16) {
-            s_wave[lane] = wi - w;  // exclusive wave offsets
-            s_cw[lane] = cwi - cw;
-        }
-    }
-    __syncthreads();
-    uint32_t run = s_wave[wave] + inc - sum;
-    uint32_t crun = s_cw[wave] + cinc - csum;
-    for (int k = b; k < e; ++k) {
-        const uint32_t ck = count[k];
-        start[k] = run;
-        cstart[k] = crun;
-        run += ck;
-        crun += (ck + 63u) >> 6;
-        fill[k] = 0u;
-        if (zero_counts) count[k] = 0u;   // ready for the next count pass
-    }
-    if (tid == 1023) {
-        const uint32_t tot = s_wave[wave] + inc;
-        start[M] = tot;
-        cstart[M] = s_cw[wave] + cinc;
-        st->total = tot;
-        st->overflow = tot > capacity ? 1u : 0u;
+    if (tid == 0) {
+        start[M] = carry;
+        cstart[M] = ccarry;
+        st->total = carry;
+        st->overflow = carry > capacity ? 1u : 0u;
         st->queue = 0u;
         uint32_t m = 0;
         for (int w = 0; w < 16; ++w) m = max(m, s_max[w]);
