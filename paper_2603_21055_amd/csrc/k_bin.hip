@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
     rec[1] = make_float4(fa, fb, fc, kp.opacity[pix]);
     rec[2] = make_float4(c0, c1, c2, fz);
     rec[3] = make_float4(ok ? (float)x : 0.f, ok ? (float)y : 0.f, Rf, s >= 0.0 ? 1.f : -1.f);
-    {
+    if (B.pre.dir) {   // (tracking has no adjoint and leaves it out)
         // offset direction: the view-space centre moves by R (xn, yn, 1) per
         // unit of |D + delta|, and |D + delta| by sign(D + delta) per unit of delta
         const double sg = s >= 0.0 ? 1.0 : -1.0;
@@ -488,8 +488,9 @@ __device__ void sort_long_segment(uint64_t* g, int n, uint64_t* s) {
 }
 
 // Segments longer than 1024 keys, launched when the previous forward of the
-// workload had one (the scan records the longest segment); one workgroup per
-// segment, LDS up to kSortLds keys.
+// workload had one (the scan records the longest segment), and always for
+// tracking; one workgroup per segment (long segments come in numbers when
+// several keyframes overlap a view), LDS up to kSortLds keys.
 __global__ __launch_bounds__(256) void k_sort_long(Geometry G, RenderBufs B) {
     __shared__ uint64_t s[kSortLds];
     if (B.status->overflow) return;

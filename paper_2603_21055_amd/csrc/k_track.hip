@@ -35,9 +35,9 @@ __device__ __forceinline__ float twave_sum(float v) {
 
 // Relative pose of the geometry keyframe in the view whose world->camera pose
 // is the device FP64 state, same operation order as the host version.
-__global__ void k_track_pair(const double* pose, sgad_pose kf_pose, sgad_cam kc, sgad_cam vc, PairConst* out) {
+__device__ void make_track_pair(const double* pose, const sgad_pose& kf_pose, const sgad_cam& kc,
+                                const sgad_cam& vc, PairConst* out) {
 #pragma clang fp contract(off)
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     PairConst pc;
     double Rf[9], tf[3];
     for (int i = 0; i < 9; ++i) Rf[i] = (double)kf_pose.R[i];
@@ -71,6 +71,11 @@ __global__ void k_track_pair(const double* pose, sgad_pose kf_pose, sgad_cam kc,
     pc.job = 0;
     pc.kf = 0;
     *out = pc;
+}
+
+__global__ void k_track_pair(const double* pose, sgad_pose kf_pose, sgad_cam kc, sgad_cam vc, PairConst* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    make_track_pair(pose, kf_pose, kc, vc, out);
 }
 
 struct TrackEntry {
@@ -232,7 +237,7 @@ __global__ __launch_bounds__(TW* TH) void k_track(Geometry G, RenderBufs B, cons
     if (tid < kTrackVals) {
         float acc = 0.f;
         for (int w = 0; w < NW; ++w) acc += s_red[w][tid];
-        part[(size_t)item * 32 + tid] = acc;
+        part[(size_t)tid * gridDim.x + item] = acc;   // value-major: [value][item]
     }
 }
 
@@ -408,7 +413,7 @@ __global__ __launch_bounds__(256) void k_track8(Geometry G, RenderBufs B, const 
     __syncthreads();
     if (threadIdx.x < kTrackVals) {
         const int t = threadIdx.x;
-        part[(size_t)blk * 32 + t] = (s_red[0][t] + s_red[1][t]) + (s_red[2][t] + s_red[3][t]);
+        part[(size_t)t * gridDim.x + blk] = (s_red[0][t] + s_red[1][t]) + (s_red[2][t] + s_red[3][t]);
     }
 }
 
@@ -431,16 +436,18 @@ __device__ bool chol6(const double* A, double* L) {
     return true;
 }
 
-__global__ __launch_bounds__(256) void k_track_solve(const float* part, int nitems, double* pose, double* trace,
-                                                      int it, const DevStatus* st) {
-    __shared__ double s_acc[4][kTrackVals];
+// Also forms the next iteration's relative pose (`next`, when not null).
+__global__ __launch_bounds__(512) void k_track_solve(const float* part, int nitems, double* pose, double* trace,
+                                                      int it, const DevStatus* st, sgad_pose kf_pose, sgad_cam kc,
+                                                      sgad_cam vc, PairConst* next) {
+    __shared__ double s_acc[8][kTrackVals];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double acc[kTrackVals];
 #pragma unroll
     for (int i = 0; i < kTrackVals; ++i) acc[i] = 0.0;
     for (int t = tid; t < nitems; t += blockDim.x)
 #pragma unroll
-        for (int i = 0; i < kTrackVals; ++i) acc[i] += (double)part[(size_t)t * 32 + i];
+        for (int i = 0; i < kTrackVals; ++i) acc[i] += (double)part[(size_t)i * nitems + t];
 #pragma unroll
     for (int i = 0; i < kTrackVals; ++i) {
         double v = acc[i];
@@ -450,7 +457,11 @@ __global__ __launch_bounds__(256) void k_track_solve(const float* part, int nite
     __syncthreads();
     if (tid != 0) return;
     double S[kTrackVals];
-    for (int i = 0; i < kTrackVals; ++i) S[i] = s_acc[0][i] + s_acc[1][i] + s_acc[2][i] + s_acc[3][i];
+    for (int i = 0; i < kTrackVals; ++i) {
+        double v = 0.0;
+        for (int w = 0; w < 8; ++w) v += s_acc[w][i];
+        S[i] = v;
+    }
     double H[36], g[6];
     int q = 0;
     for (int i = 0; i < 6; ++i)
@@ -535,6 +546,7 @@ __global__ __launch_bounds__(256) void k_track_solve(const float* part, int nite
     }
     for (int i = 0; i < 9; ++i) pose[i] = Rn[i];
     for (int i = 0; i < 3; ++i) pose[9 + i] = tn[i];
+    if (next) make_track_pair(pose, kf_pose, kc, vc, next);
 }
 
 void launch_track_pair(const double* pose, const sgad_pose& kf_pose, const sgad_cam& kc, const sgad_cam& vc,
@@ -557,8 +569,10 @@ bool launch_track(const Geometry& G, const RenderBufs& B, const float* obs, floa
 }
 
 void launch_track_solve(const float* part, int nitems, double* pose, double* trace, int it, const DevStatus* st,
+                        const sgad_pose& kf_pose, const sgad_cam& kc, const sgad_cam& vc, PairConst* next,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_track_solve, dim3(1), dim3(256), 0, s, part, nitems, pose, trace, it, st);
+    hipLaunchKernelGGL(k_track_solve, dim3(1), dim3(512), 0, s, part, nitems, pose, trace, it, st, kf_pose, kc, vc,
+                       next);
 }
 
 }  // namespace sgad

@@ -41,6 +41,7 @@ void launch_track_pair(const double* pose, const sgad_pose& kf_pose, const sgad_
 bool launch_track(const Geometry& G, const RenderBufs& B, const float* obs, float* part, hipStream_t s);
 int track_parts(const Geometry& G);
 void launch_track_solve(const float* part, int nitems, double* pose, double* trace, int it, const DevStatus* st,
+                        const sgad_pose& kf_pose, const sgad_cam& kc, const sgad_cam& vc, PairConst* next,
                         hipStream_t s);
 }  // namespace sgad
 
@@ -1208,7 +1209,7 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     B.pair_of = (const int32_t*)(pb + 768);
     char* pp = (char*)T.pre.p;
     B.pre.rec = (float4*)pp;
-    B.pre.dir = (float4*)(pp + (size_t)N * 64);
+    B.pre.dir = nullptr;   // no adjoint: the offset directions are not needed
     B.pre.z = (float*)(pp + (size_t)N * 80);
     B.pre.rx = (uint32_t*)(pp + (size_t)N * 84);
     B.pre.ry = (uint32_t*)(pp + (size_t)N * 88);
@@ -1254,14 +1255,16 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     // overflow and queue; a non-finite flag, once raised, stays for the call.
     auto enqueue = [&](hipStream_t q) -> bool {
         launch_zero2_u32((uint32_t*)B.status, sizeof(DevStatus) / 4, B.tile_count, (int64_t)M, q);
+        launch_track_pair(pose, geo->T_cw, geo->cam, *vcam, pair_dev, q);
         for (int it = 0; it < iters; ++it) {
-            launch_track_pair(pose, geo->T_cw, geo->cam, *vcam, pair_dev, q);
             launch_preprocess(G, B, q);
             launch_scan(G, B, true, q);
             launch_scatter(G, B, q);
             launch_sort(G, B, q);
             if (!launch_track(G, B, obs_depth, (float*)T.part.p, q)) return false;
-            launch_track_solve((const float*)T.part.p, track_parts(G), pose, tr, it, B.status, q);
+            // the solve also forms the next iteration's relative pose
+            launch_track_solve((const float*)T.part.p, track_parts(G), pose, tr, it, B.status, geo->T_cw,
+                               geo->cam, *vcam, it + 1 < iters ? pair_dev : nullptr, q);
         }
         return true;
     };

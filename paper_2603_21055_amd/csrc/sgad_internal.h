@@ -63,7 +63,7 @@ struct DevStatus {
 // depth, (x, y) the view-space centre, r the radius.
 struct Preproc {
     float4* rec;   // [n_pairs * N * 4]
-    float4* dir;   // [n_pairs * N]: d(view-space centre)/d(offset) = sign(D + delta) R_rel (xn, yn, 1), 0
+    float4* dir;   // [n_pairs * N]: d(view-space centre)/d(offset) = sign(D + delta) R_rel (xn, yn, 1), 0; null: not written
     uint32_t* rx;  // tile x0 | x1 << 16
     uint32_t* ry;  // tile y0 | y1 << 16
     float* z;      // view depth (float), the sort key source
