@@ -458,8 +458,68 @@ __global__ __launch_bounds__(64) void k_sort(Geometry G, RenderBufs B) {
     sort_segment(g, n, threadIdx.x, G.sort_long != 0);
 }
 
+// Segments of 1025..4096 keys by a 256-thread workgroup: each wave sorts a
+// run of 1024 keys in registers (padded with all-ones keys past n) into LDS,
+// then the runs are merged pairwise, 1024 + 1024 and 2048 + 2048.  Each
+// thread merges E consecutive outputs of a pair: it finds how many of them
+// come from the first run by a binary search along its output diagonal
+// (merge path; keys are unique, so the split is unambiguous), merges into
+// registers, and writes them back after the whole workgroup has read.
+__device__ void sort_merge_segment(uint64_t* g, int n, uint64_t* s) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int np2 = n <= 2048 ? 2048 : 4096;
+    if (wave < np2 / 1024) {
+        uint64_t x[16];
+        const int b = wave * 1024 + lane * 16;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = b + r < n ? g[b + r] : ~0ull;
+        wave_sort_regs<16>(x, lane);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s[b + r] = x[r];
+    }
+    __syncthreads();
+    constexpr int kMaxE = 16;
+    const int E = np2 / 256;   // outputs per thread: 8 or 16
+    for (int width = 1024; width < np2; width <<= 1) {
+        const int o0 = tid * E;
+        const int base = (o0 / (2 * width)) * (2 * width);
+        const uint64_t* A = s + base;
+        const uint64_t* Bv = A + width;
+        const int o = o0 - base;
+        int lo = o > width ? o - width : 0, hi = o < width ? o : width;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (A[mid] < Bv[o - mid - 1]) lo = mid + 1;
+            else hi = mid;
+        }
+        int i = lo, j = o - lo;
+        uint64_t out[kMaxE];
+#pragma unroll
+        for (int e = 0; e < kMaxE; ++e) {
+            if (e < E) {
+                const uint64_t a = i < width ? A[i] : ~0ull;
+                const uint64_t bb = j < width ? Bv[j] : ~0ull;
+                const bool ta = j >= width || (i < width && a < bb);
+                out[e] = ta ? a : bb;
+                i += ta ? 1 : 0;
+                j += ta ? 0 : 1;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kMaxE; ++e)
+            if (e < E) s[o0 + e] = out[e];
+        __syncthreads();
+    }
+    for (int k = tid; k < n; k += blockDim.x) g[k] = s[k];
+}
+
 __device__ void sort_long_segment(uint64_t* g, int n, uint64_t* s) {
     const int tid = threadIdx.x;
+    if (n <= 4096 && blockDim.x == 256) {
+        sort_merge_segment(g, n, s);
+        return;
+    }
     int np2 = 1;
     while (np2 < n) np2 <<= 1;
     if (np2 <= kSortLds) {

@@ -38,14 +38,10 @@ __device__ __forceinline__ void sort_in_lane(uint64_t (&x)[K], int j) {
     }
 }
 
+// Ascending bitonic sort of the 64 K keys a wave holds in registers (key
+// i = lane * K + r in register r).
 template <int K>
-__device__ __forceinline__ void wave_sort_segment(uint64_t* g, int n, int lane) {
-    uint64_t x[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-        const int i = lane * K + r;
-        x[r] = i < n ? g[i] : ~0ull;
-    }
+__device__ __forceinline__ void wave_sort_regs(uint64_t (&x)[K], int lane) {
 #pragma unroll
     for (int k = 2; k <= 64 * K; k <<= 1) {
         if (k <= K) {
@@ -88,6 +84,17 @@ __device__ __forceinline__ void wave_sort_segment(uint64_t* g, int n, int lane) 
             }
         }
     }
+}
+
+template <int K>
+__device__ __forceinline__ void wave_sort_segment(uint64_t* g, int n, int lane) {
+    uint64_t x[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int i = lane * K + r;
+        x[r] = i < n ? g[i] : ~0ull;
+    }
+    wave_sort_regs<K>(x, lane);
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         const int i = lane * K + r;
