@@ -111,15 +111,17 @@ sgad_status sgad_sync(sgad_ctx* ctx);
 /* Tile shape of the compositing kernels: (8,8) (one tile per wavefront,
  * per-pixel candidate masks), (16,8), (16,16) or (32,8) (one tile per
  * workgroup, full-list walk); (0,0), the default, uses the configuration
- * sgad_autotune measured for the workload, else (8,8).  Results do not
- * depend on the tile shape. */
+ * sgad_autotune measured for the workload, else (8,8).  Forward outputs do
+ * not depend on the tile shape; gradients agree to rounding. */
 sgad_status sgad_set_tile(sgad_ctx* ctx, int tile_w, int tile_h);
 /* Tile shape used by the last forward (after autotuning). */
 sgad_status sgad_get_tile(const sgad_ctx* ctx, int* tile_w, int* tile_h);
 /* Kernel variant used with a tile of (8,8) set by sgad_set_tile:
  * fwd_chunks = 64-entry chunks the forward publishes at once (1, 2 or 4;
  * default 4), bwd_sub = entries per adjoint sub-chunk (16 or 32; default
- * 16).  Results do not depend on it.  SGAD_EINVAL for other values. */
+ * 16).  Forward outputs do not depend on it; gradients agree to rounding
+ * (the adjoint's sums are grouped differently).  SGAD_EINVAL for other
+ * values. */
 sgad_status sgad_set_tile_variant(sgad_ctx* ctx, int fwd_chunks, int bwd_sub);
 /* Kernel variant of the last forward's 8x8 wave tiles (after autotuning):
  * *fwd_chunks = 64-entry chunks the forward publishes at once (1, 2 or 4),

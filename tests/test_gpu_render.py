@@ -98,6 +98,42 @@ def test_tile_shape_does_not_change_forward(ctx):
             assert np.array_equal(o[k], outs[0][k]), k
 
 
+VARIANTS = [(1, 16), (2, 16), (4, 16), (1, 32), (4, 32)]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_wave_tile_variants_parity(ctx, variant):
+    """Every 8x8 kernel variant (chunks the forward publishes at once, adjoint
+    sub-chunk) matches the oracle, forward and gradients."""
+    ctx.set_tile_variant(*variant)
+    try:
+        sc = synth.small_scene(25, 100, 75, n_kf=2, n_views=1, offset_amp=0.03, max_trans=0.05, max_rot=3)
+        _run_case(ctx, sc, [(0, [0, 1])], (8, 8), learnable=[0, 1])
+    finally:
+        ctx.set_tile_variant(4, 16)
+
+
+def test_wave_tile_variants_do_not_change_forward(ctx):
+    import torch
+    sc = synth.small_scene(26, 100, 75, n_kf=2, n_views=1, offset_amp=0.03, max_trans=0.05, max_rot=3)
+    kfs_d = H.upload(sc["kfs"], ctx.device)
+    ctx.set_tile(8, 8)
+    outs = []
+    try:
+        for v in VARIANTS:
+            ctx.set_tile_variant(*v)
+            saved, out = H.gpu_render(ctx, kfs_d, sc["views"], [(0, [0, 1])])
+            torch.cuda.synchronize()
+            assert ctx.get_tile_variant() == v
+            outs.append({k: x.cpu().numpy() for k, x in out.items()})
+            ctx.release(saved)
+    finally:
+        ctx.set_tile_variant(4, 16)
+    for o in outs[1:]:
+        for k in ("rgb", "depth", "alpha", "count"):
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
 def test_forward_is_deterministic(ctx):
     import torch
     sc = synth.small_scene(25, 64, 48, n_kf=2, n_views=1, offset_amp=0.03)
