@@ -46,10 +46,10 @@ KERNEL_SOURCES = {
     "composite_fwd": ("k_raster8.hip", "raster_common.h", "segsort.h", "sgad_internal.h"),
 }
 PMC = {    # kernel -> counters per dispatch and the sources they were taken on
-    "composite_bwd": dict(fetch_kib=26848.5, write_kib=84981.3,
-                          sha="a8519670ce324b43505e9c54dfa041991711d775292873896d165b8a784628aa"),
-    "composite_fwd": dict(fetch_kib=16246.1, write_kib=28953.7,
-                          sha="a8519670ce324b43505e9c54dfa041991711d775292873896d165b8a784628aa"),
+    "composite_bwd": dict(fetch_kib=26844.2, write_kib=84981.1,
+                          sha="7477b35d226677134d26dc5eec54330fa1b162d609c8b2baa4a5417e86936584"),
+    "composite_fwd": dict(fetch_kib=16218.2, write_kib=28956.3,
+                          sha="7477b35d226677134d26dc5eec54330fa1b162d609c8b2baa4a5417e86936584"),
 }
 
 
