@@ -458,29 +458,39 @@ __global__ __launch_bounds__(64) void k_sort(Geometry G, RenderBufs B) {
     sort_segment(g, n, threadIdx.x, G.sort_long != 0);
 }
 
-// Segments of 1025..4096 keys by a 256-thread workgroup: each wave sorts a
-// run of 1024 keys in registers (padded with all-ones keys past n) into LDS,
-// then the runs are merged pairwise, 1024 + 1024 and 2048 + 2048.  Each
-// thread merges E consecutive outputs of a pair: it finds how many of them
-// come from the first run by a binary search along its output diagonal
-// (merge path; keys are unique, so the split is unambiguous), merges into
-// registers, and writes them back after the whole workgroup has read.
+// Segments of 1025..4096 keys by a 256-thread workgroup: each of the four
+// waves sorts a run of np2 / 4 keys (512 or 1024, padded with all-ones keys
+// past n) in registers into LDS, then the runs are merged pairwise in two
+// levels.  Each thread merges E consecutive outputs of a pair: it finds how
+// many of them come from the first run by a binary search along its output
+// diagonal (merge path; keys are unique, so the split is unambiguous),
+// merges into registers, and writes them back after the whole workgroup has
+// read.
+template <int K>
+__device__ __forceinline__ void sort_run(const uint64_t* g, int n, uint64_t* s, int wave, int lane) {
+    uint64_t x[K];
+    const int b = wave * 64 * K + lane * K;
+#pragma unroll
+    for (int r = 0; r < K; ++r) x[r] = b + r < n ? g[b + r] : ~0ull;
+    wave_sort_regs<K>(x, lane);
+#pragma unroll
+    for (int r = 0; r < K; ++r) s[b + r] = x[r];
+}
+
+template <int NMAX>
 __device__ void sort_merge_segment(uint64_t* g, int n, uint64_t* s) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int np2 = n <= 2048 ? 2048 : 4096;
-    if (wave < np2 / 1024) {
-        uint64_t x[16];
-        const int b = wave * 1024 + lane * 16;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = b + r < n ? g[b + r] : ~0ull;
-        wave_sort_regs<16>(x, lane);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) s[b + r] = x[r];
+    if constexpr (NMAX <= 2048) {
+        sort_run<8>(g, n, s, wave, lane);   // (n <= NMAX here)
+    } else {
+        if (np2 == 2048) sort_run<8>(g, n, s, wave, lane);
+        else sort_run<16>(g, n, s, wave, lane);
     }
     __syncthreads();
     constexpr int kMaxE = 16;
     const int E = np2 / 256;   // outputs per thread: 8 or 16
-    for (int width = 1024; width < np2; width <<= 1) {
+    for (int width = np2 / 4; width < np2; width <<= 1) {
         const int o0 = tid * E;
         const int base = (o0 / (2 * width)) * (2 * width);
         const uint64_t* A = s + base;
@@ -514,15 +524,18 @@ __device__ void sort_merge_segment(uint64_t* g, int n, uint64_t* s) {
     for (int k = tid; k < n; k += blockDim.x) g[k] = s[k];
 }
 
+// LDS of NMAX keys: merge sort up to min(NMAX, 4096) keys, the bitonic
+// network in LDS up to NMAX, else in place in global memory.
+template <int NMAX>
 __device__ void sort_long_segment(uint64_t* g, int n, uint64_t* s) {
     const int tid = threadIdx.x;
-    if (n <= 4096 && blockDim.x == 256) {
-        sort_merge_segment(g, n, s);
+    if (n <= NMAX && n <= 4096 && blockDim.x == 256) {
+        sort_merge_segment<NMAX>(g, n, s);
         return;
     }
     int np2 = 1;
     while (np2 < n) np2 <<= 1;
-    if (np2 <= kSortLds) {
+    if (np2 <= NMAX) {
         for (int k = tid; k < np2; k += blockDim.x) s[k] = k < n ? g[k] : ~0ull;
         __syncthreads();
         for (int k = 2; k <= np2; k <<= 1) {
@@ -550,15 +563,17 @@ __device__ void sort_long_segment(uint64_t* g, int n, uint64_t* s) {
 // Segments longer than 1024 keys, launched when the previous forward of the
 // workload had one (the scan records the longest segment), and always for
 // tracking; one workgroup per segment (long segments come in numbers when
-// several keyframes overlap a view), LDS up to kSortLds keys.
+// several keyframes overlap a view).  NMAX = 2048 when the previous forward's
+// longest segment fit (twice the workgroups per CU), else 4096.
+template <int NMAX>
 __global__ __launch_bounds__(256) void k_sort_long(Geometry G, RenderBufs B) {
-    __shared__ uint64_t s[kSortLds];
+    __shared__ uint64_t s[NMAX];
     if (B.status->overflow) return;
     const int seg = blockIdx.x;
     const uint32_t st = B.tile_start[seg];
     const int n = (int)(B.tile_start[seg + 1] - st);
     if (n <= 1024) return;
-    sort_long_segment(B.keys + st, n, s);
+    sort_long_segment<NMAX>(B.keys + st, n, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -608,7 +623,8 @@ void launch_scatter(const Geometry& G, const RenderBufs& B, hipStream_t s) {
 void launch_sort(const Geometry& G, const RenderBufs& B, hipStream_t s) {
     const int M = G.n_jobs * G.ntiles;
     if (!G.fuse_sort) hipLaunchKernelGGL(k_sort, dim3(M), dim3(64), 0, s, G, B);
-    if (G.sort_long) hipLaunchKernelGGL(k_sort_long, dim3(M), dim3(256), 0, s, G, B);
+    if (G.sort_long == 1) hipLaunchKernelGGL(k_sort_long<2048>, dim3(M), dim3(256), 0, s, G, B);
+    else if (G.sort_long) hipLaunchKernelGGL(k_sort_long<kSortLds>, dim3(M), dim3(256), 0, s, G, B);
 }
 
 }  // namespace sgad

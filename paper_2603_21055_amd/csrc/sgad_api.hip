@@ -733,7 +733,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     // the long-segment sort pass only when the last forward of this workload
     // had a segment over 1024 keys (or is unknown); else the register sort
     // falls back to a global-memory network for any segment that grew past it
-    G.sort_long = S->last_max_seg > 1024u ? 1 : 0;
+    G.sort_long = S->last_max_seg <= 1024u ? 0 : (S->last_max_seg <= 2048u ? 1 : 2);
     if (!S->sized && S->capacity == 0) {
         // first use: a generous guess that is corrected after the count pass
         const size_t guess = NP * 3 + 65536;

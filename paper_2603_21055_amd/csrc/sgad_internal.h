@@ -75,7 +75,8 @@ struct Geometry {
     int Hv, Wv, P;        // view size
     int TW, TH, ntx, nty, ntiles;
     int sc_fwd = 4;    // 64-entry chunks the 8x8 forward publishes at once (1, 2 or 4)
-    int sort_long = 1; // run the long-segment sort pass (else the register sort takes all)
+    int sort_long = 2; // long-segment sort pass: 0 none (the register sort takes all), 1 LDS for up to
+                       // 2048 keys, 2 up to 4096
     int sc_bwd = 16;   // backward sub-chunk of the 8x8 kernels (16 or 32 entries)
     int fuse_sort = 0; // the 8x8 forward sorts its own segment (no separate sort launch)
 };

@@ -228,6 +228,34 @@ def test_long_lists_sorted_without_the_long_pass(ctx):
     ctx.sync()
 
 
+def test_long_lists_two_kilo_pass(ctx):
+    """Once the workload's longest segment is known to be <= 2048 keys the
+    long pass runs with half the LDS (1025..2048-key segments as four
+    512-key runs merged in two levels); a segment that then grows past 2048
+    is sorted in global memory by the same pass."""
+    import torch
+    print("long lists: 2048-key pass", flush=True)
+    ctx.set_tile(8, 8)
+
+    def check(sc):
+        saved, _ = H.gpu_render(ctx, H.upload(sc["kfs"], ctx.device), sc["views"], [(0, [0, 1, 2])])
+        torch.cuda.synchronize()
+        ranges, keys = ctx.instances(saved, 0)
+        g = splat.gather_job(sc["kfs"], sc["views"][0], [0, 1, 2])
+        b = splat.bin_and_sort(g, 48, 32, 8, 8)
+        assert np.array_equal(ranges.astype(np.int64), b["ranges"])
+        assert np.array_equal((keys >> np.uint64(32)).astype(np.uint32), b["zbits"])
+        assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.int64), b["gid"])
+        ctx.release(saved)
+        ctx.sync()              # the slot records the longest segment
+        return (b["ranges"][:, 1] - b["ranges"][:, 0]).max()
+
+    mid = _wide_scene(2.5)      # lists of 748-1898 keys
+    assert 1024 < check(mid) <= 2048
+    assert 1024 < check(mid) <= 2048     # now through the 2048-key pass
+    assert check(_wide_scene(3.5)) > 2048   # past it: the global-memory network
+
+
 @pytest.mark.parametrize("fac", [1, 4])
 def test_long_lists_render_parity(ctx, fac):
     """Faint wide Gaussians: hundreds of contributors per pixel, so the walks
