@@ -46,10 +46,10 @@ KERNEL_SOURCES = {
     "composite_fwd": ("k_raster8.hip", "raster_common.h", "segsort.h", "sgad_internal.h"),
 }
 PMC = {    # kernel -> counters per dispatch and the sources they were taken on
-    "composite_bwd": dict(fetch_kib=26844.2, write_kib=84981.1,
-                          sha="7477b35d226677134d26dc5eec54330fa1b162d609c8b2baa4a5417e86936584"),
-    "composite_fwd": dict(fetch_kib=16218.2, write_kib=28956.3,
-                          sha="7477b35d226677134d26dc5eec54330fa1b162d609c8b2baa4a5417e86936584"),
+    "composite_bwd": dict(fetch_kib=26837.8, write_kib=84982.0,
+                          sha="ebeec503754b6262fa7528add994ea0853911354f9e5cd71f959e90906daab55"),
+    "composite_fwd": dict(fetch_kib=16235.0, write_kib=28966.9,
+                          sha="ebeec503754b6262fa7528add994ea0853911354f9e5cd71f959e90906daab55"),
 }
 
 
