@@ -78,14 +78,16 @@ __global__ void k_track_pair(const double* pose, sgad_pose kf_pose, sgad_cam kc,
     make_track_pair(pose, kf_pose, kc, vc, out);
 }
 
+// 96 bytes per entry in LDS; the Jacobian's jx = fx / z and jy = fy / z are
+// formed by the walk as fx * (1/z), fy * (1/z), the products the entry would
+// have stored.
 struct TrackEntry {
     float4 u;   // u, v, dx, dy
     float4 g;   // conic a, b, c, opacity
     float4 c;   // sigma^2, z, x, y
-    float4 m;   // jx, jy, dmx/dz, dmy/dz
+    float4 m;   // 1/z, dmx/dz, dmy/dz, dc/dz
     float4 q0;  // da/dx, da/dy, da/dz, db/dx
     float4 q1;  // db/dy, db/dz, dc/dx, dc/dy
-    float4 q2;  // dc/dz, -, -, -
 };
 
 __device__ void load_track_entry(const Geometry& G, const RenderBufs& B, uint64_t key, TrackEntry& e) {
@@ -104,7 +106,7 @@ __device__ void load_track_entry(const Geometry& G, const RenderBufs& B, uint64_
     const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz, iz4 = iz2 * iz2, iz5 = iz4 * iz;
     const float r2 = r * r;
     e.c = make_float4(sg2, z, x, y);
-    e.m = make_float4(fx * iz, fy * iz, -fx * x * iz2, -fy * y * iz2);
+    e.m = make_float4(iz, -fx * x * iz2, -fy * y * iz2, 0.f);
     // dSigma/dX_k (s00, s01, s11), k = x, y, z
     const float p[3] = {r2 * 2.f * fx * fx * x * iz4, 0.f, r2 * fx * fx * (-2.f * iz3 - 4.f * x * x * iz5)};
     const float q[3] = {r2 * fx * fy * y * iz4, r2 * fx * fy * x * iz4, -4.f * r2 * fx * fy * x * y * iz5};
@@ -121,7 +123,7 @@ __device__ void load_track_entry(const Geometry& G, const RenderBufs& B, uint64_
     }
     e.q0 = make_float4(da[0], da[1], da[2], db[0]);
     e.q1 = make_float4(db[1], db[2], dc[0], dc[1]);
-    e.q2 = make_float4(dc[2], 0.f, 0.f, 0.f);
+    e.m.w = dc[2];
 }
 
 template <int TW, int TH>
@@ -140,6 +142,7 @@ __global__ __launch_bounds__(TW* TH) void k_track(Geometry G, RenderBufs B, cons
     const uint32_t st = B.tile_start[item];
     const uint32_t en = ovf ? st : B.tile_start[item + 1];
     const float fpx = (float)px, fpy = (float)py;
+    const float vfx = (float)B.pairs[0].vfx, vfy = (float)B.pairs[0].vfy;
     float T = 1.f, Dp = 0.f, Ss = 0.f;
     float dD[6] = {0, 0, 0, 0, 0, 0}, dT[6] = {0, 0, 0, 0, 0, 0};
     bool done = !inside;
@@ -168,13 +171,14 @@ __global__ __launch_bounds__(TW* TH) void k_track(Geometry G, RenderBufs B, cons
                 const float w = alpha * T;
                 float da[6];
                 if (raw < kAlphaMax) {
-                    const float4 em = s_e[k].m, q0 = s_e[k].q0, q1 = s_e[k].q1, q2 = s_e[k].q2;
+                    const float4 em = s_e[k].m, q0 = s_e[k].q0, q1 = s_e[k].q1;
+                    const float jx = vfx * em.x, jy = vfy * em.x;
                     const float gmx = -2.f * (g.x * dx + g.y * dy);
                     const float gmy = -2.f * (g.y * dx + g.z * dy);
                     const float ga = dx * dx, gb = 2.f * dx * dy, gc = dy * dy;
-                    const float vx = gmx * em.x + ga * q0.x + gb * q0.w + gc * q1.z;
-                    const float vy = gmy * em.y + ga * q0.y + gb * q1.x + gc * q1.w;
-                    const float vz = gmx * em.z + gmy * em.w + ga * q0.z + gb * q1.y + gc * q2.x;
+                    const float vx = gmx * jx + ga * q0.x + gb * q0.w + gc * q1.z;
+                    const float vy = gmy * jy + ga * q0.y + gb * q1.x + gc * q1.w;
+                    const float vz = gmx * em.y + gmy * em.z + ga * q0.z + gb * q1.y + gc * em.w;
                     const float x = ec.z, y = ec.w, z = ec.y;
                     const float h = -0.5f * alpha;
                     da[0] = h * vx;
@@ -248,7 +252,8 @@ struct TrackPix {
     float T, Dp, Ss, dD[6], dT[6];
 };
 
-__device__ __forceinline__ bool track_step(TrackPix& s, const TrackEntry& e, float fpx, float fpy) {
+__device__ __forceinline__ bool track_step(TrackPix& s, const TrackEntry& e, float fpx, float fpy, float vfx,
+                                           float vfy) {
     const float4 eu = e.u;
     const float dx = (fpx - eu.x) - eu.z, dy = (fpy - eu.y) - eu.w;
     const float4 g = e.g;
@@ -265,13 +270,14 @@ __device__ __forceinline__ bool track_step(TrackPix& s, const TrackEntry& e, flo
     const float w = alpha * s.T;
     float da[6];
     if (raw < kAlphaMax) {
-        const float4 em = e.m, q0 = e.q0, q1 = e.q1, q2 = e.q2;
+        const float4 em = e.m, q0 = e.q0, q1 = e.q1;
+        const float jx = vfx * em.x, jy = vfy * em.x;
         const float gmx = -2.f * (g.x * dx + g.y * dy);
         const float gmy = -2.f * (g.y * dx + g.z * dy);
         const float ga = dx * dx, gb = 2.f * dx * dy, gc = dy * dy;
-        const float vx = gmx * em.x + ga * q0.x + gb * q0.w + gc * q1.z;
-        const float vy = gmy * em.y + ga * q0.y + gb * q1.x + gc * q1.w;
-        const float vz = gmx * em.z + gmy * em.w + ga * q0.z + gb * q1.y + gc * q2.x;
+        const float vx = gmx * jx + ga * q0.x + gb * q0.w + gc * q1.z;
+        const float vy = gmy * jy + ga * q0.y + gb * q1.x + gc * q1.w;
+        const float vz = gmx * em.y + gmy * em.z + ga * q0.z + gb * q1.y + gc * em.w;
         const float x = ec.z, y = ec.w, z = ec.y;
         const float h = -0.5f * alpha;
         da[0] = h * vx;
@@ -350,6 +356,7 @@ __global__ __launch_bounds__(256) void k_track8(Geometry G, RenderBufs B, const 
     __syncthreads();   // sorted keys visible to every lane
     const float fpx = (float)px, fpy = (float)py;
     const float fx0 = (float)(tx * 8), fy0 = (float)(ty * 8);
+    const float vfx = (float)B.pairs[0].vfx, vfy = (float)B.pairs[0].vfy;
     TrackPix s;
     s.T = 1.f;
     s.Dp = 0.f;
@@ -394,7 +401,7 @@ __global__ __launch_bounds__(256) void k_track8(Geometry G, RenderBufs B, const 
             while (m != 0ull) {
                 const int b = (int)__builtin_ctzll(m);
                 m &= m - 1ull;
-                if (!track_step(s, se[b], fpx, fpy)) {
+                if (!track_step(s, se[b], fpx, fpy, vfx, vfy)) {
                     done = true;
                     break;
                 }
