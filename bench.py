@@ -46,9 +46,9 @@ KERNEL_SOURCES = {
     "composite_fwd": ("k_raster8.hip", "raster_common.h", "segsort.h", "sgad_internal.h"),
 }
 PMC = {    # kernel -> counters per dispatch and the sources they were taken on
-    "composite_bwd": dict(fetch_kib=26837.8, write_kib=84982.0,
+    "composite_bwd": dict(fetch_kib=26837.8, write_kib=84982.0, tile=(8, 8), variant=(1, 16),
                           sha="ebeec503754b6262fa7528add994ea0853911354f9e5cd71f959e90906daab55"),
-    "composite_fwd": dict(fetch_kib=16235.0, write_kib=28966.9,
+    "composite_fwd": dict(fetch_kib=16235.0, write_kib=28966.9, tile=(8, 8), variant=(1, 16),
                           sha="ebeec503754b6262fa7528add994ea0853911354f9e5cd71f959e90906daab55"),
 }
 
@@ -62,9 +62,15 @@ def sources_sha(kernel):
     return h.hexdigest()
 
 
-def traffic_bytes(kernel):
+def traffic_bytes(kernel, tile=None, variant=None):
+    """Counter-based HBM bytes per launch, or None when the counters were
+    taken on other sources, another tile shape or another 8x8 variant."""
     e = PMC.get(kernel)
     if e is None or e["sha"] != sources_sha(kernel):
+        return None
+    if tile is not None and tuple(tile) != e["tile"]:
+        return None
+    if variant is not None and tuple(variant) != e["variant"]:
         return None
     return (e["fetch_kib"] * FETCH_SCALE + e["write_kib"] * WRITE_SCALE) * 1024.0
 
@@ -298,16 +304,17 @@ def main():
     kern = {k: v[1] / v[0] for k, v in rep.items()}       # average ms per launch, timed region
     log("warmup kernel avg ms: " + ", ".join(f"{k}={v:.4f}" for k, v in sorted(warm.items(), key=lambda x: -x[1])))
     t_dom = kern[dom] * 1e-3
+    traffic = traffic_bytes(dom, (tw, th), ctx.get_tile_variant())   # null unless measured on this config
     if dom in FLOPS_PER_PAIR:
         achieved = pairs * FLOPS_PER_PAIR[dom] / t_dom
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=FP32_VECTOR_PEAK / 1e12, unit="TFLOP/s",
-                    frac=achieved / FP32_VECTOR_PEAK, traffic=traffic_bytes(dom), kernel=dom,
+                    frac=achieved / FP32_VECTOR_PEAK, traffic=traffic, kernel=dom,
                     kernel_ms=kern[dom], pairs_per_launch=pairs, flops_per_pair=FLOPS_PER_PAIR[dom])
     else:
         bg, bp = BYTES_BY_KERNEL.get(dom, (0, 0))
         achieved = (bg * N + bp * P) / t_dom
         roof = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                    frac=achieved / HBM_PEAK, traffic=traffic_bytes(dom), kernel=dom, kernel_ms=kern[dom])
+                    frac=achieved / HBM_PEAK, traffic=traffic, kernel=dom, kernel_ms=kern[dom])
     algo_bytes = BYTES_PER_GAUSSIAN * N + BYTES_PER_PIXEL * P
     out = dict(
         metric="fwd+bwd splat frames/s at 640x480 (%HBM roofline); mapping iters to loss, warm vs plain",
