@@ -86,7 +86,7 @@ def cpu_baseline():
 
     from oracle import splat
     from paper_2603_21055_amd import synth
-    sc = synth.c2_scene(10)
+    sc = synth.room_frame_scene(10)
     rng = np.random.default_rng(0)
     H, W = 480, 640
     gr = [rng.normal(size=(3, H, W)) / (H * W)]
@@ -98,7 +98,7 @@ def cpu_baseline():
         splat.render_backward(sc["kfs"], sc["views"], [(0, [0])], [f], gr, gd, ga)
         dt = time.perf_counter() - t0
     return dict(value=1.0 / dt, unit="frames/s", cores=1, kind="oracle",
-                sample=f"one full 640x480 frame fwd+bwd (C2 scene seed 10), {dt:.1f} s on 1 thread")
+                sample=f"one full 640x480 frame fwd+bwd (room frame, seed 10), {dt:.1f} s on 1 thread")
 
 
 def _timed(fn, steps, warmup):
@@ -122,7 +122,7 @@ def bench_window(args):
     from paper_2603_21055_amd.mapping import Mapper
     log("building 8-keyframe window")
     dev = torch.device("cuda", 0)
-    sc = synth.c3_window(20)
+    sc = synth.room_window(20)
     ctx = sgad.Context(0)
     kfs = [sgad.to_device(k, dev) for k in sc["kfs"]]
     jobs = [(v, list(range(8))) for v in range(8)]
@@ -151,7 +151,7 @@ def bench_tracking(args):
     from paper_2603_21055_amd import sgad, synth
     log("building 1200x680 tracking scene")
     dev = torch.device("cuda", 0)
-    sc = synth.c4_tracking(30)
+    sc = synth.tracking_scene(30)
     ctx = sgad.Context(0)
     geo = sgad.to_device(sc["geo"], dev)
     obs = torch.from_numpy(sc["obs_depth"]).to(dev)
@@ -214,9 +214,10 @@ def main():
     ap.add_argument("--print-sha", action="store_true", help="print the kernel-source hashes and exit")
     ap.add_argument("--graph", action="store_true", help="time replays of a captured graph of one step")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start comparison")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "copy"], default="c2",
-                    help="c2: the headline 640x480 frame; c3: 8-keyframe x 8-view window; "
-                         "c4: 1200x680 tracking; copy: plain device copy (counter calibration)")
+    ap.add_argument("--workload", choices=["frame", "window", "tracking", "copy"], default="frame",
+                    help="frame: one 640x480 keyframe into one view (the headline step); window: 8 keyframes "
+                         "x 8 views at 640x480; tracking: 1200x680 Gauss-Newton; copy: plain device copy "
+                         "(counter calibration)")
     args = ap.parse_args()
     if args.print_sha:
         print(json.dumps({k: sources_sha(k) for k in KERNEL_SOURCES}))
@@ -225,8 +226,8 @@ def main():
         print("bench.py measures one GPU only; this build has no multi-GPU path (--gpus 1).",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload != "c2":
-        return {"c3": bench_window, "c4": bench_tracking, "copy": bench_copy}[args.workload](args)
+    if args.workload != "frame":
+        return {"window": bench_window, "tracking": bench_tracking, "copy": bench_copy}[args.workload](args)
 
     frames = None
     if not args.no_warm_start:
@@ -238,7 +239,7 @@ def main():
     from paper_2603_21055_amd import sgad, synth
     log("building scene")
     dev = torch.device("cuda", 0)
-    sc = synth.c2_scene(10)
+    sc = synth.room_frame_scene(10)
     H, W = 480, 640
     N = P = H * W
     ctx = sgad.Context(0)

@@ -25,7 +25,7 @@ from scipy.spatial.transform import Rotation
 
 __all__ = [
     "intrinsics", "perturb_pose", "pose_from_c2w", "Room", "make_room",
-    "keyframe_from_frame", "c1_scene", "c2_scene", "c3_window", "c4_tracking",
+    "keyframe_from_frame", "plane_scene", "room_frame_scene", "room_window", "tracking_scene",
     "small_scene", "crop_camera",
 ]
 
@@ -179,7 +179,7 @@ def keyframe_from_frame(cam, R, t, depth, rgb, opacity, offset=None, sigma=None)
 # ----------------------------------------------------------------------------
 # workloads
 # ----------------------------------------------------------------------------
-def c1_scene(seed: int = 0) -> dict:
+def plane_scene(seed: int = 0) -> dict:
     """64x48 tilted plane, fx = fy = 60, cx = 32, cy = 24, keyframe at identity.
 
     Depth: 1/z affine in u from 1 m (u = 0) to 4 m (u = 63) plus N(0, 1 cm);
@@ -204,7 +204,7 @@ def c1_scene(seed: int = 0) -> dict:
     return dict(kfs=[kf], views=views, target=target)
 
 
-def c2_scene(seed: int = 10, W: int = 640, H: int = 480) -> dict:
+def room_frame_scene(seed: int = 10, W: int = 640, H: int = 480) -> dict:
     """One keyframe of a box room (walls 0.5-5 m), value-noise colour, opacity
     ~ U[0.5, 1], offsets 0, rendered into one view perturbed by up to 2 cm and
     1 degree.  The target is the analytic ray-cast frame at the view."""
@@ -221,7 +221,7 @@ def c2_scene(seed: int = 10, W: int = 640, H: int = 480) -> dict:
                 target=dict(rgb=trgb, depth=tdepth), room=room)
 
 
-def c3_window(seed: int = 20, W: int = 640, H: int = 480, n: int = 8) -> dict:
+def room_window(seed: int = 20, W: int = 640, H: int = 480, n: int = 8) -> dict:
     """Mapping window: n keyframes of one room at centres (0.05k - 0.175, 0, 0)
     with yaw (k - 3.5) * 2 degrees; offsets ~ U[-0.05, 0.05]; n views are the
     keyframe poses perturbed by up to 5 cm / 3 degrees; targets are ray-cast."""
@@ -245,7 +245,7 @@ def c3_window(seed: int = 20, W: int = 640, H: int = 480, n: int = 8) -> dict:
     return dict(kfs=kfs, views=views, targets=targets, room=room)
 
 
-def c4_tracking(seed: int = 30, W: int = 1200, H: int = 680) -> dict:
+def tracking_scene(seed: int = 30, W: int = 1200, H: int = 680) -> dict:
     """Tracking: geometry Gaussians of the previous frame (identity pose) with
     per-pixel depth std sigma ~ U[0.005, 0.05] m, opacity 0.9, offsets 0;
     the new frame's ground-truth pose is exactly 3 cm and 2 degrees away.

@@ -105,7 +105,7 @@ def train(ctx, data, epochs: int = 20, batch: int = 8, lr: float = 1e-3, seed: i
 
 def eval_window(seed: int = 3000, W: int = 640, H: int = 480, n: int = 8) -> dict:
     """8-keyframe window with noisy keyframe depth (CPU, numpy)."""
-    sc = synth.c3_window(seed, W=W, H=H, n=n)
+    sc = synth.room_window(seed, W=W, H=H, n=n)
     rng = np.random.default_rng(seed + 1)
     for kf in sc["kfs"]:
         kf["depth"] = (kf["depth"] + rng.normal(0.0, DEPTH_NOISE, size=kf["depth"].shape)).astype(np.float32)

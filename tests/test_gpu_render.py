@@ -54,13 +54,13 @@ def _run_case(ctx, sc, jobs, tile, learnable, seed=0, check_grads=True, max_flag
 
 
 @pytest.mark.parametrize("tile", TILES)
-def test_c1_forward_backward_parity(ctx, tile):
-    sc = synth.c1_scene(0)
+def test_plane_forward_backward_parity(ctx, tile):
+    sc = synth.plane_scene(0)
     _run_case(ctx, sc, [(1, [0])], tile, learnable=[0])
 
 
-def test_c1_identity_view(ctx):
-    sc = synth.c1_scene(0)
+def test_plane_identity_view(ctx):
+    sc = synth.plane_scene(0)
     _run_case(ctx, sc, [(0, [0])], (16, 16), learnable=[0])
 
 
@@ -266,8 +266,8 @@ def test_long_lists_render_parity(ctx, fac):
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
-def test_c2_full_frame_parity(ctx, tile):
-    sc = synth.c2_scene(10)
+def test_full_frame_640x480_parity(ctx, tile):
+    sc = synth.room_frame_scene(10)
     _run_case(ctx, sc, [(0, [0])], tile, learnable=[0])
 
 

@@ -37,7 +37,7 @@ def _pose_err(p, R, t):
 
 @pytest.fixture(scope="module")
 def small():
-    sc = synth.c4_tracking(31, W=160, H=90)
+    sc = synth.tracking_scene(31, W=160, H=90)
     lin = track.linearise(sc["geo"], sc["cam"], sc["gt"]["R"].astype(np.float64),
                           sc["gt"]["t"].astype(np.float64), np.ones((90, 160)))
     sc["obs_model"] = np.where(lin["valid"], lin["mu"], 0.0).reshape(90, 160).astype(np.float32)
@@ -130,30 +130,30 @@ def test_single_plane_takes_damped_steps(ctx):
 
 
 @pytest.fixture(scope="module")
-def c4():
-    print("C4 1200x680 scene and oracle linearisation (~1 min)", flush=True)
-    sc = synth.c4_tracking(30)
+def tracking_1200x680():
+    print("1200x680 tracking scene and oracle linearisation (~1 min)", flush=True)
+    sc = synth.tracking_scene(30)
     lin = track.linearise(sc["geo"], sc["cam"], sc["init"]["R"].astype(np.float64),
                           sc["init"]["t"].astype(np.float64), sc["obs_depth"].astype(np.float64))
     return sc, lin
 
 
-def test_c4_full_size_first_iteration(ctx, c4):
-    print("track C4 1200x680 first iteration", flush=True)
-    sc, lin = c4
+def test_tracking_1200x680_first_iteration(ctx, tracking_1200x680):
+    print("track 1200x680 first iteration", flush=True)
+    sc, lin = tracking_1200x680
     pose, tr = _run(ctx, sc, sc["obs_depth"], 1, graph=False)
     H = _unpack_H(tr[0])
     assert np.linalg.norm(H - lin["H"]) <= 1e-3 * np.linalg.norm(lin["H"])
     assert np.linalg.norm(tr[0, 21:27] - lin["g"]) <= 1e-3 * np.linalg.norm(lin["g"])
 
 
-def test_c4_full_size_converges(ctx, c4):
-    print("track C4 1200x680 30 iterations", flush=True)
-    sc, _ = c4
+def test_tracking_1200x680_converges(ctx, tracking_1200x680):
+    print("track 1200x680 30 iterations", flush=True)
+    sc, _ = tracking_1200x680
     pose, tr = _run(ctx, sc, sc["obs_depth"], 30, graph=True)
     et, er = _pose_err(pose, sc["gt"]["R"], sc["gt"]["t"])
     # analytic box depth vs the splatted model (a blurred surface): the
     # estimate converges near, not onto, the truth
-    print(f"C4 realistic: translation error {et * 1e3:.2f} mm, rotation error {er:.4f} deg", flush=True)
+    print(f"1200x680: translation error {et * 1e3:.2f} mm, rotation error {er:.4f} deg", flush=True)
     assert et < 1e-2 and er < 0.1, (et, er)
     assert tr[-1, 27] > tr[0, 27]

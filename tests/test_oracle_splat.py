@@ -79,7 +79,7 @@ def test_footprint_matches_fd_of_projected_mean():
 
 
 def test_identity_pose_projects_to_own_pixel():
-    sc = synth.c1_scene(0)
+    sc = synth.plane_scene(0)
     g = splat.preprocess(sc["kfs"][0], sc["views"][0]["cam"], sc["views"][0]["R"], sc["views"][0]["t"])
     assert np.abs(g["mx"] - g["u"]).max() < 1e-12
     assert np.abs(g["my"] - g["v"]).max() < 1e-12
@@ -175,7 +175,7 @@ def test_alpha_clamp_and_min_alpha():
 
 
 def test_bruteforce_equals_culled_c1_both_views():
-    sc = synth.c1_scene(0)
+    sc = synth.plane_scene(0)
     for view in sc["views"]:
         a = splat.render_job(sc["kfs"], view, [0])
         b = splat.render_bruteforce(sc["kfs"], view, [0])
@@ -345,7 +345,7 @@ def test_paper_constants_fixture():
     for k in ("rgb", "radius", "opacity", "offset"):
         assert optim.LR[k] == c["learning_rates"][k]
     # the per-Gaussian learnable planes: offset, radius, opacity, 3 colours
-    kf = synth.c1_scene(0)["kfs"][0]
+    kf = synth.plane_scene(0)["kfs"][0]
     n_attr = sum(kf[k].reshape(-1, kf["depth"].size).shape[0] for k in ("offset", "radius", "opacity", "rgb"))
     assert n_attr == c["attributes_per_gaussian"]["value"]
     W, H = c["learnable_gaussians_one_frame"]["frame"]

@@ -38,7 +38,7 @@ def test_se3_exp_matches_library_routines():
 # ---------------------------------------------------------------- tracking
 @pytest.fixture(scope="module")
 def small_track():
-    sc = synth.c4_tracking(31, W=96, H=54)
+    sc = synth.tracking_scene(31, W=96, H=54)
     sc["obs_model"] = _model_obs(sc, sc["gt"]["R"].astype(np.float64), sc["gt"]["t"].astype(np.float64))
     return sc
 
