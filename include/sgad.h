@@ -179,6 +179,21 @@ sgad_status sgad_render_bwd(sgad_ctx* ctx, sgad_saved* saved,
                             const sgad_kf_grads* grads, float* d_pose,
                             uint32_t learn_lo, uint32_t learn_hi, void* stream);
 
+/*
+ * Device workspace (bytes) that sgad_render_fwd and sgad_render_bwd of this
+ * workload hold in one saved slot: preprocessed records, tile tables, the
+ * instance keys and contributor masks, per-pixel state, pose partials.
+ * instances: the instance count the key list is sized for (0: the size of a
+ * first call, before the exact count is known; after it the library sizes
+ * the list to 1.25x the count + 65536).  Computed for 8x8 tiles, the shape
+ * with the most tiles, so it bounds every tile shape.  Pinned host staging
+ * and the L1-loss scratch are not included.  Keyframe planes may be null.
+ * SGAD_EINVAL for invalid sizes, jobs or a null `bytes`.
+ */
+sgad_status sgad_workspace_bytes(sgad_ctx* ctx, int n_kf, const sgad_keyframe* kf, int n_views,
+                                 const sgad_cam* vcam, int n_jobs, const sgad_job* jobs, uint64_t instances,
+                                 size_t* bytes);
+
 /* Return a saved handle to the context. */
 sgad_status sgad_saved_release(sgad_ctx* ctx, sgad_saved* saved);
 

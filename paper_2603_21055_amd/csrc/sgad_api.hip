@@ -330,6 +330,34 @@ hipError_t ensure_pin(PinBuf& b, size_t bytes) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Device buffers of one saved slot (a forward and its adjoint), in bytes;
+// the forward allocates exactly these and sgad_workspace_bytes reports them.
+struct SlotBytes {
+    size_t params, pre, tiles, pix, pose_part, status, keys, cmask, gradptrs;
+    size_t total() const { return params + pre + tiles + pix + pose_part + status + keys + cmask + gradptrs; }
+};
+
+SlotBytes slot_bytes(int n_kf, int n_pairs, int n_jobs, size_t N, size_t P, size_t M, size_t capacity) {
+    SlotBytes b{};
+    const size_t o_kfs = align256(sizeof(PairConst) * n_pairs);
+    const size_t o_pof = align256(o_kfs + sizeof(KfPtrs) * n_kf);
+    b.params = align256(o_pof + sizeof(int32_t) * n_jobs * n_kf);
+    b.pre = (size_t)n_pairs * N * 92 + 256;
+    b.tiles = (4 * M + 2) * 4 + 256;
+    b.pix = (size_t)n_jobs * P * 8;
+    b.pose_part = M * 6 * 4;
+    b.status = sizeof(DevStatus);
+    b.keys = capacity * 8;
+    b.cmask = (capacity / 64 + M + 1) * 64 * 8;
+    b.gradptrs = align256(sizeof(KfGradPtrs) * n_kf);
+    return b;
+}
+
+// Instance capacity: the first-use guess before any count, and the size
+// after an exact count.
+size_t first_capacity(size_t NP) { return std::min<size_t>(NP * 3 + 65536, 0xffffffffu); }
+size_t counted_capacity(size_t total) { return std::min<size_t>(total + total / 4 + 65536, 0xffffffffu); }
+
 void latch(sgad_ctx* c, sgad_status st, const char* msg) {
     if (c->latched != SGAD_OK) return;
     c->latched = st;
@@ -566,6 +594,36 @@ sgad_status sgad_get_tile_variant(const sgad_ctx* c, int* fwd_chunks, int* bwd_s
     return SGAD_OK;
 }
 
+sgad_status sgad_workspace_bytes(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_views,
+                                 const sgad_cam* vcam, int n_jobs, const sgad_job* jobs, uint64_t instances,
+                                 size_t* bytes) {
+    if (!c) return SGAD_EINVAL;
+    if (!bytes) return fail(c, SGAD_EINVAL, "bytes is null");
+    if (n_kf < 1 || n_kf > kMaxKf || !kf) return fail(c, SGAD_EINVAL, "n_kf must be in [1, 64]");
+    if (n_views < 1 || !vcam) return fail(c, SGAD_EINVAL, "need at least one view");
+    if (n_jobs < 1 || !jobs) return fail(c, SGAD_EINVAL, "need at least one job");
+    for (int f = 0; f < n_kf; ++f)
+        if (!cam_ok(kf[f].cam) || kf[f].cam.H != kf[0].cam.H || kf[f].cam.W != kf[0].cam.W)
+            return fail(c, SGAD_EINVAL, "keyframes must share a valid H x W");
+    for (int v = 0; v < n_views; ++v)
+        if (!cam_ok(vcam[v]) || vcam[v].H != vcam[0].H || vcam[v].W != vcam[0].W)
+            return fail(c, SGAD_EINVAL, "views must share a valid H x W");
+    int n_pairs = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        if (jobs[j].view < 0 || jobs[j].view >= n_views) return fail(c, SGAD_EINVAL, "job view out of range");
+        const uint64_t m = (uint64_t)jobs[j].kf_mask_lo | ((uint64_t)jobs[j].kf_mask_hi << 32);
+        if (n_kf < 64 && (m >> n_kf) != 0) return fail(c, SGAD_EINVAL, "job mask names a missing keyframe");
+        n_pairs += __builtin_popcountll(m);
+    }
+    const size_t N = (size_t)kf[0].cam.H * kf[0].cam.W, P = (size_t)vcam[0].H * vcam[0].W;
+    // 8x8 tiles give the most (job, tile) items of all tile shapes
+    const size_t M = (size_t)n_jobs * (size_t)((vcam[0].W + 7) / 8) * (size_t)((vcam[0].H + 7) / 8);
+    const size_t cap = instances ? counted_capacity((size_t)std::min<uint64_t>(instances, 0xffffffffu))
+                                 : first_capacity((size_t)n_pairs * N);
+    *bytes = slot_bytes(n_kf, n_pairs, n_jobs, N, P, M, cap).total();
+    return SGAD_OK;
+}
+
 sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_views, const sgad_cam* vcam,
                             const sgad_pose* vpose, int n_jobs, const sgad_job* jobs, float* out_rgb,
                             float* out_depth, float* out_alpha, int32_t* out_count, sgad_saved** saved,
@@ -720,11 +778,12 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
 
     // workspace
     const size_t PJ = (size_t)n_jobs * G.P;
-    HIPCHK(c, ensure_c(c, S->pre, NP * 92 + 256, s));
-    HIPCHK(c, ensure_c(c, S->tiles, (4 * M + 2) * 4 + 256, s));
-    HIPCHK(c, ensure_c(c, S->pix, PJ * 8, s));
-    HIPCHK(c, ensure_c(c, S->pose_part, M * 6 * 4, s));
-    HIPCHK(c, ensure_c(c, S->status, sizeof(DevStatus), s));
+    const SlotBytes sb = slot_bytes(n_kf, n_pairs, n_jobs, (size_t)N, (size_t)G.P, M, 0);
+    HIPCHK(c, ensure_c(c, S->pre, sb.pre, s));
+    HIPCHK(c, ensure_c(c, S->tiles, sb.tiles, s));
+    HIPCHK(c, ensure_c(c, S->pix, sb.pix, s));
+    HIPCHK(c, ensure_c(c, S->pose_part, sb.pose_part, s));
+    HIPCHK(c, ensure_c(c, S->status, sb.status, s));
     if (std::memcmp(size_key, S->size_key, sizeof(size_key)) != 0) {
         S->sized = false;
         S->last_max_seg = 0xffffffffu;
@@ -736,9 +795,9 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     G.sort_long = S->last_max_seg <= 1024u ? 0 : (S->last_max_seg <= 2048u ? 1 : 2);
     if (!S->sized && S->capacity == 0) {
         // first use: a generous guess that is corrected after the count pass
-        const size_t guess = NP * 3 + 65536;
+        const size_t guess = first_capacity(NP);
         HIPCHK(c, ensure(S->keys, guess * 8, s));
-        S->capacity = (uint32_t)std::min<size_t>(guess, 0xffffffffu);
+        S->capacity = (uint32_t)guess;
     }
 
     RenderBufs& B = S->B;
@@ -787,7 +846,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
         HIPCHK(c, hipStreamSynchronize(s));
         const uint32_t total = S->status_h->total;
         if ((size_t)total + (size_t)total / 4 > S->capacity || S->capacity == 0) {
-            const size_t cap = std::min<size_t>((size_t)total + total / 4 + 65536, 0xffffffffu);
+            const size_t cap = counted_capacity(total);
             HIPCHK(c, ensure(S->keys, cap * 8, s));
             S->capacity = (uint32_t)cap;
             B.keys = (uint64_t*)S->keys.p;
@@ -798,7 +857,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     }
     // contributor masks: one u64 per (64-entry chunk, pixel); at most
     // capacity / 64 + M chunks
-    HIPCHK(c, ensure_c(c, S->cmask, ((size_t)S->capacity / 64 + M + 1) * 64 * 8, s));
+    HIPCHK(c, ensure_c(c, S->cmask, slot_bytes(n_kf, n_pairs, n_jobs, (size_t)N, (size_t)G.P, M, S->capacity).cmask, s));
     B.cmask = (uint64_t*)S->cmask.p;
     {
         TimeScope ts(c, "scatter", s);

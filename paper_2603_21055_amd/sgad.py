@@ -73,6 +73,8 @@ _SIGS = {
                                   C.POINTER(Pose), C.c_int, C.POINTER(Job), _P, _P, _P, _P,
                                   C.POINTER(_P), _P]),
     "sgad_render_bwd": (C.c_int, [_P, _P, _P, _P, _P, C.POINTER(KfGrads), _P, C.c_uint32, C.c_uint32, _P]),
+    "sgad_workspace_bytes": (C.c_int, [_P, C.c_int, C.POINTER(Keyframe), C.c_int, C.POINTER(Cam), C.c_int,
+                                       C.POINTER(Job), C.c_uint64, C.POINTER(C.c_size_t)]),
     "sgad_saved_release": (C.c_int, [_P, _P]),
     "sgad_track_gn": (C.c_int, [_P, C.POINTER(Keyframe), C.POINTER(Cam), _P, _P, C.c_int, _P, C.c_uint32,
                                 _P]),
@@ -289,6 +291,16 @@ class Context:
                                       C.byref(saved), _stream(stream))
         self._check(st)
         return saved
+
+    def workspace_bytes(self, kfs, views, jobs, instances=0):
+        """Device bytes a forward + adjoint of this workload holds (instance
+        list sized for `instances` keys; 0: the first call's size)."""
+        kfa = self._kf_array(kfs)
+        cams, _, ja = self._views_jobs(views, jobs)
+        out = C.c_size_t()
+        self._check(self.lib.sgad_workspace_bytes(self.h, len(kfs), kfa, len(views), cams, len(jobs), ja,
+                                                  int(instances), C.byref(out)))
+        return out.value
 
     def render_bwd(self, saved, g_rgb, g_depth, g_alpha, grads, d_pose, learnable, stream=None):
         """grads: list (len n_kf) of dicts with d_rgb/d_opacity/d_radius/d_offset
