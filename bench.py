@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12                   # bytes/s, MI355X HBM3E
 FP32_VECTOR_PEAK = 157.3e12         # flop/s, MI355X published FP32 vector peak
+BF16_MFMA_PEAK = 2.5e15             # flop/s, MI355X published dense BF16 matrix peak
 # algorithmic bytes of one fwd+bwd of one view (per Gaussian: 28 B read by the
 # forward, 28 B read by the backward, 24 B of gradients written; per pixel:
 # 24 B of outputs and saved state, 20 B of upstream gradients, 8 B re-read)
@@ -171,6 +172,50 @@ def bench_tracking(args):
                           dtype="f32 (FP64 solve)", data="synthetic")), flush=True)
 
 
+def bench_offsetnet(args):
+    """The warm-start conv net (3x3, 4 -> 32 x5 -> 1, BF16 MFMA) on one
+    640x480 frame: forward, and forward + L1 gradient + backward."""
+    import numpy as np
+    import torch
+
+    from paper_2603_21055_amd import sgad
+    from paper_2603_21055_amd.offsetnet import CHANNELS, OffsetNet
+    H, W = 480, 640
+    dev = torch.device("cuda", 0)
+    ctx = sgad.Context(0)
+    net = OffsetNet(ctx, seed=0)
+    rng = np.random.default_rng(0)
+    rgb = torch.from_numpy(rng.uniform(size=(3, H, W)).astype(np.float32)).to(dev)
+    dep = torch.from_numpy(rng.uniform(0.5, 5.0, size=(H, W)).astype(np.float32)).to(dev)
+    tgt = torch.from_numpy((rng.normal(size=(H, W)) * 0.01).astype(np.float32)).to(dev)
+    g = torch.empty((H, W), dtype=torch.bfloat16, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def fwd_bwd():
+        d = net.forward(rgb, dep)
+        ctx.offset_l1(d, tgt, g, loss)
+        net.backward(g)
+
+    steps = max(1, min(args.steps, 100))
+    t_f = _timed(lambda: net.forward(rgb, dep), steps, min(args.warmup, 5))
+    t_fb = _timed(fwd_bwd, steps, min(args.warmup, 5))
+    ctx.sync()
+    # flops per pixel: 2 * 9 * cin * cout per layer forward; the backward
+    # takes the weight gradient of every layer and the input gradient of
+    # layers 1..5
+    lay = [(CHANNELS[l], CHANNELS[l + 1]) for l in range(6)]
+    f_fwd = sum(18 * ci * co for ci, co in lay) * H * W
+    f_bwd = (sum(18 * ci * co for ci, co in lay) + sum(18 * ci * co for ci, co in lay[1:])) * H * W
+    print(json.dumps(dict(metric="warm-start conv net frames/s (640x480, BF16 MFMA)", value=1.0 / t_f,
+                          unit="frames/s", ms_forward=t_f * 1e3, ms_forward_backward=t_fb * 1e3,
+                          tflops_forward=f_fwd / t_f / 1e12, tflops_forward_backward=(f_fwd + f_bwd) / t_fb / 1e12,
+                          roofline=dict(bound="mfma", achieved=f_fwd / t_f / 1e12, peak=BF16_MFMA_PEAK / 1e12,
+                                        unit="TFLOP/s", frac=f_fwd / t_f / BF16_MFMA_PEAK),
+                          gflop_forward=f_fwd / 1e9, gflop_backward=f_bwd / 1e9, steps=steps, dtype="bf16",
+                          data="synthetic")), flush=True)
+    ctx.close()
+
+
 def bench_copy(args):
     """A plain 1 GiB device-to-device copy, for scaling the FETCH_SIZE /
     WRITE_SIZE counters (bytes per copy are known exactly)."""
@@ -214,10 +259,10 @@ def main():
     ap.add_argument("--print-sha", action="store_true", help="print the kernel-source hashes and exit")
     ap.add_argument("--graph", action="store_true", help="time replays of a captured graph of one step")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start comparison")
-    ap.add_argument("--workload", choices=["frame", "window", "tracking", "copy"], default="frame",
+    ap.add_argument("--workload", choices=["frame", "window", "tracking", "offsetnet", "copy"], default="frame",
                     help="frame: one 640x480 keyframe into one view (the headline step); window: 8 keyframes "
-                         "x 8 views at 640x480; tracking: 1200x680 Gauss-Newton; copy: plain device copy "
-                         "(counter calibration)")
+                         "x 8 views at 640x480; tracking: 1200x680 Gauss-Newton; offsetnet: the warm-start conv "
+                         "net on one 640x480 frame; copy: plain device copy (counter calibration)")
     args = ap.parse_args()
     if args.print_sha:
         print(json.dumps({k: sources_sha(k) for k in KERNEL_SOURCES}))
@@ -227,7 +272,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.workload != "frame":
-        return {"window": bench_window, "tracking": bench_tracking, "copy": bench_copy}[args.workload](args)
+        return {"window": bench_window, "tracking": bench_tracking, "offsetnet": bench_offsetnet,
+                "copy": bench_copy}[args.workload](args)
 
     frames = None
     if not args.no_warm_start:

@@ -281,7 +281,9 @@ bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, c
 bool launch_conv_wgrad(int H, int W, int cin, int cout, const void* x, const void* dy, float* dw, float* db,
                        hipStream_t s) {
     const int ntiles = ((W + 15) / 16) * ((H + 15) / 16);
-    const dim3 grid(std::min(ntiles, 256)), blk(256);
+    // two persistent workgroups per CU: one leaves each wave's tile loads
+    // exposed, more multiply the final atomics (measured at 640x480)
+    const dim3 grid(std::min(ntiles, 512)), blk(256);
     const __bf16* xb = (const __bf16*)x;
     const __bf16* db16 = (const __bf16*)dy;
     if (cin == 4 && cout == 32) hipLaunchKernelGGL((k_wgrad<4, 32>), grid, blk, 0, s, H, W, xb, db16, dw, db);
