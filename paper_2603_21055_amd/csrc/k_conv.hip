@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const __bf16* __rest
 
 // Weight and bias gradients: dw[t][co][ci] += sum_p dy[p][co] x[p + off(t)][ci],
 // db[co] += sum_p dy[p][co].  Each workgroup walks 16x16 tiles and keeps its
-// partial sums in registers (wave w owns taps w, w + 4, w + 8), then adds
+// partial sums in registers (the nine taps split evenly over the four waves), then adds
 // them to the FP32 outputs with atomics once.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __restrict__ x,
@@ -135,13 +135,19 @@ __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __res
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
     const int ntx = (W + 15) / 16, nty = (H + 15) / 16, ntiles = ntx * nty;
-    f32x4 acc[3][MB][NB];
+    // wave w: taps w and w + 4 whole (A and B reused across the row and column
+    // blocks), and (row block, column block) unit w of tap 8 if it exists,
+    // so the 9 taps' MB * NB units are spread evenly over the four waves
+    f32x4 acc[2][MB][NB];
 #pragma unroll
-    for (int k3 = 0; k3 < 3; ++k3)
+    for (int k3 = 0; k3 < 2; ++k3)
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[k3][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 acc8 = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bool has8 = wave < MB * NB;
+    const int mb8 = has8 ? wave / NB : 0, nb8 = has8 ? wave % NB : 0;
     float dbp = 0.f;
     const int bco = tid & 31, bgrp = tid >> 5;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -166,9 +172,8 @@ __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __res
         if (bco < COUT)
             for (int j = 0; j < 32; ++j) dbp += (float)s_dy[bco * DS + bgrp * 32 + j];
 #pragma unroll
-        for (int k3 = 0; k3 < 3; ++k3) {
+        for (int k3 = 0; k3 < 2; ++k3) {
             const int t = wave + 4 * k3;
-            if (t >= 9) continue;
             const int ky = t / 3, kx = t - ky * 3;
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks) {
@@ -190,11 +195,28 @@ __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __res
                 }
             }
         }
-    }
+        if (has8) {   // tap 8 = (ky, kx) = (2, 2): this wave's unit
 #pragma unroll
-    for (int k3 = 0; k3 < 3; ++k3) {
+            for (int ks = 0; ks < 8; ++ks) {
+                const int row = 2 * ks + (g >> 1), col = (g & 1) * 8;
+                const bf16x8 Am = *(const bf16x8*)(s_dy + (mb8 * 16 + r16) * DS + 32 * ks + 8 * g);
+                const __bf16* src = s_x + ((nb8 * 16 + r16) * 18 + row + 2) * 24 + col + 2;
+                bf16x8 Bv;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) Bv[j] = src[j];
+                acc8 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am, Bv, acc8, 0, 0, 0);
+            }
+        }
+    }
+    if (has8)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int co = mb8 * 16 + 4 * g + e, ci = nb8 * 16 + r16;
+            if (co < COUT && ci < CIN) atomicAdd(&dw[((size_t)8 * COUT + co) * CIN + ci], acc8[e]);
+        }
+#pragma unroll
+    for (int k3 = 0; k3 < 2; ++k3) {
         const int t = wave + 4 * k3;
-        if (t >= 9) continue;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
