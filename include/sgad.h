@@ -339,7 +339,9 @@ sgad_status sgad_adam_step(sgad_ctx* ctx, int n_groups, const sgad_adam_group* g
  * five.  Activations are bf16 NHWC ([H][W][C]); weights [9][cout][cin]
  * (tap = 3 ky + kx, taps reading x[y + ky - 1][x + kx - 1]); products run on
  * BF16 MFMA with FP32 accumulation.  Supported layers: (cin, cout) = (4, 32),
- * (32, 32), (32, 1).  All pointers are device pointers.
+ * (32, 32), (32, 1).  All pointers are device pointers; the bf16 activation
+ * and weight pointers and the forward's output must be 16-byte aligned
+ * (SGAD_EINVAL otherwise: the kernels move a pixel's channels in 16-byte loads).
  */
 #define SGAD_CONV_RELU_BF16 0  /* y = relu(conv + bias), bf16 [H][W][cout] */
 #define SGAD_CONV_LINEAR_F32 1 /* y = conv + bias, f32 [H][W] (cout == 1) */

@@ -120,6 +120,21 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const __bf16* __rest
     }
 }
 
+// The channels of one NHWC pixel that one load moves (raw bf16 bits):
+// 8 (16 bytes) when C is a multiple of 8, else all C.
+template <int C>
+struct ChanVec {
+    static constexpr int V = C % 8 == 0 ? 8 : C;
+    typedef unsigned short T __attribute__((ext_vector_type(V)));
+    static __device__ __forceinline__ unsigned short get(const T& v, int j) { return v[j]; }
+};
+template <>
+struct ChanVec<1> {
+    static constexpr int V = 1;
+    typedef unsigned short T;
+    static __device__ __forceinline__ unsigned short get(const T& v, int) { return v; }
+};
+
 // Weight and bias gradients: dw[t][co][ci] += sum_p dy[p][co] x[p + off(t)][ci],
 // db[co] += sum_p dy[p][co].  Each workgroup walks 16x16 tiles and keeps its
 // partial sums in registers (the nine taps split evenly over the four waves), then adds
@@ -150,23 +165,54 @@ __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __res
     const int mb8 = has8 ? wave / NB : 0, nb8 = has8 ? wave % NB : 0;
     float dbp = 0.f;
     const int bco = tid & 31, bgrp = tid >> 5;
+    // channel rows past COUT / CIN stay zero (the tile loads never write them)
+    for (int i = tid; i < (32 - COUT) * DS; i += 256) s_dy[COUT * DS + i] = (__bf16)0.f;
+    for (int i = tid; i < (32 - CIN) * 18 * 24; i += 256) s_x[CIN * 18 * 24 + i] = (__bf16)0.f;
+    // tile staging: each thread loads whole pixels' channel vectors (up to 16
+    // bytes), every global load of the tile issued before the LDS stores
+    typedef typename ChanVec<COUT>::T VecY;
+    typedef typename ChanVec<CIN>::T VecX;
+    constexpr int VY = ChanVec<COUT>::V, NVY = COUT / VY, LY = (256 * NVY + 255) / 256;
+    constexpr int VX = ChanVec<CIN>::V, NVX = CIN / VX, LX = (324 * NVX + 255) / 256;
+    const unsigned short* dyr = (const unsigned short*)dy;
+    const unsigned short* xr = (const unsigned short*)x;
+    unsigned short* s_dyr = (unsigned short*)s_dy;
+    unsigned short* s_xr = (unsigned short*)s_x;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int x0 = (tile % ntx) * 16, y0 = (tile / ntx) * 16;
-        __syncthreads();
-        for (int i = tid; i < 256 * 32; i += 256) {
-            const int p = i >> 5, co = i & 31;
+        VecY ry[LY];
+        VecX rx[LX];
+#pragma unroll
+        for (int k = 0; k < LY; ++k) {
+            const int i = tid + 256 * k, p = i / NVY, c = (i - p * NVY) * VY;
             const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
-            __bf16 v = (__bf16)0.f;
-            if (co < COUT && gy < H && gx < W) v = dy[((size_t)gy * W + gx) * COUT + co];
-            s_dy[co * DS + p] = v;
+            ry[k] = VecY(0);
+            if (i < 256 * NVY && gy < H && gx < W) ry[k] = *(const VecY*)(dyr + ((size_t)gy * W + gx) * COUT + c);
         }
-        for (int i = tid; i < 324 * 32; i += 256) {
-            const int pix = i >> 5, ci = i & 31;
+#pragma unroll
+        for (int k = 0; k < LX; ++k) {
+            const int i = tid + 256 * k, pix = i / NVX, c = (i - pix * NVX) * VX;
             const int ty = pix / 18, tx = pix - ty * 18;
             const int gy = y0 + ty - 1, gx = x0 + tx - 1;
-            __bf16 v = (__bf16)0.f;
-            if (ci < CIN && gy >= 0 && gy < H && gx >= 0 && gx < W) v = x[((size_t)gy * W + gx) * CIN + ci];
-            s_x[(ci * 18 + ty) * 24 + tx] = v;
+            rx[k] = VecX(0);
+            if (i < 324 * NVX && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                rx[k] = *(const VecX*)(xr + ((size_t)gy * W + gx) * CIN + c);
+        }
+        __syncthreads();   // the previous tile's MFMA reads are done
+#pragma unroll
+        for (int k = 0; k < LY; ++k) {
+            const int i = tid + 256 * k, p = i / NVY, c = (i - p * NVY) * VY;
+            if (i < 256 * NVY)
+#pragma unroll
+                for (int j = 0; j < VY; ++j) s_dyr[(c + j) * DS + p] = ChanVec<COUT>::get(ry[k], j);
+        }
+#pragma unroll
+        for (int k = 0; k < LX; ++k) {
+            const int i = tid + 256 * k, pix = i / NVX, c = (i - pix * NVX) * VX;
+            const int ty = pix / 18, tx = pix - ty * 18;
+            if (i < 324 * NVX)
+#pragma unroll
+                for (int j = 0; j < VX; ++j) s_xr[((c + j) * 18 + ty) * 24 + tx] = ChanVec<CIN>::get(rx[k], j);
         }
         __syncthreads();
         if (bco < COUT)
@@ -263,7 +309,7 @@ __global__ void k_net_input(int H, int W, const float* rgb, const float* depth, 
 }
 
 // L1 training loss mean|pred - target| and its gradient (bf16, one channel).
-__global__ void k_offset_l1(int n, const float* pred, const float* target, __bf16* grad, double* loss) {
+__global__ __launch_bounds__(256) void k_offset_l1(int n, const float* pred, const float* target, __bf16* grad, double* loss) {
     double acc = 0.0;
     const float inv = 1.f / (float)n;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -273,7 +319,11 @@ __global__ void k_offset_l1(int n, const float* pred, const float* target, __bf1
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss, acc / (double)n);
+    // one atomic per block: same-address FP64 atomics serialise in L2
+    __shared__ double s_acc[4];
+    if ((threadIdx.x & 63) == 0) s_acc[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, (s_acc[0] + s_acc[1] + s_acc[2] + s_acc[3]) / (double)n);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,7 +378,7 @@ void launch_net_input(int H, int W, const float* rgb, const float* depth, void* 
 }
 
 void launch_offset_l1(int n, const float* pred, const float* target, void* grad, double* loss, hipStream_t s) {
-    hipLaunchKernelGGL(k_offset_l1, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, s, n, pred, target,
+    hipLaunchKernelGGL(k_offset_l1, dim3(std::min(256, (n + 255) / 256)), dim3(256), 0, s, n, pred, target,
                        (__bf16*)grad, loss);
 }
 

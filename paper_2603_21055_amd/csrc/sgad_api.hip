@@ -1469,6 +1469,8 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
 
 // ---------------------------------------------------------------- conv net
 static bool conv_dims_ok(int H, int W) { return H > 0 && W > 0 && H < 65536 && W < 65536; }
+// the conv kernels move a pixel's channels (and a weight row) in 16-byte loads
+static bool conv_aligned(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 sgad_status sgad_conv_weights(sgad_ctx* c, int cin, int cout, const float* w, uint16_t* w_bf16, uint16_t* wt_bf16,
                               void* stream) {
@@ -1487,6 +1489,8 @@ sgad_status sgad_conv3x3_fwd(sgad_ctx* c, int H, int W, int cin, int cout, int m
     if (!c) return SGAD_EINVAL;
     if (!conv_dims_ok(H, W) || !x || !w_bf16 || !bias || !y) return fail(c, SGAD_EINVAL, "bad conv arguments");
     if (mode != SGAD_CONV_RELU_BF16 && mode != SGAD_CONV_LINEAR_F32) return fail(c, SGAD_EINVAL, "bad conv mode");
+    if (!conv_aligned(x) || !conv_aligned(w_bf16) || !conv_aligned(y))
+        return fail(c, SGAD_EINVAL, "conv pointers must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
     TimeScope ts(c, "conv_fwd", s);
@@ -1500,6 +1504,8 @@ sgad_status sgad_conv3x3_dgrad(sgad_ctx* c, int H, int W, int cin, int cout, con
                                const uint16_t* wt_bf16, const uint16_t* mask, uint16_t* dx, void* stream) {
     if (!c) return SGAD_EINVAL;
     if (!conv_dims_ok(H, W) || !dy || !wt_bf16 || !mask || !dx) return fail(c, SGAD_EINVAL, "bad dgrad arguments");
+    if (!conv_aligned(dy) || !conv_aligned(wt_bf16) || !conv_aligned(mask) || !conv_aligned(dx))
+        return fail(c, SGAD_EINVAL, "conv pointers must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
     TimeScope ts(c, "conv_dgrad", s);
@@ -1514,6 +1520,7 @@ sgad_status sgad_conv3x3_wgrad(sgad_ctx* c, int H, int W, int cin, int cout, con
                                float* dw, float* db, void* stream) {
     if (!c) return SGAD_EINVAL;
     if (!conv_dims_ok(H, W) || !x || !dy || !dw || !db) return fail(c, SGAD_EINVAL, "bad wgrad arguments");
+    if (!conv_aligned(x) || !conv_aligned(dy)) return fail(c, SGAD_EINVAL, "conv pointers must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
     TimeScope ts(c, "conv_wgrad", s);

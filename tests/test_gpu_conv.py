@@ -97,11 +97,13 @@ def test_single_layer_input_gradient(ctx, cin, cout):
     assert viol.max() <= 0, (float(viol.max()), int((viol > 0).sum()))
 
 
-@pytest.mark.parametrize("cin,cout", [(4, 32), (32, 32), (32, 1)])
-def test_single_layer_weight_gradient(ctx, cin, cout):
+@pytest.mark.parametrize("cin,cout,H,W", [(4, 32, 50, 70), (32, 32, 50, 70), (32, 1, 50, 70),
+                                          (32, 32, 330, 530), (4, 32, 330, 530)])
+def test_single_layer_weight_gradient(ctx, cin, cout, H, W):
+    """50x70: 20 ragged tiles; 330x530: 714 tiles, more than the persistent
+    workgroups, so workgroups accumulate several tiles."""
     import torch
-    print(f"conv wgrad {cin}->{cout}", flush=True)
-    H, W = 50, 70
+    print(f"conv wgrad {cin}->{cout} {H}x{W}", flush=True)
     rng = np.random.default_rng(11 + cin + cout)
     x = rng.normal(size=(H, W, cin)).astype(np.float32)
     dy = rng.normal(size=(H, W, cout)).astype(np.float32)
@@ -173,3 +175,25 @@ def test_training_reduces_loss(ctx):
         last = net.train_step(batch)
     torch.cuda.synchronize()
     assert last.mean().item() < first
+
+
+def test_misaligned_pointers_rejected(ctx):
+    """The conv entry points refuse activation pointers that are not 16-byte
+    aligned (checked on the host, before any launch)."""
+    import torch
+    from paper_2603_21055_amd import sgad
+    H, W = 16, 16
+    buf = torch.zeros(H * W * 32 + 8, dtype=torch.bfloat16, device=ctx.device)
+    x_bad = buf[1:1 + H * W * 32]
+    dy = torch.zeros((H, W, 32), dtype=torch.bfloat16, device=ctx.device)
+    dw = torch.zeros((9, 32, 32), dtype=torch.float32, device=ctx.device)
+    db = torch.zeros(32, dtype=torch.float32, device=ctx.device)
+    with pytest.raises(sgad.SgadError, match="16-byte aligned"):
+        ctx.conv_wgrad(H, W, 32, 32, x_bad, dy, dw, db)
+    w16 = torch.zeros((9, 32, 32), dtype=torch.bfloat16, device=ctx.device)
+    bias = torch.zeros(32, dtype=torch.float32, device=ctx.device)
+    y = torch.empty((H, W, 32), dtype=torch.bfloat16, device=ctx.device)
+    with pytest.raises(sgad.SgadError, match="16-byte aligned"):
+        ctx.conv_fwd(H, W, 32, 32, 0, x_bad, w16, bias, y)
+    torch.cuda.synchronize()
+    assert float(dw.abs().sum()) == 0.0
