@@ -206,11 +206,19 @@ def bench_offsetnet(args):
     lay = [(CHANNELS[l], CHANNELS[l + 1]) for l in range(6)]
     f_fwd = sum(18 * ci * co for ci, co in lay) * H * W
     f_bwd = (sum(18 * ci * co for ci, co in lay) + sum(18 * ci * co for ci, co in lay[1:])) * H * W
+    # algorithmic bytes per pixel of the forward: the input (RGB + D as f32
+    # read, 4 bf16 written), then every layer reads its bf16 input and writes
+    # its output (bf16, the last one f32).  A 32 -> 32 layer does 18 * 32 * 32
+    # flop per 128 bytes (144 flop/B), below the 312 flop/B at which the BF16
+    # MFMA peak and HBM balance, so the net is HBM-bound.
+    b_fwd = (16 + 8 + sum(2 * ci + (2 * co if l < 5 else 4) for l, (ci, co) in enumerate(lay))) * H * W
     print(json.dumps(dict(metric="warm-start conv net frames/s (640x480, BF16 MFMA)", value=1.0 / t_f,
                           unit="frames/s", ms_forward=t_f * 1e3, ms_forward_backward=t_fb * 1e3,
                           tflops_forward=f_fwd / t_f / 1e12, tflops_forward_backward=(f_fwd + f_bwd) / t_fb / 1e12,
-                          roofline=dict(bound="mfma", achieved=f_fwd / t_f / 1e12, peak=BF16_MFMA_PEAK / 1e12,
-                                        unit="TFLOP/s", frac=f_fwd / t_f / BF16_MFMA_PEAK),
+                          mfma_frac_forward=f_fwd / t_f / BF16_MFMA_PEAK,
+                          roofline=dict(bound="hbm", achieved=b_fwd / t_f / 1e9, peak=HBM_PEAK / 1e9,
+                                        unit="GB/s", frac=b_fwd / t_f / HBM_PEAK, traffic=None,
+                                        algorithmic_bytes=b_fwd, scope="forward: input + 6 conv layers"),
                           gflop_forward=f_fwd / 1e9, gflop_backward=f_bwd / 1e9, steps=steps, dtype="bf16",
                           data="synthetic")), flush=True)
     ctx.close()

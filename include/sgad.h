@@ -359,7 +359,11 @@ sgad_status sgad_conv3x3_fwd(sgad_ctx* ctx, int H, int W, int cin, int cout, int
  * (the gradient of the previous layer's pre-activation). */
 sgad_status sgad_conv3x3_dgrad(sgad_ctx* ctx, int H, int W, int cin, int cout, const uint16_t* dy,
                                const uint16_t* wt_bf16, const uint16_t* mask, uint16_t* dx, void* stream);
-/* Weight and bias gradients, ACCUMULATED into FP32 dw [9][cout][cin], db [cout]. */
+/* Weight and bias gradients, ACCUMULATED into FP32 dw [9][cout][cin], db [cout].
+ * Partial sums go through a context-owned device workspace (one row per
+ * workgroup, up to 512 x (9 cout cin + cout) floats, grown by the first call
+ * that needs more; SGAD_EHIP if that happens while calls are captured):
+ * wgrad calls of one context that overlap on different streams race on it. */
 sgad_status sgad_conv3x3_wgrad(sgad_ctx* ctx, int H, int W, int cin, int cout, const uint16_t* x,
                                const uint16_t* dy, float* dw, float* db, void* stream);
 /* Network input (R, G, B, D / 5 m) as bf16 [H][W][4] from planar rgb [3][H][W] and depth [H][W]. */

@@ -137,11 +137,13 @@ struct ChanVec<1> {
 
 // Weight and bias gradients: dw[t][co][ci] += sum_p dy[p][co] x[p + off(t)][ci],
 // db[co] += sum_p dy[p][co].  Each workgroup walks 16x16 tiles and keeps its
-// partial sums in registers (the nine taps split evenly over the four waves), then adds
-// them to the FP32 outputs with atomics once.
+// partial sums in registers (the nine taps split evenly over the four waves),
+// then stores them as its row of part ([workgroup][9 * COUT * CIN + COUT],
+// every entry written); k_wgrad_reduce sums the rows.  Same-address atomics
+// from every workgroup on the chip would serialise.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __restrict__ x,
-                                               const __bf16* __restrict__ dy, float* dw, float* db) {
+                                               const __bf16* __restrict__ dy, float* __restrict__ part) {
     constexpr int MB = (COUT + 15) / 16, NB = (CIN + 15) / 16;
     constexpr int DS = 264;  // [co][pixel] row stride
     __shared__ __attribute__((aligned(16))) __bf16 s_dy[32 * DS];
@@ -254,11 +256,12 @@ __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __res
             }
         }
     }
+    float* __restrict__ dw = part + (size_t)blockIdx.x * (9 * COUT * CIN + COUT);
     if (has8)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int co = mb8 * 16 + 4 * g + e, ci = nb8 * 16 + r16;
-            if (co < COUT && ci < CIN) atomicAdd(&dw[((size_t)8 * COUT + co) * CIN + ci], acc8[e]);
+            if (co < COUT && ci < CIN) dw[(8 * COUT + co) * CIN + ci] = acc8[e];
         }
 #pragma unroll
     for (int k3 = 0; k3 < 2; ++k3) {
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __res
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int co = mb * 16 + 4 * g + e, ci = nb * 16 + r16;
-                    if (co < COUT && ci < CIN) atomicAdd(&dw[((size_t)t * COUT + co) * CIN + ci], acc[k3][mb][nb][e]);
+                    if (co < COUT && ci < CIN) dw[(t * COUT + co) * CIN + ci] = acc[k3][mb][nb][e];
                 }
     }
     s_db[bgrp][bco] = dbp;
@@ -278,8 +281,31 @@ __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __res
     if (tid < COUT) {
         float s = 0.f;
         for (int k = 0; k < 8; ++k) s += s_db[k][tid];
-        atomicAdd(&db[tid], s);
+        dw[9 * COUT * CIN + tid] = s;
     }
+}
+
+constexpr int kWgradBlocks = 512;  // persistent weight-gradient workgroups (two per CU)
+constexpr int kWgradSplit = 16;    // row groups of the partial-sum reduction
+
+// dw[j] (j < ndw) or db[j - ndw] += sum of column j over the nrow rows of
+// part ([nrow][S]); blockIdx.y takes rows y, y + kWgradSplit, ...
+__global__ __launch_bounds__(256) void k_wgrad_reduce(int S, int ndw, int nrow, const float* __restrict__ part,
+                                                      float* dw, float* db) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= S) return;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int r = blockIdx.y;
+    for (; r + 3 * kWgradSplit < nrow; r += 4 * kWgradSplit) {
+        s0 += part[(size_t)r * S + j];
+        s1 += part[(size_t)(r + kWgradSplit) * S + j];
+        s2 += part[(size_t)(r + 2 * kWgradSplit) * S + j];
+        s3 += part[(size_t)(r + 3 * kWgradSplit) * S + j];
+    }
+    for (; r < nrow; r += kWgradSplit) s0 += part[(size_t)r * S + j];
+    const float v = (s0 + s1) + (s2 + s3);
+    if (j < ndw) atomicAdd(&dw[j], v);
+    else atomicAdd(&db[j - ndw], v);
 }
 
 // FP32 master weights [9][cout][cin] -> bf16 copy and the transposed,
@@ -350,18 +376,28 @@ bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, c
     return true;
 }
 
-bool launch_conv_wgrad(int H, int W, int cin, int cout, const void* x, const void* dy, float* dw, float* db,
-                       hipStream_t s) {
-    const int ntiles = ((W + 15) / 16) * ((H + 15) / 16);
-    // two persistent workgroups per CU: one leaves each wave's tile loads
-    // exposed, more multiply the final atomics (measured at 640x480)
-    const dim3 grid(std::min(ntiles, 512)), blk(256);
+// Workgroups of the weight gradient (one partial-sum row each): two
+// persistent workgroups per CU (measured at 640x480: one leaves each wave's
+// tile loads exposed).
+static int wgrad_blocks(int H, int W) { return std::min(((W + 15) / 16) * ((H + 15) / 16), kWgradBlocks); }
+
+size_t conv_wgrad_part_bytes(int H, int W, int cin, int cout) {
+    return (size_t)wgrad_blocks(H, W) * (size_t)(9 * cout * cin + cout) * sizeof(float);
+}
+
+bool launch_conv_wgrad(int H, int W, int cin, int cout, const void* x, const void* dy, float* part, float* dw,
+                       float* db, hipStream_t s) {
+    const int nrow = wgrad_blocks(H, W);
+    const dim3 grid(nrow), blk(256);
     const __bf16* xb = (const __bf16*)x;
     const __bf16* db16 = (const __bf16*)dy;
-    if (cin == 4 && cout == 32) hipLaunchKernelGGL((k_wgrad<4, 32>), grid, blk, 0, s, H, W, xb, db16, dw, db);
-    else if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_wgrad<32, 32>), grid, blk, 0, s, H, W, xb, db16, dw, db);
-    else if (cin == 32 && cout == 1) hipLaunchKernelGGL((k_wgrad<32, 1>), grid, blk, 0, s, H, W, xb, db16, dw, db);
+    if (cin == 4 && cout == 32) hipLaunchKernelGGL((k_wgrad<4, 32>), grid, blk, 0, s, H, W, xb, db16, part);
+    else if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_wgrad<32, 32>), grid, blk, 0, s, H, W, xb, db16, part);
+    else if (cin == 32 && cout == 1) hipLaunchKernelGGL((k_wgrad<32, 1>), grid, blk, 0, s, H, W, xb, db16, part);
     else return false;
+    const int ndw = 9 * cout * cin, S = ndw + cout;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((S + 255) / 256, std::min(nrow, kWgradSplit)), dim3(256), 0, s, S, ndw,
+                       nrow, part, dw, db);
     return true;
 }
 

@@ -31,7 +31,8 @@ void launch_adam(AdamGroups& A, float b1, float b2, float eps, float c1, float c
                  float* cdev, hipStream_t s);
 bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* bias,
                      const void* mask, void* y, hipStream_t s);
-bool launch_conv_wgrad(int H, int W, int cin, int cout, const void* x, const void* dy, float* dw, float* db,
+size_t conv_wgrad_part_bytes(int H, int W, int cin, int cout);
+bool launch_conv_wgrad(int H, int W, int cin, int cout, const void* x, const void* dy, float* part, float* dw, float* db,
                        hipStream_t s);
 void launch_conv_weights(int cin, int cout, const float* w, void* wb, void* wt, hipStream_t s);
 void launch_net_input(int H, int W, const float* rgb, const float* depth, void* x0, hipStream_t s);
@@ -141,6 +142,7 @@ struct sgad_ctx {
         std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> timed;
     } capture;
     DevBuf scratch;  // small per-context scratch (loss counters)
+    DevBuf conv_part;  // conv weight-gradient partial sums (one row per workgroup)
     struct Track {
         bool sized = false;
         Geometry G{};
@@ -531,6 +533,7 @@ void sgad_destroy(sgad_ctx* c) {
     (void)hipDeviceSynchronize();
     for (sgad_saved* s : c->slots) free_slot(s);
     if (c->scratch.p) (void)hipFree(c->scratch.p);
+    if (c->conv_part.p) (void)hipFree(c->conv_part.p);
     {
         auto& T = c->track;
         for (DevBuf* b : {&T.params, &T.pre, &T.tiles, &T.keys, &T.part, &T.status, &T.trace})
@@ -1524,7 +1527,10 @@ sgad_status sgad_conv3x3_wgrad(sgad_ctx* c, int H, int W, int cin, int cout, con
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
     TimeScope ts(c, "conv_wgrad", s);
-    if (!launch_conv_wgrad(H, W, cin, cout, x, dy, dw, db, s)) return fail(c, SGAD_EINVAL, "unsupported (cin, cout)");
+    if (!((cin == 4 && cout == 32) || (cin == 32 && cout == 32) || (cin == 32 && cout == 1)))
+        return fail(c, SGAD_EINVAL, "unsupported (cin, cout)");
+    HIPCHK(c, ensure_c(c, c->conv_part, conv_wgrad_part_bytes(H, W, cin, cout), s));
+    launch_conv_wgrad(H, W, cin, cout, x, dy, (float*)c->conv_part.p, dw, db, s);
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
 }

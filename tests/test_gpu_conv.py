@@ -115,6 +115,12 @@ def test_single_layer_weight_gradient(ctx, cin, cout, H, W):
     got = dw.cpu().numpy().reshape(3, 3, cout, cin)
     assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
     np.testing.assert_allclose(db.cpu().numpy(), oconv.bf16(dy).sum((0, 1)), rtol=1e-5, atol=1e-3)
+    # the outputs accumulate: a second call on the same inputs adds the same sums
+    first_w, first_b = dw.clone(), db.clone()
+    ctx.conv_wgrad(H, W, cin, cout, _bf(x, ctx.device), _bf(dy, ctx.device), dw, db)
+    torch.cuda.synchronize()
+    torch.testing.assert_close(dw, 2 * first_w, rtol=1e-6, atol=1e-6 * float(first_w.abs().max()))
+    torch.testing.assert_close(db, 2 * first_b, rtol=1e-6, atol=1e-6 * float(first_b.abs().max()))
 
 
 def test_network_forward_and_gradients(ctx):
