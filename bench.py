@@ -102,6 +102,69 @@ def cpu_baseline():
                 sample=f"one full 640x480 frame fwd+bwd (room frame, seed 10), {dt:.1f} s on 1 thread")
 
 
+def cpu_baseline_window():
+    """The oracle on one host core, sampled: view 0 of the 8-keyframe window
+    rendering keyframe 0 (one of the 64 keyframe-view pairs), fwd+bwd,
+    scaled to whole-window iterations."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import splat
+    from paper_2603_21055_amd import synth
+    sc = synth.room_window(20)
+    rng = np.random.default_rng(0)
+    H, W = 480, 640
+    gr = [rng.normal(size=(3, H, W)) / (H * W)]
+    gd = [rng.normal(size=(H, W)) / (H * W)]
+    ga = [rng.normal(size=(H, W)) / (H * W)]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        f = splat.render_job(sc["kfs"], sc["views"][0], [0])
+        splat.render_backward(sc["kfs"], sc["views"], [(0, [0])], [f], gr, gd, ga)
+        dt = time.perf_counter() - t0
+    return dict(value=1.0 / (64 * dt), unit="iterations/s", cores=1, kind="oracle",
+                sample=f"view 0 x keyframe 0 (1 of 64 pairs) fwd+bwd, {dt:.1f} s on 1 thread, x64")
+
+
+def cpu_baseline_tracking():
+    """The oracle on one host core, sampled: one Gauss-Newton iteration
+    (linearise + damped FP64 solve) over the top 170 of the 680 rows (same
+    intrinsics, every Gaussian preprocessed), scaled by 4 to the frame."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import track
+    from paper_2603_21055_amd import synth
+    sc = synth.tracking_scene(30)
+    cam = dict(sc["cam"], H=170)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        lin = track.linearise(sc["geo"], cam, sc["init"]["R"], sc["init"]["t"], sc["obs_depth"][:170])
+        track.solve(lin["H"], lin["g"])
+        dt = time.perf_counter() - t0
+    return dict(value=1.0 / (4 * dt), unit="iterations/s", cores=1, kind="oracle",
+                sample=f"one iteration over rows 0-169 of 680, {dt:.1f} s on 1 thread, x4")
+
+
+def cpu_baseline_offsetnet():
+    """The oracle on one host core: the warm-start net's forward (bf16 roundings
+    emulated, FP64 arithmetic) on one 640x480 frame."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import conv
+    H, W = 480, 640
+    rng = np.random.default_rng(0)
+    rgb = rng.uniform(size=(3, H, W))
+    dep = rng.uniform(0.5, 5.0, size=(H, W))
+    params = conv.init_params(0)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        conv.forward(params, conv.net_input(rgb, dep))
+        dt = time.perf_counter() - t0
+    return dict(value=1.0 / dt, unit="frames/s", cores=1, kind="oracle",
+                sample=f"one 640x480 frame forward, {dt:.1f} s on 1 thread")
+
+
 def _timed(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -138,10 +201,13 @@ def bench_window(args):
     ctx.sync()
     N, P = 8 * 640 * 480, 640 * 480
     algo = 80 * N + 8 * 52 * P
-    print(json.dumps(dict(metric="batched mapping window iterations/s (8 keyframes x 8 views, 640x480)",
-                          value=1.0 / sec, unit="iterations/s", ms_per_step=sec * 1e3, steps=steps,
-                          hbm_frac=algo / sec / HBM_PEAK, tile=[tw, th], dtype="f32", data="synthetic")),
-          flush=True)
+    out = dict(metric="batched mapping window iterations/s (8 keyframes x 8 views, 640x480)",
+               value=1.0 / sec, unit="iterations/s", ms_per_step=sec * 1e3, steps=steps,
+               hbm_frac=algo / sec / HBM_PEAK, tile=[tw, th], dtype="f32", data="synthetic")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline_window()
+    print(json.dumps(out), flush=True)
 
 
 def bench_tracking(args):
@@ -167,9 +233,13 @@ def bench_tracking(args):
     steps = max(1, min(args.steps, 20))
     sec = _timed(run, steps, min(args.warmup, 3))
     ctx.sync()
-    print(json.dumps(dict(metric="tracking Gauss-Newton iterations/s (1200x680, 30 per graph launch)",
-                          value=30.0 / sec, unit="iterations/s", ms_per_graph=sec * 1e3, steps=steps,
-                          dtype="f32 (FP64 solve)", data="synthetic")), flush=True)
+    out = dict(metric="tracking Gauss-Newton iterations/s (1200x680, 30 per graph launch)",
+               value=30.0 / sec, unit="iterations/s", ms_per_graph=sec * 1e3, steps=steps,
+               dtype="f32 (FP64 solve)", data="synthetic")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline_tracking()
+    print(json.dumps(out), flush=True)
 
 
 def bench_offsetnet(args):
@@ -212,15 +282,19 @@ def bench_offsetnet(args):
     # flop per 128 bytes (144 flop/B), below the 312 flop/B at which the BF16
     # MFMA peak and HBM balance, so the net is HBM-bound.
     b_fwd = (16 + 8 + sum(2 * ci + (2 * co if l < 5 else 4) for l, (ci, co) in enumerate(lay))) * H * W
-    print(json.dumps(dict(metric="warm-start conv net frames/s (640x480, BF16 MFMA)", value=1.0 / t_f,
-                          unit="frames/s", ms_forward=t_f * 1e3, ms_forward_backward=t_fb * 1e3,
-                          tflops_forward=f_fwd / t_f / 1e12, tflops_forward_backward=(f_fwd + f_bwd) / t_fb / 1e12,
-                          mfma_frac_forward=f_fwd / t_f / BF16_MFMA_PEAK,
-                          roofline=dict(bound="hbm", achieved=b_fwd / t_f / 1e9, peak=HBM_PEAK / 1e9,
-                                        unit="GB/s", frac=b_fwd / t_f / HBM_PEAK, traffic=None,
-                                        algorithmic_bytes=b_fwd, scope="forward: input + 6 conv layers"),
-                          gflop_forward=f_fwd / 1e9, gflop_backward=f_bwd / 1e9, steps=steps, dtype="bf16",
-                          data="synthetic")), flush=True)
+    out = dict(metric="warm-start conv net frames/s (640x480, BF16 MFMA)", value=1.0 / t_f,
+               unit="frames/s", ms_forward=t_f * 1e3, ms_forward_backward=t_fb * 1e3,
+               tflops_forward=f_fwd / t_f / 1e12, tflops_forward_backward=(f_fwd + f_bwd) / t_fb / 1e12,
+               mfma_frac_forward=f_fwd / t_f / BF16_MFMA_PEAK,
+               roofline=dict(bound="hbm", achieved=b_fwd / t_f / 1e9, peak=HBM_PEAK / 1e9,
+                             unit="GB/s", frac=b_fwd / t_f / HBM_PEAK, traffic=None,
+                             algorithmic_bytes=b_fwd, scope="forward: input + 6 conv layers"),
+               gflop_forward=f_fwd / 1e9, gflop_backward=f_bwd / 1e9, steps=steps, dtype="bf16",
+               data="synthetic")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline_offsetnet()
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 
