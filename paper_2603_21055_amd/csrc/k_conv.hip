@@ -30,34 +30,28 @@ __device__ __forceinline__ bf16x8 zero8() {
     return v;
 }
 
+// v clamped into [0, n - 1] (n > 0): a load address that is always in bounds
+__device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
 // MODE 0: y = relu(conv + bias) as bf16 [H][W][COUT]
 // MODE 1: y = conv + bias as f32 [H][W] (COUT == 1)
 // MODE 2: y = conv * [mask > 0] as bf16 [H][W][COUT] (input gradient through a ReLU)
+//
+// Persistent: a workgroup loads the weights once and walks 16x16 output
+// tiles; the next tile's 18x18 input patch is loaded into registers while
+// the MFMAs of the current tile run.  The patch loads read addresses clamped
+// into the image and are zeroed outside it when they are stored to LDS, so
+// no load waits at a branch.
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv(int H, int W, const __bf16* __restrict__ x,
                                               const __bf16* __restrict__ w, const float* __restrict__ bias,
                                               const __bf16* __restrict__ mask, void* __restrict__ yout) {
     constexpr int MB = (COUT + 15) / 16;
+    constexpr int L = (324 * 4 + 255) / 256;   // 16-byte patch loads per thread
     __shared__ __attribute__((aligned(16))) __bf16 s_x[18 * 18 * kPS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
-    for (int i = tid; i < 324 * 4; i += 256) {
-        const int pix = i >> 2, ch = i & 3;
-        const int ty = pix / 18, tx = pix - ty * 18;
-        const int gy = y0 + ty - 1, gx = x0 + tx - 1;
-        bf16x8 v = zero8();
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-            const size_t base = ((size_t)gy * W + gx) * CIN;
-            if (CIN == 32) {
-                v = *(const bf16x8*)(x + base + ch * 8);
-            } else if (ch == 0) {
-#pragma unroll
-                for (int c = 0; c < CIN; ++c) v[c] = x[base + c];
-            }
-        }
-        *(bf16x8*)(s_x + pix * kPS + ch * 8) = v;
-    }
+    const int ntx = (W + 15) / 16, ntiles = ntx * ((H + 15) / 16);
     bf16x8 A[9][MB];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
@@ -76,46 +70,79 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const __bf16* __rest
             }
             A[t][mb] = v;
         }
-    __syncthreads();
-    f32x4 acc[MB][4];
+    bf16x8 xv[L];
+    auto load_patch = [&](int tile) {
+        const int x0 = (tile % ntx) * 16, y0 = (tile / ntx) * 16;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+        for (int k = 0; k < L; ++k) {
+            const int i = tid + 256 * k, pix = i >> 2, ch = i & 3;
+            const int ty = pix / 18, tx = pix - ty * 18;
+            const size_t base = ((size_t)clampi(y0 + ty - 1, H) * W + clampi(x0 + tx - 1, W)) * CIN;
+            if (CIN == 32) {
+                xv[k] = *(const bf16x8*)(x + base + ch * 8);
+            } else {
+                xv[k] = zero8();
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int c = 0; c < CIN; ++c) xv[k][c] = x[base + c];
+            }
+        }
+    };
+    int tile = blockIdx.x;
+    if (tile < ntiles) load_patch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int x0 = (tile % ntx) * 16, y0 = (tile / ntx) * 16;
+        __syncthreads();   // the previous tile's MFMAs have read s_x
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int ky = t / 3, kx = t - ky * 3;
+        for (int k = 0; k < L; ++k) {
+            const int i = tid + 256 * k, pix = i >> 2, ch = i & 3;
+            const int ty = pix / 18, tx = pix - ty * 18;
+            const int gy = y0 + ty - 1, gx = x0 + tx - 1;
+            const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W && (CIN == 32 || ch == 0);
+            if (i < 324 * 4) *(bf16x8*)(s_x + pix * kPS + ch * 8) = in ? xv[k] : zero8();
+        }
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) load_patch(tile + gridDim.x);
+        f32x4 acc[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t - ky * 3;
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const int ry = wave * 4 + nb + ky, rx = r16 + kx;
+                const bf16x8 B = *(const bf16x8*)(s_x + (ry * 18 + rx) * kPS + g * 8);
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[t][mb], B, acc[mb][nb], 0, 0, 0);
+            }
+        }
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
-            const int ry = wave * 4 + nb + ky, rx = r16 + kx;
-            const bf16x8 B = *(const bf16x8*)(s_x + (ry * 18 + rx) * kPS + g * 8);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[t][mb], B, acc[mb][nb], 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        const int py = y0 + wave * 4 + nb, px = x0 + r16;
-        if (py >= H || px >= W) continue;
-        const size_t p = (size_t)py * W + px;
-        if (MODE == 1) {
-            if (g == 0) ((float*)yout)[p] = acc[0][nb][0] + bias[0];
-            continue;
-        }
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const int co0 = mb * 16 + 4 * g;
-            if (co0 >= COUT) continue;
-            bf16x4 o;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                float v = acc[mb][nb][e];
-                if (MODE == 0) v = fmaxf(v + bias[co0 + e], 0.f);
-                else if ((float)mask[p * COUT + co0 + e] <= 0.f) v = 0.f;
-                o[e] = (__bf16)v;
+            const int py = y0 + wave * 4 + nb, px = x0 + r16;
+            if (py >= H || px >= W) continue;
+            const size_t p = (size_t)py * W + px;
+            if (MODE == 1) {
+                if (g == 0) ((float*)yout)[p] = acc[0][nb][0] + bias[0];
+                continue;
             }
-            *(bf16x4*)((__bf16*)yout + p * COUT + co0) = o;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int co0 = mb * 16 + 4 * g;
+                if (co0 >= COUT) continue;
+                bf16x4 o;
+                if (MODE == 2) {
+                    const bf16x4 mk = *(const bf16x4*)(mask + p * COUT + co0);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[e] = (__bf16)((float)mk[e] > 0.f ? acc[mb][nb][e] : 0.f);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[e] = (__bf16)fmaxf(acc[mb][nb][e] + bias[co0 + e], 0.f);
+                }
+                *(bf16x4*)((__bf16*)yout + p * COUT + co0) = o;
+            }
         }
     }
 }
@@ -355,9 +382,11 @@ __global__ __launch_bounds__(256) void k_offset_l1(int n, const float* pred, con
 // ---------------------------------------------------------------------------
 // host launchers (return false for an unsupported channel configuration)
 // ---------------------------------------------------------------------------
+constexpr int kConvBlocks = 512;   // persistent conv workgroups
+
 bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* bias,
                      const void* mask, void* y, hipStream_t s) {
-    const dim3 grid((W + 15) / 16, (H + 15) / 16), blk(256);
+    const dim3 grid(std::min(((W + 15) / 16) * ((H + 15) / 16), kConvBlocks)), blk(256);
     const __bf16* xb = (const __bf16*)x;
     const __bf16* wb = (const __bf16*)w;
     const __bf16* mb = (const __bf16*)mask;
