@@ -47,7 +47,8 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const __bf16* __rest
                                               const __bf16* __restrict__ w, const float* __restrict__ bias,
                                               const __bf16* __restrict__ mask, void* __restrict__ yout) {
     constexpr int MB = (COUT + 15) / 16;
-    constexpr int L = (324 * 4 + 255) / 256;   // 16-byte patch loads per thread
+    constexpr int NCH = CIN == 32 ? 4 : 1;          // 8-channel groups loaded per pixel
+    constexpr int L = (324 * NCH + 255) / 256;      // patch loads per thread
     __shared__ __attribute__((aligned(16))) __bf16 s_x[18 * 18 * kPS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
@@ -70,16 +71,26 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const __bf16* __rest
             }
             A[t][mb] = v;
         }
+    // with fewer than 32 input channels only the first 8-channel group of a
+    // pixel is loaded; the other groups stay zero from here on
+    if (CIN < 32)
+        for (int i = tid; i < 324 * 4; i += 256)
+            if ((i & 3) != 0) *(bf16x8*)(s_x + (i >> 2) * kPS + (i & 3) * 8) = zero8();
     bf16x8 xv[L];
     auto load_patch = [&](int tile) {
         const int x0 = (tile % ntx) * 16, y0 = (tile / ntx) * 16;
 #pragma unroll
         for (int k = 0; k < L; ++k) {
-            const int i = tid + 256 * k, pix = i >> 2, ch = i & 3;
+            const int i = tid + 256 * k, pix = i / NCH, ch = i % NCH;
             const int ty = pix / 18, tx = pix - ty * 18;
             const size_t base = ((size_t)clampi(y0 + ty - 1, H) * W + clampi(x0 + tx - 1, W)) * CIN;
             if (CIN == 32) {
                 xv[k] = *(const bf16x8*)(x + base + ch * 8);
+            } else if (CIN == 4) {
+                const bf16x4 v = *(const bf16x4*)(x + base);
+                xv[k] = zero8();
+#pragma unroll
+                for (int c = 0; c < 4; ++c) xv[k][c] = v[c];
             } else {
                 xv[k] = zero8();
 #pragma unroll
@@ -94,11 +105,11 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const __bf16* __rest
         __syncthreads();   // the previous tile's MFMAs have read s_x
 #pragma unroll
         for (int k = 0; k < L; ++k) {
-            const int i = tid + 256 * k, pix = i >> 2, ch = i & 3;
+            const int i = tid + 256 * k, pix = i / NCH, ch = i % NCH;
             const int ty = pix / 18, tx = pix - ty * 18;
             const int gy = y0 + ty - 1, gx = x0 + tx - 1;
-            const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W && (CIN == 32 || ch == 0);
-            if (i < 324 * 4) *(bf16x8*)(s_x + pix * kPS + ch * 8) = in ? xv[k] : zero8();
+            const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            if (i < 324 * NCH) *(bf16x8*)(s_x + pix * kPS + ch * 8) = in ? xv[k] : zero8();
         }
         __syncthreads();
         if (tile + (int)gridDim.x < ntiles) load_patch(tile + gridDim.x);
