@@ -158,6 +158,31 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const __bf16* __rest
     }
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// The 8 bf16 that start kx (0, 1 or 2; uniform across the wave) elements
+// after a 16-byte aligned LDS address, from one 16-byte and one 4-byte read
+// joined by byte shifts (v_alignbyte) instead of eight 2-byte reads.
+__device__ __forceinline__ bf16x8 lds_shifted8(const __bf16* p, int kx) {
+    const u32x4 lo = *(const u32x4*)p;
+    const uint32_t hi = *(const uint32_t*)(p + 8);
+    u32x4 o;
+    if (kx == 0) {
+        o = lo;
+    } else if (kx == 1) {
+        o[0] = __builtin_amdgcn_alignbyte(lo[1], lo[0], 2);
+        o[1] = __builtin_amdgcn_alignbyte(lo[2], lo[1], 2);
+        o[2] = __builtin_amdgcn_alignbyte(lo[3], lo[2], 2);
+        o[3] = __builtin_amdgcn_alignbyte(hi, lo[3], 2);
+    } else {
+        o[0] = lo[1];
+        o[1] = lo[2];
+        o[2] = lo[3];
+        o[3] = hi;
+    }
+    return __builtin_bit_cast(bf16x8, o);
+}
+
 // The channels of one NHWC pixel that one load moves (raw bf16 bits):
 // 8 (16 bytes) when C is a multiple of 8, else all C.
 template <int C>
@@ -180,12 +205,12 @@ struct ChanVec<1> {
 // every entry written); k_wgrad_reduce sums the rows.  Same-address atomics
 // from every workgroup on the chip would serialise.
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __restrict__ x,
+__global__ __launch_bounds__(256, 2) void k_wgrad(int H, int W, const __bf16* __restrict__ x,
                                                const __bf16* __restrict__ dy, float* __restrict__ part) {
     constexpr int MB = (COUT + 15) / 16, NB = (CIN + 15) / 16;
     constexpr int DS = 264;  // [co][pixel] row stride
     __shared__ __attribute__((aligned(16))) __bf16 s_dy[32 * DS];
-    __shared__ __bf16 s_x[32 * 18 * 24];
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[32 * 18 * 24];
     __shared__ float s_db[8][32];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
@@ -271,10 +296,7 @@ __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __res
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     const int ci = nb * 16 + r16;
-                    bf16x8 Bv;
-                    const __bf16* src = s_x + (ci * 18 + row + ky) * 24 + col + kx;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) Bv[j] = src[j];
+                    const bf16x8 Bv = lds_shifted8(s_x + (ci * 18 + row + ky) * 24 + col, kx);
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb)
                         acc[k3][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am[mb], Bv, acc[k3][mb][nb], 0, 0, 0);
@@ -286,10 +308,7 @@ __global__ __launch_bounds__(256) void k_wgrad(int H, int W, const __bf16* __res
             for (int ks = 0; ks < 8; ++ks) {
                 const int row = 2 * ks + (g >> 1), col = (g & 1) * 8;
                 const bf16x8 Am = *(const bf16x8*)(s_dy + (mb8 * 16 + r16) * DS + 32 * ks + 8 * g);
-                const __bf16* src = s_x + ((nb8 * 16 + r16) * 18 + row + 2) * 24 + col + 2;
-                bf16x8 Bv;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) Bv[j] = src[j];
+                const bf16x8 Bv = lds_shifted8(s_x + ((nb8 * 16 + r16) * 18 + row + 2) * 24 + col, 2);
                 acc8 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am, Bv, acc8, 0, 0, 0);
             }
         }
