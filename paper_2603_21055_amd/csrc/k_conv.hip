@@ -237,47 +237,91 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(int H, int W, const __bf16* __
     // bytes), every global load of the tile issued before the LDS stores
     typedef typename ChanVec<COUT>::T VecY;
     typedef typename ChanVec<CIN>::T VecX;
-    constexpr int VY = ChanVec<COUT>::V, NVY = COUT / VY, LY = (256 * NVY + 255) / 256;
-    constexpr int VX = ChanVec<CIN>::V, NVX = CIN / VX, LX = (324 * NVX + 255) / 256;
+    constexpr int VY = ChanVec<COUT>::V, NVY = COUT / VY;
+    constexpr int VX = ChanVec<CIN>::V, NVX = CIN / VX;
     const unsigned short* dyr = (const unsigned short*)dy;
     const unsigned short* xr = (const unsigned short*)x;
     unsigned short* s_dyr = (unsigned short*)s_dy;
     unsigned short* s_xr = (unsigned short*)s_x;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int x0 = (tile % ntx) * 16, y0 = (tile / ntx) * 16;
-        VecY ry[LY];
-        VecX rx[LX];
+        // A channel count that is a multiple of 8 is staged two horizontally
+        // adjacent pixels per item, stored as 4-byte pairs into the
+        // [channel][pixel] tiles (half the LDS writes of one pixel per item).
+        constexpr bool PY = COUT % 8 == 0, PX = CIN % 8 == 0;
+        constexpr int NY = PY ? 128 * NVY : 256 * NVY;   // items of the dy tile
+        constexpr int NX = PX ? 162 * NVX : 324 * NVX;   // items of the x patch
+        constexpr int KY = (NY + 255) / 256, KX = (NX + 255) / 256;
+        VecY ry[PY ? 2 * KY : KY];
+        VecX rx[PX ? 2 * KX : KX];
 #pragma unroll
-        for (int k = 0; k < LY; ++k) {
-            const int i = tid + 256 * k, p = i / NVY, c = (i - p * NVY) * VY;
-            const int gy = y0 + (p >> 4), gx = x0 + (p & 15);
-            ry[k] = VecY(0);
-            if (i < 256 * NVY && gy < H && gx < W) ry[k] = *(const VecY*)(dyr + ((size_t)gy * W + gx) * COUT + c);
+        for (int k = 0; k < KY; ++k) {
+            const int i = tid + 256 * k, q = i / NVY, c = (i - q * NVY) * VY;
+            if (PY) {
+                const int p0 = 2 * q, gy = y0 + (p0 >> 4), gx = x0 + (p0 & 15);
+                ry[2 * k] = VecY(0);
+                ry[2 * k + 1] = VecY(0);
+                if (i < NY && gy < H) {
+                    const unsigned short* src = dyr + ((size_t)gy * W + gx) * COUT + c;
+                    if (gx < W) ry[2 * k] = *(const VecY*)src;
+                    if (gx + 1 < W) ry[2 * k + 1] = *(const VecY*)(src + COUT);
+                }
+            } else {
+                const int gy = y0 + (q >> 4), gx = x0 + (q & 15);
+                ry[k] = VecY(0);
+                if (i < NY && gy < H && gx < W) ry[k] = *(const VecY*)(dyr + ((size_t)gy * W + gx) * COUT + c);
+            }
         }
 #pragma unroll
-        for (int k = 0; k < LX; ++k) {
-            const int i = tid + 256 * k, pix = i / NVX, c = (i - pix * NVX) * VX;
-            const int ty = pix / 18, tx = pix - ty * 18;
-            const int gy = y0 + ty - 1, gx = x0 + tx - 1;
-            rx[k] = VecX(0);
-            if (i < 324 * NVX && gy >= 0 && gy < H && gx >= 0 && gx < W)
-                rx[k] = *(const VecX*)(xr + ((size_t)gy * W + gx) * CIN + c);
+        for (int k = 0; k < KX; ++k) {
+            const int i = tid + 256 * k, q = i / NVX, c = (i - q * NVX) * VX;
+            if (PX) {
+                const int ty = q / 9, tx0 = (q - ty * 9) * 2;
+                const int gy = y0 + ty - 1, gx = x0 + tx0 - 1;
+                rx[2 * k] = VecX(0);
+                rx[2 * k + 1] = VecX(0);
+                if (i < NX && gy >= 0 && gy < H) {
+                    const unsigned short* src = xr + ((size_t)gy * W + gx) * CIN + c;
+                    if (gx >= 0 && gx < W) rx[2 * k] = *(const VecX*)src;
+                    if (gx + 1 >= 0 && gx + 1 < W) rx[2 * k + 1] = *(const VecX*)(src + CIN);
+                }
+            } else {
+                const int ty = q / 18, tx = q - ty * 18;
+                const int gy = y0 + ty - 1, gx = x0 + tx - 1;
+                rx[k] = VecX(0);
+                if (i < NX && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                    rx[k] = *(const VecX*)(xr + ((size_t)gy * W + gx) * CIN + c);
+            }
         }
         __syncthreads();   // the previous tile's MFMA reads are done
 #pragma unroll
-        for (int k = 0; k < LY; ++k) {
-            const int i = tid + 256 * k, p = i / NVY, c = (i - p * NVY) * VY;
-            if (i < 256 * NVY)
+        for (int k = 0; k < KY; ++k) {
+            const int i = tid + 256 * k, q = i / NVY, c = (i - q * NVY) * VY;
+            if (i >= NY) continue;
 #pragma unroll
-                for (int j = 0; j < VY; ++j) s_dyr[(c + j) * DS + p] = ChanVec<COUT>::get(ry[k], j);
+            for (int j = 0; j < VY; ++j) {
+                if (PY)
+                    *(uint32_t*)(s_dyr + (c + j) * DS + 2 * q) =
+                        (uint32_t)ChanVec<COUT>::get(ry[2 * k], j) | ((uint32_t)ChanVec<COUT>::get(ry[2 * k + 1], j) << 16);
+                else
+                    s_dyr[(c + j) * DS + q] = ChanVec<COUT>::get(ry[k], j);
+            }
         }
 #pragma unroll
-        for (int k = 0; k < LX; ++k) {
-            const int i = tid + 256 * k, pix = i / NVX, c = (i - pix * NVX) * VX;
-            const int ty = pix / 18, tx = pix - ty * 18;
-            if (i < 324 * NVX)
+        for (int k = 0; k < KX; ++k) {
+            const int i = tid + 256 * k, q = i / NVX, c = (i - q * NVX) * VX;
+            if (i >= NX) continue;
+            if (PX) {
+                const int ty = q / 9, tx0 = (q - ty * 9) * 2;
+#pragma unroll
+                for (int j = 0; j < VX; ++j)
+                    *(uint32_t*)(s_xr + ((c + j) * 18 + ty) * 24 + tx0) =
+                        (uint32_t)ChanVec<CIN>::get(rx[2 * k], j) | ((uint32_t)ChanVec<CIN>::get(rx[2 * k + 1], j) << 16);
+            } else {
+                const int ty = q / 18, tx = q - ty * 18;
 #pragma unroll
                 for (int j = 0; j < VX; ++j) s_xr[((c + j) * 18 + ty) * 24 + tx] = ChanVec<CIN>::get(rx[k], j);
+            }
         }
         __syncthreads();
         if (bco < COUT)
