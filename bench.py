@@ -45,12 +45,17 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = {
     "composite_bwd": ("k_raster8.hip", "raster_common.h", "segsort.h", "sgad_internal.h"),
     "composite_fwd": ("k_raster8.hip", "raster_common.h", "segsort.h", "sgad_internal.h"),
+    "offsetnet_forward": ("k_conv.hip",),
 }
 PMC = {    # kernel -> counters per dispatch and the sources they were taken on
     "composite_bwd": dict(fetch_kib=26837.8, write_kib=84982.0, tile=(8, 8), variant=(1, 16),
                           sha="ebeec503754b6262fa7528add994ea0853911354f9e5cd71f959e90906daab55"),
     "composite_fwd": dict(fetch_kib=16235.0, write_kib=28966.9, tile=(8, 8), variant=(1, 16),
                           sha="ebeec503754b6262fa7528add994ea0853911354f9e5cd71f959e90906daab55"),
+    # the warm-start net's forward at 640x480: k_net_input + the six conv
+    # launches, counters summed over the seven dispatches
+    "offsetnet_forward": dict(fetch_kib=66241.5, write_kib=99600.0,
+                              sha="6f5a528b9d3db3c3fc9058cb6c7d67a137c0f625dcae8373c1b577e46a1676c8"),
 }
 
 
@@ -287,7 +292,7 @@ def bench_offsetnet(args):
                tflops_forward=f_fwd / t_f / 1e12, tflops_forward_backward=(f_fwd + f_bwd) / t_fb / 1e12,
                mfma_frac_forward=f_fwd / t_f / BF16_MFMA_PEAK,
                roofline=dict(bound="hbm", achieved=b_fwd / t_f / 1e9, peak=HBM_PEAK / 1e9,
-                             unit="GB/s", frac=b_fwd / t_f / HBM_PEAK, traffic=None,
+                             unit="GB/s", frac=b_fwd / t_f / HBM_PEAK, traffic=traffic_bytes("offsetnet_forward"),
                              algorithmic_bytes=b_fwd, scope="forward: input + 6 conv layers"),
                gflop_forward=f_fwd / 1e9, gflop_backward=f_bwd / 1e9, steps=steps, dtype="bf16",
                data="synthetic")
