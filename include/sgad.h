@@ -334,7 +334,7 @@ sgad_status sgad_adam_step(sgad_ctx* ctx, int n_groups, const sgad_adam_group* g
 /* ---------------------------------------------------------------- conv net */
 /*
  * Learned offset warm start (this library's addition; the paper starts the
- * offsets at zero, Sec. 3.2): delta0 = Net(R, G, B, D / 5 m), six 3x3 'same'
+ * offsets at zero, Sec. 3.2): delta0 = Net(R, G, B, h), six 3x3 'same'
  * convolutions 4 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 with ReLU after the first
  * five.  Activations are bf16 NHWC ([H][W][C]); weights [9][cout][cin]
  * (tap = 3 ky + kx, taps reading x[y + ky - 1][x + kx - 1]); products run on
@@ -366,7 +366,8 @@ sgad_status sgad_conv3x3_dgrad(sgad_ctx* ctx, int H, int W, int cin, int cout, c
  * wgrad calls of one context that overlap on different streams race on it. */
 sgad_status sgad_conv3x3_wgrad(sgad_ctx* ctx, int H, int W, int cin, int cout, const uint16_t* x,
                                const uint16_t* dy, float* dw, float* db, void* stream);
-/* Network input (R, G, B, D / 5 m) as bf16 [H][W][4] from planar rgb [3][H][W] and depth [H][W]. */
+/* Network input (R, G, B, h) as bf16 [H][W][4] from planar rgb [3][H][W] and depth [H][W]:
+ * h = (D - mean of D over the 3x3 neighbourhood inside the image) / 0.02 m. */
 sgad_status sgad_net_input(sgad_ctx* ctx, int H, int W, const float* rgb, const float* depth, uint16_t* x0,
                            void* stream);
 /* Training loss mean |pred - target| over n values (device double, written)

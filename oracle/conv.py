@@ -3,9 +3,15 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 The paper initialises offsets at zero (Sec. 3.2); the learned warm start is
-this build's addition: delta0 = Net(R, G, B, D / 5 m) with six 3x3 'same'
+this build's addition: delta0 = Net(R, G, B, h) with six 3x3 'same'
 (zero-padded) convolutions 4 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, ReLU after the
 first five, no output activation; the output is an offset in metres.
+
+The depth channel h is the observed depth minus its local 3x3 mean (over
+the neighbours inside the image), in units of 2 cm.  Depth itself (metres,
+0.5-5 m) would be stored in BF16 with a spacing of 4-31 mm, as coarse as the
+centimetre-level sensor noise the converged offsets undo; the high-passed
+depth keeps that noise resolvable (BF16 spacing below 0.1 mm at |h| < 1).
 
 Precision model of the GPU path, emulated here where it rounds: weights,
 the network input and every stored activation are BF16 (round to nearest
@@ -20,7 +26,7 @@ from __future__ import annotations
 import numpy as np
 
 CHANNELS = [4, 32, 32, 32, 32, 32, 1]
-DEPTH_SCALE = 5.0
+DEPTH_HP_SCALE = 0.02   # metres per unit of the depth channel
 
 
 def bf16(x):
@@ -37,10 +43,27 @@ def bf16(x):
     return out
 
 
+def depth_channel(depth):
+    """h = (D - mean of D over the 3x3 neighbourhood inside the image) / 2 cm."""
+    D = np.asarray(depth, np.float64)
+    H, W = D.shape
+    s = np.zeros((H, W))
+    n = np.zeros((H, W))
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            ys = slice(max(0, dy), H + min(0, dy))
+            yd = slice(max(0, -dy), H + min(0, -dy))
+            xs = slice(max(0, dx), W + min(0, dx))
+            xd = slice(max(0, -dx), W + min(0, -dx))
+            s[yd, xd] += D[ys, xs]
+            n[yd, xd] += 1.0
+    return (D - s / n) / DEPTH_HP_SCALE
+
+
 def net_input(rgb, depth):
-    """[H][W][4] input: colour planes and depth / 5 m."""
+    """[H][W][4] input: colour planes and the high-passed depth channel."""
     rgb = np.asarray(rgb, np.float64)
-    return np.concatenate([rgb.transpose(1, 2, 0), (np.asarray(depth, np.float64) / DEPTH_SCALE)[..., None]], 2)
+    return np.concatenate([rgb.transpose(1, 2, 0), depth_channel(depth)[..., None]], 2)
 
 
 def conv3x3(x, w, b=None):

@@ -128,6 +128,10 @@ def preprocess(kf: dict, vcam: dict, vR, vt) -> dict:
 # ----------------------------------------------------------------------------
 # the job's Gaussian set
 # ----------------------------------------------------------------------------
+GAUSS_KEYS = ("x", "y", "z", "valid", "mx", "my", "s00", "s01", "s11", "ca", "cb", "cc",
+              "rho", "zkey", "d", "sgn", "xn", "yn", "r", "gid", "kf", "part", "o", "u", "v")
+
+
 def gather_job(kfs, view, kf_ids, channels="rgb") -> dict:
     """Concatenate the preprocessed Gaussians of keyframes ``kf_ids`` seen
     from ``view``; colour channels are RGB or, for tracking, sigma^2."""
@@ -138,6 +142,7 @@ def gather_job(kfs, view, kf_ids, channels="rgb") -> dict:
         N = g["N"]
         g["gid"] = f * N + np.arange(N, dtype=np.int64)
         g["kf"] = np.full(N, f, np.int64)
+        g["part"] = np.full(N, len(parts), np.int64)
         g["o"] = kf["opacity"].astype(np.float64).ravel()
         if channels == "rgb":
             g["col"] = kf["rgb"].astype(np.float64).reshape(3, -1).T
@@ -146,8 +151,7 @@ def gather_job(kfs, view, kf_ids, channels="rgb") -> dict:
             g["col"] = (sg * sg)[:, None]
         parts.append(g)
     out = {}
-    for key in ("x", "y", "z", "valid", "mx", "my", "s00", "s01", "s11", "ca", "cb", "cc",
-                "rho", "zkey", "d", "sgn", "xn", "yn", "r", "gid", "kf", "o", "u", "v"):
+    for key in GAUSS_KEYS:
         out[key] = np.concatenate([p[key] for p in parts])
     out["col"] = np.concatenate([p["col"] for p in parts], 0)
     out["parts"] = parts
@@ -279,6 +283,46 @@ def render_job(kfs, view, kf_ids, channels="rgb"):
     return dict(rgb=out["col"].T.reshape(C, H, W), depth=out["depth"].reshape(H, W),
                 alpha=out["alpha"].reshape(H, W), n=out["n"].reshape(H, W),
                 flags=flags.reshape(H, W), g=g, P=P, comp=out, H=H, W=W)
+
+
+def render_window(kfs, view, kf_ids, win, channels="rgb"):
+    """``render_job`` evaluated on the pixels of the window win = (x0, y0, x1,
+    y1) (half-open) only: the job's Gaussians whose integer bounding square
+    meets the window are the only ones that can reach its pixels, and their
+    pairs with pixels outside it are dropped.  Pixel outputs inside the window
+    equal render_job's; per-Gaussian gradients of ``backward_job`` on the
+    result are complete for the Gaussians whose in-image square lies inside
+    the window (``complete`` mask, aligned with the returned Gaussian set)."""
+    cam = view["cam"]
+    H, W = cam["H"], cam["W"]
+    x0, y0, x1, y1 = win
+    g = gather_job(kfs, view, kf_ids, channels)
+    lo_x = np.maximum(np.ceil(g["mx"] - g["rho"]), 0)
+    hi_x = np.minimum(np.floor(g["mx"] + g["rho"]), W - 1)
+    lo_y = np.maximum(np.ceil(g["my"] - g["rho"]), 0)
+    hi_y = np.minimum(np.floor(g["my"] + g["rho"]), H - 1)
+    meets = g["valid"] & (hi_x >= x0) & (lo_x <= x1 - 1) & (hi_y >= y0) & (lo_y <= y1 - 1)
+    idx = np.nonzero(meets)[0]
+    sub = {k: g[k][idx] for k in GAUSS_KEYS}
+    sub["col"] = g["col"][idx]
+    sub["parts"] = g["parts"]
+    sub["kf_ids"] = g["kf_ids"]
+    P, flags = contributor_pairs(sub, W, H)
+    px, py = P["pix"] % W, P["pix"] // W
+    inside = (px >= x0) & (px < x1) & (py >= y0) & (py < y1)
+    P = {k: v[inside] for k, v in P.items()}
+    flags = flags.reshape(H, W)
+    wmask = np.zeros((H, W), bool)
+    wmask[y0:y1, x0:x1] = True
+    flags &= wmask
+    out = composite(sub, P, H * W, flags.ravel())
+    flags = out_flags = flags.ravel()
+    complete = (lo_x[idx] >= x0) & (hi_x[idx] <= x1 - 1) & (lo_y[idx] >= y0) & (hi_y[idx] <= y1 - 1)
+    C = sub["col"].shape[1]
+    return dict(rgb=out["col"].T.reshape(C, H, W), depth=out["depth"].reshape(H, W),
+                alpha=out["alpha"].reshape(H, W), n=out["n"].reshape(H, W),
+                flags=out_flags.reshape(H, W), window=wmask, g=sub, P=P, comp=out, H=H, W=W,
+                complete=complete)
 
 
 def render_bruteforce(kfs, view, kf_ids):
@@ -514,10 +558,7 @@ def backward_job(kfs, view, fwd, g_rgb, g_depth, g_alpha):
                                           A["g_b"][idx], A["g_c"][idx], A["g_z"][idx])
     # X = R_rel (d * ray) + t_rel: dL/dd = (R^T gX) . ray, then |D + delta|
     ray = np.stack([g["xn"], g["yn"], np.ones(M)], 1)
-    Rs = []
-    for part in g["parts"]:
-        Rs.append(np.broadcast_to(part["R"], (part["N"], 3, 3)))
-    Rall = np.concatenate(Rs, 0)
+    Rall = np.stack([p["R"] for p in g["parts"]], 0)[g["part"]]
     gXf = np.einsum("nji,nj->ni", Rall, gX)            # R^T gX
     g_d = (gXf * ray).sum(1)
     g_off = g_d * g["sgn"]

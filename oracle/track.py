@@ -20,6 +20,12 @@ to each back-projected point.  Specialised to one dimension along the ray:
 * T5  H = sum J^T J, g = sum J^T r, dxi = -H^-1 g by Cholesky (damped by
       DAMP * tr(H), growing x10, when H is not positive definite), then
       T <- Exp(dxi) T, for a fixed number of iterations.
+
+``linearise`` also returns, per entry of H, g and the log-likelihood, the
+sum of the absolute values of every term that forms it (aH, ag, aloglik)
+and the absolute contribution of the pixels whose validity or contributor
+set is decided within rounding of a threshold (fH, fg, floglik): the
+elementwise parity bound of a lower-precision evaluation is built from them.
 """
 from __future__ import annotations
 
@@ -29,6 +35,7 @@ from . import se3, splat
 
 A_VALID = 0.9
 DAMP = 1e-9
+FLAG_A = 1e-6   # |A - A_VALID| below which FP32 and FP64 may disagree on validity
 
 
 def _pair_jacobians(g, P, fx, fy):
@@ -80,17 +87,62 @@ def linearise(geo, cam, R, t, obs_depth):
     Ss = comp["col"][:, 0]
     obs = np.asarray(obs_depth, np.float64).ravel()
     valid = (Apix >= A_VALID) & (obs > 0)
-    Av = np.where(valid, Apix, 1.0)
+    # every pixel with some coverage gets its residual and Jacobian, so the
+    # pixels next to the validity threshold can be bounded below
+    cov = (Apix > 0) & (Ss > 0) & (obs > 0)
+    Av = np.where(cov, Apix, 1.0)
     mu = Dp / Av
-    s = np.sqrt(np.where(valid, Ss / Av, 1.0))
-    r = np.where(valid, (obs - mu) / s, 0.0)
-    J = -(dD - mu[:, None] * dA) / (Av * s)[:, None]
-    J[~valid] = 0.0
+    s = np.sqrt(np.where(cov, Ss / Av, 1.0))
+    r_all = np.where(cov, (obs - mu) / s, 0.0)
+    J_all = -(dD - mu[:, None] * dA) / (Av * s)[:, None]
+    J_all[~cov] = 0.0
+    r = np.where(valid, r_all, 0.0)
+    J = np.where(valid[:, None], J_all, 0.0)
     Hm = J.T @ J
     gv = J.T @ r
-    ll = float(np.sum(np.where(valid, -0.5 * r * r - np.log(s) - 0.5 * np.log(2 * np.pi), 0.0)))
+    llp = -0.5 * r_all * r_all - np.log(s) - 0.5 * np.log(2 * np.pi)
+    ll = float(np.sum(np.where(valid, llp, 0.0)))
+
+    # Tolerance terms.  (1) Absolute-term sums: every product and difference
+    # of the per-pair partials, the per-pixel sums and the normal-equation
+    # sums taken with absolute values (a bound on the rounding error of any
+    # evaluation order, in units of the working precision).
+    aX, _ = splat.geom_to_X_abs(g, P["gi"], fx, fy,
+                                a_mx=2.0 * (np.abs(g["ca"][P["gi"]] * P["dx"]) + np.abs(g["cb"][P["gi"]] * P["dy"])),
+                                a_my=2.0 * (np.abs(g["cb"][P["gi"]] * P["dx"]) + np.abs(g["cc"][P["gi"]] * P["dy"])),
+                                a_a=P["dx"] ** 2, a_b=2.0 * np.abs(P["dx"] * P["dy"]), a_c=P["dy"] ** 2,
+                                a_z=np.zeros(len(P["gi"])))
+    Xa = np.abs(np.stack([g["x"][P["gi"]], g["y"][P["gi"]], z], 1))
+    adq = np.concatenate([aX, Xa[:, [1, 2, 0]] * aX[:, [2, 0, 1]] + Xa[:, [2, 0, 1]] * aX[:, [1, 2, 0]]], 1)
+    adalpha = np.where(P["raw"] < splat.ALPHA_MAX, 0.5 * a, 0.0)[:, None] * adq
+    adz = np.stack([np.zeros_like(z), np.zeros_like(z), np.ones_like(z), Xa[:, 1], Xa[:, 0],
+                    np.zeros_like(z)], 1)
+    acD = np.where(con, z * Ti + S * inv, 0.0)
+    aD = np.zeros((n_pix, 6))
+    aA = np.zeros((n_pix, 6))
+    for k in range(6):
+        aD[:, k] = np.bincount(pix, weights=acD * adalpha[:, k] + w * adz[:, k], minlength=n_pix)
+        aA[:, k] = np.bincount(pix, weights=cA * adalpha[:, k], minlength=n_pix)
+    aJ = np.where(cov[:, None], (aD + np.abs(mu)[:, None] * aA) / (Av * s)[:, None], 0.0)
+    ar = np.where(cov, (np.abs(obs) + np.abs(mu)) / s, 0.0)
+    Ja = np.abs(J_all)
+    ra = np.abs(r_all)
+    vm = valid[:, None].astype(np.float64)
+    aH = (aJ * vm).T @ Ja + (Ja * vm).T @ aJ + (Ja * vm).T @ Ja
+    ag = (aJ * vm).T @ ra + (Ja * vm).T @ ar + (Ja * vm).T @ ra
+    all_ = float(np.sum(np.where(valid, 0.5 * r_all * r_all + np.abs(np.log(s)) + 0.5 * np.log(2 * np.pi)
+                                 + ra * ar, 0.0)))
+    # (2) Pixels whose validity or contributor set a rounding-level
+    # difference can change (splat flags, or A within FLAG_A of A_VALID):
+    # their whole absolute contribution.
+    amb = (fwd["flags"].ravel() | (np.abs(Apix - A_VALID) < FLAG_A)) & cov
+    am = amb[:, None].astype(np.float64)
+    fH = (Ja * am).T @ Ja
+    fg = (Ja * am).T @ ra
+    fll = float(np.sum(np.where(amb, np.abs(llp), 0.0)))
     return dict(H=Hm, g=gv, loglik=ll, r=r, J=J, valid=valid, mu=mu, s=s, A=Apix,
-                flags=fwd["flags"].ravel(), n_valid=int(valid.sum()), fwd=fwd)
+                flags=fwd["flags"].ravel(), n_valid=int(valid.sum()), fwd=fwd,
+                aH=aH, ag=ag, aloglik=all_, fH=fH, fg=fg, floglik=fll, n_ambiguous=int(amb.sum()))
 
 
 def solve(Hm, gv):

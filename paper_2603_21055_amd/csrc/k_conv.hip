@@ -423,14 +423,26 @@ __global__ void k_conv_weights(int cin, int cout, const float* w, __bf16* wb, __
 }
 
 // Network input: (R, G, B, D / 5 m) as bf16 [H][W][4].
+// Network input (R, G, B, h): h = (D - mean of D over the in-image 3x3
+// neighbourhood) / 2 cm.  Depth in metres would be stored in bf16 with a
+// 4-31 mm spacing, as coarse as the sensor noise the offsets undo; the
+// high-passed depth resolves it.  The sum runs row by row, left to right.
 __global__ void k_net_input(int H, int W, const float* rgb, const float* depth, __bf16* x0) {
     const int P = H * W;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const int y = p / W, x = p - y * W;
+        float s = 0.f;
+        int n = 0;
+        for (int yy = max(0, y - 1); yy <= min(H - 1, y + 1); ++yy)
+            for (int xx = max(0, x - 1); xx <= min(W - 1, x + 1); ++xx) {
+                s += depth[yy * W + xx];
+                ++n;
+            }
         bf16x4 v;
         v[0] = (__bf16)rgb[p];
         v[1] = (__bf16)rgb[P + p];
         v[2] = (__bf16)rgb[2 * P + p];
-        v[3] = (__bf16)(depth[p] / 5.f);
+        v[3] = (__bf16)((depth[p] - s / (float)n) * (1.f / 0.02f));
         *(bf16x4*)(x0 + (size_t)p * 4) = v;
     }
 }

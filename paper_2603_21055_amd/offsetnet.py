@@ -1,4 +1,4 @@
-"""Offset warm-start network: delta0 = Net(R, G, B, D / 5 m).
+"""Offset warm-start network: delta0 = Net(R, G, B, h), h the high-passed depth.
 
 Six 3x3 convolutions 4 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 with ReLU after the
 first five, BF16 MFMA with FP32 accumulation, all in the HIP library; this

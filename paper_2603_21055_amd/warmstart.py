@@ -7,7 +7,8 @@ rooms seen from random orientations; the keyframe depth carries N(0, 1 cm)
 noise.  The target offsets are what plain mapping converges to: a fixed
 number of mapping iterations of the keyframe (offsets from zero) against
 noise-free ray-cast renders at its own view and two neighbours perturbed by
-up to 2 cm / 1 degree.  The network sees (R, G, B, noisy D / 5 m).
+up to 2 cm / 1 degree.  The network sees (R, G, B, h) with h the noisy depth minus its
+local 3x3 mean, in units of 2 cm.
 
 Evaluation: an 8-keyframe 640x480 window with the same depth noise, every
 view rendering all keyframes; plain mapping starts from zero offsets, warm

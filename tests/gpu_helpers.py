@@ -52,11 +52,21 @@ def rel_err(gpu, orc, mask=None):
     return float(np.abs(gpu - orc).max() / max(np.abs(orc).max(), 1e-6))
 
 
-def assert_forward_parity(out, orc_jobs, tol=1e-5, max_flag_frac=2e-3):
+# Fraction of pixels the oracle may flag as threshold-ambiguous.  A pixel is
+# flagged when one of its ~37 candidates has |q - 9| < 1e-4 (or alpha, the
+# clamp or the stop test within their margins): q is spread over [0, 9] at
+# about pi * 1.3 = 4.1 candidates per unit of q for a 1.3 px^2 footprint, so
+# the q band alone flags ~2 * 1e-4 * 4.1 = 8e-4 of the pixels (measured
+# 0.03-0.17 % on the test scenes, 0.091 % on the 640x480 room frame).
+MAX_FLAG_FRAC = 2e-3
+
+
+def assert_forward_parity(out, orc_jobs, tol=1e-5, max_flag_frac=MAX_FLAG_FRAC):
     """Values within tol (per channel, relative to the channel max) on pixels
     the oracle does not flag as threshold-ambiguous; counts bit-exact there."""
     for j, o in enumerate(orc_jobs):
         ok = ~o["flags"]
+        print(f"job {j}: {int(o['flags'].sum())} flagged pixels ({o['flags'].mean():.3%})", flush=True)
         assert o["flags"].mean() <= max_flag_frac, o["flags"].mean()
         g_rgb = out["rgb"][j].cpu().numpy()
         for c in range(3):
@@ -71,31 +81,24 @@ def assert_forward_parity(out, orc_jobs, tol=1e-5, max_flag_frac=2e-3):
             assert (cnt[ok] == o["n"][ok]).all(), ("count", j, int((cnt[ok] != o["n"][ok]).sum()))
 
 
-def flagged_gaussians(orc_job):
-    """Gaussians (as (kf, pixel) pairs) with a candidate pair at a flagged pixel."""
-    g = orc_job["g"]
-    W = orc_job["W"]
-    gi, px, py = splat.candidate_pairs(g, W, orc_job["H"])
-    bad = orc_job["flags"].ravel()[py * W + px]
-    sel = np.unique(gi[bad])
-    N = orc_job["g"]["parts"][0]["N"]
-    return set(zip((g["gid"][sel] // N).tolist(), (g["gid"][sel] % N).tolist()))
+def zero_flagged(planes, orc_jobs):
+    """Upstream gradients with the oracle's flagged pixels set to zero, per
+    job (planes [n_jobs][..., H, W]).  Every pair's adjoint term is linear in
+    its pixel's upstream gradient, so a pixel whose contributor set FP32 and
+    FP64 may decide differently then adds nothing on either side, and every
+    Gaussian's gradient can be compared."""
+    out = np.array(planes, np.float64, copy=True)
+    for j, o in enumerate(orc_jobs):
+        out[j][..., o["flags"]] = 0.0
+    return out
 
 
 def assert_grad_parity(gpu_grads, gpu_pose, orc_b, orc_jobs, learnable, rtol=1e-3, atol_rel=1e-5):
-    """|g - o| <= rtol |o| + atol_rel * A elementwise, A the oracle's sum of
-    absolute terms; Gaussians next to flagged pixels are excluded."""
-    bad = set()
-    for o in orc_jobs:
-        bad |= flagged_gaussians(o)
+    """|g - o| <= rtol |o| + atol_rel * A elementwise for every Gaussian, A the
+    oracle's sum of absolute terms (upstream gradients zero on flagged
+    pixels, see zero_flagged)."""
     for f, gg in enumerate(gpu_grads):
         ob = orc_b["kf"][f]
-        H, W = ob["d_offset"].shape
-        mask = np.ones(H * W, bool)
-        for (kf, pix) in bad:
-            if kf == f:
-                mask[pix] = False
-        mask = mask.reshape(H, W)
         for name, gk, ak in (("offset", "d_offset", "a_offset"), ("radius", "d_radius", "a_radius"),
                              ("opacity", "d_opacity", "a_opacity")):
             g = gg[gk].cpu().numpy().astype(np.float64)
@@ -105,11 +108,11 @@ def assert_grad_parity(gpu_grads, gpu_pose, orc_b, orc_jobs, learnable, rtol=1e-
                 assert np.abs(g).max() == 0.0
                 continue
             err = np.abs(g - o) - (rtol * np.abs(o) + atol_rel * a)
-            assert (err[mask] <= 0).all(), (name, f, float(err[mask].max()), int((err[mask] > 0).sum()))
+            assert (err <= 0).all(), (name, f, float(err.max()), int((err > 0).sum()))
         g = gg["d_rgb"].cpu().numpy().astype(np.float64)
         if f in learnable:
             err = np.abs(g - ob["d_rgb"]) - (rtol * np.abs(ob["d_rgb"]) + atol_rel * ob["a_rgb"])
-            assert (err[:, mask] <= 0).all(), ("rgb", f, float(err[:, mask].max()))
+            assert (err <= 0).all(), ("rgb", f, float(err.max()))
     p = gpu_pose.cpu().numpy().astype(np.float64)
     err = np.abs(p - orc_b["d_pose"]) - (rtol * np.abs(orc_b["d_pose"]) + atol_rel * orc_b["a_pose"])
     assert (err <= 0).all(), ("pose", p, orc_b["d_pose"], orc_b["a_pose"])

@@ -27,7 +27,7 @@ def _upstream(seed, nj, Hh, W):
             rng.normal(size=(nj, Hh, W)) / (Hh * W))
 
 
-def _run_case(ctx, sc, jobs, tile, learnable, seed=0, check_grads=True, max_flag_frac=2e-3):
+def _run_case(ctx, sc, jobs, tile, learnable, seed=0, check_grads=True, max_flag_frac=H.MAX_FLAG_FRAC):
     import torch
     print(f"case tile={tile} jobs={jobs} size={sc['views'][0]['cam']['W']}x{sc['views'][0]['cam']['H']}",
           flush=True)
@@ -39,7 +39,7 @@ def _run_case(ctx, sc, jobs, tile, learnable, seed=0, check_grads=True, max_flag
     H.assert_forward_parity(out, orc, max_flag_frac=max_flag_frac)
     if check_grads:
         Hh, W = sc["views"][0]["cam"]["H"], sc["views"][0]["cam"]["W"]
-        gr, gd, ga = _upstream(seed, len(jobs), Hh, W)
+        gr, gd, ga = (H.zero_flagged(u, orc) for u in _upstream(seed, len(jobs), Hh, W))
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(ctx.device)
         grads, d_pose = H.gpu_backward(ctx, saved, kfs_d, t(gr), t(gd), t(ga), len(jobs), learnable)
         torch.cuda.synchronize()

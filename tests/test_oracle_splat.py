@@ -350,3 +350,28 @@ def test_paper_constants_fixture():
     assert n_attr == c["attributes_per_gaussian"]["value"]
     W, H = c["learnable_gaussians_one_frame"]["frame"]
     assert W * H == c["learnable_gaussians_one_frame"]["value"]
+
+
+def test_window_render_equals_full_render_inside_the_window():
+    """render_window: pixel outputs inside the window and the gradients of the
+    Gaussians it marks complete equal the whole-frame oracle's."""
+    sc = synth.small_scene(13, 45, 29, n_kf=2, n_views=1, offset_amp=0.03, max_trans=0.05, max_rot=3)
+    view = sc["views"][0]
+    full = splat.render_job(sc["kfs"], view, [0, 1])
+    win = (9, 4, 33, 22)
+    wr = splat.render_window(sc["kfs"], view, [0, 1], win)
+    sl = (slice(win[1], win[3]), slice(win[0], win[2]))
+    for k in ("depth", "alpha", "n"):
+        np.testing.assert_array_equal(wr[k][sl], full[k][sl])
+    np.testing.assert_array_equal(wr["rgb"][:, sl[0], sl[1]], full["rgb"][:, sl[0], sl[1]])
+    np.testing.assert_array_equal(wr["flags"][sl], full["flags"][sl])
+    rng = np.random.default_rng(3)
+    gr, gd, ga = rng.normal(size=(3, 29, 45)), rng.normal(size=(29, 45)), rng.normal(size=(29, 45))
+    bf = splat.backward_job(sc["kfs"], view, full, gr, gd, ga)
+    bw = splat.backward_job(sc["kfs"], view, wr, gr, gd, ga)
+    comp = wr["complete"]
+    assert comp.sum() > 50
+    pos = {int(x): i for i, x in enumerate(full["g"]["gid"])}
+    at = np.array([pos[int(x)] for x in wr["g"]["gid"][comp]])
+    for k in ("d_rgb", "d_opacity", "d_radius", "d_offset", "a_offset"):
+        np.testing.assert_allclose(bw[k][comp], bf[k][at], rtol=1e-12, atol=1e-15)

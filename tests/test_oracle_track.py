@@ -144,3 +144,15 @@ def test_adam_first_step_is_sign_step_and_scale_invariant():
     _, m5, v5 = optim.adam_step(p, 5.0 * g, z, z, 1, 0.01)
     b, _, _ = optim.adam_step(p1, 5.0 * g2, m5, v5, 2, 0.01)
     np.testing.assert_allclose(a, b, atol=1e-8)
+
+
+def test_linearise_tolerance_terms_bound_the_values(small_track):
+    """The absolute-term sums dominate the values they bound (triangle
+    inequality), and the per-pixel pieces reassemble H and g."""
+    sc = small_track
+    lin = track.linearise(sc["geo"], sc["cam"], sc["init"]["R"].astype(np.float64),
+                          sc["init"]["t"].astype(np.float64), np.asarray(sc["obs_depth"], np.float64))
+    assert (lin["aH"] >= np.abs(lin["H"])).all() and (lin["ag"] >= np.abs(lin["g"])).all()
+    assert lin["aloglik"] >= abs(lin["loglik"])
+    np.testing.assert_allclose(lin["J"].T @ lin["J"], lin["H"], rtol=1e-12)
+    assert (lin["fH"] >= 0).all() and lin["floglik"] >= 0
