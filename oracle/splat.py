@@ -246,6 +246,12 @@ def composite(g, P, n_pix, flags=None):
     cnt = np.zeros(n_pix, np.int64)
     Tb = np.zeros(n)
     con = np.zeros(n, bool)
+    # conditioning of the transmittance product: a relative perturbation e of
+    # alpha_i moves T after it by e * alpha_i / (1 - alpha_i) relatively, so
+    # kappa sums that factor over the contributors composited so far (Kb:
+    # before each pair, K: the pixel's total)
+    K = np.zeros(n_pix)
+    Kb = np.zeros(n)
     kmax = int(counts.max()) if n else 0
     for k in range(kmax):
         p = np.nonzero((counts > k) & ~done)[0]
@@ -260,14 +266,16 @@ def composite(g, P, n_pix, flags=None):
         done[p[stop]] = True
         p, idx, a, test = p[~stop], idx[~stop], a[~stop], test[~stop]
         Tb[idx] = T[p]
+        Kb[idx] = K[p]
         con[idx] = True
         w = a * T[p]
         gi = P["gi"][idx]
         col[p] += w[:, None] * g["col"][gi]
         dep[p] += w * g["z"][gi]
         T[p] = test
+        K[p] += a / (1.0 - a)
         cnt[p] += 1
-    return dict(col=col, depth=dep, alpha=1.0 - T, T=T, n=cnt, Tb=Tb, con=con)
+    return dict(col=col, depth=dep, alpha=1.0 - T, T=T, n=cnt, Tb=Tb, con=con, Kb=Kb, K=K)
 
 
 def render_job(kfs, view, kf_ids, channels="rgb"):
@@ -427,15 +435,26 @@ def pair_grads(g, P, comp, g_col, g_dep, g_alp):
         g_o=g_o, g_col=gc * w[:, None], g_z=gd * w, galpha=galpha,
     )
     # the same terms with every product expanded to absolute values: bounds
-    # the rounding error of any evaluation order (tolerances, not the value)
-    aal = (np.abs(gc) * (np.abs(col) * Ti[:, None] + np.abs(S[:, :C]) * inv[:, None])).sum(1) \
-        + np.abs(gd) * (np.abs(z) * Ti + np.abs(S[:, C]) * inv) + np.abs(ga) * Tf * inv
+    # the rounding error of any evaluation order (tolerances, not the value).
+    # Each term is also scaled by its conditioning: a term carrying T before
+    # pair k by 1 + kappa_k (the prefix conditioning of the transmittance
+    # product, see composite), so the suffix sums take every later
+    # contributor with its own factor; a term divided by 1 - alpha_j by
+    # 1 + alpha_j / (1 - alpha_j); the final T by the pixel's total 1 + kappa.
+    kb = 1.0 + comp["Kb"]
+    ka = 1.0 + a / (1.0 - a)
+    kt = 1.0 + comp["K"][pix]
+    avals = np.concatenate([np.abs(w * kb)[:, None] * np.abs(col), np.abs(w * kb * z)[:, None]], 1)
+    aS = _suffix_sums(P, comp, avals, n_pix)
+    aal = (np.abs(gc) * (np.abs(col) * (Ti * kb)[:, None] + aS[:, :C] * (inv * ka)[:, None])).sum(1) \
+        + np.abs(gd) * (np.abs(z) * Ti * kb + aS[:, C] * inv * ka) + np.abs(ga) * Tf * inv * ka * kt
     aq = np.where(unclamped, 0.5 * a * aal, 0.0)
     out.update(
         a_mx=aq * 2.0 * (np.abs(A * dx) + np.abs(B * dy)),
         a_my=aq * 2.0 * (np.abs(B * dx) + np.abs(Cc * dy)),
         a_a=aq * dx * dx, a_b=aq * 2.0 * np.abs(dx * dy), a_c=aq * dy * dy,
-        a_o=np.where(unclamped, aal * P["G"], 0.0), a_col=np.abs(gc) * w[:, None], a_z=np.abs(gd) * w,
+        a_o=np.where(unclamped, aal * P["G"], 0.0), a_col=np.abs(gc) * (w * kb)[:, None],
+        a_z=np.abs(gd) * w * kb,
     )
     for k in list(out):
         v = out[k]
