@@ -366,6 +366,19 @@ sgad_status sgad_conv3x3_dgrad(sgad_ctx* ctx, int H, int W, int cin, int cout, c
  * wgrad calls of one context that overlap on different streams race on it. */
 sgad_status sgad_conv3x3_wgrad(sgad_ctx* ctx, int H, int W, int cin, int cout, const uint16_t* x,
                                const uint16_t* dy, float* dw, float* db, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * weight and bias gradients as sgad_conv3x3_wgrad (ACCUMULATED into dw, db),
+ * with the partial-sum rows taken from a static device array of the library
+ * (512 rows x (9 * 32 * 32 + 32) floats = 18.9 MB per device, resident on
+ * every device the library runs on until the process ends) instead of the
+ * context's growable workspace.  Allocates nothing and issues no memset: each
+ * workgroup writes its whole row before the rows are summed.  SGAD_ERANGE if
+ * the layer's rows would not fit (not reachable for the supported layers),
+ * SGAD_EINVAL as sgad_conv3x3_wgrad.  All calls on one device share the
+ * array: calls that overlap on one device (any context, any stream) race. */
+sgad_status sgad_conv3x3_wgrad_noalloc(sgad_ctx* ctx, int H, int W, int cin, int cout, const uint16_t* x,
+                                       const uint16_t* dy, float* dw, float* db, void* stream);
 /* Network input (R, G, B, h) as bf16 [H][W][4] from planar rgb [3][H][W] and depth [H][W]:
  * h = (D - mean of D over the 3x3 neighbourhood inside the image) / 0.02 m. */
 sgad_status sgad_net_input(sgad_ctx* ctx, int H, int W, const float* rgb, const float* depth, uint16_t* x0,

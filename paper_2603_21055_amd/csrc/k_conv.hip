@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "sgad_internal.h"
 
@@ -388,6 +389,37 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(int H, int W, const __bf16* __
 
 constexpr int kWgradBlocks = 512;  // persistent weight-gradient workgroups (two per CU)
 constexpr int kWgradSplit = 16;    // row groups of the partial-sum reduction
+
+// Partial-sum rows of the weight gradient for callers that cannot allocate
+// (sgad_conv3x3_wgrad_noalloc): one row per persistent workgroup, each row
+// wide enough for the largest supported layer (9 * 32 * 32 weights + 32
+// biases): 512 x 9248 floats = 18.9 MB, held on every device the library
+// runs on until the process ends.  Host code never passes this name to a
+// kernel: it stands for a host-side shadow there; conv_scratch_setup gives
+// each device's own address.
+constexpr size_t kWgradScratchFloats = (size_t)kWgradBlocks * (9 * 32 * 32 + 32);
+static __device__ __align__(256) float scratch[kWgradScratchFloats];
+constexpr int kScratchDevices = 64;
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (the caller makes `device` current first).
+hipError_t conv_scratch_setup(int device, float** out) {
+    static std::mutex mu;
+    static float* addr[kScratchDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        float* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+size_t conv_scratch_bytes() { return sizeof(float) * kWgradScratchFloats; }
 
 // dw[j] (j < ndw) or db[j - ndw] += sum of column j over the nrow rows of
 // part ([nrow][S]); blockIdx.y takes rows y, y + kWgradSplit, ...

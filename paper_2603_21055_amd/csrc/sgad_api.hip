@@ -32,6 +32,8 @@ void launch_adam(AdamGroups& A, float b1, float b2, float eps, float c1, float c
 bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* bias,
                      const void* mask, void* y, hipStream_t s);
 size_t conv_wgrad_part_bytes(int H, int W, int cin, int cout);
+hipError_t conv_scratch_setup(int device, float** out);
+size_t conv_scratch_bytes();
 bool launch_conv_wgrad(int H, int W, int cin, int cout, const void* x, const void* dy, float* part, float* dw, float* db,
                        hipStream_t s);
 void launch_conv_weights(int cin, int cout, const float* w, void* wb, void* wt, hipStream_t s);
@@ -143,6 +145,7 @@ struct sgad_ctx {
     } capture;
     DevBuf scratch;  // small per-context scratch (loss counters)
     DevBuf conv_part;  // conv weight-gradient partial sums (one row per workgroup)
+    float* conv_scratch = nullptr;  // this device's static partial-sum rows (sgad_conv3x3_wgrad_noalloc)
     struct Track {
         bool sized = false;
         Geometry G{};
@@ -513,8 +516,11 @@ sgad_status sgad_create(int device, sgad_ctx** out) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SGAD_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return SGAD_EHIP;
+    float* scratch = nullptr;
+    if (conv_scratch_setup(device, &scratch) != hipSuccess) return SGAD_EHIP;
     sgad_ctx* c = new sgad_ctx();
     c->device = device;
+    c->conv_scratch = scratch;
     *out = c;
     return SGAD_OK;
 }
@@ -1531,6 +1537,28 @@ sgad_status sgad_conv3x3_wgrad(sgad_ctx* c, int H, int W, int cin, int cout, con
         return fail(c, SGAD_EINVAL, "unsupported (cin, cout)");
     HIPCHK(c, ensure_c(c, c->conv_part, conv_wgrad_part_bytes(H, W, cin, cout), s));
     launch_conv_wgrad(H, W, cin, cout, x, dy, (float*)c->conv_part.p, dw, db, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_conv3x3_wgrad_noalloc(sgad_ctx* c, int H, int W, int cin, int cout, const uint16_t* x,
+                                       const uint16_t* dy, float* dw, float* db, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!conv_dims_ok(H, W) || !x || !dy || !dw || !db) return fail(c, SGAD_EINVAL, "bad wgrad arguments");
+    if (!conv_aligned(x) || !conv_aligned(dy)) return fail(c, SGAD_EINVAL, "conv pointers must be 16-byte aligned");
+    if (!((cin == 4 && cout == 32) || (cin == 32 && cout == 32) || (cin == 32 && cout == 1)))
+        return fail(c, SGAD_EINVAL, "unsupported (cin, cout)");
+    const size_t need = conv_wgrad_part_bytes(H, W, cin, cout);
+    if (need > conv_scratch_bytes()) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "wgrad needs %zu bytes of partial sums, the static scratch holds %zu", need,
+                      conv_scratch_bytes());
+        return fail(c, SGAD_ERANGE, msg);
+    }
+    if (!c->conv_scratch) return fail(c, SGAD_EHIP, "static scratch address not set up");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick_stream(c, stream);
+    launch_conv_wgrad(H, W, cin, cout, x, dy, c->conv_scratch, dw, db, s);
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
 }

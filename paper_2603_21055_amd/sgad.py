@@ -89,6 +89,7 @@ _SIGS = {
     "sgad_conv3x3_fwd": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, _P]),
     "sgad_conv3x3_dgrad": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, _P]),
     "sgad_conv3x3_wgrad": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, _P]),
+    "sgad_conv3x3_wgrad_noalloc": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, _P]),
     "sgad_net_input": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
     "sgad_offset_l1": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
     "sgad_autotune": (C.c_int, [_P, C.c_int, C.POINTER(Keyframe), C.c_int, C.POINTER(Cam), C.POINTER(Pose),
@@ -386,6 +387,10 @@ class Context:
     def conv_wgrad(self, H, W, cin, cout, x, dy, dw, db, stream=None):
         self._check(self.lib.sgad_conv3x3_wgrad(self.h, H, W, cin, cout, _ptr(x), _ptr(dy), _ptr(dw), _ptr(db),
                                                 _stream(stream)))
+
+    def conv_wgrad_noalloc(self, H, W, cin, cout, x, dy, dw, db, stream=None):
+        self._check(self.lib.sgad_conv3x3_wgrad_noalloc(self.h, H, W, cin, cout, _ptr(x), _ptr(dy), _ptr(dw),
+                                                        _ptr(db), _stream(stream)))
 
     def net_input(self, H, W, rgb, depth, x0, stream=None):
         self._check(self.lib.sgad_net_input(self.h, H, W, _ptr(rgb), _ptr(depth), _ptr(x0), _stream(stream)))
