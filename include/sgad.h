@@ -295,6 +295,27 @@ sgad_status sgad_l1_loss(sgad_ctx* ctx, int n_jobs, int H, int W,
                          float w_rgb, float w_depth, float* g_rgb, float* g_depth, double* loss,
                          void* stream);
 
+/*
+ * The whole of Eq. 1 for n_jobs rendered views:
+ *   L_j = w_rgb * mean|rgb - t_rgb| + w_ssim * L_S + w_depth * sum_U |depth - t_depth| / |U|,
+ * the L1 terms as in sgad_l1_loss, and L_S = 1 - mean over the three colour
+ * channels and all pixels of SSIM(t_rgb, rgb) with the SSIM reference's
+ * statistics (11 x 11 Gaussian window of standard deviation 1.5, normalised,
+ * 'same' correlation with zero padding; C1 = 0.01^2, C2 = 0.03^2).  The
+ * supplement's weights are (w_rgb, w_ssim, w_depth) = (0.8, 0.2, 1.0).
+ * Same layouts as sgad_l1_loss; g_rgb, g_depth and loss are WRITTEN.  The
+ * SSIM statistics are evaluated in FP64.  Uses a context workspace of
+ * about 36 bytes per pixel and job when w_ssim != 0 (the three derivative
+ * maps per channel and one partial sum per 16 x 16 tile; grown by the first
+ * call that needs more; SGAD_EHIP if that happens while calls are captured).
+ * SGAD_EINVAL on null pointers, sizes < 1 or non-finite weights;
+ * SGAD_ERANGE above 21845 jobs.
+ */
+sgad_status sgad_eq1_loss(sgad_ctx* ctx, int n_jobs, int H, int W,
+                          const float* rgb, const float* depth, const float* t_rgb, const float* t_depth,
+                          float w_rgb, float w_ssim, float w_depth, float* g_rgb, float* g_depth, double* loss,
+                          void* stream);
+
 /* One parameter tensor for sgad_adam_step (all device pointers, n floats;
  * the pointers may be null when n is 0).  Arrays that start on a 16-byte
  * boundary are read and written four floats at a time. */

@@ -86,7 +86,7 @@ def ssim_map(x, y):
     return ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
 
 
-def ssim_loss(rgb, t_rgb):
+def ssim_loss(rgb, t_rgb, with_abs=False):
     """L_S = 1 - mean SSIM over the channels of the rendered colour ``rgb``
     [C, H, W] against the observed ``t_rgb``, and dL_S / d rgb.
 
@@ -99,13 +99,16 @@ def ssim_loss(rgb, t_rgb):
     and the adjoint of the correlation is the correlation with the flipped
     (here identical) window, so
       dL/dy = -(1 / n) [G*(dS/dmu_y) + 2 y G*(dS/de_yy) + x G*(dS/de_xy)]
-    with n = C H W."""
+    with n = C H W.  with_abs: also the same sum with every term replaced by
+    its absolute value (a bound on the magnitudes an evaluation combines, for
+    tolerances)."""
     rgb = np.asarray(rgb, np.float64)
     t_rgb = np.asarray(t_rgb, np.float64)
     C, H, W = rgb.shape
     n = C * H * W
     total = 0.0
     grad = np.zeros_like(rgb)
+    gabs = np.zeros_like(rgb)
     for c in range(C):
         x, y = t_rgb[c], rgb[c]
         mx, my = ssim_filter(x), ssim_filter(y)
@@ -122,6 +125,11 @@ def ssim_loss(rgb, t_rgb):
         d_eyy = -S / B2
         d_exy = 2 * S / A2
         grad[c] = -(ssim_filter(d_my) + 2 * y * ssim_filter(d_eyy) + x * ssim_filter(d_exy)) / n
+        if with_abs:
+            gabs[c] = (ssim_filter(np.abs(d_my)) + 2 * np.abs(y) * ssim_filter(np.abs(d_eyy))
+                       + np.abs(x) * ssim_filter(np.abs(d_exy))) / n
+    if with_abs:
+        return 1.0 - total / n, grad, gabs
     return 1.0 - total / n, grad
 
 

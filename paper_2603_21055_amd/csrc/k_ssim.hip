@@ -1,0 +1,204 @@
+// Structural-similarity term of the mapping loss (Eq. 1, weight tau): with x
+// the observed colour plane and y the rendered one,
+//   L_S = 1 - (1 / (3 P)) sum over channels and pixels of SSIM(x, y),
+//   SSIM = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_xx + s_yy + C2)),
+// with the SSIM reference's local statistics: an 11 x 11 Gaussian window of
+// standard deviation 1.5 (normalised to sum 1) applied as a 'same'
+// correlation with zero padding, C1 = 0.01^2, C2 = 0.03^2 (dynamic range 1).
+//
+// Two launches per call, both over (16 x 16 tile, plane) with a 26 x 26 patch
+// (tile plus a 5-pixel halo) in LDS and the window applied as a row pass then
+// a column pass:
+//   k_ssim_maps: the five filtered moments, SSIM and the three partials
+//     dS/dmu_y, dS/de_yy, dS/de_xy per pixel (written), the SSIM sum;
+//   k_ssim_grad: the adjoint of the correlation (the same symmetric window)
+//     applied to the three maps, giving
+//     dL_S/dy = -(1 / (3 P)) [G*(dS/dmu_y) + 2 y G*(dS/de_yy) + x G*(dS/de_xy)],
+//     added to the colour gradient with weight tau.
+// The moments and everything formed from them are FP64: s_xx = G*x^2 - mu_x^2
+// cancels down to ~C2 = 9e-4 on smooth patches, where FP32 moments of unit-
+// range colours would leave errors of ~1e-4 relative.  The maps are stored as
+// FP32.
+#include <hip/hip_runtime.h>
+
+#include "sgad_internal.h"
+
+namespace sgad {
+
+constexpr int kSsimR = 5;                    // window radius
+constexpr int kSsimT = 16;                   // output tile side, one pixel per thread
+constexpr int kSsimE = kSsimT + 2 * kSsimR;  // patch side (tile + halo)
+constexpr double kSsimC1 = 0.01 * 0.01;
+constexpr double kSsimC2 = 0.03 * 0.03;
+
+// Normalised window taps g[k] = exp(-(k - 5)^2 / (2 * 1.5^2)) / sum_j exp(-(j - 5)^2 / 4.5),
+// k = 0..10, written out to 17 digits.
+__constant__ double c_ssim_g[2 * kSsimR + 1] = {
+    0.0010283800844791101, 0.007598758135239185, 0.036000772128430829, 0.10936068950970002,
+    0.21300553771125369,   0.26601172486179436,  0.21300553771125369,  0.10936068950970002,
+    0.036000772128430829,  0.007598758135239185, 0.0010283800844791101};
+
+// Patch of `n` planes at (blockIdx.x, blockIdx.y), zero outside the image.
+template <int NPL>
+__device__ __forceinline__ void ssim_load(int H, int W, const float* const* src, float (*dst)[kSsimE][kSsimE + 1]) {
+    const int ox = (int)blockIdx.x * kSsimT - kSsimR, oy = (int)blockIdx.y * kSsimT - kSsimR;
+    for (int i = threadIdx.x; i < kSsimE * kSsimE; i += 256) {
+        const int r = i / kSsimE, c = i - r * kSsimE;
+        const int gx = ox + c, gy = oy + r;
+        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const size_t o = (size_t)gy * W + gx;
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) dst[p][r][c] = in ? src[p][o] : 0.f;
+    }
+}
+
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// grid (tiles x, tiles y, n_jobs * 3): plane z is colour channel z % 3 of job
+// z / 3.  dmap [n_jobs * 3][3][H][W]; part[z][tile] = the tile's SSIM sum
+// (written; k_ssim_grad adds them to the loss in a fixed order).
+__global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __restrict__ rgb,
+                                                   const float* __restrict__ t_rgb, float* __restrict__ dmap,
+                                                   double* __restrict__ part) {
+    __shared__ float s_in[2][kSsimE][kSsimE + 1];    // observed x, rendered y
+    __shared__ double s_h[5][kSsimE][kSsimT];        // row-filtered x, y, x^2, y^2, xy
+    __shared__ double s_red[4];
+    const int plane = blockIdx.z;
+    const size_t P = (size_t)H * W;
+    const float* src[2] = {t_rgb + (size_t)plane * P, rgb + (size_t)plane * P};
+    const double* s_g = c_ssim_g;
+    ssim_load<2>(H, W, src, s_in);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSsimE * kSsimT; i += 256) {
+        const int r = i / kSsimT, c = i - r * kSsimT;
+        double a = 0.0, b = 0.0, xx = 0.0, yy = 0.0, xy = 0.0;
+#pragma unroll
+        for (int k = 0; k <= 2 * kSsimR; ++k) {
+            const double g = s_g[k];
+            const double x = (double)s_in[0][r][c + k], y = (double)s_in[1][r][c + k];
+            a += g * x;
+            b += g * y;
+            xx += g * (x * x);
+            yy += g * (y * y);
+            xy += g * (x * y);
+        }
+        s_h[0][r][c] = a;
+        s_h[1][r][c] = b;
+        s_h[2][r][c] = xx;
+        s_h[3][r][c] = yy;
+        s_h[4][r][c] = xy;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & (kSsimT - 1), ty = threadIdx.x >> 4;
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k <= 2 * kSsimR; ++k) {
+        const double g = s_g[k];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) m[q] += g * s_h[q][ty + k][tx];
+    }
+    const int px = (int)blockIdx.x * kSsimT + tx, py = (int)blockIdx.y * kSsimT + ty;
+    double S = 0.0;
+    if (px < W && py < H) {
+        const double mx = m[0], my = m[1];
+        const double sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+        const double A1 = 2.0 * mx * my + kSsimC1, A2 = 2.0 * sxy + kSsimC2;
+        const double B1 = mx * mx + my * my + kSsimC1, B2 = sxx + syy + kSsimC2;
+        S = (A1 * A2) / (B1 * B2);
+        const double d_my = S * (2.0 * mx / A1 - 2.0 * mx / A2 - 2.0 * my / B1 + 2.0 * my / B2);
+        const double d_eyy = -S / B2;
+        const double d_exy = 2.0 * S / A2;
+        const size_t o = (size_t)py * W + px;
+        float* dm = dmap + (size_t)plane * 3 * P;
+        dm[o] = (float)d_my;
+        dm[P + o] = (float)d_eyy;
+        dm[2 * P + o] = (float)d_exy;
+    }
+    const double sum = block_sum_d(S, s_red);
+    if (threadIdx.x == 0) part[(size_t)plane * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = sum;
+}
+
+// Same grid: g_rgb[plane] += -tau / (3 P) [G*d_my + 2 y G*d_eyy + x G*d_exy].
+// The first tile of each job's first plane also adds tau (1 - (sum of the
+// job's 3 x tiles partial SSIM sums, in index order) / (3 P)) to loss[job].
+__global__ __launch_bounds__(256) void k_ssim_grad(int H, int W, const float* __restrict__ rgb,
+                                                   const float* __restrict__ t_rgb, const float* __restrict__ dmap,
+                                                   const double* __restrict__ part, double tau,
+                                                   float* __restrict__ g_rgb, double* loss) {
+    __shared__ float s_in[3][kSsimE][kSsimE + 1];
+    __shared__ double s_h[3][kSsimE][kSsimT];
+    __shared__ double s_red[4];
+    const int plane = blockIdx.z;
+    const size_t P = (size_t)H * W;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && plane % 3 == 0) {
+        const int nt = (int)(gridDim.x * gridDim.y) * 3;
+        const double* pp = part + (size_t)plane * gridDim.x * gridDim.y;
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < nt; i += 256) acc += pp[i];
+        const double sum = block_sum_d(acc, s_red);
+        if (threadIdx.x == 0) loss[plane / 3] += tau * (1.0 - sum / (3.0 * (double)P));
+    }
+    const float* dm = dmap + (size_t)plane * 3 * P;
+    const float* src[3] = {dm, dm + P, dm + 2 * P};
+    const double* s_g = c_ssim_g;
+    ssim_load<3>(H, W, src, s_in);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSsimE * kSsimT; i += 256) {
+        const int r = i / kSsimT, c = i - r * kSsimT;
+        double a = 0.0, b = 0.0, d = 0.0;
+#pragma unroll
+        for (int k = 0; k <= 2 * kSsimR; ++k) {
+            const double g = s_g[k];
+            a += g * (double)s_in[0][r][c + k];
+            b += g * (double)s_in[1][r][c + k];
+            d += g * (double)s_in[2][r][c + k];
+        }
+        s_h[0][r][c] = a;
+        s_h[1][r][c] = b;
+        s_h[2][r][c] = d;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & (kSsimT - 1), ty = threadIdx.x >> 4;
+    const int px = (int)blockIdx.x * kSsimT + tx, py = (int)blockIdx.y * kSsimT + ty;
+    if (px >= W || py >= H) return;
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+    for (int k = 0; k <= 2 * kSsimR; ++k) {
+        const double g = s_g[k];
+        f0 += g * s_h[0][ty + k][tx];
+        f1 += g * s_h[1][ty + k][tx];
+        f2 += g * s_h[2][ty + k][tx];
+    }
+    const size_t o = (size_t)plane * P + (size_t)py * W + px;
+    const double x = (double)t_rgb[o], y = (double)rgb[o];
+    const double gr = -tau / (3.0 * (double)P) * (f0 + 2.0 * y * f1 + x * f2);
+    g_rgb[o] = (float)((double)g_rgb[o] + gr);
+}
+
+static size_t ssim_tiles(int H, int W) {
+    return (size_t)((W + kSsimT - 1) / kSsimT) * (size_t)((H + kSsimT - 1) / kSsimT);
+}
+
+// Workspace of one call: the maps, then one FP64 partial sum per (plane, tile).
+size_t ssim_map_bytes(int n_jobs, int H, int W) {
+    const size_t maps = (size_t)n_jobs * 9 * (size_t)H * W * sizeof(float);
+    return ((maps + 255) & ~(size_t)255) + (size_t)n_jobs * 3 * ssim_tiles(H, W) * sizeof(double);
+}
+
+void launch_ssim(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
+                 float* g_rgb, double* loss, hipStream_t s) {
+    const dim3 grid((W + kSsimT - 1) / kSsimT, (H + kSsimT - 1) / kSsimT, 3 * n_jobs), blk(256);
+    float* dmap = (float*)ws;
+    const size_t maps = (size_t)n_jobs * 9 * (size_t)H * W * sizeof(float);
+    double* part = (double*)((char*)ws + ((maps + 255) & ~(size_t)255));
+    hipLaunchKernelGGL(k_ssim_maps, grid, blk, 0, s, H, W, rgb, t_rgb, dmap, part);
+    hipLaunchKernelGGL(k_ssim_grad, grid, blk, 0, s, H, W, rgb, t_rgb, dmap, part, (double)w_ssim, g_rgb, loss);
+}
+
+}  // namespace sgad

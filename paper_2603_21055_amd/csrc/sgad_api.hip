@@ -27,6 +27,9 @@ void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const floa
                float w_rgb, float w_dep, uint32_t* count, float* g_rgb, float* g_dep, double* loss,
                hipStream_t s);
 int l1_blocks(int P);
+size_t ssim_map_bytes(int n_jobs, int H, int W);
+void launch_ssim(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
+                 float* g_rgb, double* loss, hipStream_t s);
 void launch_adam(AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
                  float* cdev, hipStream_t s);
 bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* bias,
@@ -145,6 +148,7 @@ struct sgad_ctx {
     } capture;
     DevBuf scratch;  // small per-context scratch (loss counters)
     DevBuf conv_part;  // conv weight-gradient partial sums (one row per workgroup)
+    DevBuf ssim_maps;  // SSIM partial-derivative maps of the loss call ([n_jobs * 3][3][H][W] floats)
     float* conv_scratch = nullptr;  // this device's static partial-sum rows (sgad_conv3x3_wgrad_noalloc)
     struct Track {
         bool sized = false;
@@ -540,6 +544,7 @@ void sgad_destroy(sgad_ctx* c) {
     for (sgad_saved* s : c->slots) free_slot(s);
     if (c->scratch.p) (void)hipFree(c->scratch.p);
     if (c->conv_part.p) (void)hipFree(c->conv_part.p);
+    if (c->ssim_maps.p) (void)hipFree(c->ssim_maps.p);
     {
         auto& T = c->track;
         for (DevBuf* b : {&T.params, &T.pre, &T.tiles, &T.keys, &T.part, &T.status, &T.trace})
@@ -996,6 +1001,34 @@ sgad_status sgad_l1_loss(sgad_ctx* c, int n_jobs, int H, int W, const float* rgb
     uint32_t* cnt = (uint32_t*)c->scratch.p;
     TimeScope ts(c, "l1_loss", s);
     launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, g_rgb, g_depth, loss, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_eq1_loss(sgad_ctx* c, int n_jobs, int H, int W, const float* rgb, const float* depth,
+                          const float* t_rgb, const float* t_depth, float w_rgb, float w_ssim, float w_depth,
+                          float* g_rgb, float* g_depth, double* loss, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (n_jobs < 1 || H < 1 || W < 1) return fail(c, SGAD_EINVAL, "bad sizes");
+    if (n_jobs > 65535 / 3) return fail(c, SGAD_ERANGE, "at most 21845 jobs");
+    if (!rgb || !depth || !t_rgb || !t_depth || !g_rgb || !g_depth || !loss)
+        return fail(c, SGAD_EINVAL, "null pointer");
+    if (!std::isfinite(w_rgb) || !std::isfinite(w_ssim) || !std::isfinite(w_depth))
+        return fail(c, SGAD_EINVAL, "non-finite weight");
+    hipStream_t s = pick_stream(c, stream);
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((int64_t)H * W > INT32_MAX / 2) return fail(c, SGAD_ERANGE, "image too large");
+    HIPCHK(c, ensure_c(c, c->scratch, (size_t)n_jobs * l1_blocks(H * W) * 4, s));
+    if (w_ssim != 0.f) HIPCHK(c, ensure_c(c, c->ssim_maps, ssim_map_bytes(n_jobs, H, W), s));
+    uint32_t* cnt = (uint32_t*)c->scratch.p;
+    {
+        TimeScope ts(c, "l1_loss", s);
+        launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, g_rgb, g_depth, loss, s);
+    }
+    if (w_ssim != 0.f) {
+        TimeScope ts(c, "ssim_loss", s);
+        launch_ssim(n_jobs, H, W, rgb, t_rgb, w_ssim, c->ssim_maps.p, g_rgb, loss, s);
+    }
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
 }

@@ -1,9 +1,10 @@
 """Mapping driver: autograd wrapper and the per-iteration optimiser loop.
 
 ``SplatFn`` is a torch.autograd.Function around the library's forward and
-adjoint; ``Mapper`` runs the paper's mapping iteration (Sec. 3.2, Eq. 1 L1
-terms; supplement learning rates) entirely in library kernels: forward
-splat -> L1 loss and upstream grads -> adjoint -> multi-tensor Adam.
+adjoint; ``Mapper`` runs the paper's mapping iteration (Sec. 3.2, Eq. 1 with
+its L1 colour, SSIM and masked L1 depth terms; supplement weights and
+learning rates) entirely in library kernels: forward splat -> Eq. 1 loss and
+upstream grads -> adjoint -> multi-tensor Adam.
 """
 from __future__ import annotations
 
@@ -14,7 +15,7 @@ from . import sgad
 # supplement learning rates; radius steps as log r and opacity as logit o (the
 # spaces these rates belong to in 3DGS), colour and offset linearly
 LR = dict(rgb=0.0025, radius=0.005, opacity=0.05, offset=0.01)
-W_RGB, W_DEPTH = 0.8, 1.0                                         # Eq. 1 weights (supplement)
+W_RGB, W_SSIM, W_DEPTH = 0.8, 0.2, 1.0                           # Eq. 1 weights (supplement)
 R_MIN = 1e-6
 
 
@@ -82,8 +83,10 @@ class Mapper:
     views / jobs: as for sgad.Context.render_fwd; targets: per-job device
     tensors t_rgb [n_jobs, 3, H, W], t_depth [n_jobs, H, W]."""
 
-    def __init__(self, ctx, kfs, views, jobs, learnable, t_rgb, t_depth, with_count=False, lr=None):
+    def __init__(self, ctx, kfs, views, jobs, learnable, t_rgb, t_depth, with_count=False, lr=None,
+                 w_ssim=W_SSIM):
         import torch
+        self.w_ssim = float(w_ssim)
         self.ctx, self.kfs, self.views, self.jobs = ctx, kfs, views, jobs
         self.learn = list(learnable)
         self.t_rgb, self.t_depth = t_rgb, t_depth
@@ -119,8 +122,8 @@ class Mapper:
         """One mapping iteration; returns nothing (loss stays on the device)."""
         c = self.ctx
         saved = c.render_fwd(self.kfs, self.views, self.jobs, self.rgb, self.dep, self.alp, self.cnt)
-        c.l1_loss(self.rgb, self.dep, self.t_rgb, self.t_depth, self.g_rgb, self.g_dep, self.loss,
-                  W_RGB, W_DEPTH)
+        c.eq1_loss(self.rgb, self.dep, self.t_rgb, self.t_depth, self.g_rgb, self.g_dep, self.loss,
+                   W_RGB, self.w_ssim, W_DEPTH)
         c.render_bwd(saved, self.g_rgb, self.g_dep, None, self.grads, None, self.learn)
         c.release(saved)
         self.t += 1

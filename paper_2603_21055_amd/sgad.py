@@ -82,6 +82,8 @@ _SIGS = {
     "sgad_timing_only": (C.c_int, [_P, C.c_char_p]),
     "sgad_l1_loss": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, C.c_float, C.c_float, _P, _P,
                                _P, _P]),
+    "sgad_eq1_loss": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float,
+                                _P, _P, _P, _P]),
     "sgad_adam_step": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_int, C.c_float, C.c_float, C.c_float,
                                  C.c_int, _P]),
     "sgad_timing_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
@@ -337,6 +339,21 @@ class Context:
         st = self.lib.sgad_l1_loss(self.h, nj, Hh, W, _ptr(rgb), _ptr(depth), _ptr(t_rgb), _ptr(t_depth),
                                    float(w_rgb), float(w_depth), _ptr(g_rgb), _ptr(g_depth), _ptr(loss),
                                    _stream(stream))
+        self._check(st)
+
+    def eq1_loss(self, rgb, depth, t_rgb, t_depth, g_rgb, g_depth, loss, w_rgb=0.8, w_ssim=0.2, w_depth=1.0,
+                 stream=None):
+        """All of Eq. 1 (L1 colour, SSIM, masked L1 depth): writes g_rgb, g_depth
+        and loss [n_jobs] (float64)."""
+        import torch
+        for name, t in (("rgb", rgb), ("depth", depth), ("t_rgb", t_rgb), ("t_depth", t_depth),
+                        ("g_rgb", g_rgb), ("g_depth", g_depth)):
+            _check_tensor(t, name, self.device)
+        _check_tensor(loss, "loss", self.device, torch.float64)
+        nj, Hh, W = depth.shape
+        st = self.lib.sgad_eq1_loss(self.h, nj, Hh, W, _ptr(rgb), _ptr(depth), _ptr(t_rgb), _ptr(t_depth),
+                                    float(w_rgb), float(w_ssim), float(w_depth), _ptr(g_rgb), _ptr(g_depth),
+                                    _ptr(loss), _stream(stream))
         self._check(st)
 
     def adam_step(self, groups, step, beta1=0.9, beta2=0.999, eps=1e-8, zero_grad=True, stream=None):
