@@ -431,11 +431,13 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     int maxlast = last;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, o, 64));
-    const float Tf = T;
+    const float gATf = gA * T;   // alpha-channel term of dL/dalpha: gA T_final / (1 - alpha)
     const float fpx = (float)px, fpy = (float)py;
     const float fx0 = (float)(ti.tx * 8), fy0 = (float)(ti.ty * 8);
     const int sub = lane & (SUB - 1), grp = lane / SUB;
-    float S0 = 0.f, S1 = 0.f, S2 = 0.f, SD = 0.f;
+    // g . S: the upstream colour/depth gradient dotted with the suffix sum of
+    // w c over the later contributors, carried as one scalar
+    float GS = 0.f;
     float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     wave_lds_sync();
     // the view's focal lengths (every pair of a job shares the view)
@@ -485,16 +487,15 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
             const int cut = lim - s * SUB;
             uint32_t m = cut <= 0 ? 0u : (uint32_t)((mine >> (s * SUB)) & low_bits(min(cut, SUB)));
             uint32_t cmask = 0u;   // entries of the sub-chunk this pixel contributed to
+            // dL/dalpha = sum_c g_c (c T - S_c / (1 - alpha)) + gA T_final / (1 - alpha)
+            //           = T (g . c) - (g . S - gA T_final) / (1 - alpha)
             auto contribute = [&](float alpha, float raw, float4 c, int bit) {
                 const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
                 T = T * inv;
                 const float w = alpha * T;
-                const float gal = gC0 * (c.x * T - S0 * inv) + gC1 * (c.y * T - S1 * inv) +
-                                  gC2 * (c.z * T - S2 * inv) + gD * (c.w * T - SD * inv) + gA * Tf * inv;
-                S0 += w * c.x;
-                S1 += w * c.y;
-                S2 += w * c.z;
-                SD += w * c.w;
+                const float gc = gC0 * c.x + gC1 * c.y + gC2 * c.z + gD * c.w;
+                const float gal = T * gc - inv * (GS - gATf);
+                GS += w * gc;
                 const float gq = raw < kAlphaMax ? -0.5f * alpha * gal : 0.f;
                 *(float2*)&s_M[lane * LS + 2 * bit] = make_float2(w, gq);
                 cmask |= 1u << bit;
