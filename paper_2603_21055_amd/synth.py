@@ -78,6 +78,19 @@ def pose_from_c2w(R_wc, C):
     return R_wc.T.astype(np.float32), (-R_wc.T @ C).astype(np.float32)
 
 
+def corner_pose(room, C=(0.0, 0.0, 0.0)):
+    """World->camera pose of a camera at C looking at the room's (+x, +y, +z)
+    corner (image y down): three walls in view, so a frame's geometry pins
+    all six degrees of freedom."""
+    C = np.asarray(C, np.float64)
+    z = np.asarray(room.hi, np.float64) - C
+    z /= np.linalg.norm(z)
+    x = np.cross(np.array([0.0, 1.0, 0.0]), z)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    return pose_from_c2w(np.stack([x, y, z], 1), C)
+
+
 # ----------------------------------------------------------------------------
 # analytic room: an axis-aligned box around the origin, value-noise colour
 # ----------------------------------------------------------------------------
