@@ -4,8 +4,11 @@
 Workload: one 640x480 keyframe of pixel-aligned Gaussians (307,200) rendered
 into one view perturbed by up to 2 cm / 1 degree (synthetic box room, seed
 10).  One step = one mapping iteration of that frame through the HIP library:
-forward splat, L1 loss and upstream gradients, adjoint (colour, opacity,
-radius, offset and pose gradients) and the Adam update.  Inputs are resident
+forward splat, Eq. 1 loss (L1 colour, SSIM, masked L1 depth) and its
+upstream gradients, adjoint (colour, opacity, radius, offset and pose
+gradients) and the Adam update.  The default line also carries the
+warm-start comparison, the 8-keyframe window, the 1200x680 per-pixel and
+GICP tracking workloads and the oracle's CPU baselines as extra keys.  Inputs are resident
 in HBM before the timed region.
 
 Prints ONE JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
@@ -107,6 +110,47 @@ def cpu_baseline():
                 sample=f"one full 640x480 frame fwd+bwd (room frame, seed 10), {dt:.1f} s on 1 thread")
 
 
+def _band_work(band):
+    """One horizontal band of the 640x480 room frame through the oracle
+    (forward of the band's pixels, adjoint of their pairs) on one thread;
+    returns its compute time (the scene is built before the clock starts)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import splat
+    from paper_2603_21055_amd import synth
+    y0, y1 = band
+    sc = synth.room_frame_scene(10)
+    rng = np.random.default_rng(0)
+    H, W = 480, 640
+    gr = rng.normal(size=(3, H, W)) / (H * W)
+    gd = rng.normal(size=(H, W)) / (H * W)
+    ga = rng.normal(size=(H, W)) / (H * W)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        f = splat.render_window(sc["kfs"], sc["views"][0], [0], (0, y0, W, y1))
+        splat.backward_job(sc["kfs"], sc["views"][0], f, gr, gd, ga)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores():
+    """The oracle over all host cores (up to the 16 a one-GPU host grants):
+    the 640x480 frame cut into one horizontal band per worker process, each
+    band's forward and adjoint on one thread; the frame time is the slowest
+    band's.  Runs in forked workers before the GPU is opened."""
+    from multiprocessing import Pool
+    n = max(1, min(16, os.cpu_count() or 1))
+    edges = [round(480 * i / n) for i in range(n + 1)]
+    bands = [(edges[i], edges[i + 1]) for i in range(n)]
+    with Pool(n) as pool:
+        times = pool.map(_band_work, bands)
+    dt = max(times)
+    return dict(value=1.0 / dt, unit="frames/s", cores=n, kind="oracle",
+                sample=f"one full 640x480 frame fwd+bwd cut into {n} row bands, one per process on one thread "
+                       f"each; slowest band {dt:.2f} s (sum over bands {sum(times):.1f} s)",
+                nproc=os.cpu_count())
+
+
 def cpu_baseline_window():
     """The oracle on one host core, sampled: view 0 of the 8-keyframe window
     rendering keyframe 0 (one of the 64 keyframe-view pairs), fwd+bwd,
@@ -182,7 +226,7 @@ def _timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def bench_window(args):
+def bench_window(args, emit=True):
     """8 keyframes x 8 views, every view renders all keyframes, all learnable."""
     import numpy as np
     import torch
@@ -209,13 +253,16 @@ def bench_window(args):
     out = dict(metric="batched mapping window iterations/s (8 keyframes x 8 views, 640x480)",
                value=1.0 / sec, unit="iterations/s", ms_per_step=sec * 1e3, steps=steps,
                hbm_frac=algo / sec / HBM_PEAK, tile=[tw, th], dtype="f32", data="synthetic")
+    ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline_window()
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
-def bench_tracking(args):
+def bench_tracking(args, emit=True):
     """30 Gauss-Newton iterations at 1200x680 in one hipGraph launch."""
     import numpy as np
     import torch
@@ -241,10 +288,63 @@ def bench_tracking(args):
     out = dict(metric="tracking Gauss-Newton iterations/s (1200x680, 30 per graph launch)",
                value=30.0 / sec, unit="iterations/s", ms_per_graph=sec * 1e3, steps=steps,
                dtype="f32 (FP64 solve)", data="synthetic")
+    ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline_tracking()
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_gicp(args, emit=True):
+    """GICP tracking (Eq. 2) at 1200x680 with R = 10 and K_c = 10: a frame
+    looking into a room corner and a new frame 3 cm / 2 degrees away; one
+    track = building the new frame's set and 30 Gauss-Newton iterations
+    against the previous frame's set."""
+    import numpy as np
+    import torch
+
+    from paper_2603_21055_amd import sgad, synth
+    log("building 1200x680 GICP frame pair")
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(60)
+    room = synth.make_room(rng)
+    cam = synth.intrinsics(1200, 680)
+    R0, t0 = synth.corner_pose(room)
+    d0, _ = room.raycast(cam, R0, t0)
+    Rg, tg = synth.perturb_pose(R0, t0, rng, 0.03, 2.0, exact=True)
+    d1, _ = room.raycast(cam, Rg, tg)
+    ctx = sgad.Context(0)
+    R_s, K = 10, 10
+    n = ctx.gicp_set_size(680, 1200, R_s)
+    tgt = torch.empty((12, n), dtype=torch.float64, device=dev)
+    src = torch.empty((12, n), dtype=torch.float64, device=dev)
+    dd0 = torch.from_numpy(d0.astype(np.float32)).to(dev)
+    dd1 = torch.from_numpy(d1.astype(np.float32)).to(dev)
+    ctx.gicp_prepare(dd0, cam, R_s, K, tgt)
+    pose = torch.empty(12, dtype=torch.float64, device=dev)
+    ident = torch.from_numpy(np.concatenate([np.eye(3).ravel(), np.zeros(3)])).to(dev)
+
+    def run():
+        ctx.gicp_prepare(dd1, cam, R_s, K, src)
+        pose.copy_(ident)
+        ctx.gicp_track(src, tgt, K, pose, 30)
+
+    steps = max(1, min(args.steps, 20))
+    sec = _timed(run, steps, min(args.warmup, 3))
+    ctx.sync()
+    Rc = np.asarray(R0, np.float64) @ np.asarray(Rg, np.float64).T
+    tc = np.asarray(t0, np.float64) - Rc @ np.asarray(tg, np.float64)
+    p = pose.cpu().numpy()
+    err_mm = float(np.linalg.norm(p[9:] - tc) * 1e3)
+    out = dict(metric="GICP tracking frames/s (1200x680, R=10, K_c=10, 30 Gauss-Newton iterations)",
+               value=1.0 / sec, unit="frames/s", ms_per_frame=sec * 1e3, points=n, steps=steps,
+               translation_error_mm=err_mm, dtype="f64", data="synthetic")
+    ctx.close()
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_offsetnet(args):
@@ -315,11 +415,11 @@ def bench_copy(args):
                           bytes_read_per_copy=4 * n, bytes_written_per_copy=4 * n)), flush=True)
 
 
-def warm_frames(n_frames=400):
+def warm_frames(n_frames=2000):
     """Training frames of the warm-start comparison (CPU worker processes;
     made before the GPU is opened)."""
     from paper_2603_21055_amd import warmstart
-    return warmstart.make_frames(range(1000, 1000 + n_frames), workers=min(8, os.cpu_count() or 1))
+    return warmstart.make_frames(range(1000, 1000 + n_frames), workers=min(16, os.cpu_count() or 1))
 
 
 def warm_start(ctx, log, frames, epochs=20):
@@ -330,7 +430,8 @@ def warm_start(ctx, log, frames, epochs=20):
     log(f"warm start: {len(frames)} training frames, {epochs} epochs")
     res = warmstart.experiment(ctx, frames, epochs=epochs, map_iters=150, log=log)
     keep = ("plain_iters", "plain_first_loss", "warm_first_loss", "plain_final_loss", "warm_final_loss",
-            "warm_iters_to_plain_level", "warm_iters_to_plain_loss", "n_frames", "epochs", "seconds")
+            "warm_iters_to_plain_level", "warm_iters_to_plain_loss", "warm_offset_lr", "offset_lr_validation",
+            "n_frames", "epochs", "seconds")
     return {k: res[k] for k in keep}
 
 
@@ -346,9 +447,13 @@ def main():
     ap.add_argument("--print-sha", action="store_true", help="print the kernel-source hashes and exit")
     ap.add_argument("--graph", action="store_true", help="time replays of a captured graph of one step")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start comparison")
-    ap.add_argument("--workload", choices=["frame", "window", "tracking", "offsetnet", "copy"], default="frame",
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the window, tracking and GICP results the default line carries as extra keys")
+    ap.add_argument("--workload", choices=["frame", "window", "tracking", "gicp", "offsetnet", "copy"],
+                    default="frame",
                     help="frame: one 640x480 keyframe into one view (the headline step); window: 8 keyframes "
-                         "x 8 views at 640x480; tracking: 1200x680 Gauss-Newton; offsetnet: the warm-start conv "
+                         "x 8 views at 640x480; tracking: 1200x680 Gauss-Newton; gicp: 1200x680 GICP tracking; "
+                         "offsetnet: the warm-start conv "
                          "net on one 640x480 frame; copy: plain device copy (counter calibration)")
     args = ap.parse_args()
     if args.print_sha:
@@ -359,13 +464,17 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.workload != "frame":
-        return {"window": bench_window, "tracking": bench_tracking, "offsetnet": bench_offsetnet,
-                "copy": bench_copy}[args.workload](args)
+        return {"window": bench_window, "tracking": bench_tracking, "gicp": bench_gicp,
+                "offsetnet": bench_offsetnet, "copy": bench_copy}[args.workload](args)
 
     frames = None
     if not args.no_warm_start:
         log("warm-start training frames (CPU)")
         frames = warm_frames()
+    all_cores = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline over all host cores (oracle, forked before the GPU is opened)")
+        all_cores = cpu_baseline_all_cores()
     import numpy as np
     import torch
 
@@ -455,7 +564,8 @@ def main():
         value=fps, unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms,
         higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload="one 640x480 keyframe (307,200 pixel-aligned Gaussians) splatted into one "
-                             "view perturbed <=2 cm / 1 deg; step = forward, L1 loss, adjoint, Adam",
+                             "view perturbed <=2 cm / 1 deg; step = forward, Eq. 1 loss (L1 colour, SSIM, "
+                             "masked L1 depth), adjoint, Adam",
                     frame=[W, H], gaussians=N, tile=[tw, th],
                     tile_variant=dict(zip(("fwd_chunks", "bwd_sub"), ctx.get_tile_variant())),
                     launch="one captured graph per step" if args.graph else "eager calls"),
@@ -466,9 +576,22 @@ def main():
     )
     if not args.no_warm_start:
         out["warm_start"] = warm_start(ctx, log, frames)
+    if not args.no_other_workloads:
+        import argparse as _ap
+        sub = _ap.Namespace(**vars(args))
+        sub.no_cpu_baseline = True
+        sub.steps, sub.warmup = 5, 2
+        log("other workloads: 8-keyframe window, 1200x680 tracking, 1200x680 GICP")
+        ctx.close()
+        keep = ("value", "unit", "ms_per_step", "ms_per_graph", "ms_per_frame", "hbm_frac", "translation_error_mm",
+                "steps", "metric")
+        for name, fn in (("window", bench_window), ("tracking", bench_tracking), ("gicp", bench_gicp)):
+            r = fn(sub, emit=False)
+            out[name] = {k: r[k] for k in keep if k in r}
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, ~20 s)")
-        out["cpu_baseline"] = cpu_baseline()
+        log("cpu baseline (oracle, one thread)")
+        one = cpu_baseline()
+        out["cpu_baseline"] = dict(all_cores, single_thread=one)
     print(json.dumps(out), flush=True)
 
 

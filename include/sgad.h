@@ -316,6 +316,49 @@ sgad_status sgad_eq1_loss(sgad_ctx* ctx, int n_jobs, int H, int W,
                           float w_rgb, float w_ssim, float w_depth, float* g_rgb, float* g_depth, double* loss,
                           void* stream);
 
+/* ---------------------------------------------------------------- GICP */
+/*
+ * Tracking a depth frame against a set of geometry Gaussians with
+ * Generalized ICP (Sec. 3.3, Eq. 2; the supplement's sampling ratio R and
+ * neighbour count K_c; Tab. 11's point-to-surface correspondences and
+ * "ellipse" scale normalisation).  A set is a caller-owned device buffer of
+ * 12 * n doubles, SoA [12][n] = (x, y, z, c00, c01, c02, c11, c12, c22, nx,
+ * ny, nz) for the n = sgad_gicp_set_size(H, W, R) pixels of the frame's
+ * stride-R grid (row-major): the back-projected point in its camera's frame,
+ * the normalised covariance C' = U diag(max(l0/l2, 1e-3), max(l1/l2, 1e-3),
+ * 1) U^T of its K_c nearest points of the set (the point itself included,
+ * ties by index) and the normal (eigenvector of the smallest eigenvalue).
+ * Grid pixels without depth are all zero (z = 0) and take no part.
+ * Poses are camera-to-target P = (R, t): device double[12], R row-major
+ * then t; a source point a maps to X = R a + t.
+ */
+/* Points of the stride-`ratio` grid of an H x W frame; -1 on bad sizes. */
+int32_t sgad_gicp_set_size(int H, int W, int ratio);
+/* Build a set from a depth map [H][W] (metres; <= 0: no depth) with the
+ * pinhole camera cam (cam->H, cam->W give the frame size).  K_c = k in
+ * 1..32 (SGAD_ERANGE otherwise).  `set` is WRITTEN. */
+sgad_status sgad_gicp_prepare(sgad_ctx* ctx, const float* depth, const sgad_cam* cam, int ratio, int k,
+                              double* set, void* stream);
+/* One linearisation of Eq. 2 at the device pose: each valid source point X
+ * is matched among its K_c nearest target points (Euclidean, ties by index)
+ * to the one minimising (n_b . e)^2 + 1e-3 |e|^2, e = X - b (first minimum in
+ * distance order), and kept when |e|^2 <= 0.1^2 m^2; with M = (C_b + R C_a
+ * R^T)^-1 and J = de/dxi = [-I | [X]x] for the left twist xi = (rho, phi):
+ * out (device double[29]) = H = sum J^T M J (upper triangle, row-major, 21),
+ * g = sum J^T M (b - X) (6), the cost sum e^T M e and the pair count,
+ * WRITTEN.  corr (device int32[n_src], may be NULL): the matched target index
+ * per source point, -1 for none.  Uses a context workspace of 29 doubles per
+ * 256 source points. */
+sgad_status sgad_gicp_linearise(sgad_ctx* ctx, const double* src, int n_src, const double* tgt, int n_tgt, int k,
+                                const double* pose, double* out, int32_t* corr, void* stream);
+/* `iters` Gauss-Newton steps from the device pose (updated in place):
+ * dxi = -H^-1 g by a damped Cholesky (1e-9 tr H, x10 per retry, FP64),
+ * P <- Exp(dxi) P.  trace (device double[iters][48], may be NULL): per step
+ * H (21), g (6), cost, pair count, damping (-1: no solve), dxi (6) and the
+ * pose before the step (R 9, t 3). */
+sgad_status sgad_gicp_track(sgad_ctx* ctx, const double* src, int n_src, const double* tgt, int n_tgt, int k,
+                            double* pose, int iters, double* trace, void* stream);
+
 /* One parameter tensor for sgad_adam_step (all device pointers, n floats;
  * the pointers may be null when n is 0).  Arrays that start on a 16-byte
  * boundary are read and written four floats at a time. */

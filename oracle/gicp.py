@@ -100,22 +100,51 @@ def local_gaussians(points, k):
     return dict(points=p, cov=Cn, normal=U[:, :, 0], eig=lam, nb=nb)
 
 
-def correspond(src, tgt, R, t, k):
-    """Point-to-surface correspondences of the source points moved by (R, t):
-    target index per source point (-1: none within D_MAX) and X = R a + t."""
+def transform(points, R, t):
+    """X = R a + t with each row summed in the fixed order ((r0 a0 + r1 a1) +
+    r2 a2) + t (the order is part of the correspondence decision)."""
+    a = np.asarray(points, np.float64)
     R = np.asarray(R, np.float64)
     t = np.asarray(t, np.float64)
-    X = src["points"] @ R.T + t
-    nb = knn(X, tgt["points"], k)
-    B = tgt["points"][nb]                        # [n, k, 3]
-    Nrm = tgt["normal"][nb]
+    return np.stack([((R[i, 0] * a[:, 0] + R[i, 1] * a[:, 1]) + R[i, 2] * a[:, 2]) + t[i] for i in range(3)], 1)
+
+
+def surface_distance(E, Nrm):
+    """(n . e)^2 + EPS |e|^2 with both dot products summed in the order
+    (x + y) + z."""
+    dn = (Nrm[..., 0] * E[..., 0] + Nrm[..., 1] * E[..., 1]) + Nrm[..., 2] * E[..., 2]
+    ee = (E[..., 0] * E[..., 0] + E[..., 1] * E[..., 1]) + E[..., 2] * E[..., 2]
+    return dn * dn + EPS * ee
+
+
+def correspond(src, tgt, R, t, k, with_margins=False):
+    """Point-to-surface correspondences of the source points moved by (R, t):
+    target index per source point (-1: none within D_MAX) and X = R a + t.
+    with_margins: also, per source point, the relative gaps of the three
+    decisions (K-th vs (K+1)-th Euclidean distance, best vs second surface
+    distance, squared distance vs D_MAX^2), for flagging near-ties."""
+    X = transform(src["points"], R, t)
+    nb = knn(X, tgt["points"], k + 1 if with_margins else k)
+    nbk = nb[:, :k]
+    B = tgt["points"][nbk]                       # [n, k, 3]
     E = X[:, None, :] - B
-    dist = np.einsum("nkj,nkj->nk", Nrm, E) ** 2 + EPS * np.einsum("nkj,nkj->nk", E, E)
+    dist = surface_distance(E, tgt["normal"][nbk])
     best = np.argmin(dist, 1)                    # first minimum = lowest Euclidean rank
-    j = nb[np.arange(len(X)), best]
-    d = np.linalg.norm(tgt["points"][j] - X, axis=1)
-    j = np.where(d <= D_MAX, j, -1)
-    return j, X
+    j = nbk[np.arange(len(X)), best]
+    e = tgt["points"][j] - X
+    d2 = (e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1]) + e[:, 2] * e[:, 2]
+    j = np.where(d2 <= D_MAX * D_MAX, j, -1)
+    if not with_margins:
+        return j, X
+    P = tgt["points"]
+    def sq(i):
+        f = X - P[nb[:, i]]
+        return (f[:, 0] * f[:, 0] + f[:, 1] * f[:, 1]) + f[:, 2] * f[:, 2]
+    gap_knn = (np.abs(sq(k) - sq(k - 1)) / np.maximum(sq(k), 1e-300)) if nb.shape[1] > k else np.full(len(X), np.inf)
+    srt = np.sort(dist, 1)
+    gap_best = np.abs(srt[:, 1] - srt[:, 0]) / np.maximum(srt[:, 1], 1e-300) if k > 1 else np.full(len(X), np.inf)
+    gap_dmax = np.abs(d2 - D_MAX * D_MAX) / (D_MAX * D_MAX)
+    return j, X, dict(knn=gap_knn, best=gap_best, dmax=gap_dmax)
 
 
 def linearise(src, tgt, R, t, k):

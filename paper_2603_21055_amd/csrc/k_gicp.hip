@@ -1,0 +1,545 @@
+// Tracking a depth frame against a set of geometry Gaussians with
+// Generalized ICP (Sec. 3.3, Eq. 2; the supplement's sampling ratio R and
+// neighbour count K_c; Tab. 11's point-to-surface correspondences and
+// "ellipse" scale normalisation).
+//
+// A set holds the Gaussians of one frame's stride-R pixel grid, SoA, FP64:
+//   [12][n] = x y z | c00 c01 c02 c11 c12 c22 | nx ny nz
+// (point in its camera's frame, normalised covariance, normal).  A grid
+// pixel without depth has z = 0 there and is never a neighbour or a source.
+//
+// k_gicp_prepare   one thread per grid point: back-projection, its K_c
+//                  nearest points of the set (brute force over LDS tiles of
+//                  the set, squared distance ((dx^2 + dy^2) + dz^2), ties by
+//                  index, a register top-K), their covariance, a cyclic
+//                  Jacobi eigen-decomposition, C' = U diag(max(l0/l2, eps),
+//                  max(l1/l2, eps), 1) U^T and the normal (smallest).
+// k_gicp_linearise one thread per source point: X = R a + t, its K_c
+//                  nearest target points, the one with the smallest
+//                  (n . e)^2 + eps |e|^2 (first minimum in distance rank),
+//                  pairs with |e|^2 <= D_MAX^2 kept; M = (C_b + R C_a R^T)^-1,
+//                  J = [-I | [X]x], per-block FP64 partial sums of
+//                  H = J^T M J (21), g = J^T M e (6), e^T M e and the count.
+// k_gicp_solve     one block: the partial sums in a fixed order, damped
+//                  Cholesky (1e-9 tr H, x10 per retry), dxi = -H^-1 g,
+//                  P <- Exp(dxi) P on the device pose, and a trace record.
+// Every decision (neighbour sets, correspondences, the distance cut) is
+// taken in FP64 with the operation order written here and no contraction,
+// so an independent FP64 evaluation in the same order reproduces it.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+
+#include "sgad_internal.h"
+
+namespace sgad {
+
+constexpr int kGicpMaxK = 32;
+constexpr double kGicpEps = 1e-3;
+constexpr double kGicpDMax = 0.1;
+constexpr int kGicpVals = 29;      // H upper triangle (21), g (6), cost, pair count
+constexpr int kGicpTile = 256;     // candidate points staged in LDS per round
+constexpr int kGicpTrace = 48;     // trace record: H 21, g 6, cost, n, lambda, dxi 6, R 9, t 3
+
+// Top-K in registers, sorted by (distance, index); every comparison is on
+// the pair, so the result does not depend on the order candidates arrive in.
+struct TopK {
+    double d[kGicpMaxK];
+    int i[kGicpMaxK];
+    double worst;
+    int worst_i;
+};
+
+__device__ __forceinline__ void topk_init(TopK& t) {
+#pragma unroll
+    for (int s = 0; s < kGicpMaxK; ++s) {
+        t.d[s] = DBL_MAX;
+        t.i[s] = INT_MAX;
+    }
+    t.worst = DBL_MAX;
+    t.worst_i = INT_MAX;
+}
+
+__device__ __forceinline__ void topk_insert(TopK& t, int k, double d, int j) {
+    double cd = d;
+    int ci = j;
+#pragma unroll
+    for (int s = 0; s < kGicpMaxK; ++s) {
+        if (s < k) {
+            const bool sw = cd < t.d[s] || (cd == t.d[s] && ci < t.i[s]);
+            const double td = sw ? t.d[s] : cd;
+            const int ti = sw ? t.i[s] : ci;
+            t.d[s] = sw ? cd : t.d[s];
+            t.i[s] = sw ? ci : t.i[s];
+            cd = td;
+            ci = ti;
+        }
+    }
+    double w = t.d[0];
+    int wi = t.i[0];
+#pragma unroll
+    for (int s = 0; s < kGicpMaxK; ++s)
+        if (s == k - 1) {
+            w = t.d[s];
+            wi = t.i[s];
+        }
+    t.worst = w;
+    t.worst_i = wi;
+}
+
+// The k nearest points of `set` (n points) to q, over LDS tiles.  Every
+// thread of the block takes part in the staging (valid or not).  The tiles
+// are visited outward from tile `home` (home, home + 1, home - 1, ...): sets
+// are in pixel-grid order, so the points near the block's queries come
+// first and fill the list, and far ones rarely enter it.
+__device__ void knn_scan(const double* __restrict__ set, int n, int k, double qx, double qy, double qz, bool active,
+                         TopK& t, double (*s_p)[kGicpTile], int home) {
+#pragma clang fp contract(off)
+    topk_init(t);
+    const int ntile = (n + kGicpTile - 1) / kGicpTile;
+    home = min(max(home, 0), ntile - 1);
+    for (int step = 0; step < 2 * ntile; ++step) {
+        const int off = (step + 1) >> 1;
+        const int tile = (step & 1) ? home + off : home - off;
+        if (tile < 0 || tile >= ntile || (step > 0 && off == 0)) continue;
+        const int b0 = tile * kGicpTile;
+        __syncthreads();
+        for (int c = threadIdx.x; c < kGicpTile; c += blockDim.x) {
+            const int j = b0 + c;
+            const bool in = j < n;
+            s_p[0][c] = in ? set[j] : 0.0;
+            s_p[1][c] = in ? set[(size_t)n + j] : 0.0;
+            s_p[2][c] = in ? set[2 * (size_t)n + j] : 0.0;
+        }
+        __syncthreads();
+        if (!active) continue;
+        const int m = min(kGicpTile, n - b0);
+        for (int c = 0; c < m; ++c) {
+            const double pz = s_p[2][c];
+            if (pz == 0.0) continue;          // grid pixel without depth
+            const double dx = qx - s_p[0][c], dy = qy - s_p[1][c], dz = qz - pz;
+            const double d = (dx * dx + dy * dy) + dz * dz;
+            const int j = b0 + c;
+            if (d < t.worst || (d == t.worst && j < t.worst_i)) topk_insert(t, k, d, j);
+        }
+    }
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix a (row-major,
+// overwritten); eigenvalues in w, eigenvectors in the columns of v.
+__device__ void jacobi3(double* a, double* w, double* v) {
+    for (int i = 0; i < 9; ++i) v[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 32; ++sweep) {
+        const double off = a[1] * a[1] + a[2] * a[2] + a[5] * a[5];
+        const double scale = a[0] * a[0] + a[4] * a[4] + a[8] * a[8];
+        if (off <= 1e-30 * scale || off == 0.0) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                const double apq = a[p * 3 + q];
+                if (apq == 0.0) continue;
+                const double app = a[p * 3 + p], aqq = a[q * 3 + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(tt * tt + 1.0), s = tt * c;
+                for (int r = 0; r < 3; ++r) {       // A <- A J
+                    const double arp = a[r * 3 + p], arq = a[r * 3 + q];
+                    a[r * 3 + p] = c * arp - s * arq;
+                    a[r * 3 + q] = s * arp + c * arq;
+                }
+                for (int r = 0; r < 3; ++r) {       // A <- J^T A
+                    const double apr = a[p * 3 + r], aqr = a[q * 3 + r];
+                    a[p * 3 + r] = c * apr - s * aqr;
+                    a[q * 3 + r] = s * apr + c * aqr;
+                }
+                for (int r = 0; r < 3; ++r) {       // V <- V J
+                    const double vrp = v[r * 3 + p], vrq = v[r * 3 + q];
+                    v[r * 3 + p] = c * vrp - s * vrq;
+                    v[r * 3 + q] = s * vrp + c * vrq;
+                }
+            }
+    }
+    w[0] = a[0];
+    w[1] = a[4];
+    w[2] = a[8];
+}
+
+// Runs after k_gicp_points: reads the coordinate rows, writes rows 3..11.
+__global__ __launch_bounds__(256) void k_gicp_prepare(int k, double* __restrict__ set, int n) {
+#pragma clang fp contract(off)
+    __shared__ double s_p[3][kGicpTile];
+    const int g = (int)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = g < n;
+    double qx = 0.0, qy = 0.0, qz = 0.0;
+    if (in) {
+        qx = set[g];
+        qy = set[(size_t)n + g];
+        qz = set[2 * (size_t)n + g];
+    }
+    const bool active = in && qz != 0.0;
+    TopK t;
+    knn_scan(set, n, k, qx, qy, qz, active, t, s_p, (int)blockIdx.x * (int)blockDim.x / kGicpTile);
+    if (!active) {
+        if (in)
+            for (int r = 3; r < 12; ++r) set[(size_t)r * n + g] = 0.0;
+        return;
+    }
+    int kk = 0;
+    double mx = 0.0, my = 0.0, mz = 0.0;
+#pragma unroll
+    for (int s = 0; s < kGicpMaxK; ++s)
+        if (s < k && t.i[s] != INT_MAX) {
+            const int j = t.i[s];
+            mx += set[j];
+            my += set[(size_t)n + j];
+            mz += set[2 * (size_t)n + j];
+            ++kk;
+        }
+    mx /= (double)kk;
+    my /= (double)kk;
+    mz /= (double)kk;
+    double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < kGicpMaxK; ++s)
+        if (s < k && t.i[s] != INT_MAX) {
+            const int j = t.i[s];
+            const double dx = set[j] - mx, dy = set[(size_t)n + j] - my, dz = set[2 * (size_t)n + j] - mz;
+            c[0] += dx * dx;
+            c[1] += dx * dy;
+            c[2] += dx * dz;
+            c[4] += dy * dy;
+            c[5] += dy * dz;
+            c[8] += dz * dz;
+        }
+    for (int i = 0; i < 9; ++i) c[i] /= (double)kk;
+    c[3] = c[1];
+    c[6] = c[2];
+    c[7] = c[5];
+    double w[3], v[9];
+    jacobi3(c, w, v);
+    // ascending order of the eigenvalues
+    int o[3] = {0, 1, 2};
+    if (w[o[0]] > w[o[1]]) { const int x = o[0]; o[0] = o[1]; o[1] = x; }
+    if (w[o[1]] > w[o[2]]) { const int x = o[1]; o[1] = o[2]; o[2] = x; }
+    if (w[o[0]] > w[o[1]]) { const int x = o[0]; o[0] = o[1]; o[1] = x; }
+    const double l2 = w[o[2]];
+    double sc[3];
+    if (l2 > 0.0) {
+        sc[0] = fmax(w[o[0]] / l2, kGicpEps);
+        sc[1] = fmax(w[o[1]] / l2, kGicpEps);
+        sc[2] = 1.0;
+    } else {
+        sc[0] = kGicpEps;
+        sc[1] = kGicpEps;
+        sc[2] = 1.0;
+    }
+    double cn[6] = {0, 0, 0, 0, 0, 0};   // c00 c01 c02 c11 c12 c22
+    for (int e = 0; e < 3; ++e) {
+        const double ux = v[0 * 3 + o[e]], uy = v[1 * 3 + o[e]], uz = v[2 * 3 + o[e]];
+        cn[0] += sc[e] * ux * ux;
+        cn[1] += sc[e] * ux * uy;
+        cn[2] += sc[e] * ux * uz;
+        cn[3] += sc[e] * uy * uy;
+        cn[4] += sc[e] * uy * uz;
+        cn[5] += sc[e] * uz * uz;
+    }
+    for (int r = 0; r < 6; ++r) set[(size_t)(3 + r) * n + g] = cn[r];
+    set[(size_t)9 * n + g] = v[0 * 3 + o[0]];
+    set[(size_t)10 * n + g] = v[1 * 3 + o[0]];
+    set[(size_t)11 * n + g] = v[2 * 3 + o[0]];
+}
+
+// Grid point g = (gy, gx) of a stride-R grid: a = D ((u - cx) / fx, (v - cy) / fy, 1).
+__global__ __launch_bounds__(256) void k_gicp_points(const float* __restrict__ depth, int H, int W, int R,
+                                                     double fx, double fy, double cx, double cy,
+                                                     double* __restrict__ set, int n) {
+#pragma clang fp contract(off)
+    const int gw = (W + R - 1) / R;
+    const int g = (int)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int gy = g / gw, gx = g - gy * gw;
+    const int u = gx * R, v = gy * R;
+    const double d = (double)depth[(size_t)v * W + u];
+    double x = 0.0, y = 0.0, z = 0.0;
+    if (d > 0.0) {
+        x = d * (((double)u - cx) / fx);
+        y = d * (((double)v - cy) / fy);
+        z = d;
+    }
+    set[g] = x;
+    set[(size_t)n + g] = y;
+    set[2 * (size_t)n + g] = z;
+}
+
+// Pose P = (R row-major, t) at pose[0..11].
+__global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict__ src, int ns,
+                                                        const double* __restrict__ tgt, int nt, int k,
+                                                        const double* __restrict__ pose, double* __restrict__ part,
+                                                        int* __restrict__ corr) {
+#pragma clang fp contract(off)
+    __shared__ double s_p[3][kGicpTile];
+    __shared__ double s_acc[4][kGicpVals];
+    const int i = (int)blockIdx.x * blockDim.x + threadIdx.x;
+    double Rm[9], tv[3];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) Rm[r] = pose[r];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) tv[r] = pose[9 + r];
+    const bool in = i < ns;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (in) {
+        a0 = src[i];
+        a1 = src[(size_t)ns + i];
+        a2 = src[2 * (size_t)ns + i];
+    }
+    const bool active = in && a2 != 0.0;
+    const double X0 = ((Rm[0] * a0 + Rm[1] * a1) + Rm[2] * a2) + tv[0];
+    const double X1 = ((Rm[3] * a0 + Rm[4] * a1) + Rm[5] * a2) + tv[1];
+    const double X2 = ((Rm[6] * a0 + Rm[7] * a1) + Rm[8] * a2) + tv[2];
+    TopK t;
+    // source and target grids cover the same image region for small motions
+    knn_scan(tgt, nt, k, X0, X1, X2, active, t, s_p,
+             (int)((long long)blockIdx.x * blockDim.x * nt / ((long long)ns * kGicpTile)));
+    double acc[kGicpVals];
+#pragma unroll
+    for (int q = 0; q < kGicpVals; ++q) acc[q] = 0.0;
+    int j = -1;
+    if (active) {
+        double best = DBL_MAX;
+#pragma unroll
+        for (int s = 0; s < kGicpMaxK; ++s)
+            if (s < k && t.i[s] != INT_MAX) {
+                const int c = t.i[s];
+                const double e0 = X0 - tgt[c], e1 = X1 - tgt[(size_t)nt + c], e2 = X2 - tgt[2 * (size_t)nt + c];
+                const double n0 = tgt[(size_t)9 * nt + c], n1 = tgt[(size_t)10 * nt + c], n2 = tgt[(size_t)11 * nt + c];
+                const double dn = (n0 * e0 + n1 * e1) + n2 * e2;
+                const double ee = (e0 * e0 + e1 * e1) + e2 * e2;
+                const double ds = dn * dn + kGicpEps * ee;
+                if (ds < best) {
+                    best = ds;
+                    j = c;
+                }
+            }
+        if (j >= 0) {
+            const double e0 = tgt[j] - X0, e1 = tgt[(size_t)nt + j] - X1, e2 = tgt[2 * (size_t)nt + j] - X2;
+            const double d2 = (e0 * e0 + e1 * e1) + e2 * e2;
+            if (!(d2 <= kGicpDMax * kGicpDMax)) j = -1;
+        }
+    }
+    if (corr && in) corr[i] = j;
+    if (j >= 0) {
+        // C = C_b + R C_a R^T
+        const double ca[9] = {src[(size_t)3 * ns + i], src[(size_t)4 * ns + i], src[(size_t)5 * ns + i],
+                              src[(size_t)4 * ns + i], src[(size_t)6 * ns + i], src[(size_t)7 * ns + i],
+                              src[(size_t)5 * ns + i], src[(size_t)7 * ns + i], src[(size_t)8 * ns + i]};
+        double RC[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                RC[r * 3 + c] = Rm[r * 3 + 0] * ca[0 * 3 + c] + Rm[r * 3 + 1] * ca[1 * 3 + c] + Rm[r * 3 + 2] * ca[2 * 3 + c];
+        double C[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                C[r * 3 + c] = RC[r * 3 + 0] * Rm[c * 3 + 0] + RC[r * 3 + 1] * Rm[c * 3 + 1] + RC[r * 3 + 2] * Rm[c * 3 + 2];
+        const double cb[6] = {tgt[(size_t)3 * nt + j], tgt[(size_t)4 * nt + j], tgt[(size_t)5 * nt + j],
+                              tgt[(size_t)6 * nt + j], tgt[(size_t)7 * nt + j], tgt[(size_t)8 * nt + j]};
+        C[0] += cb[0];
+        C[1] += cb[1];
+        C[2] += cb[2];
+        C[3] += cb[1];
+        C[4] += cb[3];
+        C[5] += cb[4];
+        C[6] += cb[2];
+        C[7] += cb[4];
+        C[8] += cb[5];
+        // M = C^-1 by the adjugate (C symmetric positive definite)
+        const double m00 = C[4] * C[8] - C[5] * C[7], m01 = C[2] * C[7] - C[1] * C[8], m02 = C[1] * C[5] - C[2] * C[4];
+        const double m11 = C[0] * C[8] - C[2] * C[6], m12 = C[2] * C[3] - C[0] * C[5], m22 = C[0] * C[4] - C[1] * C[3];
+        const double det = C[0] * m00 + C[1] * (C[5] * C[6] - C[3] * C[8]) + C[2] * (C[3] * C[7] - C[4] * C[6]);
+        const double id = 1.0 / det;
+        const double M[9] = {m00 * id, m01 * id, m02 * id, m01 * id, m11 * id, m12 * id, m02 * id, m12 * id, m22 * id};
+        const double e[3] = {tgt[j] - X0, tgt[(size_t)nt + j] - X1, tgt[(size_t)2 * nt + j] - X2};
+        // J = [-I | [X]x] (3 x 6)
+        const double X[3] = {X0, X1, X2};
+        double J[18];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) J[r * 6 + c] = (r == c) ? -1.0 : 0.0;
+        J[0 * 6 + 3] = 0.0;   J[0 * 6 + 4] = -X[2]; J[0 * 6 + 5] = X[1];
+        J[1 * 6 + 3] = X[2];  J[1 * 6 + 4] = 0.0;   J[1 * 6 + 5] = -X[0];
+        J[2 * 6 + 3] = -X[1]; J[2 * 6 + 4] = X[0];  J[2 * 6 + 5] = 0.0;
+        double MJ[18], Me[3];
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 6; ++c) MJ[r * 6 + c] = M[r * 3 + 0] * J[0 * 6 + c] + M[r * 3 + 1] * J[1 * 6 + c] + M[r * 3 + 2] * J[2 * 6 + c];
+            Me[r] = M[r * 3 + 0] * e[0] + M[r * 3 + 1] * e[1] + M[r * 3 + 2] * e[2];
+        }
+        int q = 0;
+        for (int r = 0; r < 6; ++r)
+            for (int c = r; c < 6; ++c) acc[q++] = J[0 * 6 + r] * MJ[0 * 6 + c] + J[1 * 6 + r] * MJ[1 * 6 + c] + J[2 * 6 + r] * MJ[2 * 6 + c];
+        for (int r = 0; r < 6; ++r) acc[21 + r] = J[0 * 6 + r] * Me[0] + J[1 * 6 + r] * Me[1] + J[2 * 6 + r] * Me[2];
+        acc[27] = e[0] * Me[0] + e[1] * Me[1] + e[2] * Me[2];
+        acc[28] = 1.0;
+    }
+    // block sum: wave shuffles, then the four waves in order
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kGicpVals; ++q) {
+        double v = acc[q];
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) s_acc[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kGicpVals) {
+        const int q = threadIdx.x;
+        part[(size_t)blockIdx.x * kGicpVals + q] = ((s_acc[0][q] + s_acc[1][q]) + s_acc[2][q]) + s_acc[3][q];
+    }
+}
+
+// Sum of the partial records in block order (one thread per value).
+__device__ __forceinline__ void gicp_sum(const double* part, int nb, double* S) {
+    if (threadIdx.x < kGicpVals) {
+        double v = 0.0;
+        for (int b = 0; b < nb; ++b) v += part[(size_t)b * kGicpVals + threadIdx.x];
+        S[threadIdx.x] = v;
+    }
+}
+
+__global__ void k_gicp_sum(const double* part, int nb, double* out) {
+    __shared__ double S[kGicpVals];
+    gicp_sum(part, nb, S);
+    __syncthreads();
+    if (threadIdx.x < kGicpVals) out[threadIdx.x] = S[threadIdx.x];
+}
+
+__device__ bool gicp_chol6(const double* A, double* L) {
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i * 6 + j];
+            for (int k = 0; k < j; ++k) s -= L[i * 6 + k] * L[j * 6 + k];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                L[i * 6 + i] = sqrt(s);
+            } else {
+                L[i * 6 + j] = s / L[j * 6 + j];
+            }
+        }
+    return true;
+}
+
+// One Gauss-Newton step on the device pose; trace record `it` if trace.
+__global__ void k_gicp_solve(const double* part, int nb, double* pose, double* trace, int it) {
+    __shared__ double S[kGicpVals];
+    gicp_sum(part, nb, S);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double Hm[36], g[6];
+    int q = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+            Hm[i * 6 + j] = S[q];
+            Hm[j * 6 + i] = S[q];
+            ++q;
+        }
+    for (int i = 0; i < 6; ++i) g[i] = S[21 + i];
+    double tr = 0.0;
+    for (int i = 0; i < 6; ++i) tr += Hm[i * 6 + i];
+    double lam = 0.0, L[36], dxi[6] = {0, 0, 0, 0, 0, 0};
+    bool ok = false;
+    for (int attempt = 0; attempt < 12; ++attempt) {
+        double A[36];
+        for (int i = 0; i < 36; ++i) A[i] = Hm[i];
+        for (int i = 0; i < 6; ++i) A[i * 6 + i] += lam;
+        for (int i = 0; i < 36; ++i) L[i] = 0.0;
+        if (gicp_chol6(A, L)) {
+            ok = true;
+            break;
+        }
+        lam = lam == 0.0 ? 1e-9 * tr : lam * 10.0;
+    }
+    if (ok) {
+        double y[6];
+        for (int i = 0; i < 6; ++i) {
+            double s = -g[i];
+            for (int k = 0; k < i; ++k) s -= L[i * 6 + k] * y[k];
+            y[i] = s / L[i * 6 + i];
+        }
+        for (int i = 5; i >= 0; --i) {
+            double s = y[i];
+            for (int k = i + 1; k < 6; ++k) s -= L[k * 6 + i] * dxi[k];
+            dxi[i] = s / L[i * 6 + i];
+        }
+    }
+    // Exp(dxi) = [[Re, V rho], [0, 1]]: Re = I + A K + B K^2, V = I + B K + C K^2
+    const double* rho = dxi;
+    const double* phi = dxi + 3;
+    const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+    const double th = sqrt(th2);
+    double Ac, Bc, Cc;
+    if (th < 1e-4) {
+        Ac = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+        Bc = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+        Cc = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+    } else {
+        Ac = sin(th) / th;
+        Bc = (1.0 - cos(th)) / th2;
+        Cc = (th - sin(th)) / (th2 * th);
+    }
+    const double K[9] = {0, -phi[2], phi[1], phi[2], 0, -phi[0], -phi[1], phi[0], 0};
+    double K2[9], Re[9], V[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            K2[i * 3 + j] = K[i * 3 + 0] * K[0 * 3 + j] + K[i * 3 + 1] * K[1 * 3 + j] + K[i * 3 + 2] * K[2 * 3 + j];
+    for (int i = 0; i < 9; ++i) {
+        const double I = (i % 4 == 0) ? 1.0 : 0.0;
+        Re[i] = I + Ac * K[i] + Bc * K2[i];
+        V[i] = I + Bc * K[i] + Cc * K2[i];
+    }
+    double Rn[9], tn[3];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+            Rn[i * 3 + j] = Re[i * 3 + 0] * pose[0 * 3 + j] + Re[i * 3 + 1] * pose[1 * 3 + j] + Re[i * 3 + 2] * pose[2 * 3 + j];
+        tn[i] = Re[i * 3 + 0] * pose[9] + Re[i * 3 + 1] * pose[10] + Re[i * 3 + 2] * pose[11] +
+                (V[i * 3 + 0] * rho[0] + V[i * 3 + 1] * rho[1] + V[i * 3 + 2] * rho[2]);
+    }
+    if (trace) {
+        double* rec = trace + (size_t)it * kGicpTrace;
+        for (int i = 0; i < 27; ++i) rec[i] = S[i];
+        rec[27] = S[27];
+        rec[28] = S[28];
+        rec[29] = ok ? lam : -1.0;
+        for (int i = 0; i < 6; ++i) rec[30 + i] = dxi[i];
+        for (int i = 0; i < 9; ++i) rec[36 + i] = pose[i];
+        for (int i = 0; i < 3; ++i) rec[45 + i] = pose[9 + i];
+    }
+    for (int i = 0; i < 9; ++i) pose[i] = Rn[i];
+    for (int i = 0; i < 3; ++i) pose[9 + i] = tn[i];
+}
+
+int gicp_grid_points(int H, int W, int R) { return ((H + R - 1) / R) * ((W + R - 1) / R); }
+int gicp_blocks(int n) { return (n + 255) / 256; }
+int gicp_vals() { return kGicpVals; }
+int gicp_trace_stride() { return kGicpTrace; }
+int gicp_max_k() { return kGicpMaxK; }
+
+void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam& cam, int k, double* set,
+                         hipStream_t s) {
+    const int n = gicp_grid_points(H, W, R);
+    const dim3 grid(gicp_blocks(n)), blk(256);
+    hipLaunchKernelGGL(k_gicp_points, grid, blk, 0, s, depth, H, W, R, (double)cam.fx, (double)cam.fy,
+                       (double)cam.cx, (double)cam.cy, set, n);
+    hipLaunchKernelGGL(k_gicp_prepare, grid, blk, 0, s, k, set, n);
+}
+
+void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, int k, const double* pose,
+                           double* part, int* corr, hipStream_t s) {
+    hipLaunchKernelGGL(k_gicp_linearise, dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tgt, nt, k, pose, part,
+                       corr);
+}
+
+void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gicp_sum, dim3(1), dim3(64), 0, s, part, nb, out);
+}
+
+void launch_gicp_solve(const double* part, int nb, double* pose, double* trace, int it, hipStream_t s) {
+    hipLaunchKernelGGL(k_gicp_solve, dim3(1), dim3(64), 0, s, part, nb, pose, trace, it);
+}
+
+}  // namespace sgad

@@ -28,6 +28,16 @@ void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const floa
                hipStream_t s);
 int l1_blocks(int P);
 size_t ssim_map_bytes(int n_jobs, int H, int W);
+int gicp_grid_points(int H, int W, int R);
+int gicp_blocks(int n);
+int gicp_vals();
+int gicp_max_k();
+void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam& cam, int k, double* set,
+                         hipStream_t s);
+void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, int k, const double* pose,
+                           double* part, int* corr, hipStream_t s);
+void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s);
+void launch_gicp_solve(const double* part, int nb, double* pose, double* trace, int it, hipStream_t s);
 void launch_ssim(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
                  float* g_rgb, double* loss, hipStream_t s);
 void launch_adam(AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
@@ -149,6 +159,7 @@ struct sgad_ctx {
     DevBuf scratch;  // small per-context scratch (loss counters)
     DevBuf conv_part;  // conv weight-gradient partial sums (one row per workgroup)
     DevBuf ssim_maps;  // SSIM partial-derivative maps of the loss call ([n_jobs * 3][3][H][W] floats)
+    DevBuf gicp_part;  // GICP per-block partial sums of the normal equations
     float* conv_scratch = nullptr;  // this device's static partial-sum rows (sgad_conv3x3_wgrad_noalloc)
     struct Track {
         bool sized = false;
@@ -545,6 +556,7 @@ void sgad_destroy(sgad_ctx* c) {
     if (c->scratch.p) (void)hipFree(c->scratch.p);
     if (c->conv_part.p) (void)hipFree(c->conv_part.p);
     if (c->ssim_maps.p) (void)hipFree(c->ssim_maps.p);
+    if (c->gicp_part.p) (void)hipFree(c->gicp_part.p);
     {
         auto& T = c->track;
         for (DevBuf* b : {&T.params, &T.pre, &T.tiles, &T.keys, &T.part, &T.status, &T.trace})
@@ -1028,6 +1040,75 @@ sgad_status sgad_eq1_loss(sgad_ctx* c, int n_jobs, int H, int W, const float* rg
     if (w_ssim != 0.f) {
         TimeScope ts(c, "ssim_loss", s);
         launch_ssim(n_jobs, H, W, rgb, t_rgb, w_ssim, c->ssim_maps.p, g_rgb, loss, s);
+    }
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+int32_t sgad_gicp_set_size(int H, int W, int ratio) {
+    if (H < 1 || W < 1 || ratio < 1) return -1;
+    const int64_t n = (int64_t)((H + ratio - 1) / ratio) * ((W + ratio - 1) / ratio);
+    return n > (int64_t)INT32_MAX / 12 ? -1 : (int32_t)n;
+}
+
+sgad_status sgad_gicp_prepare(sgad_ctx* c, const float* depth, const sgad_cam* cam, int ratio, int k, double* set,
+                              void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!depth || !cam || !set) return fail(c, SGAD_EINVAL, "null pointer");
+    if (cam->H < 1 || cam->W < 1 || ratio < 1) return fail(c, SGAD_EINVAL, "bad sizes");
+    if (!(std::isfinite(cam->fx) && std::isfinite(cam->fy) && cam->fx > 0.f && cam->fy > 0.f &&
+          std::isfinite(cam->cx) && std::isfinite(cam->cy)))
+        return fail(c, SGAD_EINVAL, "bad intrinsics");
+    if (k < 1 || k > gicp_max_k()) return fail(c, SGAD_ERANGE, "K_c must be 1..32");
+    if (sgad_gicp_set_size(cam->H, cam->W, ratio) < 1) return fail(c, SGAD_ERANGE, "set too large");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick_stream(c, stream);
+    TimeScope ts(c, "gicp_prepare", s);
+    launch_gicp_prepare(depth, cam->H, cam->W, ratio, *cam, k, set, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+static sgad_status gicp_args(sgad_ctx* c, const double* src, int n_src, const double* tgt, int n_tgt, int k,
+                             const double* pose) {
+    if (!src || !tgt || !pose) return fail(c, SGAD_EINVAL, "null pointer");
+    if (n_src < 1 || n_tgt < 1) return fail(c, SGAD_EINVAL, "empty set");
+    if (n_src > INT32_MAX / 12 || n_tgt > INT32_MAX / 12) return fail(c, SGAD_ERANGE, "set too large");
+    if (k < 1 || k > gicp_max_k()) return fail(c, SGAD_ERANGE, "K_c must be 1..32");
+    return SGAD_OK;
+}
+
+sgad_status sgad_gicp_linearise(sgad_ctx* c, const double* src, int n_src, const double* tgt, int n_tgt, int k,
+                                const double* pose, double* out, int32_t* corr, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (const sgad_status st = gicp_args(c, src, n_src, tgt, n_tgt, k, pose)) return st;
+    if (!out) return fail(c, SGAD_EINVAL, "null pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick_stream(c, stream);
+    const int nb = gicp_blocks(n_src);
+    HIPCHK(c, ensure_c(c, c->gicp_part, (size_t)nb * gicp_vals() * sizeof(double), s));
+    double* part = (double*)c->gicp_part.p;
+    TimeScope ts(c, "gicp_linearise", s);
+    launch_gicp_linearise(src, n_src, tgt, n_tgt, k, pose, part, corr, s);
+    launch_gicp_sum(part, nb, out, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_gicp_track(sgad_ctx* c, const double* src, int n_src, const double* tgt, int n_tgt, int k,
+                            double* pose, int iters, double* trace, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (const sgad_status st = gicp_args(c, src, n_src, tgt, n_tgt, k, pose)) return st;
+    if (iters < 1) return fail(c, SGAD_EINVAL, "iters must be >= 1");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick_stream(c, stream);
+    const int nb = gicp_blocks(n_src);
+    HIPCHK(c, ensure_c(c, c->gicp_part, (size_t)nb * gicp_vals() * sizeof(double), s));
+    double* part = (double*)c->gicp_part.p;
+    TimeScope ts(c, "gicp_iteration", s);
+    for (int it = 0; it < iters; ++it) {
+        launch_gicp_linearise(src, n_src, tgt, n_tgt, k, pose, part, nullptr, s);
+        launch_gicp_solve(part, nb, pose, trace, it, s);
     }
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;

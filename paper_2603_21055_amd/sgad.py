@@ -84,6 +84,10 @@ _SIGS = {
                                _P, _P]),
     "sgad_eq1_loss": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float,
                                 _P, _P, _P, _P]),
+    "sgad_gicp_set_size": (C.c_int32, [C.c_int, C.c_int, C.c_int]),
+    "sgad_gicp_prepare": (C.c_int, [_P, _P, C.c_void_p, C.c_int, C.c_int, _P, _P]),
+    "sgad_gicp_linearise": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_int, _P, _P, _P, _P]),
+    "sgad_gicp_track": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_int, _P, C.c_int, _P, _P]),
     "sgad_adam_step": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_int, C.c_float, C.c_float, C.c_float,
                                  C.c_int, _P]),
     "sgad_timing_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
@@ -383,6 +387,41 @@ class Context:
         st = self.lib.sgad_track_gn(self.h, kfa, C.byref(cam), _ptr(obs_depth), _ptr(pose), int(iters),
                                     _ptr(trace), 1 if graph else 0, _stream(stream))
         self._check(st)
+
+    # ------------------------------------------------------------------ GICP
+    def gicp_set_size(self, H, W, ratio):
+        """Points n of a frame's stride-ratio grid (a set is float64 [12, n])."""
+        return int(self.lib.sgad_gicp_set_size(int(H), int(W), int(ratio)))
+
+    def gicp_prepare(self, depth, cam, ratio, k, set_, stream=None):
+        """Build the GICP set [12, n] (float64, written) of a depth map [H, W]."""
+        import torch
+        _check_tensor(depth, "depth", self.device)
+        _check_tensor(set_, "set", self.device, torch.float64)
+        c = _cam(cam)
+        self._check(self.lib.sgad_gicp_prepare(self.h, _ptr(depth), C.byref(c), int(ratio), int(k), _ptr(set_),
+                                               _stream(stream)))
+
+    def gicp_linearise(self, src, tgt, k, pose, out, corr=None, stream=None):
+        """One linearisation of Eq. 2 at the device pose (float64 [12]): out
+        float64 [29] (H upper triangle, g, cost, pair count); corr int32
+        [n_src] or None."""
+        import torch
+        for name, t in (("src", src), ("tgt", tgt), ("pose", pose), ("out", out)):
+            _check_tensor(t, name, self.device, torch.float64)
+        _check_tensor(corr, "corr", self.device, torch.int32)
+        self._check(self.lib.sgad_gicp_linearise(self.h, _ptr(src), src.shape[1], _ptr(tgt), tgt.shape[1],
+                                                 int(k), _ptr(pose), _ptr(out), _ptr(corr), _stream(stream)))
+
+    def gicp_track(self, src, tgt, k, pose, iters, trace=None, stream=None):
+        """`iters` Gauss-Newton steps on the device pose (float64 [12], in
+        place); trace float64 [iters, 48] or None."""
+        import torch
+        for name, t in (("src", src), ("tgt", tgt), ("pose", pose)):
+            _check_tensor(t, name, self.device, torch.float64)
+        _check_tensor(trace, "trace", self.device, torch.float64)
+        self._check(self.lib.sgad_gicp_track(self.h, _ptr(src), src.shape[1], _ptr(tgt), tgt.shape[1], int(k),
+                                             _ptr(pose), int(iters), _ptr(trace), _stream(stream)))
 
     # -------------------------------------------------------------- conv net
     def conv_weights(self, cin, cout, w, w_bf16, wt_bf16=None, stream=None):

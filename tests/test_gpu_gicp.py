@@ -1,0 +1,178 @@
+"""GPU parity of GICP tracking (Sec. 3.3, Eq. 2) against the FP64 oracle
+through the C ABI: the prepared sets (points bit-exact, normalised
+covariances and normals), one linearisation at a perturbed pose
+(correspondences bit-exact except near-ties the oracle flags, the normal
+equations to FP64 summation-order rounding), and the Gauss-Newton loop
+(the oracle's pose trace; recovery of the true motion)."""
+import numpy as np
+import pytest
+
+from oracle import gicp, se3
+from paper_2603_21055_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+K = 10
+
+
+def _corner_pair(seed, W, H, trans=0.03, deg=2.0):
+    rng = np.random.default_rng(seed)
+    room = synth.make_room(rng)
+    cam = synth.intrinsics(W, H)
+    R0, t0 = synth.corner_pose(room)
+    d0, _ = room.raycast(cam, R0, t0)
+    Rg, tg = synth.perturb_pose(R0, t0, rng, trans, deg, exact=True)
+    d1, _ = room.raycast(cam, Rg, tg)
+    Rc = np.asarray(R0, np.float64) @ np.asarray(Rg, np.float64).T
+    tc = np.asarray(t0, np.float64) - Rc @ np.asarray(tg, np.float64)
+    return cam, d0.astype(np.float32), d1.astype(np.float32), Rc, tc
+
+
+def _prepare(ctx, depth, cam, ratio):
+    import torch
+    n = ctx.gicp_set_size(cam["H"], cam["W"], ratio)
+    s = torch.full((12, n), float("nan"), dtype=torch.float64, device=ctx.device)
+    ctx.gicp_prepare(torch.from_numpy(depth).to(ctx.device), cam, ratio, K, s)
+    return s
+
+
+def _grid_pixels(cam, ratio):
+    H, W = cam["H"], cam["W"]
+    vs, us = np.mgrid[0:H:ratio, 0:W:ratio]
+    return (vs * W + us).ravel()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2603_21055_amd import sgad
+    assert torch.cuda.is_available()
+    c = sgad.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("W,H,ratio", [(200, 150, 4), (1200, 680, 10)])
+def test_prepare_matches_oracle(ctx, W, H, ratio):
+    import torch
+    print(f"gicp prepare {W}x{H} R={ratio}", flush=True)
+    cam, d0, _, _, _ = _corner_pair(40 + ratio, W, H)
+    d0[::7, ::11] = 0.0                                  # pixels without depth
+    s = _prepare(ctx, d0, cam, ratio)
+    torch.cuda.synchronize()
+    got = s.cpu().numpy()
+    pts, pix = gicp.sample_points(d0, cam, ratio)
+    orc = gicp.local_gaussians(pts, K)
+    grid = _grid_pixels(cam, ratio)
+    pos = {p: i for i, p in enumerate(grid)}
+    idx = np.array([pos[p] for p in pix])
+    invalid = np.setdiff1d(np.arange(len(grid)), idx)
+    assert len(invalid) > 0 and (got[:, invalid] == 0).all()
+    # points: the same FP64 expression on both sides
+    assert (got[:3, idx].T == pts).all()
+    C = got[3:9, idx].T
+    Co = orc["cov"]
+    Co6 = np.stack([Co[:, 0, 0], Co[:, 0, 1], Co[:, 0, 2], Co[:, 1, 1], Co[:, 1, 2], Co[:, 2, 2]], 1)
+    err = np.abs(C - Co6).max()
+    print(f"normalised covariance max abs error {err:.3g}", flush=True)
+    assert err <= 1e-7
+    dots = np.abs((got[9:12, idx].T * orc["normal"]).sum(1))
+    # normals up to sign, where the two smallest eigenvalues are apart
+    lam = orc["eig"]
+    sep = (lam[:, 1] - lam[:, 0]) > 1e-3 * lam[:, 2]
+    assert sep.mean() > 0.9
+    assert (dots[sep] >= 1 - 1e-7).all(), float(dots[sep].min())
+
+
+def _oracle_set(depth, cam, ratio):
+    """The oracle's own set of a frame and the grid index of each of its points."""
+    pts, pix = gicp.sample_points(depth, cam, ratio)
+    grid = _grid_pixels(cam, ratio)
+    pos = {p: i for i, p in enumerate(grid)}
+    return gicp.local_gaussians(pts, K), np.array([pos[p] for p in pix])
+
+
+@pytest.mark.parametrize("W,H,ratio", [(200, 150, 4), (1200, 680, 10)])
+def test_linearise_matches_oracle(ctx, W, H, ratio):
+    """At a pose half-way to the true motion.  Near-ties flagged at a relative
+    gap of 1e-8: the two sides' normals and covariances agree to ~1e-10."""
+    import torch
+    print(f"gicp linearise {W}x{H} R={ratio}", flush=True)
+    cam, d0, d1, Rc, tc = _corner_pair(50 + ratio, W, H)
+    dev = ctx.device
+    tgt = _prepare(ctx, d0, cam, ratio)
+    src = _prepare(ctx, d1, cam, ratio)
+    T = np.eye(4)
+    T[:3, :3], T[:3, 3] = Rc, tc
+    Th = se3.exp(0.5 * se3.log(T))
+    Rp, tp = Th[:3, :3], Th[:3, 3]
+    pose = torch.from_numpy(np.concatenate([Rp.ravel(), tp])).to(dev)
+    ns = src.shape[1]
+    out = torch.zeros(29, dtype=torch.float64, device=dev)
+    corr = torch.full((ns,), -7, dtype=torch.int32, device=dev)
+    ctx.gicp_linearise(src, tgt, K, pose, out, corr)
+    torch.cuda.synchronize()
+    got_corr = corr.cpu().numpy()
+    o = out.cpu().numpy()
+    so, sidx = _oracle_set(d1, cam, ratio)
+    to, tidx = _oracle_set(d0, cam, ratio)
+    j, X, gaps = gicp.correspond(so, to, Rp, tp, K, with_margins=True)
+    flag = (gaps["knn"] < 1e-8) | (gaps["best"] < 1e-8) | (gaps["dmax"] < 1e-8)
+    want = np.where(j >= 0, tidx[np.maximum(j, 0)], -1)
+    assert (got_corr[np.setdiff1d(np.arange(ns), sidx)] == -1).all()
+    mism = (got_corr[sidx] != want) & ~flag
+    print(f"{len(sidx)} source points, {int(flag.sum())} flagged near-ties, {int(mism.sum())} mismatches", flush=True)
+    assert mism.sum() == 0
+    assert flag.mean() < 1e-3
+    if flag.sum() == 0:
+        lin = gicp.linearise(so, to, Rp, tp, K)
+        iu = np.triu_indices(6)
+        Ho, go = lin["H"][iu], lin["g"]
+        assert o[28] == lin["n"]
+        assert np.abs(o[:21] - Ho).max() <= 1e-8 * np.abs(Ho).max()
+        assert np.abs(o[21:27] - go).max() <= 1e-8 * np.abs(go).max()
+        assert abs(o[27] - lin["cost"]) <= 1e-8 * lin["cost"]
+
+
+def test_track_follows_oracle_and_recovers_motion(ctx):
+    """30 iterations at 1200x680, R = 10: every step's pose equals the
+    oracle's loop (to 1e-8), and the last one is within 5 mm / 0.05 degree of
+    the true 3 cm / 2 degree motion (the two frames' samples lie ~3 cm apart
+    on the walls and differ between the frames)."""
+    import torch
+    cam, d0, d1, Rc, tc = _corner_pair(60, 1200, 680)
+    dev = ctx.device
+    tgt = _prepare(ctx, d0, cam, 10)
+    src = _prepare(ctx, d1, cam, 10)
+    pose = torch.from_numpy(np.concatenate([np.eye(3).ravel(), np.zeros(3)])).to(dev)
+    trace = torch.zeros((30, 48), dtype=torch.float64, device=dev)
+    ctx.gicp_track(src, tgt, K, pose, 30, trace)
+    torch.cuda.synchronize()
+    p = pose.cpu().numpy()
+    tr = trace.cpu().numpy()
+    so, _ = _oracle_set(d1, cam, 10)
+    to, _ = _oracle_set(d0, cam, 10)
+    orc = gicp.track(so, to, np.eye(3), np.zeros(3), K, iters=30)
+    for it, o in enumerate(orc["trace"]):
+        assert np.abs(tr[it, 36:45] - o["R"].ravel()).max() < 1e-8, it
+        assert np.abs(tr[it, 45:48] - o["t"]).max() < 1e-8, it
+        assert tr[it, 28] == o["n"], it
+    R, t = p[:9].reshape(3, 3), p[9:]
+    assert np.abs(R - orc["R"]).max() < 1e-8 and np.abs(t - orc["t"]).max() < 1e-8
+    ang = np.degrees(np.arccos(np.clip((np.trace(R.T @ Rc) - 1) / 2, -1, 1)))
+    print(f"gicp: {np.linalg.norm(t - tc) * 1e3:.3f} mm, {ang:.4f} deg from the true pose", flush=True)
+    assert np.linalg.norm(t - tc) < 5e-3 and ang < 0.05
+
+
+def test_bad_arguments(ctx):
+    import torch
+    from paper_2603_21055_amd import sgad
+    cam = synth.intrinsics(64, 48)
+    d = torch.ones((48, 64), device=ctx.device)
+    n = ctx.gicp_set_size(48, 64, 4)
+    s = torch.zeros((12, n), dtype=torch.float64, device=ctx.device)
+    with pytest.raises(sgad.SgadError):
+        ctx.gicp_prepare(d, cam, 4, 33, s)          # K_c above 32
+    with pytest.raises(sgad.SgadError):
+        ctx.gicp_prepare(d, cam, 0, 10, s)          # ratio 0
+    assert ctx.gicp_set_size(48, 64, 0) == -1
