@@ -329,7 +329,7 @@ def bench_gicp(args, emit=True):
     def run():
         ctx.gicp_prepare(dd1, cam, R_s, K, src)
         pose.copy_(ident)
-        ctx.gicp_track(src, tgt, K, pose, 30)
+        ctx.gicp_track(src, tgt, cam, R_s, K, pose, 30)
 
     steps = max(1, min(args.steps, 20))
     sec = _timed(run, steps, min(args.warmup, 3))
@@ -428,9 +428,10 @@ def warm_start(ctx, log, frames, epochs=20):
     here on the offsets plain mapping converges to on the given frames."""
     from paper_2603_21055_amd import warmstart
     log(f"warm start: {len(frames)} training frames, {epochs} epochs")
-    res = warmstart.experiment(ctx, frames, epochs=epochs, map_iters=150, log=log)
+    res = warmstart.experiment(ctx, frames, epochs=epochs, map_iters=150, log=log, other_seeds=(3001, 3002))
     keep = ("plain_iters", "plain_first_loss", "warm_first_loss", "plain_final_loss", "warm_final_loss",
             "warm_iters_to_plain_level", "warm_iters_to_plain_loss", "warm_offset_lr", "offset_lr_validation",
+            "eval_seed", "other_seeds",
             "n_frames", "epochs", "seconds")
     return {k: res[k] for k in keep}
 

@@ -348,16 +348,22 @@ sgad_status sgad_gicp_prepare(sgad_ctx* ctx, const float* depth, const sgad_cam*
  * g = sum J^T M (b - X) (6), the cost sum e^T M e and the pair count,
  * WRITTEN.  corr (device int32[n_src], may be NULL): the matched target index
  * per source point, -1 for none.  Uses a context workspace of 29 doubles per
- * 256 source points. */
-sgad_status sgad_gicp_linearise(sgad_ctx* ctx, const double* src, int n_src, const double* tgt, int n_tgt, int k,
-                                const double* pose, double* out, int32_t* corr, void* stream);
+ * 256 source points.  tgt_cam / tgt_ratio: the camera and stride the target
+ * set was prepared with (SGAD_EINVAL unless they give n_tgt grid points): the
+ * neighbour search first scans the grid cells around the one X projects to
+ * and falls back to all target points unless that window provably holds the
+ * K_c nearest. */
+sgad_status sgad_gicp_linearise(sgad_ctx* ctx, const double* src, int n_src, const double* tgt, int n_tgt,
+                                const sgad_cam* tgt_cam, int tgt_ratio, int k, const double* pose, double* out,
+                                int32_t* corr, void* stream);
 /* `iters` Gauss-Newton steps from the device pose (updated in place):
  * dxi = -H^-1 g by a damped Cholesky (1e-9 tr H, x10 per retry, FP64),
  * P <- Exp(dxi) P.  trace (device double[iters][48], may be NULL): per step
  * H (21), g (6), cost, pair count, damping (-1: no solve), dxi (6) and the
  * pose before the step (R 9, t 3). */
-sgad_status sgad_gicp_track(sgad_ctx* ctx, const double* src, int n_src, const double* tgt, int n_tgt, int k,
-                            double* pose, int iters, double* trace, void* stream);
+sgad_status sgad_gicp_track(sgad_ctx* ctx, const double* src, int n_src, const double* tgt, int n_tgt,
+                            const sgad_cam* tgt_cam, int tgt_ratio, int k, double* pose, int iters, double* trace,
+                            void* stream);
 
 /* One parameter tensor for sgad_adam_step (all device pointers, n floats;
  * the pointers may be null when n is 0).  Arrays that start on a 16-byte

@@ -29,7 +29,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <algorithm>
 #include <climits>
+#include <cmath>
 
 #include "sgad_internal.h"
 
@@ -88,6 +90,49 @@ __device__ __forceinline__ void topk_insert(TopK& t, int k, double d, int j) {
     t.worst_i = wi;
 }
 
+// Pixel grid a set was sampled on: camera, stride and grid size.
+struct GicpGrid {
+    double fx, fy, cx, cy;
+    int R, gw, gh;
+    double bound;   // (w + 1/2) R / max(fx, fy) / max over the image of |(x, y, 1)|, per unit depth
+};
+
+constexpr int kGicpWin = 4;   // half-width (cells) of the window searched first
+
+// The k nearest points of `set` to q among the grid cells within kGicpWin of
+// the cell q projects to.  Returns true when that is the exact answer over
+// the whole set: q projects inside the grid (within half a cell of a cell
+// centre), the window held k points, and the k-th distance is below the
+// smallest distance any point outside the window can have.  A point c on the
+// ray of a pixel p is at least |q| sin(angle(q, p)) from q; for p outside the
+// window its normalised image coordinates differ from q's by at least
+// D = (w + 1/2) R / max(fx, fy) in x or y, so |r_q x r_p| >= D and
+// |q| sin(angle) >= q_z D / |r_p| >= q_z * bound.
+__device__ bool knn_window(const double* __restrict__ set, int n, const GicpGrid& g, int k, double qx, double qy,
+                           double qz, TopK& t) {
+#pragma clang fp contract(off)
+    topk_init(t);
+    if (!(qz > 0.0)) return false;
+    const double u = g.fx * (qx / qz) + g.cx, v = g.fy * (qy / qz) + g.cy;
+    const double gu = rint(u / g.R), gv = rint(v / g.R);
+    if (!(gu >= 0.0 && gu <= g.gw - 1 && gv >= 0.0 && gv <= g.gh - 1)) return false;
+    if (fabs(u - gu * g.R) > 0.5 * g.R || fabs(v - gv * g.R) > 0.5 * g.R) return false;
+    const int cu = (int)gu, cv = (int)gv;
+    int found = 0;
+    for (int j = max(0, cv - kGicpWin); j <= min(g.gh - 1, cv + kGicpWin); ++j)
+        for (int i = max(0, cu - kGicpWin); i <= min(g.gw - 1, cu + kGicpWin); ++i) {
+            const int c = j * g.gw + i;
+            const double pz = set[2 * (size_t)n + c];
+            if (pz == 0.0) continue;
+            ++found;
+            const double dx = qx - set[c], dy = qy - set[(size_t)n + c], dz = qz - pz;
+            const double d = (dx * dx + dy * dy) + dz * dz;
+            if (d < t.worst || (d == t.worst && c < t.worst_i)) topk_insert(t, k, d, c);
+        }
+    const double lb = qz * g.bound;
+    return found >= k && t.worst < lb * lb * (1.0 - 1e-12);
+}
+
 // The k nearest points of `set` (n points) to q, over LDS tiles.  Every
 // thread of the block takes part in the staging (valid or not).  The tiles
 // are visited outward from tile `home` (home, home + 1, home - 1, ...): sets
@@ -96,7 +141,7 @@ __device__ __forceinline__ void topk_insert(TopK& t, int k, double d, int j) {
 __device__ void knn_scan(const double* __restrict__ set, int n, int k, double qx, double qy, double qz, bool active,
                          TopK& t, double (*s_p)[kGicpTile], int home) {
 #pragma clang fp contract(off)
-    topk_init(t);
+    if (active) topk_init(t);
     const int ntile = (n + kGicpTile - 1) / kGicpTile;
     home = min(max(home, 0), ntile - 1);
     for (int step = 0; step < 2 * ntile; ++step) {
@@ -165,7 +210,7 @@ __device__ void jacobi3(double* a, double* w, double* v) {
 }
 
 // Runs after k_gicp_points: reads the coordinate rows, writes rows 3..11.
-__global__ __launch_bounds__(256) void k_gicp_prepare(int k, double* __restrict__ set, int n) {
+__global__ __launch_bounds__(256) void k_gicp_prepare(int k, double* __restrict__ set, int n, GicpGrid grid) {
 #pragma clang fp contract(off)
     __shared__ double s_p[3][kGicpTile];
     const int g = (int)blockIdx.x * blockDim.x + threadIdx.x;
@@ -178,7 +223,9 @@ __global__ __launch_bounds__(256) void k_gicp_prepare(int k, double* __restrict_
     }
     const bool active = in && qz != 0.0;
     TopK t;
-    knn_scan(set, n, k, qx, qy, qz, active, t, s_p, (int)blockIdx.x * (int)blockDim.x / kGicpTile);
+    const bool exact = active && knn_window(set, n, grid, k, qx, qy, qz, t);
+    if (__syncthreads_or(active && !exact))
+        knn_scan(set, n, k, qx, qy, qz, active && !exact, t, s_p, (int)blockIdx.x * (int)blockDim.x / kGicpTile);
     if (!active) {
         if (in)
             for (int r = 3; r < 12; ++r) set[(size_t)r * n + g] = 0.0;
@@ -273,9 +320,9 @@ __global__ __launch_bounds__(256) void k_gicp_points(const float* __restrict__ d
 
 // Pose P = (R row-major, t) at pose[0..11].
 __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict__ src, int ns,
-                                                        const double* __restrict__ tgt, int nt, int k,
-                                                        const double* __restrict__ pose, double* __restrict__ part,
-                                                        int* __restrict__ corr) {
+                                                        const double* __restrict__ tgt, int nt, GicpGrid tgrid,
+                                                        int k, const double* __restrict__ pose,
+                                                        double* __restrict__ part, int* __restrict__ corr) {
 #pragma clang fp contract(off)
     __shared__ double s_p[3][kGicpTile];
     __shared__ double s_acc[4][kGicpVals];
@@ -297,9 +344,11 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
     const double X1 = ((Rm[3] * a0 + Rm[4] * a1) + Rm[5] * a2) + tv[1];
     const double X2 = ((Rm[6] * a0 + Rm[7] * a1) + Rm[8] * a2) + tv[2];
     TopK t;
+    const bool exact = active && knn_window(tgt, nt, tgrid, k, X0, X1, X2, t);
     // source and target grids cover the same image region for small motions
-    knn_scan(tgt, nt, k, X0, X1, X2, active, t, s_p,
-             (int)((long long)blockIdx.x * blockDim.x * nt / ((long long)ns * kGicpTile)));
+    if (__syncthreads_or(active && !exact))
+        knn_scan(tgt, nt, k, X0, X1, X2, active && !exact, t, s_p,
+                 (int)((long long)blockIdx.x * blockDim.x * nt / ((long long)ns * kGicpTile)));
     double acc[kGicpVals];
 #pragma unroll
     for (int q = 0; q < kGicpVals; ++q) acc[q] = 0.0;
@@ -514,6 +563,27 @@ __global__ void k_gicp_solve(const double* part, int nb, double* pose, double* t
 }
 
 int gicp_grid_points(int H, int W, int R) { return ((H + R - 1) / R) * ((W + R - 1) / R); }
+
+static GicpGrid gicp_grid(const sgad_cam& cam, int R) {
+    GicpGrid g;
+    g.fx = cam.fx;
+    g.fy = cam.fy;
+    g.cx = cam.cx;
+    g.cy = cam.cy;
+    g.R = R;
+    g.gw = (cam.W + R - 1) / R;
+    g.gh = (cam.H + R - 1) / R;
+    // the largest |(x, y, 1)| over the image is at a corner
+    double m = 0.0;
+    for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+            const double x = ((double)(cx ? cam.W - 1 : 0) - g.cx) / g.fx;
+            const double y = ((double)(cy ? cam.H - 1 : 0) - g.cy) / g.fy;
+            m = std::max(m, std::sqrt(1.0 + x * x + y * y));
+        }
+    g.bound = (kGicpWin + 0.5) * R / std::max(g.fx, g.fy) / m;
+    return g;
+}
 int gicp_blocks(int n) { return (n + 255) / 256; }
 int gicp_vals() { return kGicpVals; }
 int gicp_trace_stride() { return kGicpTrace; }
@@ -525,13 +595,13 @@ void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam
     const dim3 grid(gicp_blocks(n)), blk(256);
     hipLaunchKernelGGL(k_gicp_points, grid, blk, 0, s, depth, H, W, R, (double)cam.fx, (double)cam.fy,
                        (double)cam.cx, (double)cam.cy, set, n);
-    hipLaunchKernelGGL(k_gicp_prepare, grid, blk, 0, s, k, set, n);
+    hipLaunchKernelGGL(k_gicp_prepare, grid, blk, 0, s, k, set, n, gicp_grid(cam, R));
 }
 
-void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, int k, const double* pose,
-                           double* part, int* corr, hipStream_t s) {
-    hipLaunchKernelGGL(k_gicp_linearise, dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tgt, nt, k, pose, part,
-                       corr);
+void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, const sgad_cam& tcam, int tR,
+                           int k, const double* pose, double* part, int* corr, hipStream_t s) {
+    hipLaunchKernelGGL(k_gicp_linearise, dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tgt, nt,
+                       gicp_grid(tcam, tR), k, pose, part, corr);
 }
 
 void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s) {

@@ -34,8 +34,8 @@ int gicp_vals();
 int gicp_max_k();
 void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam& cam, int k, double* set,
                          hipStream_t s);
-void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, int k, const double* pose,
-                           double* part, int* corr, hipStream_t s);
+void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, const sgad_cam& tcam, int tR,
+                           int k, const double* pose, double* part, int* corr, hipStream_t s);
 void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s);
 void launch_gicp_solve(const double* part, int nb, double* pose, double* trace, int it, hipStream_t s);
 void launch_ssim(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
@@ -1069,19 +1069,25 @@ sgad_status sgad_gicp_prepare(sgad_ctx* c, const float* depth, const sgad_cam* c
     return SGAD_OK;
 }
 
-static sgad_status gicp_args(sgad_ctx* c, const double* src, int n_src, const double* tgt, int n_tgt, int k,
-                             const double* pose) {
-    if (!src || !tgt || !pose) return fail(c, SGAD_EINVAL, "null pointer");
+static sgad_status gicp_args(sgad_ctx* c, const double* src, int n_src, const double* tgt, int n_tgt,
+                             const sgad_cam* tcam, int tratio, int k, const double* pose) {
+    if (!src || !tgt || !pose || !tcam) return fail(c, SGAD_EINVAL, "null pointer");
     if (n_src < 1 || n_tgt < 1) return fail(c, SGAD_EINVAL, "empty set");
     if (n_src > INT32_MAX / 12 || n_tgt > INT32_MAX / 12) return fail(c, SGAD_ERANGE, "set too large");
     if (k < 1 || k > gicp_max_k()) return fail(c, SGAD_ERANGE, "K_c must be 1..32");
+    if (tratio < 1 || sgad_gicp_set_size(tcam->H, tcam->W, tratio) != n_tgt)
+        return fail(c, SGAD_EINVAL, "target camera and ratio do not give n_tgt grid points");
+    if (!(std::isfinite(tcam->fx) && std::isfinite(tcam->fy) && tcam->fx > 0.f && tcam->fy > 0.f &&
+          std::isfinite(tcam->cx) && std::isfinite(tcam->cy)))
+        return fail(c, SGAD_EINVAL, "bad intrinsics");
     return SGAD_OK;
 }
 
-sgad_status sgad_gicp_linearise(sgad_ctx* c, const double* src, int n_src, const double* tgt, int n_tgt, int k,
-                                const double* pose, double* out, int32_t* corr, void* stream) {
+sgad_status sgad_gicp_linearise(sgad_ctx* c, const double* src, int n_src, const double* tgt, int n_tgt,
+                                const sgad_cam* tgt_cam, int tgt_ratio, int k, const double* pose, double* out,
+                                int32_t* corr, void* stream) {
     if (!c) return SGAD_EINVAL;
-    if (const sgad_status st = gicp_args(c, src, n_src, tgt, n_tgt, k, pose)) return st;
+    if (const sgad_status st = gicp_args(c, src, n_src, tgt, n_tgt, tgt_cam, tgt_ratio, k, pose)) return st;
     if (!out) return fail(c, SGAD_EINVAL, "null pointer");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
@@ -1089,16 +1095,17 @@ sgad_status sgad_gicp_linearise(sgad_ctx* c, const double* src, int n_src, const
     HIPCHK(c, ensure_c(c, c->gicp_part, (size_t)nb * gicp_vals() * sizeof(double), s));
     double* part = (double*)c->gicp_part.p;
     TimeScope ts(c, "gicp_linearise", s);
-    launch_gicp_linearise(src, n_src, tgt, n_tgt, k, pose, part, corr, s);
+    launch_gicp_linearise(src, n_src, tgt, n_tgt, *tgt_cam, tgt_ratio, k, pose, part, corr, s);
     launch_gicp_sum(part, nb, out, s);
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
 }
 
-sgad_status sgad_gicp_track(sgad_ctx* c, const double* src, int n_src, const double* tgt, int n_tgt, int k,
-                            double* pose, int iters, double* trace, void* stream) {
+sgad_status sgad_gicp_track(sgad_ctx* c, const double* src, int n_src, const double* tgt, int n_tgt,
+                            const sgad_cam* tgt_cam, int tgt_ratio, int k, double* pose, int iters, double* trace,
+                            void* stream) {
     if (!c) return SGAD_EINVAL;
-    if (const sgad_status st = gicp_args(c, src, n_src, tgt, n_tgt, k, pose)) return st;
+    if (const sgad_status st = gicp_args(c, src, n_src, tgt, n_tgt, tgt_cam, tgt_ratio, k, pose)) return st;
     if (iters < 1) return fail(c, SGAD_EINVAL, "iters must be >= 1");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
@@ -1107,7 +1114,7 @@ sgad_status sgad_gicp_track(sgad_ctx* c, const double* src, int n_src, const dou
     double* part = (double*)c->gicp_part.p;
     TimeScope ts(c, "gicp_iteration", s);
     for (int it = 0; it < iters; ++it) {
-        launch_gicp_linearise(src, n_src, tgt, n_tgt, k, pose, part, nullptr, s);
+        launch_gicp_linearise(src, n_src, tgt, n_tgt, *tgt_cam, tgt_ratio, k, pose, part, nullptr, s);
         launch_gicp_solve(part, nb, pose, trace, it, s);
     }
     HIPCHK(c, hipGetLastError());

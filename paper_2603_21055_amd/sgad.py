@@ -86,8 +86,10 @@ _SIGS = {
                                 _P, _P, _P, _P]),
     "sgad_gicp_set_size": (C.c_int32, [C.c_int, C.c_int, C.c_int]),
     "sgad_gicp_prepare": (C.c_int, [_P, _P, C.c_void_p, C.c_int, C.c_int, _P, _P]),
-    "sgad_gicp_linearise": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_int, _P, _P, _P, _P]),
-    "sgad_gicp_track": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_int, _P, C.c_int, _P, _P]),
+    "sgad_gicp_linearise": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_void_p, C.c_int, C.c_int, _P, _P, _P,
+                                      _P]),
+    "sgad_gicp_track": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_void_p, C.c_int, C.c_int, _P, C.c_int, _P,
+                                  _P]),
     "sgad_adam_step": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_int, C.c_float, C.c_float, C.c_float,
                                  C.c_int, _P]),
     "sgad_timing_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
@@ -402,26 +404,30 @@ class Context:
         self._check(self.lib.sgad_gicp_prepare(self.h, _ptr(depth), C.byref(c), int(ratio), int(k), _ptr(set_),
                                                _stream(stream)))
 
-    def gicp_linearise(self, src, tgt, k, pose, out, corr=None, stream=None):
+    def gicp_linearise(self, src, tgt, tgt_cam, ratio, k, pose, out, corr=None, stream=None):
         """One linearisation of Eq. 2 at the device pose (float64 [12]): out
         float64 [29] (H upper triangle, g, cost, pair count); corr int32
-        [n_src] or None."""
+        [n_src] or None; tgt_cam / ratio: the target set's camera and stride."""
         import torch
         for name, t in (("src", src), ("tgt", tgt), ("pose", pose), ("out", out)):
             _check_tensor(t, name, self.device, torch.float64)
         _check_tensor(corr, "corr", self.device, torch.int32)
+        c = _cam(tgt_cam)
         self._check(self.lib.sgad_gicp_linearise(self.h, _ptr(src), src.shape[1], _ptr(tgt), tgt.shape[1],
-                                                 int(k), _ptr(pose), _ptr(out), _ptr(corr), _stream(stream)))
+                                                 C.byref(c), int(ratio), int(k), _ptr(pose), _ptr(out), _ptr(corr),
+                                                 _stream(stream)))
 
-    def gicp_track(self, src, tgt, k, pose, iters, trace=None, stream=None):
+    def gicp_track(self, src, tgt, tgt_cam, ratio, k, pose, iters, trace=None, stream=None):
         """`iters` Gauss-Newton steps on the device pose (float64 [12], in
         place); trace float64 [iters, 48] or None."""
         import torch
         for name, t in (("src", src), ("tgt", tgt), ("pose", pose)):
             _check_tensor(t, name, self.device, torch.float64)
         _check_tensor(trace, "trace", self.device, torch.float64)
-        self._check(self.lib.sgad_gicp_track(self.h, _ptr(src), src.shape[1], _ptr(tgt), tgt.shape[1], int(k),
-                                             _ptr(pose), int(iters), _ptr(trace), _stream(stream)))
+        c = _cam(tgt_cam)
+        self._check(self.lib.sgad_gicp_track(self.h, _ptr(src), src.shape[1], _ptr(tgt), tgt.shape[1], C.byref(c),
+                                             int(ratio), int(k), _ptr(pose), int(iters), _ptr(trace),
+                                             _stream(stream)))
 
     # -------------------------------------------------------------- conv net
     def conv_weights(self, cin, cout, w, w_bf16, wt_bf16=None, stream=None):

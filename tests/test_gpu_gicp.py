@@ -52,12 +52,16 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("W,H,ratio", [(200, 150, 4), (1200, 680, 10)])
-def test_prepare_matches_oracle(ctx, W, H, ratio):
+@pytest.mark.parametrize("W,H,ratio,sparse", [(200, 150, 4, False), (1200, 680, 10, False), (200, 150, 2, True)])
+def test_prepare_matches_oracle(ctx, W, H, ratio, sparse):
+    """sparse: 90 % of the pixels without depth, so most neighbour searches
+    leave the window around their own cell for the scan over all points."""
     import torch
-    print(f"gicp prepare {W}x{H} R={ratio}", flush=True)
+    print(f"gicp prepare {W}x{H} R={ratio} sparse={sparse}", flush=True)
     cam, d0, _, _, _ = _corner_pair(40 + ratio, W, H)
     d0[::7, ::11] = 0.0                                  # pixels without depth
+    if sparse:
+        d0[np.random.default_rng(3).uniform(size=d0.shape) < 0.9] = 0.0
     s = _prepare(ctx, d0, cam, ratio)
     torch.cuda.synchronize()
     got = s.cpu().numpy()
@@ -110,7 +114,7 @@ def test_linearise_matches_oracle(ctx, W, H, ratio):
     ns = src.shape[1]
     out = torch.zeros(29, dtype=torch.float64, device=dev)
     corr = torch.full((ns,), -7, dtype=torch.int32, device=dev)
-    ctx.gicp_linearise(src, tgt, K, pose, out, corr)
+    ctx.gicp_linearise(src, tgt, cam, ratio, K, pose, out, corr)
     torch.cuda.synchronize()
     got_corr = corr.cpu().numpy()
     o = out.cpu().numpy()
@@ -146,7 +150,7 @@ def test_track_follows_oracle_and_recovers_motion(ctx):
     src = _prepare(ctx, d1, cam, 10)
     pose = torch.from_numpy(np.concatenate([np.eye(3).ravel(), np.zeros(3)])).to(dev)
     trace = torch.zeros((30, 48), dtype=torch.float64, device=dev)
-    ctx.gicp_track(src, tgt, K, pose, 30, trace)
+    ctx.gicp_track(src, tgt, cam, 10, K, pose, 30, trace)
     torch.cuda.synchronize()
     p = pose.cpu().numpy()
     tr = trace.cpu().numpy()
