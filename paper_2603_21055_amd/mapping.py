@@ -85,6 +85,7 @@ class Mapper:
 
     def __init__(self, ctx, kfs, views, jobs, learnable, t_rgb, t_depth, with_count=False, lr=None,
                  w_ssim=W_SSIM):
+        """lr: learning rates per parameter group (default the supplement's)."""
         import torch
         self.w_ssim = float(w_ssim)
         self.ctx, self.kfs, self.views, self.jobs = ctx, kfs, views, jobs

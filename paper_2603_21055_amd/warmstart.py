@@ -11,10 +11,17 @@ up to 2 cm / 1 degree.  The network sees (R, G, B, h) with h the noisy depth min
 local 3x3 mean, in units of 2 cm.
 
 Evaluation: an 8-keyframe 640x480 window with the same depth noise, every
-view rendering all keyframes; plain mapping starts from zero offsets, warm
-mapping from the network's prediction; reported are the plain loss after
-`plain_iters` iterations and the first iteration at which the warm run's loss
-is at or below it.
+view rendering all keyframes; plain mapping starts from zero offsets at the
+supplement's learning rates, warm mapping from the network's prediction;
+reported are the plain loss after `plain_iters` iterations and the first
+iteration at which the warm run's loss is at or below it.
+
+Adam moves every parameter by about its learning rate in its first steps
+whatever the gradient, so the supplement's 1 cm offset step undoes a
+prediction that is already closer than that.  The warm start therefore comes
+with its own offset step size, a hyperparameter of the warm start chosen on
+a validation window (a different seed from the evaluation window): the
+candidate with the lowest loss after the selection horizon.
 """
 from __future__ import annotations
 
@@ -61,11 +68,14 @@ def _gen(args):
     return training_frame(*args)
 
 
-def make_frames(seeds, workers: int = 8):
+def make_frames(seeds, workers: int = 8, start: str = "fork"):
+    """Training frames on `workers` CPU processes; start="spawn" starts fresh
+    interpreters (for a caller that has already opened the GPU, which must
+    not fork)."""
     if workers <= 1:
         return [training_frame(s) for s in seeds]
-    from multiprocessing import Pool
-    with Pool(workers) as p:
+    import multiprocessing
+    with multiprocessing.get_context(start).Pool(workers) as p:
         return p.map(_gen, [(s,) for s in seeds])
 
 
@@ -115,9 +125,10 @@ def eval_window(seed: int = 3000, W: int = 640, H: int = 480, n: int = 8) -> dic
     return sc
 
 
-def mapping_curve(ctx, sc, net, iters: int):
+def mapping_curve(ctx, sc, net, iters: int, lr=None):
     """Loss after each of `iters` mapping iterations of the whole window; the
-    offsets start at zero (net None) or at the network's prediction."""
+    offsets start at zero (net None) or at the network's prediction; lr:
+    learning rates per parameter group (default: the supplement's)."""
     import torch
     dev = ctx.device
     kfs = [sgad.to_device(k, dev) for k in sc["kfs"]]
@@ -128,7 +139,7 @@ def mapping_curve(ctx, sc, net, iters: int):
     t_rgb = torch.from_numpy(np.stack([t["rgb"] for t in sc["targets"]])).to(dev)
     t_dep = torch.from_numpy(np.stack([t["depth"] for t in sc["targets"]])).to(dev)
     jobs = [(v, list(range(n))) for v in range(n)]
-    m = Mapper(ctx, kfs, sc["views"], jobs, list(range(n)), t_rgb, t_dep)
+    m = Mapper(ctx, kfs, sc["views"], jobs, list(range(n)), t_rgb, t_dep, lr=lr)
     curve = torch.zeros(iters, dtype=torch.float64, device=dev)
     for i in range(iters):
         m.step()
@@ -137,8 +148,31 @@ def mapping_curve(ctx, sc, net, iters: int):
     return curve.cpu().numpy()
 
 
+OFFSET_STEPS = (0.01, 0.005, 0.003, 0.002)   # candidate warm-start offset learning rates (m)
+
+
+def select_offset_lr(ctx, net, seed=2990, size=(640, 480), n=4, iters=30, candidates=OFFSET_STEPS):
+    """Offset learning rate of warm-started mapping: the candidate whose run
+    on a validation window (seed `seed`, never the evaluation window) ends
+    with the lowest loss after `iters` iterations.  Returns (lr, losses)."""
+    from .mapping import LR
+    sc = eval_window(seed, W=size[0], H=size[1], n=n)
+    losses = {}
+    for lr in candidates:
+        losses[lr] = float(mapping_curve(ctx, sc, net, iters, lr=dict(LR, offset=lr))[-1])
+    best = min(candidates, key=lambda c: losses[c])
+    return best, losses
+
+
+def iters_to_level(plain, warm, k):
+    """First iteration (1-based) at which the warm curve is at or below the
+    plain curve's loss after k iterations, or None."""
+    hit = np.nonzero(warm <= plain[k - 1])[0]
+    return int(hit[0]) + 1 if len(hit) else None
+
+
 def experiment(ctx, frames, epochs=20, batch=8, map_iters=200, plain_iters=50, log=print,
-               eval_seed=3000, eval_size=(640, 480)):
+               eval_seed=3000, eval_size=(640, 480), eval_n=8, select=True, other_seeds=()):
     """frames: from make_frames (generated before the device is opened, so the
     worker processes never inherit a device context)."""
     t0 = time.time()
@@ -152,22 +186,33 @@ def experiment(ctx, frames, epochs=20, batch=8, map_iters=200, plain_iters=50, l
             log(f"  {i + 1} frames ({time.time() - t0:.0f} s)")
     log("training")
     net, hist = train(ctx, data, epochs=epochs, batch=batch, log=log)
+    from .mapping import LR
+    warm_lr = LR["offset"]
+    sel = {}
+    if select:
+        warm_lr, sel = select_offset_lr(ctx, net)
+        log(f"warm-start offset learning rate {warm_lr} (validation losses {sel})")
     log("evaluating")
-    sc = eval_window(eval_seed, W=eval_size[0], H=eval_size[1])
+    sc = eval_window(eval_seed, W=eval_size[0], H=eval_size[1], n=eval_n)
     plain = mapping_curve(ctx, sc, None, plain_iters)
-    warm = mapping_curve(ctx, sc, net, plain_iters)
+    warm = mapping_curve(ctx, sc, net, plain_iters, lr=dict(LR, offset=warm_lr))
     # iterations the warm start needs to reach the loss plain mapping has after
     # k iterations, for several k
-    levels = {}
-    for k in (2, 5, 10, 20, plain_iters):
-        hit = np.nonzero(warm <= plain[k - 1])[0]
-        levels[str(k)] = int(hit[0]) + 1 if len(hit) else None
+    levels = {str(k): iters_to_level(plain, warm, k) for k in (2, 5, 10, 20, plain_iters)}
     target = plain[-1]
-    hit = np.nonzero(warm <= target)[0]
-    warm_iters = int(hit[0]) + 1 if len(hit) else None
+    warm_iters = iters_to_level(plain, warm, plain_iters)
+    # the same comparison on further evaluation windows (other seeds)
+    others = {}
+    for sd in other_seeds:
+        sc2 = eval_window(sd, W=eval_size[0], H=eval_size[1], n=eval_n)
+        p2 = mapping_curve(ctx, sc2, None, plain_iters)
+        w2 = mapping_curve(ctx, sc2, net, plain_iters, lr=dict(LR, offset=warm_lr))
+        others[str(sd)] = {str(k): iters_to_level(p2, w2, k) for k in (5, 10, 20, plain_iters)}
     return dict(plain_iters=plain_iters, plain_final_loss=float(target), warm_iters_to_plain_loss=warm_iters,
                 warm_iters_to_plain_level=levels, plain_first_loss=float(plain[0]), warm_first_loss=float(warm[0]),
                 warm_final_loss=float(warm[-1]), plain_curve=plain.tolist(), warm_curve=warm.tolist(),
+                warm_offset_lr=warm_lr, offset_lr_validation={str(k): v for k, v in sel.items()},
+                eval_seed=eval_seed, other_seeds=others,
                 train_loss=hist, n_frames=n_frames, epochs=epochs, seconds=time.time() - t0)
 
 

@@ -1,28 +1,37 @@
-"""Learned offset warm start end to end at a small scale: offsets the method
-converges to on synthetic frames train the conv net, whose prediction must
-start mapping of an unseen window at a lower loss than zero offsets."""
+"""Learned offset warm start end to end at a reduced scale: offsets the
+method converges to on synthetic frames train the conv net (1,000 frames,
+half of the bench's); with its validation-selected offset step size,
+warm-started mapping of an unseen 8-keyframe 640x480 window starts at a
+lower loss and reaches the loss plain mapping (zero offsets, the
+supplement's rates) has after 5 iterations in fewer iterations.  (Whether it
+also reaches plain's 50-iteration loss sooner depends on the window: the
+bench reports three seeds.)"""
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
-def test_warm_start_lowers_the_first_mapping_loss():
+def test_warm_start_starts_lower_and_keeps_an_early_lead():
+    import os
+
     import torch
     from paper_2603_21055_amd import sgad, warmstart
-    print("warm start: 48 frames", flush=True)
-    frames = warmstart.make_frames(range(7000, 7048), workers=1)   # no fork of a process using the GPU
+    print("warm start: 1000 frames", flush=True)
+    # spawned workers: this process may already hold the GPU, so it must not fork
+    frames = warmstart.make_frames(range(7000, 8000), workers=min(16, os.cpu_count() or 1), start="spawn")
     ctx = sgad.Context(0)
     try:
-        data = [warmstart.converged_offsets(ctx, fr, iters=120, avg=40) for fr in frames]
-        net, hist = warmstart.train(ctx, data, epochs=12, batch=8)
-        assert hist[-1] < hist[0]
-        sc = warmstart.eval_window(3001, W=640, H=480, n=2)
-        plain = warmstart.mapping_curve(ctx, sc, None, 3)
-        warm = warmstart.mapping_curve(ctx, sc, net, 3)
-        print("plain", plain, "warm", warm, flush=True)
+        res = warmstart.experiment(ctx, frames, epochs=20, map_iters=150, plain_iters=50,
+                                   eval_seed=3001, eval_size=(640, 480), eval_n=8, log=print)
+        plain, warm = np.array(res["plain_curve"]), np.array(res["warm_curve"])
+        print("plain", plain[[0, 4, 9, 19, 49]], "warm", warm[[0, 4, 9, 19, 49]],
+              "offset lr", res["warm_offset_lr"], "levels", res["warm_iters_to_plain_level"], flush=True)
         assert np.isfinite(plain).all() and np.isfinite(warm).all()
-        assert warm[0] < plain[0]
+        assert res["train_loss"][-1] < res["train_loss"][0]
+        assert warm[0] < 0.8 * plain[0]
+        lvl = res["warm_iters_to_plain_level"]
+        assert lvl["5"] is not None and lvl["5"] < 5
         torch.cuda.synchronize()
     finally:
         ctx.close()
