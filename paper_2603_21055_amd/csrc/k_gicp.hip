@@ -9,9 +9,10 @@
 // pixel without depth has z = 0 there and is never a neighbour or a source.
 //
 // k_gicp_prepare   one thread per grid point: back-projection, its K_c
-//                  nearest points of the set (brute force over LDS tiles of
-//                  the set, squared distance ((dx^2 + dy^2) + dz^2), ties by
-//                  index, a register top-K), their covariance, a cyclic
+//                  nearest points of the set (squared distance ((dx^2 +
+//                  dy^2) + dz^2), ties by index, a register top-K, searched
+//                  in growing windows of grid cells until a distance bound
+//                  proves the window exact), their covariance, a cyclic
 //                  Jacobi eigen-decomposition, C' = U diag(max(l0/l2, eps),
 //                  max(l1/l2, eps), 1) U^T and the normal (smallest).
 // k_gicp_linearise one thread per source point: X = R a + t, its K_c
@@ -41,21 +42,22 @@ constexpr int kGicpMaxK = 32;
 constexpr double kGicpEps = 1e-3;
 constexpr double kGicpDMax = 0.1;
 constexpr int kGicpVals = 29;      // H upper triangle (21), g (6), cost, pair count
-constexpr int kGicpTile = 256;     // candidate points staged in LDS per round
 constexpr int kGicpTrace = 48;     // trace record: H 21, g 6, cost, n, lambda, dxi 6, R 9, t 3
 
 // Top-K in registers, sorted by (distance, index); every comparison is on
 // the pair, so the result does not depend on the order candidates arrive in.
+template <int KM>
 struct TopK {
-    double d[kGicpMaxK];
-    int i[kGicpMaxK];
+    double d[KM];
+    int i[KM];
     double worst;
     int worst_i;
 };
 
-__device__ __forceinline__ void topk_init(TopK& t) {
+template <int KM>
+__device__ __forceinline__ void topk_init(TopK<KM>& t) {
 #pragma unroll
-    for (int s = 0; s < kGicpMaxK; ++s) {
+    for (int s = 0; s < KM; ++s) {
         t.d[s] = DBL_MAX;
         t.i[s] = INT_MAX;
     }
@@ -63,11 +65,12 @@ __device__ __forceinline__ void topk_init(TopK& t) {
     t.worst_i = INT_MAX;
 }
 
-__device__ __forceinline__ void topk_insert(TopK& t, int k, double d, int j) {
+template <int KM>
+__device__ __forceinline__ void topk_insert(TopK<KM>& t, int k, double d, int j) {
     double cd = d;
     int ci = j;
 #pragma unroll
-    for (int s = 0; s < kGicpMaxK; ++s) {
+    for (int s = 0; s < KM; ++s) {
         if (s < k) {
             const bool sw = cd < t.d[s] || (cd == t.d[s] && ci < t.i[s]);
             const double td = sw ? t.d[s] : cd;
@@ -81,7 +84,7 @@ __device__ __forceinline__ void topk_insert(TopK& t, int k, double d, int j) {
     double w = t.d[0];
     int wi = t.i[0];
 #pragma unroll
-    for (int s = 0; s < kGicpMaxK; ++s)
+    for (int s = 0; s < KM; ++s)
         if (s == k - 1) {
             w = t.d[s];
             wi = t.i[s];
@@ -94,80 +97,69 @@ __device__ __forceinline__ void topk_insert(TopK& t, int k, double d, int j) {
 struct GicpGrid {
     double fx, fy, cx, cy;
     int R, gw, gh;
-    double bound;   // (w + 1/2) R / max(fx, fy) / max over the image of |(x, y, 1)|, per unit depth
+    double m;   // max over the image of |(x, y, 1)|
 };
 
-constexpr int kGicpWin = 4;   // half-width (cells) of the window searched first
+constexpr int kGicpWin = 4;   // half-width (cells) of the first window; doubled until exact
 
-// The k nearest points of `set` to q among the grid cells within kGicpWin of
-// the cell q projects to.  Returns true when that is the exact answer over
-// the whole set: q projects inside the grid (within half a cell of a cell
-// centre), the window held k points, and the k-th distance is below the
-// smallest distance any point outside the window can have.  A point c on the
-// ray of a pixel p is at least |q| sin(angle(q, p)) from q; for p outside the
-// window its normalised image coordinates differ from q's by at least
-// D = (w + 1/2) R / max(fx, fy) in x or y, so |r_q x r_p| >= D and
-// |q| sin(angle) >= q_z D / |r_p| >= q_z * bound.
-__device__ bool knn_window(const double* __restrict__ set, int n, const GicpGrid& g, int k, double qx, double qy,
-                           double qz, TopK& t) {
+// The k nearest points of `set` (a grid of gw x gh cells) to q: windows of
+// growing half-width around the cell q projects to, each new ring of cells
+// scanned, until the window provably holds the k nearest.  A point c on the
+// ray of a pixel p is at least |q| sin(angle(q, p)) from q, and with r_q, r_p
+// the rays (x, y, 1), |q| sin(angle) = q_z |r_q x r_p| / |r_p| >= q_z D / M,
+// D the larger of |x_p - x_q| and |y_p - y_q| and M the largest |r_p| over the
+// image.  For pixels outside the window, D is at least the normalised
+// distance from q's projection to the nearest column or row outside it, so
+// once the window's k-th distance is below (q_z D / M)^2 no point outside can
+// enter.  A window covering the whole grid is exact by itself; q behind the
+// camera scans the whole grid.
+template <int KM>
+__device__ void knn_grid(const double* __restrict__ set, int n, const GicpGrid& g, int k, double qx, double qy,
+                         double qz, TopK<KM>& t) {
 #pragma clang fp contract(off)
     topk_init(t);
-    if (!(qz > 0.0)) return false;
-    const double u = g.fx * (qx / qz) + g.cx, v = g.fy * (qy / qz) + g.cy;
-    const double gu = rint(u / g.R), gv = rint(v / g.R);
-    if (!(gu >= 0.0 && gu <= g.gw - 1 && gv >= 0.0 && gv <= g.gh - 1)) return false;
-    if (fabs(u - gu * g.R) > 0.5 * g.R || fabs(v - gv * g.R) > 0.5 * g.R) return false;
-    const int cu = (int)gu, cv = (int)gv;
+    int cu = 0, cv = 0, w = g.gw + g.gh;      // behind the camera: the whole grid at once
+    double u = 0.0, v = 0.0;
+    if (qz > 0.0) {
+        u = g.fx * (qx / qz) + g.cx;
+        v = g.fy * (qy / qz) + g.cy;
+        cu = (int)fmin(fmax(rint(u / g.R), 0.0), (double)(g.gw - 1));
+        cv = (int)fmin(fmax(rint(v / g.R), 0.0), (double)(g.gh - 1));
+        w = kGicpWin;
+    }
     int found = 0;
-    for (int j = max(0, cv - kGicpWin); j <= min(g.gh - 1, cv + kGicpWin); ++j)
-        for (int i = max(0, cu - kGicpWin); i <= min(g.gw - 1, cu + kGicpWin); ++i) {
-            const int c = j * g.gw + i;
-            const double pz = set[2 * (size_t)n + c];
-            if (pz == 0.0) continue;
-            ++found;
-            const double dx = qx - set[c], dy = qy - set[(size_t)n + c], dz = qz - pz;
-            const double d = (dx * dx + dy * dy) + dz * dz;
-            if (d < t.worst || (d == t.worst && c < t.worst_i)) topk_insert(t, k, d, c);
+    int lo_u = 1, hi_u = 0, lo_v = 1, hi_v = 0;   // region scanned so far (empty)
+    while (true) {
+        const int nlo_u = max(0, cu - w), nhi_u = min(g.gw - 1, cu + w);
+        const int nlo_v = max(0, cv - w), nhi_v = min(g.gh - 1, cv + w);
+        for (int j = nlo_v; j <= nhi_v; ++j)
+            for (int i = nlo_u; i <= nhi_u; ++i) {
+                if (i >= lo_u && i <= hi_u && j >= lo_v && j <= hi_v) continue;   // scanned before
+                const int c = j * g.gw + i;
+                const double pz = set[2 * (size_t)n + c];
+                if (pz == 0.0) continue;
+                ++found;
+                const double dx = qx - set[c], dy = qy - set[(size_t)n + c], dz = qz - pz;
+                const double d = (dx * dx + dy * dy) + dz * dz;
+                if (d < t.worst || (d == t.worst && c < t.worst_i)) topk_insert(t, k, d, c);
+            }
+        lo_u = nlo_u;
+        hi_u = nhi_u;
+        lo_v = nlo_v;
+        hi_v = nhi_v;
+        const bool all = lo_u == 0 && hi_u == g.gw - 1 && lo_v == 0 && hi_v == g.gh - 1;
+        if (all) return;
+        // normalised distance from q's projection to the nearest column / row outside
+        double D = DBL_MAX;
+        if (lo_u > 0) D = fmin(D, (u - (double)((lo_u - 1) * g.R)) / g.fx);
+        if (hi_u < g.gw - 1) D = fmin(D, ((double)((hi_u + 1) * g.R) - u) / g.fx);
+        if (lo_v > 0) D = fmin(D, (v - (double)((lo_v - 1) * g.R)) / g.fy);
+        if (hi_v < g.gh - 1) D = fmin(D, ((double)((hi_v + 1) * g.R) - v) / g.fy);
+        if (found >= k && D > 0.0) {
+            const double lb = qz * D / g.m;
+            if (t.worst < lb * lb * (1.0 - 1e-12)) return;
         }
-    const double lb = qz * g.bound;
-    return found >= k && t.worst < lb * lb * (1.0 - 1e-12);
-}
-
-// The k nearest points of `set` (n points) to q, over LDS tiles.  Every
-// thread of the block takes part in the staging (valid or not).  The tiles
-// are visited outward from tile `home` (home, home + 1, home - 1, ...): sets
-// are in pixel-grid order, so the points near the block's queries come
-// first and fill the list, and far ones rarely enter it.
-__device__ void knn_scan(const double* __restrict__ set, int n, int k, double qx, double qy, double qz, bool active,
-                         TopK& t, double (*s_p)[kGicpTile], int home) {
-#pragma clang fp contract(off)
-    if (active) topk_init(t);
-    const int ntile = (n + kGicpTile - 1) / kGicpTile;
-    home = min(max(home, 0), ntile - 1);
-    for (int step = 0; step < 2 * ntile; ++step) {
-        const int off = (step + 1) >> 1;
-        const int tile = (step & 1) ? home + off : home - off;
-        if (tile < 0 || tile >= ntile || (step > 0 && off == 0)) continue;
-        const int b0 = tile * kGicpTile;
-        __syncthreads();
-        for (int c = threadIdx.x; c < kGicpTile; c += blockDim.x) {
-            const int j = b0 + c;
-            const bool in = j < n;
-            s_p[0][c] = in ? set[j] : 0.0;
-            s_p[1][c] = in ? set[(size_t)n + j] : 0.0;
-            s_p[2][c] = in ? set[2 * (size_t)n + j] : 0.0;
-        }
-        __syncthreads();
-        if (!active) continue;
-        const int m = min(kGicpTile, n - b0);
-        for (int c = 0; c < m; ++c) {
-            const double pz = s_p[2][c];
-            if (pz == 0.0) continue;          // grid pixel without depth
-            const double dx = qx - s_p[0][c], dy = qy - s_p[1][c], dz = qz - pz;
-            const double d = (dx * dx + dy * dy) + dz * dz;
-            const int j = b0 + c;
-            if (d < t.worst || (d == t.worst && j < t.worst_i)) topk_insert(t, k, d, j);
-        }
+        w *= 2;
     }
 }
 
@@ -210,31 +202,22 @@ __device__ void jacobi3(double* a, double* w, double* v) {
 }
 
 // Runs after k_gicp_points: reads the coordinate rows, writes rows 3..11.
+template <int KM>
 __global__ __launch_bounds__(256) void k_gicp_prepare(int k, double* __restrict__ set, int n, GicpGrid grid) {
 #pragma clang fp contract(off)
-    __shared__ double s_p[3][kGicpTile];
     const int g = (int)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = g < n;
-    double qx = 0.0, qy = 0.0, qz = 0.0;
-    if (in) {
-        qx = set[g];
-        qy = set[(size_t)n + g];
-        qz = set[2 * (size_t)n + g];
-    }
-    const bool active = in && qz != 0.0;
-    TopK t;
-    const bool exact = active && knn_window(set, n, grid, k, qx, qy, qz, t);
-    if (__syncthreads_or(active && !exact))
-        knn_scan(set, n, k, qx, qy, qz, active && !exact, t, s_p, (int)blockIdx.x * (int)blockDim.x / kGicpTile);
-    if (!active) {
-        if (in)
-            for (int r = 3; r < 12; ++r) set[(size_t)r * n + g] = 0.0;
+    if (g >= n) return;
+    const double qx = set[g], qy = set[(size_t)n + g], qz = set[2 * (size_t)n + g];
+    if (qz == 0.0) {
+        for (int r = 3; r < 12; ++r) set[(size_t)r * n + g] = 0.0;
         return;
     }
+    TopK<KM> t;
+    knn_grid(set, n, grid, k, qx, qy, qz, t);
     int kk = 0;
     double mx = 0.0, my = 0.0, mz = 0.0;
 #pragma unroll
-    for (int s = 0; s < kGicpMaxK; ++s)
+    for (int s = 0; s < KM; ++s)
         if (s < k && t.i[s] != INT_MAX) {
             const int j = t.i[s];
             mx += set[j];
@@ -247,7 +230,7 @@ __global__ __launch_bounds__(256) void k_gicp_prepare(int k, double* __restrict_
     mz /= (double)kk;
     double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < kGicpMaxK; ++s)
+    for (int s = 0; s < KM; ++s)
         if (s < k && t.i[s] != INT_MAX) {
             const int j = t.i[s];
             const double dx = set[j] - mx, dy = set[(size_t)n + j] - my, dz = set[2 * (size_t)n + j] - mz;
@@ -319,12 +302,12 @@ __global__ __launch_bounds__(256) void k_gicp_points(const float* __restrict__ d
 }
 
 // Pose P = (R row-major, t) at pose[0..11].
+template <int KM>
 __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict__ src, int ns,
                                                         const double* __restrict__ tgt, int nt, GicpGrid tgrid,
                                                         int k, const double* __restrict__ pose,
                                                         double* __restrict__ part, int* __restrict__ corr) {
 #pragma clang fp contract(off)
-    __shared__ double s_p[3][kGicpTile];
     __shared__ double s_acc[4][kGicpVals];
     const int i = (int)blockIdx.x * blockDim.x + threadIdx.x;
     double Rm[9], tv[3];
@@ -343,12 +326,8 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
     const double X0 = ((Rm[0] * a0 + Rm[1] * a1) + Rm[2] * a2) + tv[0];
     const double X1 = ((Rm[3] * a0 + Rm[4] * a1) + Rm[5] * a2) + tv[1];
     const double X2 = ((Rm[6] * a0 + Rm[7] * a1) + Rm[8] * a2) + tv[2];
-    TopK t;
-    const bool exact = active && knn_window(tgt, nt, tgrid, k, X0, X1, X2, t);
-    // source and target grids cover the same image region for small motions
-    if (__syncthreads_or(active && !exact))
-        knn_scan(tgt, nt, k, X0, X1, X2, active && !exact, t, s_p,
-                 (int)((long long)blockIdx.x * blockDim.x * nt / ((long long)ns * kGicpTile)));
+    TopK<KM> t;
+    if (active) knn_grid(tgt, nt, tgrid, k, X0, X1, X2, t);
     double acc[kGicpVals];
 #pragma unroll
     for (int q = 0; q < kGicpVals; ++q) acc[q] = 0.0;
@@ -356,7 +335,7 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
     if (active) {
         double best = DBL_MAX;
 #pragma unroll
-        for (int s = 0; s < kGicpMaxK; ++s)
+        for (int s = 0; s < KM; ++s)
             if (s < k && t.i[s] != INT_MAX) {
                 const int c = t.i[s];
                 const double e0 = X0 - tgt[c], e1 = X1 - tgt[(size_t)nt + c], e2 = X2 - tgt[2 * (size_t)nt + c];
@@ -581,7 +560,7 @@ static GicpGrid gicp_grid(const sgad_cam& cam, int R) {
             const double y = ((double)(cy ? cam.H - 1 : 0) - g.cy) / g.fy;
             m = std::max(m, std::sqrt(1.0 + x * x + y * y));
         }
-    g.bound = (kGicpWin + 0.5) * R / std::max(g.fx, g.fy) / m;
+    g.m = m;
     return g;
 }
 int gicp_blocks(int n) { return (n + 255) / 256; }
@@ -595,13 +574,18 @@ void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam
     const dim3 grid(gicp_blocks(n)), blk(256);
     hipLaunchKernelGGL(k_gicp_points, grid, blk, 0, s, depth, H, W, R, (double)cam.fx, (double)cam.fy,
                        (double)cam.cx, (double)cam.cy, set, n);
-    hipLaunchKernelGGL(k_gicp_prepare, grid, blk, 0, s, k, set, n, gicp_grid(cam, R));
+    if (k <= 16) hipLaunchKernelGGL(k_gicp_prepare<16>, grid, blk, 0, s, k, set, n, gicp_grid(cam, R));
+    else hipLaunchKernelGGL(k_gicp_prepare<kGicpMaxK>, grid, blk, 0, s, k, set, n, gicp_grid(cam, R));
 }
 
 void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, const sgad_cam& tcam, int tR,
                            int k, const double* pose, double* part, int* corr, hipStream_t s) {
-    hipLaunchKernelGGL(k_gicp_linearise, dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tgt, nt,
-                       gicp_grid(tcam, tR), k, pose, part, corr);
+    if (k <= 16)
+        hipLaunchKernelGGL(k_gicp_linearise<16>, dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tgt, nt,
+                           gicp_grid(tcam, tR), k, pose, part, corr);
+    else
+        hipLaunchKernelGGL(k_gicp_linearise<kGicpMaxK>, dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tgt, nt,
+                           gicp_grid(tcam, tR), k, pose, part, corr);
 }
 
 void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s) {

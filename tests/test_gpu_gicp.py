@@ -28,11 +28,11 @@ def _corner_pair(seed, W, H, trans=0.03, deg=2.0):
     return cam, d0.astype(np.float32), d1.astype(np.float32), Rc, tc
 
 
-def _prepare(ctx, depth, cam, ratio):
+def _prepare(ctx, depth, cam, ratio, k=K):
     import torch
     n = ctx.gicp_set_size(cam["H"], cam["W"], ratio)
     s = torch.full((12, n), float("nan"), dtype=torch.float64, device=ctx.device)
-    ctx.gicp_prepare(torch.from_numpy(depth).to(ctx.device), cam, ratio, K, s)
+    ctx.gicp_prepare(torch.from_numpy(depth).to(ctx.device), cam, ratio, k, s)
     return s
 
 
@@ -52,21 +52,23 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("W,H,ratio,sparse", [(200, 150, 4, False), (1200, 680, 10, False), (200, 150, 2, True)])
-def test_prepare_matches_oracle(ctx, W, H, ratio, sparse):
+@pytest.mark.parametrize("W,H,ratio,sparse,k", [(200, 150, 4, False, K), (1200, 680, 10, False, K),
+                                                (200, 150, 2, True, K), (200, 150, 4, False, 23)])
+def test_prepare_matches_oracle(ctx, W, H, ratio, sparse, k):
     """sparse: 90 % of the pixels without depth, so most neighbour searches
-    leave the window around their own cell for the scan over all points."""
+    grow their window several times; k = 23: the supplement's TUM setting
+    (the 32-slot neighbour list)."""
     import torch
-    print(f"gicp prepare {W}x{H} R={ratio} sparse={sparse}", flush=True)
+    print(f"gicp prepare {W}x{H} R={ratio} sparse={sparse} k={k}", flush=True)
     cam, d0, _, _, _ = _corner_pair(40 + ratio, W, H)
     d0[::7, ::11] = 0.0                                  # pixels without depth
     if sparse:
         d0[np.random.default_rng(3).uniform(size=d0.shape) < 0.9] = 0.0
-    s = _prepare(ctx, d0, cam, ratio)
+    s = _prepare(ctx, d0, cam, ratio, k)
     torch.cuda.synchronize()
     got = s.cpu().numpy()
     pts, pix = gicp.sample_points(d0, cam, ratio)
-    orc = gicp.local_gaussians(pts, K)
+    orc = gicp.local_gaussians(pts, k)
     grid = _grid_pixels(cam, ratio)
     pos = {p: i for i, p in enumerate(grid)}
     idx = np.array([pos[p] for p in pix])
