@@ -21,13 +21,13 @@ What is computed, with the readings taken where the paper is silent:
   max(l3/l1, EPS)) U^T, which keeps the ellipse's in-plane shape; the
   flat-plane normalisation of GICP would be diag(1, 1, EPS).
 * Correspondence (point to surface): a source point moved into the target
-  frame, X = R a + t, is matched among its K_c nearest target points (by
-  Euclidean distance, ties by index) to the surface element closest to it,
-  min_b (n_b . (X - b))^2 + EPS |X - b|^2 (ties by Euclidean rank): the
-  distance to b's tangent plane, with EPS |X - b|^2 added so that on a
-  plane, where every candidate has zero plane distance, the nearest point
-  is taken (the plane distance alone does not identify a point there).
-  Pairs farther apart than D_MAX are dropped.
+  frame, X = R a + t, is matched among its K_c nearest target points within
+  D_MAX (by Euclidean distance, ties by index) to the surface element
+  closest to it, min_b (n_b . (X - b))^2 + EPS |X - b|^2 (ties by Euclidean
+  rank): the distance to b's tangent plane, with EPS |X - b|^2 added so that
+  on a plane, where every candidate has zero plane distance, the nearest
+  point is taken (the plane distance alone does not identify a point
+  there).  A point with no target within D_MAX has no pair.
 * Eq. 2 as GICP defines it: sum over pairs of e^T (C_b + R C_a R^T)^-1 e,
   e = b - X (the printed equation omits the inverse and writes the pose for
   its rotation).  Gauss-Newton in the left twist xi = (rho, phi) of the
@@ -124,26 +124,29 @@ def correspond(src, tgt, R, t, k, with_margins=False):
     decisions (K-th vs (K+1)-th Euclidean distance, best vs second surface
     distance, squared distance vs D_MAX^2), for flagging near-ties."""
     X = transform(src["points"], R, t)
-    nb = knn(X, tgt["points"], k + 1 if with_margins else k)
-    nbk = nb[:, :k]
-    B = tgt["points"][nbk]                       # [n, k, 3]
-    E = X[:, None, :] - B
-    dist = surface_distance(E, tgt["normal"][nbk])
-    best = np.argmin(dist, 1)                    # first minimum = lowest Euclidean rank
-    j = nbk[np.arange(len(X)), best]
-    e = tgt["points"][j] - X
-    d2 = (e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1]) + e[:, 2] * e[:, 2]
-    j = np.where(d2 <= D_MAX * D_MAX, j, -1)
-    if not with_margins:
-        return j, X
     P = tgt["points"]
+    kk = min(k + 1 if with_margins else k, len(P))
+    nb = knn(X, P, kk)
+    nbk = nb[:, :min(k, len(P))]
+
     def sq(i):
         f = X - P[nb[:, i]]
         return (f[:, 0] * f[:, 0] + f[:, 1] * f[:, 1]) + f[:, 2] * f[:, 2]
+
+    d2k = np.stack([sq(i) for i in range(nbk.shape[1])], 1)          # [n, k]
+    within = d2k <= D_MAX * D_MAX
+    E = X[:, None, :] - P[nbk]
+    dist = np.where(within, surface_distance(E, tgt["normal"][nbk]), np.inf)
+    best = np.argmin(dist, 1)                    # first minimum = lowest Euclidean rank
+    has = within.any(1)
+    j = np.where(has, nbk[np.arange(len(X)), best], -1)
+    if not with_margins:
+        return j, X
     gap_knn = (np.abs(sq(k) - sq(k - 1)) / np.maximum(sq(k), 1e-300)) if nb.shape[1] > k else np.full(len(X), np.inf)
     srt = np.sort(dist, 1)
-    gap_best = np.abs(srt[:, 1] - srt[:, 0]) / np.maximum(srt[:, 1], 1e-300) if k > 1 else np.full(len(X), np.inf)
-    gap_dmax = np.abs(d2 - D_MAX * D_MAX) / (D_MAX * D_MAX)
+    gap_best = np.where(np.isfinite(srt[:, 1]), np.abs(srt[:, 1] - srt[:, 0]) / np.maximum(srt[:, 1], 1e-300),
+                        np.inf) if k > 1 else np.full(len(X), np.inf)
+    gap_dmax = (np.abs(d2k - D_MAX * D_MAX) / (D_MAX * D_MAX)).min(1)
     return j, X, dict(knn=gap_knn, best=gap_best, dmax=gap_dmax)
 
 

@@ -87,6 +87,21 @@ def test_point_to_surface_correspondence_hand_case():
     assert j.tolist() == [-1]
 
 
+def test_distance_cut_applies_before_the_surface_match():
+    """Of the two nearest targets the one on the source's surface lies
+    0.105 m away (beyond D_MAX), the other 0.03 m away off it: the cut
+    removes the first as a candidate, so the source pairs with the second
+    instead of with nothing."""
+    tgt = dict(points=np.array([[0.03, 0.0, 1.0], [0.0, 0.0, 1.105]]),
+               normal=np.array([[1.0, 0, 0], [1.0, 0, 0]]))
+    src = dict(points=np.array([[0.0, 0.0, 1.0]]))
+    E = src["points"][:, None, :] - tgt["points"][None]
+    ds = gicp.surface_distance(E, tgt["normal"][None])
+    assert ds[0, 1] < ds[0, 0]                   # the far one is the better surface match
+    j, _ = gicp.correspond(src, tgt, np.eye(3), np.zeros(3), 2)
+    assert j.tolist() == [0]
+
+
 def test_jacobian_matches_finite_differences():
     room, cam, depth = _frame(3)
     pts, _ = gicp.sample_points(depth, cam, 4)
