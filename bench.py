@@ -341,10 +341,62 @@ def bench_gicp(args, emit=True):
     out = dict(metric="GICP tracking frames/s (1200x680, R=10, K_c=10, 30 Gauss-Newton iterations)",
                value=1.0 / sec, unit="frames/s", ms_per_frame=sec * 1e3, points=n, steps=steps,
                translation_error_mm=err_mm, dtype="f64", data="synthetic")
+    out["against_T"] = _bench_gicp_map(ctx, room, cam, rng, R_s, K, steps, min(args.warmup, 3))
     ctx.close()
     if emit:
         print(json.dumps(out), flush=True)
     return out
+
+
+def _bench_gicp_map(ctx, room, cam, rng, R_s, K, steps, warmup):
+    """Tracking against the global set T (Sec. 3.3): T holds four frames
+    inserted at their true poses along a path of 3 cm / 2 degree steps; one
+    frame = building the next frame's set and 30 Gauss-Newton iterations
+    against T from the previous frame's pose; insertion timed on the four
+    frames that built T (wall clock around each call)."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", 0)
+    H, W = cam["H"], cam["W"]
+    n = ctx.gicp_set_size(H, W, R_s)
+    from paper_2603_21055_amd import synth
+    R, t = synth.corner_pose(room)
+    poses, depths = [], []
+    for i in range(5):
+        if i:
+            R, t = synth.perturb_pose(R, t, rng, 0.03, 2.0, exact=True)
+        U, _, Vt = np.linalg.svd(np.asarray(R, np.float64))
+        R, t = U @ Vt, np.asarray(t, np.float64)
+        d, _ = room.raycast(cam, R, t)
+        depths.append(torch.from_numpy(d.astype(np.float32)).to(dev))
+        poses.append((R.T, -R.T @ t))                      # camera-to-world
+    dpose = [torch.from_numpy(np.concatenate([Rw.ravel(), tw])).to(dev) for Rw, tw in poses]
+    m = ctx.gmap_new(8 * n)
+    fs = [torch.empty((12, n), dtype=torch.float64, device=dev) for _ in range(4)]
+    for i in range(4):
+        ctx.gicp_prepare(depths[i], cam, R_s, K, fs[i])
+    torch.cuda.synchronize()
+    ins = 0.0
+    for i in range(4):                      # each insertion adds the frame's new surface
+        t0 = time.perf_counter()
+        ctx.gmap_insert(m, fs[i], dpose[i])
+        torch.cuda.synchronize()
+        ins += time.perf_counter() - t0
+    size_T = m.count()
+    src = torch.empty((12, n), dtype=torch.float64, device=dev)
+    pose = torch.empty(12, dtype=torch.float64, device=dev)
+
+    def run():
+        ctx.gicp_prepare(depths[4], cam, R_s, K, src)
+        pose.copy_(dpose[3])
+        ctx.gicp_track_map(src, m, K, pose, 30)
+
+    sec = _timed(run, steps, warmup)
+    ctx.sync()
+    p = pose.cpu().numpy()
+    err_mm = float(np.linalg.norm(p[9:] - poses[4][1]) * 1e3)
+    return dict(frames_per_s=1.0 / sec, ms_per_frame=sec * 1e3, gaussians_in_T=size_T,
+                insert_ms=ins / 4 * 1e3, translation_error_mm=err_mm)
 
 
 def bench_offsetnet(args):

@@ -365,6 +365,59 @@ sgad_status sgad_gicp_track(sgad_ctx* ctx, const double* src, int n_src, const d
                             const sgad_cam* tgt_cam, int tgt_ratio, int k, double* pose, int iters, double* trace,
                             void* stream);
 
+/*
+ * The global set T of geometry Gaussians that frames are tracked against
+ * (Sec. 3.3, matching a frame to the scene and updating T).  T holds world
+ * Gaussians (point, normalised covariance, normal) in the layout of a GICP
+ * set with row stride `capacity`: data = [12][capacity] doubles, the first
+ * *count columns in use.  T keeps at most one Gaussian per cubic voxel of
+ * side `voxel` (the voxel of p is floor(p / voxel) per axis), found through
+ * an open-addressing hash: keys (int64[slots]) and vals (int32[slots]),
+ * `slots` a power of two >= 2 * capacity.  All four arrays are caller-owned
+ * device memory; the struct itself is read on the host.  voxel must be at
+ * least D_MAX / 32 = 3.125 mm, and coordinates within +-(2^20 - 41) voxels:
+ * Gaussians outside are not inserted and queries outside find nothing.
+ */
+typedef struct {
+    double* data;    /* device [12][capacity] */
+    int64_t* keys;   /* device [slots] */
+    int32_t* vals;   /* device [slots] */
+    int32_t* count;  /* device [1]: Gaussians in T */
+    int32_t capacity;
+    int32_t slots;
+    double voxel;    /* metres */
+} sgad_gmap;
+
+/* Empty T (count 0, every slot free). */
+sgad_status sgad_gmap_reset(sgad_ctx* ctx, const sgad_gmap* map, void* stream);
+/* Add a tracked frame's set (as sgad_gicp_prepare builds it, n points) to T
+ * under its camera-to-world pose (device double[12], R row-major then t):
+ * each valid Gaussian is moved into the world (p = R a + t summed as ((r0
+ * a0 + r1 a1) + r2 a2) + t; C = R C_a R^T; n = R n_a) and appended unless
+ * its voxel already holds a Gaussian of T or of this frame with a lower
+ * index; new Gaussians are appended in index order.  Once T is at capacity
+ * further Gaussians are dropped.  Calls on one map are ordered by their
+ * stream; overlapping calls on one map race. */
+sgad_status sgad_gmap_insert(sgad_ctx* ctx, const sgad_gmap* map, const double* set, int n, const double* pose,
+                             void* stream);
+/* sgad_gicp_linearise / sgad_gicp_track with T as the target: the pose is
+ * camera-to-world, corr holds indices into T, and the K_c nearest are found
+ * by an exact search over voxel shells around X. */
+sgad_status sgad_gicp_linearise_map(sgad_ctx* ctx, const double* src, int n_src, const sgad_gmap* map, int k,
+                                    const double* pose, double* out, int32_t* corr, void* stream);
+sgad_status sgad_gicp_track_map(sgad_ctx* ctx, const double* src, int n_src, const sgad_gmap* map, int k,
+                                double* pose, int iters, double* trace, void* stream);
+/*
+ * Depth with its holes filled from a render (Sec. 3.2: Gaussians are
+ * initialised where the depth map has no value from what the previous
+ * keyframe renders there): out = depth where depth > 0, else D'/A where the
+ * rendered alpha A >= alpha_min (D' the rendered depth, the sum of alpha
+ * blended depths), else 0.  Device float[P] each, P = H * W; out may alias
+ * depth.  SGAD_EINVAL on null pointers, P < 1 or alpha_min not in (0, 1].
+ */
+sgad_status sgad_fill_depth(sgad_ctx* ctx, int P, const float* depth, const float* rdepth, const float* ralpha,
+                            float alpha_min, float* out, void* stream);
+
 /* One parameter tensor for sgad_adam_step (all device pointers, n floats;
  * the pointers may be null when n is 0).  Arrays that start on a 16-byte
  * boundary are read and written four floats at a time. */

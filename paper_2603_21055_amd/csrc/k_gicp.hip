@@ -113,9 +113,13 @@ constexpr int kGicpWin = 4;   // half-width (cells) of the first window; doubled
 // once the window's k-th distance is below (q_z D / M)^2 no point outside can
 // enter.  A window covering the whole grid is exact by itself; q behind the
 // camera scans the whole grid.
+//
+// With dmax2 finite only points within squared distance dmax2 are candidates
+// (the list is the k nearest among them), and the search also ends once no
+// point outside the window can be that close.
 template <int KM>
 __device__ void knn_grid(const double* __restrict__ set, int n, const GicpGrid& g, int k, double qx, double qy,
-                         double qz, TopK<KM>& t) {
+                         double qz, TopK<KM>& t, double dmax2) {
 #pragma clang fp contract(off)
     topk_init(t);
     int cu = 0, cv = 0, w = g.gw + g.gh;      // behind the camera: the whole grid at once
@@ -138,9 +142,10 @@ __device__ void knn_grid(const double* __restrict__ set, int n, const GicpGrid& 
                 const int c = j * g.gw + i;
                 const double pz = set[2 * (size_t)n + c];
                 if (pz == 0.0) continue;
-                ++found;
                 const double dx = qx - set[c], dy = qy - set[(size_t)n + c], dz = qz - pz;
                 const double d = (dx * dx + dy * dy) + dz * dz;
+                if (!(d <= dmax2)) continue;
+                ++found;
                 if (d < t.worst || (d == t.worst && c < t.worst_i)) topk_insert(t, k, d, c);
             }
         lo_u = nlo_u;
@@ -155,9 +160,11 @@ __device__ void knn_grid(const double* __restrict__ set, int n, const GicpGrid& 
         if (hi_u < g.gw - 1) D = fmin(D, ((double)((hi_u + 1) * g.R) - u) / g.fx);
         if (lo_v > 0) D = fmin(D, (v - (double)((lo_v - 1) * g.R)) / g.fy);
         if (hi_v < g.gh - 1) D = fmin(D, ((double)((hi_v + 1) * g.R) - v) / g.fy);
-        if (found >= k && D > 0.0) {
+        if (D > 0.0) {
             const double lb = qz * D / g.m;
-            if (t.worst < lb * lb * (1.0 - 1e-12)) return;
+            const double lb2 = lb * lb * (1.0 - 1e-12);
+            if (found >= k && t.worst < lb2) return;
+            if (lb2 >= dmax2) return;      // nothing outside is a candidate
         }
         w *= 2;
     }
@@ -213,7 +220,7 @@ __global__ __launch_bounds__(256) void k_gicp_prepare(int k, double* __restrict_
         return;
     }
     TopK<KM> t;
-    knn_grid(set, n, grid, k, qx, qy, qz, t);
+    knn_grid(set, n, grid, k, qx, qy, qz, t, DBL_MAX);
     int kk = 0;
     double mx = 0.0, my = 0.0, mz = 0.0;
 #pragma unroll
@@ -301,10 +308,115 @@ __global__ __launch_bounds__(256) void k_gicp_points(const float* __restrict__ d
     set[2 * (size_t)n + g] = z;
 }
 
+// ---------------------------------------------------------------------------
+// Global map T: world Gaussians [12][capacity] (the layout of a set, rows of
+// stride `capacity`), at most one per voxel of side `voxel`, found through an
+// open-addressing hash of the voxel coordinates (linear probing, `slots` a
+// power of two).  keys: packed voxel or kEmpty; vals: the Gaussian's index,
+// or, while an insertion runs, -(1 + lowest frame index claiming the voxel).
+// ---------------------------------------------------------------------------
+constexpr long long kEmpty = -1;
+constexpr long long kVoxelBias = 1 << 20;   // voxel coordinates in [-2^20, 2^20) per axis
+constexpr int kMapMaxShell = 40;           // voxel >= D_MAX / 32 ends the search by r = 33
+
+__device__ __forceinline__ long long voxel_pack(long long x, long long y, long long z) {
+    return ((x + kVoxelBias) << 42) | ((y + kVoxelBias) << 21) | (z + kVoxelBias);
+}
+
+__device__ __forceinline__ bool voxel_in_range(long long x, long long y, long long z) {
+    return x >= -kVoxelBias && x < kVoxelBias && y >= -kVoxelBias && y < kVoxelBias && z >= -kVoxelBias &&
+           z < kVoxelBias;
+}
+
+__device__ __forceinline__ int voxel_hash(long long key, int mask) {
+    return (int)(((unsigned long long)key * 0x9E3779B97F4A7C15ull) >> 32) & mask;
+}
+
+// Slot of `key`, or -1 when absent.
+__device__ __forceinline__ int map_find(const long long* keys, int mask, long long key) {
+    int s = voxel_hash(key, mask);
+    for (int p = 0; p <= mask; ++p) {
+        const long long k = keys[s];
+        if (k == key) return s;
+        if (k == kEmpty) return -1;
+        s = (s + 1) & mask;
+    }
+    return -1;
+}
+
+struct GridTarget {
+    const double* d;
+    size_t stride;
+    int n;
+    GicpGrid g;
+    template <int KM>
+    __device__ void knn(int k, double x, double y, double z, TopK<KM>& t) const {
+        knn_grid(d, n, g, k, x, y, z, t, kGicpDMax * kGicpDMax);
+    }
+};
+
+// The k nearest map Gaussians within D_MAX of q: shells of voxels at growing
+// Chebyshev distance r from q's voxel.  A Gaussian outside the cube of shells
+// scanned so far is at least the distance f from q to the cube's nearest face
+// (less 1e-9 m for the rounding of the voxel assignment), so the search ends
+// when the k-th distance is below f, or when f is beyond D_MAX.  Queries
+// outside the map's coordinate range find nothing.
+struct MapTarget {
+    const double* d;
+    size_t stride;
+    const long long* keys;
+    const int* vals;
+    int mask;
+    double voxel;
+
+    template <int KM>
+    __device__ __forceinline__ void visit(long long x, long long y, long long z, double qx, double qy, double qz,
+                                          int k, double dmax2, TopK<KM>& t, int& found) const {
+#pragma clang fp contract(off)
+        const int sl = map_find(keys, mask, voxel_pack(x, y, z));
+        if (sl < 0) return;
+        const int c = vals[sl];
+        if (c < 0) return;
+        const double ex = qx - d[c], ey = qy - d[stride + c], ez = qz - d[2 * stride + c];
+        const double dd = (ex * ex + ey * ey) + ez * ez;
+        if (!(dd <= dmax2)) return;
+        ++found;
+        if (dd < t.worst || (dd == t.worst && c < t.worst_i)) topk_insert(t, k, dd, c);
+    }
+
+    template <int KM>
+    __device__ void knn(int k, double x, double y, double z, TopK<KM>& t) const {
+        topk_init(t);
+        const double dmax2 = kGicpDMax * kGicpDMax;
+        const double lim = (double)(kVoxelBias - kMapMaxShell - 1);
+        const double ux = x / voxel, uy = y / voxel, uz = z / voxel;
+        if (!(fabs(ux) < lim && fabs(uy) < lim && fabs(uz) < lim)) return;
+        const long long cx = (long long)floor(ux), cy = (long long)floor(uy), cz = (long long)floor(uz);
+        int found = 0;
+        for (int r = 0; r <= kMapMaxShell; ++r) {
+            for (int dz = -r; dz <= r; ++dz)
+                for (int dy = -r; dy <= r; ++dy) {
+                    if (abs(dz) == r || abs(dy) == r) {
+                        for (int dx = -r; dx <= r; ++dx) visit(cx + dx, cy + dy, cz + dz, x, y, z, k, dmax2, t, found);
+                    } else {
+                        visit(cx - r, cy + dy, cz + dz, x, y, z, k, dmax2, t, found);
+                        if (r > 0) visit(cx + r, cy + dy, cz + dz, x, y, z, k, dmax2, t, found);
+                    }
+                }
+            const double f = fmin(fmin(fmin(x - (double)(cx - r) * voxel, (double)(cx + r + 1) * voxel - x),
+                                       fmin(y - (double)(cy - r) * voxel, (double)(cy + r + 1) * voxel - y)),
+                                  fmin(z - (double)(cz - r) * voxel, (double)(cz + r + 1) * voxel - z)) -
+                             1e-9;
+            if (f <= 0.0) continue;
+            if (found >= k && t.worst < f * f) return;
+            if (f * f > dmax2) return;
+        }
+    }
+};
+
 // Pose P = (R row-major, t) at pose[0..11].
-template <int KM>
-__global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict__ src, int ns,
-                                                        const double* __restrict__ tgt, int nt, GicpGrid tgrid,
+template <int KM, class Target>
+__global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict__ src, int ns, Target tg,
                                                         int k, const double* __restrict__ pose,
                                                         double* __restrict__ part, int* __restrict__ corr) {
 #pragma clang fp contract(off)
@@ -327,10 +439,13 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
     const double X1 = ((Rm[3] * a0 + Rm[4] * a1) + Rm[5] * a2) + tv[1];
     const double X2 = ((Rm[6] * a0 + Rm[7] * a1) + Rm[8] * a2) + tv[2];
     TopK<KM> t;
-    if (active) knn_grid(tgt, nt, tgrid, k, X0, X1, X2, t);
+    if (active) tg.knn(k, X0, X1, X2, t);
+    const double* tgt = tg.d;
+    const size_t nt = tg.stride;
     double acc[kGicpVals];
 #pragma unroll
     for (int q = 0; q < kGicpVals; ++q) acc[q] = 0.0;
+    // every listed candidate lies within D_MAX
     int j = -1;
     if (active) {
         double best = DBL_MAX;
@@ -338,8 +453,8 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
         for (int s = 0; s < KM; ++s)
             if (s < k && t.i[s] != INT_MAX) {
                 const int c = t.i[s];
-                const double e0 = X0 - tgt[c], e1 = X1 - tgt[(size_t)nt + c], e2 = X2 - tgt[2 * (size_t)nt + c];
-                const double n0 = tgt[(size_t)9 * nt + c], n1 = tgt[(size_t)10 * nt + c], n2 = tgt[(size_t)11 * nt + c];
+                const double e0 = X0 - tgt[c], e1 = X1 - tgt[nt + c], e2 = X2 - tgt[2 * nt + c];
+                const double n0 = tgt[9 * nt + c], n1 = tgt[10 * nt + c], n2 = tgt[11 * nt + c];
                 const double dn = (n0 * e0 + n1 * e1) + n2 * e2;
                 const double ee = (e0 * e0 + e1 * e1) + e2 * e2;
                 const double ds = dn * dn + kGicpEps * ee;
@@ -348,11 +463,6 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
                     j = c;
                 }
             }
-        if (j >= 0) {
-            const double e0 = tgt[j] - X0, e1 = tgt[(size_t)nt + j] - X1, e2 = tgt[2 * (size_t)nt + j] - X2;
-            const double d2 = (e0 * e0 + e1 * e1) + e2 * e2;
-            if (!(d2 <= kGicpDMax * kGicpDMax)) j = -1;
-        }
     }
     if (corr && in) corr[i] = j;
     if (j >= 0) {
@@ -368,8 +478,8 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c)
                 C[r * 3 + c] = RC[r * 3 + 0] * Rm[c * 3 + 0] + RC[r * 3 + 1] * Rm[c * 3 + 1] + RC[r * 3 + 2] * Rm[c * 3 + 2];
-        const double cb[6] = {tgt[(size_t)3 * nt + j], tgt[(size_t)4 * nt + j], tgt[(size_t)5 * nt + j],
-                              tgt[(size_t)6 * nt + j], tgt[(size_t)7 * nt + j], tgt[(size_t)8 * nt + j]};
+        const double cb[6] = {tgt[3 * nt + j], tgt[4 * nt + j], tgt[5 * nt + j],
+                              tgt[6 * nt + j], tgt[7 * nt + j], tgt[8 * nt + j]};
         C[0] += cb[0];
         C[1] += cb[1];
         C[2] += cb[2];
@@ -385,7 +495,7 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
         const double det = C[0] * m00 + C[1] * (C[5] * C[6] - C[3] * C[8]) + C[2] * (C[3] * C[7] - C[4] * C[6]);
         const double id = 1.0 / det;
         const double M[9] = {m00 * id, m01 * id, m02 * id, m01 * id, m11 * id, m12 * id, m02 * id, m12 * id, m22 * id};
-        const double e[3] = {tgt[j] - X0, tgt[(size_t)nt + j] - X1, tgt[(size_t)2 * nt + j] - X2};
+        const double e[3] = {tgt[j] - X0, tgt[nt + j] - X1, tgt[2 * nt + j] - X2};
         // J = [-I | [X]x] (3 x 6)
         const double X[3] = {X0, X1, X2};
         double J[18];
@@ -578,14 +688,189 @@ void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam
     else hipLaunchKernelGGL(k_gicp_prepare<kGicpMaxK>, grid, blk, 0, s, k, set, n, gicp_grid(cam, R));
 }
 
+template <class Target>
+static void linearise_t(const double* src, int ns, const Target& tg, int k, const double* pose, double* part,
+                        int* corr, hipStream_t s) {
+    if (k <= 16)
+        hipLaunchKernelGGL((k_gicp_linearise<16, Target>), dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tg, k,
+                           pose, part, corr);
+    else
+        hipLaunchKernelGGL((k_gicp_linearise<kGicpMaxK, Target>), dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns,
+                           tg, k, pose, part, corr);
+}
+
 void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, const sgad_cam& tcam, int tR,
                            int k, const double* pose, double* part, int* corr, hipStream_t s) {
-    if (k <= 16)
-        hipLaunchKernelGGL(k_gicp_linearise<16>, dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tgt, nt,
-                           gicp_grid(tcam, tR), k, pose, part, corr);
-    else
-        hipLaunchKernelGGL(k_gicp_linearise<kGicpMaxK>, dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tgt, nt,
-                           gicp_grid(tcam, tR), k, pose, part, corr);
+    GridTarget tg{tgt, (size_t)nt, nt, gicp_grid(tcam, tR)};
+    linearise_t(src, ns, tg, k, pose, part, corr, s);
+}
+
+void launch_gicp_linearise_map(const double* src, int ns, const sgad_gmap& m, int k, const double* pose,
+                               double* part, int* corr, hipStream_t s) {
+    MapTarget tg{m.data, (size_t)m.capacity, (const long long*)m.keys, m.vals, m.slots - 1, m.voxel};
+    linearise_t(src, ns, tg, k, pose, part, corr, s);
+}
+
+// ---------------------------------------------------------------------------
+// Map maintenance
+// ---------------------------------------------------------------------------
+__global__ void k_gmap_reset(long long* keys, int* vals, int slots, int* count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += gridDim.x * blockDim.x) {
+        keys[i] = kEmpty;
+        vals[i] = INT_MIN;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = 0;
+}
+
+// World point of frame Gaussian i under the camera-to-world pose, in the
+// fixed order ((r0 a0 + r1 a1) + r2 a2) + t.
+__device__ __forceinline__ void world_point(const double* set, int n, int i, const double* P, double* w) {
+#pragma clang fp contract(off)
+    const double a0 = set[i], a1 = set[(size_t)n + i], a2 = set[2 * (size_t)n + i];
+    for (int r = 0; r < 3; ++r) w[r] = ((P[3 * r] * a0 + P[3 * r + 1] * a1) + P[3 * r + 2] * a2) + P[9 + r];
+}
+
+__device__ __forceinline__ bool voxel_of(const double* w, double voxel, long long* key) {
+    const long long x = (long long)floor(w[0] / voxel), y = (long long)floor(w[1] / voxel),
+                    z = (long long)floor(w[2] / voxel);
+    if (!voxel_in_range(x, y, z)) return false;
+    *key = voxel_pack(x, y, z);
+    return true;
+}
+
+// Pass 1: every valid frame Gaussian whose voxel is not already in the map
+// claims it; among one frame's claims on a voxel the lowest index wins.
+__global__ __launch_bounds__(256) void k_gmap_claim(const double* __restrict__ set, int n, const double* pose,
+                                                    long long* keys, int* vals, int mask, double voxel) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || set[2 * (size_t)n + i] == 0.0) return;
+    double P[12];
+    for (int r = 0; r < 12; ++r) P[r] = pose[r];
+    double w[3];
+    world_point(set, n, i, P, w);
+    long long key;
+    if (!voxel_of(w, voxel, &key)) return;
+    int s = voxel_hash(key, mask);
+    for (int p = 0; p <= mask; ++p) {
+        long long k = keys[s];
+        if (k == kEmpty) {
+            const long long prev = (long long)atomicCAS((unsigned long long*)&keys[s], (unsigned long long)kEmpty,
+                                                        (unsigned long long)key);
+            k = prev == kEmpty ? key : prev;
+        }
+        if (k == key) {
+            if (vals[s] < 0) atomicMax(&vals[s], -(i + 1));   // existing voxels hold an index >= 0
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+// Pass 2 (one block): the winners in index order are appended after the
+// map's current count (up to the capacity), moved into the world, and
+// their voxels finalised with their map index.
+__global__ __launch_bounds__(1024) void k_gmap_commit(const double* __restrict__ set, int n, const double* pose,
+                                                      const long long* keys, int* vals, int mask, double voxel,
+                                                      double* data, int cap, int* count) {
+    __shared__ int s_sum[16];
+    __shared__ int s_base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double P[12];
+    for (int r = 0; r < 12; ++r) P[r] = pose[r];
+    const int per = (n + 1023) / 1024, b = tid * per;
+    auto winner = [&](int i, int* slot) -> bool {
+        if (set[2 * (size_t)n + i] == 0.0) return false;
+        double w[3];
+        world_point(set, n, i, P, w);
+        long long key;
+        if (!voxel_of(w, voxel, &key)) return false;
+        const int s = map_find(keys, mask, key);
+        if (s < 0 || vals[s] != -(i + 1)) return false;
+        *slot = s;
+        return true;
+    };
+    int mine = 0;
+    for (int i = b; i < min(n, b + per); ++i) {
+        int sl;
+        mine += winner(i, &sl) ? 1 : 0;
+    }
+    // exclusive scan of the per-thread counts
+    int inc = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) s_sum[wave] = inc;
+    if (tid == 0) s_base = *count;
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wave; ++w) off += s_sum[w];
+    int pos = s_base + off + inc - mine;
+    for (int i = b; i < min(n, b + per); ++i) {
+        int sl;
+        if (!winner(i, &sl)) continue;
+        if (pos < cap) {
+            double w[3];
+            world_point(set, n, i, P, w);
+            const double ca[9] = {set[(size_t)3 * n + i], set[(size_t)4 * n + i], set[(size_t)5 * n + i],
+                                  set[(size_t)4 * n + i], set[(size_t)6 * n + i], set[(size_t)7 * n + i],
+                                  set[(size_t)5 * n + i], set[(size_t)7 * n + i], set[(size_t)8 * n + i]};
+            double RC[9], C[9];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    RC[r * 3 + c] = P[r * 3] * ca[c] + P[r * 3 + 1] * ca[3 + c] + P[r * 3 + 2] * ca[6 + c];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    C[r * 3 + c] = RC[r * 3] * P[c * 3] + RC[r * 3 + 1] * P[c * 3 + 1] + RC[r * 3 + 2] * P[c * 3 + 2];
+            const double nx = set[(size_t)9 * n + i], ny = set[(size_t)10 * n + i], nz = set[(size_t)11 * n + i];
+            const size_t st = (size_t)cap;
+            data[pos] = w[0];
+            data[st + pos] = w[1];
+            data[2 * st + pos] = w[2];
+            data[3 * st + pos] = C[0];
+            data[4 * st + pos] = C[1];
+            data[5 * st + pos] = C[2];
+            data[6 * st + pos] = C[4];
+            data[7 * st + pos] = C[5];
+            data[8 * st + pos] = C[8];
+            for (int r = 0; r < 3; ++r) data[(9 + r) * st + pos] = P[r * 3] * nx + P[r * 3 + 1] * ny + P[r * 3 + 2] * nz;
+            vals[sl] = pos;
+        } else {
+            vals[sl] = INT_MIN;   // T is full: the voxel stays free for later frames
+        }
+        ++pos;
+    }
+    __syncthreads();
+    if (tid == 1023) *count = min(cap, pos);
+}
+
+void launch_gmap_reset(const sgad_gmap& m, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmap_reset, dim3(std::min(1024, (m.slots + 255) / 256)), dim3(256), 0, s,
+                       (long long*)m.keys, m.vals, m.slots, m.count);
+}
+
+void launch_gmap_insert(const sgad_gmap& m, const double* set, int n, const double* pose, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmap_claim, dim3(gicp_blocks(n)), dim3(256), 0, s, set, n, pose, (long long*)m.keys,
+                       m.vals, m.slots - 1, m.voxel);
+    hipLaunchKernelGGL(k_gmap_commit, dim3(1), dim3(1024), 0, s, set, n, pose, (const long long*)m.keys, m.vals,
+                       m.slots - 1, m.voxel, m.data, m.capacity, m.count);
+}
+
+// Depth holes (<= 0) filled by D'/A where A >= alpha_min; valid depths kept.
+__global__ void k_fill_depth(int P, const float* depth, const float* rdepth, const float* ralpha, float alpha_min,
+                             float* out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+        const float d = depth[i];
+        float o = d;
+        if (!(d > 0.f)) o = ralpha[i] >= alpha_min ? rdepth[i] / ralpha[i] : 0.f;
+        out[i] = o;
+    }
+}
+
+void launch_fill_depth(int P, const float* depth, const float* rdepth, const float* ralpha, float alpha_min,
+                       float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_depth, dim3(std::min(4096, (P + 255) / 256)), dim3(256), 0, s, P, depth, rdepth,
+                       ralpha, alpha_min, out);
 }
 
 void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s) {

@@ -37,6 +37,12 @@ void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam
 void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, const sgad_cam& tcam, int tR,
                            int k, const double* pose, double* part, int* corr, hipStream_t s);
 void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s);
+void launch_gicp_linearise_map(const double* src, int ns, const sgad_gmap& m, int k, const double* pose,
+                               double* part, int* corr, hipStream_t s);
+void launch_gmap_reset(const sgad_gmap& m, hipStream_t s);
+void launch_gmap_insert(const sgad_gmap& m, const double* set, int n, const double* pose, hipStream_t s);
+void launch_fill_depth(int P, const float* depth, const float* rdepth, const float* ralpha, float alpha_min,
+                       float* out, hipStream_t s);
 void launch_gicp_solve(const double* part, int nb, double* pose, double* trace, int it, hipStream_t s);
 void launch_ssim(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
                  float* g_rgb, double* loss, hipStream_t s);
@@ -1121,6 +1127,99 @@ sgad_status sgad_gicp_track(sgad_ctx* c, const double* src, int n_src, const dou
     return SGAD_OK;
 }
 
+static sgad_status gmap_args(sgad_ctx* c, const sgad_gmap* m) {
+    if (!m || !m->data || !m->keys || !m->vals || !m->count) return fail(c, SGAD_EINVAL, "null pointer");
+    if (m->capacity < 1 || m->capacity > INT32_MAX / 12) return fail(c, SGAD_ERANGE, "capacity out of range");
+    if (m->slots < 2 || (m->slots & (m->slots - 1)) != 0 || m->slots / 2 < m->capacity)
+        return fail(c, SGAD_EINVAL, "slots must be a power of two >= 2 * capacity");
+    if (!(std::isfinite(m->voxel) && m->voxel >= 0.1 / 32)) return fail(c, SGAD_ERANGE, "voxel below D_MAX / 32");
+    return SGAD_OK;
+}
+
+sgad_status sgad_gmap_reset(sgad_ctx* c, const sgad_gmap* m, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (const sgad_status st = gmap_args(c, m)) return st;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick_stream(c, stream);
+    launch_gmap_reset(*m, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_gmap_insert(sgad_ctx* c, const sgad_gmap* m, const double* set, int n, const double* pose,
+                             void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (const sgad_status st = gmap_args(c, m)) return st;
+    if (!set || !pose) return fail(c, SGAD_EINVAL, "null pointer");
+    if (n < 1) return fail(c, SGAD_EINVAL, "empty set");
+    if (n > INT32_MAX / 12) return fail(c, SGAD_ERANGE, "set too large");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick_stream(c, stream);
+    TimeScope ts(c, "gmap_insert", s);
+    launch_gmap_insert(*m, set, n, pose, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+static sgad_status gicp_map_args(sgad_ctx* c, const double* src, int n_src, const sgad_gmap* m, int k,
+                                 const double* pose) {
+    if (const sgad_status st = gmap_args(c, m)) return st;
+    if (!src || !pose) return fail(c, SGAD_EINVAL, "null pointer");
+    if (n_src < 1) return fail(c, SGAD_EINVAL, "empty set");
+    if (n_src > INT32_MAX / 12) return fail(c, SGAD_ERANGE, "set too large");
+    if (k < 1 || k > gicp_max_k()) return fail(c, SGAD_ERANGE, "K_c must be 1..32");
+    return SGAD_OK;
+}
+
+sgad_status sgad_gicp_linearise_map(sgad_ctx* c, const double* src, int n_src, const sgad_gmap* m, int k,
+                                    const double* pose, double* out, int32_t* corr, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (const sgad_status st = gicp_map_args(c, src, n_src, m, k, pose)) return st;
+    if (!out) return fail(c, SGAD_EINVAL, "null pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick_stream(c, stream);
+    const int nb = gicp_blocks(n_src);
+    HIPCHK(c, ensure_c(c, c->gicp_part, (size_t)nb * gicp_vals() * sizeof(double), s));
+    double* part = (double*)c->gicp_part.p;
+    TimeScope ts(c, "gicp_linearise_map", s);
+    launch_gicp_linearise_map(src, n_src, *m, k, pose, part, corr, s);
+    launch_gicp_sum(part, nb, out, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_gicp_track_map(sgad_ctx* c, const double* src, int n_src, const sgad_gmap* m, int k, double* pose,
+                                int iters, double* trace, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (const sgad_status st = gicp_map_args(c, src, n_src, m, k, pose)) return st;
+    if (iters < 1) return fail(c, SGAD_EINVAL, "iters must be >= 1");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick_stream(c, stream);
+    const int nb = gicp_blocks(n_src);
+    HIPCHK(c, ensure_c(c, c->gicp_part, (size_t)nb * gicp_vals() * sizeof(double), s));
+    double* part = (double*)c->gicp_part.p;
+    TimeScope ts(c, "gicp_map_iteration", s);
+    for (int it = 0; it < iters; ++it) {
+        launch_gicp_linearise_map(src, n_src, *m, k, pose, part, nullptr, s);
+        launch_gicp_solve(part, nb, pose, trace, it, s);
+    }
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
+sgad_status sgad_fill_depth(sgad_ctx* c, int P, const float* depth, const float* rdepth, const float* ralpha,
+                            float alpha_min, float* out, void* stream) {
+    if (!c) return SGAD_EINVAL;
+    if (!depth || !rdepth || !ralpha || !out) return fail(c, SGAD_EINVAL, "null pointer");
+    if (P < 1) return fail(c, SGAD_EINVAL, "bad sizes");
+    if (!(alpha_min > 0.f && alpha_min <= 1.f)) return fail(c, SGAD_EINVAL, "alpha_min must be in (0, 1]");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick_stream(c, stream);
+    launch_fill_depth(P, depth, rdepth, ralpha, alpha_min, out, s);
+    HIPCHK(c, hipGetLastError());
+    return SGAD_OK;
+}
+
 sgad_status sgad_adam_step(sgad_ctx* c, int n_groups, const sgad_adam_group* groups, int step, float beta1,
                            float beta2, float eps, int zero_grad, void* stream) {
     if (!c) return SGAD_EINVAL;
@@ -1533,8 +1632,8 @@ sgad_status sgad_autotune(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int n_
     struct Cand {
         int tw, th, scf, scb;
     };
-    const Cand cands[] = {{16, 16, 0, 0}, {16, 8, 0, 0}, {32, 8, 0, 0}, {8, 8, 4, 16},
-                          {8, 8, 1, 16},  {8, 8, 2, 16}, {8, 8, 4, 32}};
+    const Cand cands[] = {{16, 16, 0, 0}, {16, 8, 0, 0}, {32, 8, 0, 0}, {8, 8, 4, 16}, {8, 8, 1, 16},
+                          {8, 8, 2, 16},  {8, 8, 4, 32}, {8, 8, 1, 32}, {8, 8, 2, 32}};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));

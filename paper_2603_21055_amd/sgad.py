@@ -59,6 +59,11 @@ class KfGrads(C.Structure):
                 ("d_offset", C.c_void_p)]
 
 
+class GMapC(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("keys", C.c_void_p), ("vals", C.c_void_p), ("count", C.c_void_p),
+                ("capacity", C.c_int32), ("slots", C.c_int32), ("voxel", C.c_double)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "sgad_create": (C.c_int, [C.c_int, C.POINTER(_P)]),
@@ -90,6 +95,11 @@ _SIGS = {
                                       _P]),
     "sgad_gicp_track": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_void_p, C.c_int, C.c_int, _P, C.c_int, _P,
                                   _P]),
+    "sgad_gmap_reset": (C.c_int, [_P, C.POINTER(GMapC), _P]),
+    "sgad_gmap_insert": (C.c_int, [_P, C.POINTER(GMapC), _P, C.c_int, _P, _P]),
+    "sgad_gicp_linearise_map": (C.c_int, [_P, _P, C.c_int, C.POINTER(GMapC), C.c_int, _P, _P, _P, _P]),
+    "sgad_gicp_track_map": (C.c_int, [_P, _P, C.c_int, C.POINTER(GMapC), C.c_int, _P, C.c_int, _P, _P]),
+    "sgad_fill_depth": (C.c_int, [_P, C.c_int, _P, _P, _P, C.c_float, _P, _P]),
     "sgad_adam_step": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_int, C.c_float, C.c_float, C.c_float,
                                  C.c_int, _P]),
     "sgad_timing_report": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
@@ -145,6 +155,30 @@ def _ptr(t):
     if t is None:
         return None
     return C.c_void_p(t.data_ptr())
+
+
+class GlobalMap:
+    """Device storage of the global set T: data float64 [12, capacity], the
+    voxel hash (keys int64, vals int32, 2 x capacity rounded up to a power of
+    two) and the count."""
+
+    def __init__(self, device, capacity, voxel=0.02):
+        import torch
+        capacity = int(capacity)
+        slots = 1 << max(1, (2 * capacity - 1).bit_length())
+        self.data = torch.zeros((12, capacity), dtype=torch.float64, device=device)
+        self.keys = torch.empty(slots, dtype=torch.int64, device=device)
+        self.vals = torch.empty(slots, dtype=torch.int32, device=device)
+        self.count_t = torch.zeros(1, dtype=torch.int32, device=device)
+        self.c = GMapC(self.data.data_ptr(), self.keys.data_ptr(), self.vals.data_ptr(), self.count_t.data_ptr(),
+                       capacity, slots, float(voxel))
+
+    def count(self):
+        return int(self.count_t.item())
+
+    def view(self):
+        """The Gaussians in use, float64 [12, count]."""
+        return self.data[:, :self.count()]
 
 
 def _cam(cam) -> Cam:
@@ -428,6 +462,53 @@ class Context:
         self._check(self.lib.sgad_gicp_track(self.h, _ptr(src), src.shape[1], _ptr(tgt), tgt.shape[1], C.byref(c),
                                              int(ratio), int(k), _ptr(pose), int(iters), _ptr(trace),
                                              _stream(stream)))
+
+    # ------------------------------------------------------- global set T
+    def gmap_new(self, capacity, voxel=0.02):
+        """An empty global set T of `capacity` Gaussians on this device."""
+        m = GlobalMap(self.device, capacity, voxel)
+        self.gmap_reset(m)
+        return m
+
+    def gmap_reset(self, m, stream=None):
+        self._check(self.lib.sgad_gmap_reset(self.h, C.byref(m.c), _stream(stream)))
+
+    def gmap_insert(self, m, set_, pose, stream=None):
+        """Add a tracked frame's set [12, n] under its camera-to-world pose
+        (device float64 [12])."""
+        import torch
+        _check_tensor(set_, "set", self.device, torch.float64)
+        _check_tensor(pose, "pose", self.device, torch.float64)
+        self._check(self.lib.sgad_gmap_insert(self.h, C.byref(m.c), _ptr(set_), set_.shape[1], _ptr(pose),
+                                              _stream(stream)))
+
+    def gicp_linearise_map(self, src, m, k, pose, out, corr=None, stream=None):
+        """gicp_linearise against T (camera-to-world pose; corr indexes T)."""
+        import torch
+        for name, t in (("src", src), ("pose", pose), ("out", out)):
+            _check_tensor(t, name, self.device, torch.float64)
+        _check_tensor(corr, "corr", self.device, torch.int32)
+        self._check(self.lib.sgad_gicp_linearise_map(self.h, _ptr(src), src.shape[1], C.byref(m.c), int(k),
+                                                     _ptr(pose), _ptr(out), _ptr(corr), _stream(stream)))
+
+    def gicp_track_map(self, src, m, k, pose, iters, trace=None, stream=None):
+        """gicp_track against T."""
+        import torch
+        for name, t in (("src", src), ("pose", pose)):
+            _check_tensor(t, name, self.device, torch.float64)
+        _check_tensor(trace, "trace", self.device, torch.float64)
+        self._check(self.lib.sgad_gicp_track_map(self.h, _ptr(src), src.shape[1], C.byref(m.c), int(k),
+                                                 _ptr(pose), int(iters), _ptr(trace), _stream(stream)))
+
+    def fill_depth(self, depth, rdepth, ralpha, out, alpha_min=0.5, stream=None):
+        """Depth holes filled by rendered depth / alpha where alpha >= alpha_min."""
+        for name, t in (("depth", depth), ("rdepth", rdepth), ("ralpha", ralpha), ("out", out)):
+            _check_tensor(t, name, self.device)
+        n = depth.numel()
+        if not (rdepth.numel() == ralpha.numel() == out.numel() == n):
+            raise ValueError("fill_depth: sizes differ")
+        self._check(self.lib.sgad_fill_depth(self.h, n, _ptr(depth), _ptr(rdepth), _ptr(ralpha),
+                                             float(alpha_min), _ptr(out), _stream(stream)))
 
     # -------------------------------------------------------------- conv net
     def conv_weights(self, cin, cout, w, w_bf16, wt_bf16=None, stream=None):
