@@ -173,6 +173,9 @@ sgad_status sgad_render_fwd(sgad_ctx* ctx, int n_kf, const sgad_keyframe* kf,
  *     stay fixed (Sec. 3.2: neighbours are not learnable).
  *   d_pose [n_jobs][6]: WRITTEN, (rho, phi) left-twist gradient of each job's
  *     view pose; may be NULL.
+ * With 8x8 tiles the tiles' shares are first summed per keyframe Gaussian in
+ * a 32-byte record of the saved slot's workspace (n_kf * H * W records) and
+ * then added to grads by one more launch, which clears the records again.
  */
 sgad_status sgad_render_bwd(sgad_ctx* ctx, sgad_saved* saved,
                             const float* g_rgb, const float* g_depth, const float* g_alpha,
@@ -182,7 +185,8 @@ sgad_status sgad_render_bwd(sgad_ctx* ctx, sgad_saved* saved,
 /*
  * Device workspace (bytes) that sgad_render_fwd and sgad_render_bwd of this
  * workload hold in one saved slot: preprocessed records, tile tables, the
- * instance keys and contributor masks, per-pixel state, pose partials.
+ * instance keys and contributor masks, per-pixel state, pose partials and
+ * the adjoint's per-Gaussian gradient records.
  * instances: the instance count the key list is sized for (0: the size of a
  * first call, before the exact count is known; after it the library sizes
  * the list to 1.25x the count + 65536).  Computed for 8x8 tiles, the shape

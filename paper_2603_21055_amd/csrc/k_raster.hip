@@ -277,8 +277,8 @@ bool launch_fwd(const Geometry& G, const RenderBufs& B, float* rgb, float* depth
 
 bool launch_bwd(const Geometry& G, const RenderBufs& B, const float* g_rgb, const float* g_depth,
                 const float* g_alpha, const KfGradPtrs* grads, uint32_t lo, uint32_t hi, float* pose_part,
-                float* d_pose, hipStream_t s) {
-    BwdArgs A{g_rgb, g_depth, g_alpha, grads, lo, hi, pose_part};
+                float* acc, float* d_pose, hipStream_t s) {
+    BwdArgs A{g_rgb, g_depth, g_alpha, grads, lo, hi, pose_part, acc};
     if (G.TW == 8 && G.TH == 8) {
         if (!launch_bwd8(G, B, A, G.sc_bwd, s)) return false;
     }

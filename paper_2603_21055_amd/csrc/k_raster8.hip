@@ -575,6 +575,8 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
             wave_lds_sync();
         }
         // lane = chunk entry: chain rule to the keyframe parameters and the pose
+        int gidx = -1;   // the entry's keyframe Gaussian when it has parameter gradients
+        float gv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (lane < n) {
             bool any = false;
 #pragma unroll
@@ -594,8 +596,27 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 v[9] = r[2];
                 const uint32_t gid = (uint32_t)ck;
                 const int kf = (int)(gid / (uint32_t)G.N);
-                const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
-                chain_rule(G, A, vfx, vfy, kf, pix, c2r.w, c3r, cdr, v, pose);
+                if (chain_rule_vals(A, vfx, vfy, kf, c2r.w, c3r, cdr, v, pose, gv)) gidx = (int)gid;
+            }
+        }
+        // the shares go out eight lanes per entry, one lane per value of the
+        // entry's 32-byte accumulator record, so that one atomic instruction
+        // covers eight records instead of 64 scattered words; staged in the
+        // matrix area, which the next chunk's phase A overwrites
+        const uint64_t has = __ballot(gidx >= 0);
+        if (has != 0ull) {
+            float* st = s_M;
+            *(float4*)&st[lane * 8] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+            *(float4*)&st[lane * 8 + 4] = make_float4(gv[4], gv[5], __int_as_float(gidx), 0.f);
+            wave_lds_sync();
+            const int sub8 = lane & 7, grp8 = lane >> 3;
+#pragma unroll
+            for (int rr = 0; rr < 8; ++rr) {
+                if (((has >> (8 * rr)) & 0xffull) == 0ull) continue;
+                const int e = rr * 8 + grp8;
+                const int id = __float_as_int(st[e * 8 + 6]);
+                const float val = st[e * 8 + sub8];
+                if (id >= 0 && sub8 < 6) global_add(&A.acc[(size_t)id * 8 + sub8], val);
             }
         }
         ck = nk;
@@ -625,16 +646,45 @@ bool launch_fwd8(const Geometry& G, const RenderBufs& B, const FwdOut& O, int sc
     return true;
 }
 
+// The accumulated shares into the gradient planes of the learnable
+// keyframes (+=), clearing the accumulator for the next adjoint; records
+// that received nothing are left alone.
+__global__ __launch_bounds__(256) void k_grad_unpack(int N, const KfGradPtrs* __restrict__ grads, uint32_t lo,
+                                                     uint32_t hi, float* __restrict__ acc) {
+    const int kf = blockIdx.y;
+    const bool learn = kf < 32 ? ((lo >> kf) & 1u) : ((hi >> (kf - 32)) & 1u);
+    if (!learn) return;
+    const KfGradPtrs gp = grads[kf];
+    float4* a = (float4*)acc + (size_t)kf * N * 2;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < N; i += (int)(gridDim.x * blockDim.x)) {
+        const float4 x = a[2 * (size_t)i], y = a[2 * (size_t)i + 1];
+        if (x.x != 0.f || x.y != 0.f || x.z != 0.f || x.w != 0.f || y.x != 0.f || y.y != 0.f) {
+            gp.d_offset[i] += x.x;
+            gp.d_radius[i] += x.y;
+            gp.d_opacity[i] += x.z;
+            gp.d_rgb[i] += x.w;
+            gp.d_rgb[(size_t)N + i] += y.x;
+            gp.d_rgb[2 * (size_t)N + i] += y.y;
+            a[2 * (size_t)i] = z4;
+            a[2 * (size_t)i + 1] = z4;
+        }
+    }
+}
+
 template <int SUB>
 static void bwd8_t(const Geometry& G, const RenderBufs& B, const BwdArgs& A, hipStream_t s) {
     hipLaunchKernelGGL((k_bwd8<SUB>), dim3(G.n_jobs * G.ntiles), dim3(64), 0, s, G, B, A);
 }
 
 bool launch_bwd8(const Geometry& G, const RenderBufs& B, const BwdArgs& A, int sub, hipStream_t s) {
-    if (G.TW != 8 || G.TH != 8) return false;
+    if (G.TW != 8 || G.TH != 8 || !A.acc) return false;
     if (sub == 32) bwd8_t<32>(G, B, A, s);
     else if (sub == 16) bwd8_t<16>(G, B, A, s);
     else return false;
+    const int bx = std::min((G.N + 1023) / 1024, 1024);
+    hipLaunchKernelGGL(k_grad_unpack, dim3(bx, G.n_kf), dim3(256), 0, s, G.N, A.grads, A.learn_lo, A.learn_hi,
+                       A.acc);
     return true;
 }
 

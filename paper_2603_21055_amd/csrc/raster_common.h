@@ -63,6 +63,11 @@ struct BwdArgs {
     const KfGradPtrs* grads;  // [n_kf]
     uint32_t learn_lo, learn_hi;
     float* pose_part;         // [n_jobs * ntiles][6]
+    // 8x8 adjoint: per keyframe Gaussian gid = kf * N + pix, 8 floats at
+    // acc[8 gid] (offset, radius, opacity, r, g, b, unused, unused) that the
+    // tiles add their shares to, moved into the gradient planes afterwards;
+    // null: the shares go straight to the planes
+    float* acc;
 };
 
 // Record of the instance `key` of job `job`.
@@ -87,9 +92,11 @@ __device__ __forceinline__ void global_add(float* p, float v) {
 // Chain rule of one (Gaussian, tile) gradient to the keyframe parameters and
 // the view pose.  v = [g_mx, g_my, g_a, g_b, g_c, g_o, g_z, g_c0, g_c1, g_c2];
 // (fx, fy) the view's focal lengths, z the view depth, r3 = [x, y, r, sign]
-// and d the offset direction of the Gaussian's preprocessed data.
-__device__ __forceinline__ void chain_rule(const Geometry& G, const BwdArgs& A, float fx, float fy, int kf,
-                                           int pix, float z, float4 r3, float4 d, const float* v, float* pose) {
+// and d the offset direction of the Gaussian's preprocessed data.  Adds the
+// pose term to `pose`; for a learnable keyframe writes the parameter
+// gradients (offset, radius, opacity, r, g, b) to out and returns true.
+__device__ __forceinline__ bool chain_rule_vals(const BwdArgs& A, float fx, float fy, int kf, float z, float4 r3,
+                                                float4 d, const float* v, float* pose, float* out) {
     const float x = r3.x, y = r3.y;
     const float r = r3.z;
     const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz, iz4 = iz2 * iz2, iz5 = iz4 * iz;
@@ -120,15 +127,28 @@ __device__ __forceinline__ void chain_rule(const Geometry& G, const BwdArgs& A, 
     pose[4] += z * gx - x * gz;
     pose[5] += x * gy - y * gx;
     const bool learn = kf < 32 ? ((A.learn_lo >> kf) & 1u) : ((A.learn_hi >> (kf - 32)) & 1u);
-    if (!learn) return;
-    const float g_off = gx * d.x + gy * d.y + gz * d.z;
+    if (!learn) return false;
+    out[0] = gx * d.x + gy * d.y + gz * d.z;
+    out[1] = g_r;
+    out[2] = v[5];
+    out[3] = v[7];
+    out[4] = v[8];
+    out[5] = v[9];
+    return true;
+}
+
+// The same, adding the parameter gradients to the keyframe's gradient planes.
+__device__ __forceinline__ void chain_rule(const Geometry& G, const BwdArgs& A, float fx, float fy, int kf,
+                                           int pix, float z, float4 r3, float4 d, const float* v, float* pose) {
+    float o[6];
+    if (!chain_rule_vals(A, fx, fy, kf, z, r3, d, v, pose, o)) return;
     const KfGradPtrs gp = A.grads[kf];
-    global_add(&gp.d_offset[pix], g_off);
-    global_add(&gp.d_radius[pix], g_r);
-    global_add(&gp.d_opacity[pix], v[5]);
-    global_add(&gp.d_rgb[pix], v[7]);
-    global_add(&gp.d_rgb[(size_t)G.N + pix], v[8]);
-    global_add(&gp.d_rgb[2 * (size_t)G.N + pix], v[9]);
+    global_add(&gp.d_offset[pix], o[0]);
+    global_add(&gp.d_radius[pix], o[1]);
+    global_add(&gp.d_opacity[pix], o[2]);
+    global_add(&gp.d_rgb[pix], o[3]);
+    global_add(&gp.d_rgb[(size_t)G.N + pix], o[4]);
+    global_add(&gp.d_rgb[2 * (size_t)G.N + pix], o[5]);
 }
 
 // The same, reading the record of the instance `key` of job `job`.

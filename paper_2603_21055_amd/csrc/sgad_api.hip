@@ -22,7 +22,7 @@ bool launch_fwd(const Geometry& G, const RenderBufs& B, float* rgb, float* depth
                 hipStream_t s);
 bool launch_bwd(const Geometry& G, const RenderBufs& B, const float* g_rgb, const float* g_depth,
                 const float* g_alpha, const KfGradPtrs* grads, uint32_t lo, uint32_t hi, float* pose_part,
-                float* d_pose, hipStream_t s);
+                float* acc, float* d_pose, hipStream_t s);
 void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const float* t_rgb, const float* t_dep,
                float w_rgb, float w_dep, uint32_t* count, float* g_rgb, float* g_dep, double* loss,
                hipStream_t s);
@@ -90,6 +90,7 @@ struct sgad_saved {
     hipStream_t stream = nullptr;
     // device buffers (grow-only)
     DevBuf params, pre, tiles, keys, pix, pose_part, status, gradptrs, cmask;
+    DevBuf gacc;   // 8x8 adjoint's per-Gaussian gradient accumulator, kept zero between adjoints
     uint32_t capacity = 0;
     uint32_t last_max_seg = 0xffffffffu;  // longest segment seen by the last finished forward
     bool sized = false;
@@ -359,8 +360,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Device buffers of one saved slot (a forward and its adjoint), in bytes;
 // the forward allocates exactly these and sgad_workspace_bytes reports them.
 struct SlotBytes {
-    size_t params, pre, tiles, pix, pose_part, status, keys, cmask, gradptrs;
-    size_t total() const { return params + pre + tiles + pix + pose_part + status + keys + cmask + gradptrs; }
+    size_t params, pre, tiles, pix, pose_part, status, keys, cmask, gradptrs, gacc;
+    size_t total() const {
+        return params + pre + tiles + pix + pose_part + status + keys + cmask + gradptrs + gacc;
+    }
 };
 
 SlotBytes slot_bytes(int n_kf, int n_pairs, int n_jobs, size_t N, size_t P, size_t M, size_t capacity) {
@@ -376,6 +379,7 @@ SlotBytes slot_bytes(int n_kf, int n_pairs, int n_jobs, size_t N, size_t P, size
     b.keys = capacity * 8;
     b.cmask = (capacity / 64 + M + 1) * 64 * 8;
     b.gradptrs = align256(sizeof(KfGradPtrs) * n_kf);
+    b.gacc = (size_t)n_kf * N * 32;
     return b;
 }
 
@@ -512,7 +516,7 @@ sgad_saved* acquire_sized(sgad_ctx* c, const size_t* key) {
 
 void free_slot(sgad_saved* s) {
     for (DevBuf* b : {&s->params, &s->pre, &s->tiles, &s->keys, &s->pix, &s->pose_part, &s->status, &s->gradptrs,
-                      &s->cmask})
+                      &s->cmask, &s->gacc})
         if (b->p) (void)hipFree(b->p);
     for (PinBuf* b : {&s->up, &s->up_grad})
         if (b->p) (void)hipHostFree(b->p);
@@ -816,6 +820,10 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     HIPCHK(c, ensure_c(c, S->pix, sb.pix, s));
     HIPCHK(c, ensure_c(c, S->pose_part, sb.pose_part, s));
     HIPCHK(c, ensure_c(c, S->status, sb.status, s));
+    if (S->gacc.bytes < sb.gacc) {
+        HIPCHK(c, ensure_c(c, S->gacc, sb.gacc, s));
+        launch_fill_f32((float*)S->gacc.p, (int64_t)(S->gacc.bytes / 4), 0.f, s);
+    }
     if (std::memcmp(size_key, S->size_key, sizeof(size_key)) != 0) {
         S->sized = false;
         S->last_max_seg = 0xffffffffu;
@@ -964,7 +972,7 @@ sgad_status sgad_render_bwd(sgad_ctx* c, sgad_saved* S, const float* g_rgb, cons
     {
         TimeScope ts(c, "composite_bwd", s);
         if (!launch_bwd(G, S->B, g_rgb, g_depth, g_alpha, (const KfGradPtrs*)S->gradptrs.p, learn_lo, learn_hi,
-                        (float*)S->pose_part.p, d_pose, s))
+                        (float*)S->pose_part.p, (float*)S->gacc.p, d_pose, s))
             return fail(c, SGAD_EINVAL, "unsupported tile shape");
     }
     HIPCHK(c, hipGetLastError());

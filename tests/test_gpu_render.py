@@ -136,8 +136,9 @@ def test_wave_tile_variants_do_not_change_forward(ctx):
 
 def test_workspace_bytes(ctx):
     """The slot sizes the forward allocates: records 92 B per Gaussian-view
-    pair, tile tables, keys (8 B each) with their contributor masks, and
-    per-pixel state; the key list grows with the instance count."""
+    pair, tile tables, keys (8 B each) with their contributor masks,
+    per-pixel state and the adjoint's 32 B gradient record per keyframe
+    Gaussian; the key list grows with the instance count."""
     sc = synth.small_scene(27, 64, 48, n_kf=2, n_views=2)
     kfs_d = H.upload(sc["kfs"], ctx.device)
     jobs = [(0, [0, 1]), (1, [1])]
@@ -145,7 +146,7 @@ def test_workspace_bytes(ctx):
     b1 = ctx.workspace_bytes(kfs_d, sc["views"], jobs, instances=100_000)
     b2 = ctx.workspace_bytes(kfs_d, sc["views"], jobs, instances=200_000)
     npairs, N, P, M = 3, 64 * 48, 64 * 48, 2 * 8 * 6
-    floor = npairs * N * 92 + 2 * P * 8 + (4 * M + 2) * 4 + M * 24
+    floor = npairs * N * 92 + 2 * P * 8 + (4 * M + 2) * 4 + M * 24 + 2 * N * 32
     assert b0 > floor and b1 > floor
     # 100,000 more instances: 1.25x as many keys, 8 B each, and their masks
     # (8 B per key, allocated in whole 64-key chunks)
