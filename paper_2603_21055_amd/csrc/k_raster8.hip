@@ -111,6 +111,31 @@ __device__ __forceinline__ TileItem tile_item(const Geometry& G, const RenderBuf
     return t;
 }
 
+// Two front-to-back compositing steps with opacities a0 then a1 (0: a skipped
+// candidate, which changes nothing), evaluated without branches so that the
+// two candidates' work can overlap.  A step that would take T below kTMin
+// ends the pixel's walk: neither it nor the step after it is applied.
+// Returns the number of steps applied (0, 1 or 2); T >= kTMin on entry.
+__device__ __forceinline__ int composite2(float a0, float4 c0, float a1, float4 c1, float& T, float& cr, float& cg,
+                                          float& cb, float& dd) {
+    const float t0 = T * (1.f - a0);
+    const bool ok0 = t0 >= kTMin;
+    const float t1 = t0 * (1.f - a1);
+    const bool ok1 = ok0 && t1 >= kTMin;
+    const float w0 = ok0 ? a0 * T : 0.f;
+    const float w1 = ok1 ? a1 * t0 : 0.f;
+    cr += w0 * c0.x;
+    cg += w0 * c0.y;
+    cb += w0 * c0.z;
+    dd += w0 * c0.w;
+    cr += w1 * c1.x;
+    cg += w1 * c1.y;
+    cb += w1 * c1.z;
+    dd += w1 * c1.w;
+    T = ok1 ? t1 : (ok0 ? t0 : T);
+    return ok1 ? 2 : (ok0 ? 1 : 0);
+}
+
 __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O) {
     __shared__ float4 s_e[64][3];
     __shared__ uint64_t s_m[16];
@@ -162,47 +187,26 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
                 const bool two = m != 0ull;
                 const int b1 = two ? (int)__builtin_ctzll(m) : b0;
                 if (two) m &= m - 1ull;
-                const float4 eu0 = s_e[b0][0], eg0 = s_e[b0][1];
-                const float4 eu1 = s_e[b1][0], eg1 = s_e[b1][1];
+                const float4 eu0 = s_e[b0][0], eg0 = s_e[b0][1], ec0 = s_e[b0][2];
+                const float4 eu1 = s_e[b1][0], eg1 = s_e[b1][1], ec1 = s_e[b1][2];
                 const float dx0 = (fpx - eu0.x) - eu0.z, dy0 = (fpy - eu0.y) - eu0.w;
                 const float dx1 = (fpx - eu1.x) - eu1.z, dy1 = (fpy - eu1.y) - eu1.w;
                 const float q0 = pair_q(dx0, dy0, eg0.x, eg0.y, eg0.z);
                 const float q1 = pair_q(dx1, dy1, eg1.x, eg1.y, eg1.z);
                 const float al0 = fminf(kAlphaMax, eg0.w * gauss_of_q(q0));
                 const float al1 = fminf(kAlphaMax, eg1.w * gauss_of_q(q1));
-                if (q0 <= kQCut && al0 >= kAlphaMin) {
-                    const float test = T * (1.f - al0);
-                    if (test < kTMin) {
-                        done = true;
-                        break;
-                    }
-                    const float w = al0 * T;
-                    const float4 c = s_e[b0][2];
-                    cr += w * c.x;
-                    cg += w * c.y;
-                    cb += w * c.z;
-                    dd += w * c.w;
-                    T = test;
-                    ++cnt;
-                    last = (uint32_t)(c0 + b0 + 1);
-                    cm |= 1ull << b0;
-                }
-                if (two && q1 <= kQCut && al1 >= kAlphaMin) {
-                    const float test = T * (1.f - al1);
-                    if (test < kTMin) {
-                        done = true;
-                        break;
-                    }
-                    const float w = al1 * T;
-                    const float4 c = s_e[b1][2];
-                    cr += w * c.x;
-                    cg += w * c.y;
-                    cb += w * c.z;
-                    dd += w * c.w;
-                    T = test;
-                    ++cnt;
-                    last = (uint32_t)(c0 + b1 + 1);
-                    cm |= 1ull << b1;
+                const bool v0 = q0 <= kQCut && al0 >= kAlphaMin;
+                const bool v1 = two && q1 <= kQCut && al1 >= kAlphaMin;
+                // a skipped candidate composites with alpha 0, which leaves
+                // T and the sums exactly as they are
+                const int ap = composite2(v0 ? al0 : 0.f, ec0, v1 ? al1 : 0.f, ec1, T, cr, cg, cb, dd);
+                const bool u0 = v0 && ap >= 1, u1 = v1 && ap == 2;
+                cnt += (u0 ? 1 : 0) + (u1 ? 1 : 0);
+                last = u1 ? (uint32_t)(c0 + b1 + 1) : (u0 ? (uint32_t)(c0 + b0 + 1) : last);
+                cm |= (u0 ? 1ull << b0 : 0ull) | (u1 ? 1ull << b1 : 0ull);
+                if (ap < 2) {
+                    done = true;
+                    break;
                 }
             }
         }
@@ -309,49 +313,27 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
                 const bool two = m != 0ull;
                 const int e1 = two ? ch * 64 + (int)__builtin_ctzll(m) : e0;
                 if (two) m &= m - 1ull;
-                const float4 eu0 = s_e[e0][0], eg0 = s_e[e0][1];
-                const float4 eu1 = s_e[e1][0], eg1 = s_e[e1][1];
+                const float4 eu0 = s_e[e0][0], eg0 = s_e[e0][1], ec0 = s_e[e0][2];
+                const float4 eu1 = s_e[e1][0], eg1 = s_e[e1][1], ec1 = s_e[e1][2];
                 const float dx0 = (fpx - eu0.x) - eu0.z, dy0 = (fpy - eu0.y) - eu0.w;
                 const float dx1 = (fpx - eu1.x) - eu1.z, dy1 = (fpy - eu1.y) - eu1.w;
                 const float q0 = pair_q(dx0, dy0, eg0.x, eg0.y, eg0.z);
                 const float q1 = pair_q(dx1, dy1, eg1.x, eg1.y, eg1.z);
                 const float al0 = fminf(kAlphaMax, eg0.w * gauss_of_q(q0));
                 const float al1 = fminf(kAlphaMax, eg1.w * gauss_of_q(q1));
-                if (q0 <= kQCut && al0 >= kAlphaMin) {
-                    const float test = T * (1.f - al0);
-                    if (test < kTMin) {
-                        done = true;
-                        break;
-                    }
-                    const float w = al0 * T;
-                    const float4 c = s_e[e0][2];
-                    cr += w * c.x;
-                    cg += w * c.y;
-                    cb += w * c.z;
-                    dd += w * c.w;
-                    T = test;
-                    ++cnt;
-                    last = (uint32_t)(c0 + e0 + 1);
+                const bool v0 = q0 <= kQCut && al0 >= kAlphaMin;
+                const bool v1 = two && q1 <= kQCut && al1 >= kAlphaMin;
+                const int ap = composite2(v0 ? al0 : 0.f, ec0, v1 ? al1 : 0.f, ec1, T, cr, cg, cb, dd);
+                const bool u0 = v0 && ap >= 1, u1 = v1 && ap == 2;
+                cnt += (u0 ? 1 : 0) + (u1 ? 1 : 0);
+                last = u1 ? (uint32_t)(c0 + e1 + 1) : (u0 ? (uint32_t)(c0 + e0 + 1) : last);
 #pragma unroll
-                    for (int i = 0; i < SCH; ++i) cm[i] |= (e0 >> 6) == i ? 1ull << (e0 & 63) : 0ull;
-                }
-                if (two && q1 <= kQCut && al1 >= kAlphaMin) {
-                    const float test = T * (1.f - al1);
-                    if (test < kTMin) {
-                        done = true;
-                        break;
-                    }
-                    const float w = al1 * T;
-                    const float4 c = s_e[e1][2];
-                    cr += w * c.x;
-                    cg += w * c.y;
-                    cb += w * c.z;
-                    dd += w * c.w;
-                    T = test;
-                    ++cnt;
-                    last = (uint32_t)(c0 + e1 + 1);
-#pragma unroll
-                    for (int i = 0; i < SCH; ++i) cm[i] |= (e1 >> 6) == i ? 1ull << (e1 & 63) : 0ull;
+                for (int i = 0; i < SCH; ++i)
+                    cm[i] |= ((u0 && (e0 >> 6) == i) ? 1ull << (e0 & 63) : 0ull) |
+                             ((u1 && (e1 >> 6) == i) ? 1ull << (e1 & 63) : 0ull);
+                if (ap < 2) {
+                    done = true;
+                    break;
                 }
             }
         }
@@ -489,6 +471,9 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
             uint32_t cmask = 0u;   // entries of the sub-chunk this pixel contributed to
             // dL/dalpha = sum_c g_c (c T - S_c / (1 - alpha)) + gA T_final / (1 - alpha)
             //           = T (g . c) - (g . S - gA T_final) / (1 - alpha)
+            // cell `bit` of the pixel's matrix row gets (w, gq); the row's
+            // padding cell (bit = SUB) takes the write of an absent second
+            // candidate, whose alpha 0 leaves T and g . S exactly as they are
             auto contribute = [&](float alpha, float raw, float4 c, int bit) {
                 const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
                 T = T * inv;
@@ -498,7 +483,6 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 GS += w * gc;
                 const float gq = raw < kAlphaMax ? -0.5f * alpha * gal : 0.f;
                 *(float2*)&s_M[lane * LS + 2 * bit] = make_float2(w, gq);
-                cmask |= 1u << bit;
             };
             while (m != 0u) {
                 const int b0 = 31 - (int)__builtin_clz(m);
@@ -516,9 +500,11 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 const float q1 = pair_q(dx1, dy1, eg1.x, eg1.y, eg1.z);
                 const float raw0 = eg0.w * gauss_of_q(q0);
                 const float raw1 = eg1.w * gauss_of_q(q1);
-                const float al0 = fminf(kAlphaMax, raw0), al1 = fminf(kAlphaMax, raw1);
+                const float al0 = fminf(kAlphaMax, raw0);
+                const float al1 = two ? fminf(kAlphaMax, raw1) : 0.f;
                 contribute(al0, raw0, ec0, b0);
-                if (two) contribute(al1, raw1, ec1, b1);
+                contribute(al1, raw1, ec1, two ? b1 : SUB);
+                cmask |= (1u << b0) | (1u << b1);
             }
             // transpose the contributions: lane (grp, sub) takes the pixel set
             // of entry `sub` (one ballot per entry, published by lane 0)
