@@ -279,9 +279,9 @@ bool launch_bwd(const Geometry& G, const RenderBufs& B, const float* g_rgb, cons
                 const float* g_alpha, const KfGradPtrs* grads, uint32_t lo, uint32_t hi, float* pose_part,
                 float* acc, float* d_pose, hipStream_t s) {
     BwdArgs A{g_rgb, g_depth, g_alpha, grads, lo, hi, pose_part, acc};
-    if (G.TW == 8 && G.TH == 8) {
-        if (!launch_bwd8(G, B, A, G.sc_bwd, s)) return false;
-    }
+    // 8x8: the pose sums and the gradient records are finished by
+    // launch_bwd_finish, which the caller launches next
+    if (G.TW == 8 && G.TH == 8) return launch_bwd8(G, B, A, G.sc_bwd, s);
     else if (G.TW == 16 && G.TH == 8) bwd_t<16, 8>(G, B, A, s);
     else if (G.TW == 16 && G.TH == 16) bwd_t<16, 16>(G, B, A, s);
     else if (G.TW == 32 && G.TH == 8) bwd_t<32, 8>(G, B, A, s);

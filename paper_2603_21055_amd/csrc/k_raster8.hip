@@ -632,30 +632,62 @@ bool launch_fwd8(const Geometry& G, const RenderBufs& B, const FwdOut& O, int sc
     return true;
 }
 
-// The accumulated shares into the gradient planes of the learnable
-// keyframes (+=), clearing the accumulator for the next adjoint; records
-// that received nothing are left alone.
-__global__ __launch_bounds__(256) void k_grad_unpack(int N, const KfGradPtrs* __restrict__ grads, uint32_t lo,
-                                                     uint32_t hi, float* __restrict__ acc) {
-    const int kf = blockIdx.y;
-    const bool learn = kf < 32 ? ((lo >> kf) & 1u) : ((hi >> (kf - 32)) & 1u);
-    if (!learn) return;
-    const KfGradPtrs gp = grads[kf];
-    float4* a = (float4*)acc + (size_t)kf * N * 2;
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < N; i += (int)(gridDim.x * blockDim.x)) {
-        const float4 x = a[2 * (size_t)i], y = a[2 * (size_t)i + 1];
-        if (x.x != 0.f || x.y != 0.f || x.z != 0.f || x.w != 0.f || y.x != 0.f || y.y != 0.f) {
-            gp.d_offset[i] += x.x;
-            gp.d_radius[i] += x.y;
-            gp.d_opacity[i] += x.z;
-            gp.d_rgb[i] += x.w;
-            gp.d_rgb[(size_t)N + i] += y.x;
-            gp.d_rgb[2 * (size_t)N + i] += y.y;
-            a[2 * (size_t)i] = z4;
-            a[2 * (size_t)i + 1] = z4;
+// After the 8x8 adjoint, in one launch: blocks [0, n_pose) sum each job's
+// per-tile pose partials in FP64 (a fixed order: 32 strided partial sums per
+// component, then those in index order); the other blocks move the
+// accumulated parameter gradients of the learnable keyframes into their
+// gradient planes (+=) and clear the accumulator records for the next
+// adjoint (records that received nothing are left alone).
+constexpr int kFinishThreads = 192;   // a multiple of the 6 pose components
+
+__global__ __launch_bounds__(kFinishThreads) void k_bwd_finish(int N, int bpk, const KfGradPtrs* __restrict__ grads,
+                                                               uint32_t lo, uint32_t hi, float* __restrict__ acc,
+                                                               const float* __restrict__ part, int ntiles,
+                                                               float* __restrict__ d_pose, int n_pose) {
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.x < n_pose) {
+        __shared__ double s[kFinishThreads];
+        const int job = blockIdx.x;
+        const float* pj = part + (size_t)job * ntiles * 6;
+        const int n = ntiles * 6;
+        double a = 0.0;
+        for (int f = tid; f < n; f += kFinishThreads) a += (double)pj[f];
+        s[tid] = a;
+        __syncthreads();
+        if (tid < 6) {
+            double t = 0.0;
+            for (int g = 0; g < kFinishThreads / 6; ++g) t += s[g * 6 + tid];
+            d_pose[job * 6 + tid] = (float)t;
         }
+        return;
     }
+    const int b = (int)blockIdx.x - n_pose;
+    const int kf = b / bpk;
+    const int i = (b - kf * bpk) * kFinishThreads + tid;
+    const bool learn = kf < 32 ? ((lo >> kf) & 1u) : ((hi >> (kf - 32)) & 1u);
+    if (!learn || i >= N) return;
+    float4* a = (float4*)acc + ((size_t)kf * N + i) * 2;
+    const float4 x = a[0], y = a[1];
+    if (x.x != 0.f || x.y != 0.f || x.z != 0.f || x.w != 0.f || y.x != 0.f || y.y != 0.f) {
+        const KfGradPtrs gp = grads[kf];
+        gp.d_offset[i] += x.x;
+        gp.d_radius[i] += x.y;
+        gp.d_opacity[i] += x.z;
+        gp.d_rgb[i] += x.w;
+        gp.d_rgb[(size_t)N + i] += y.x;
+        gp.d_rgb[2 * (size_t)N + i] += y.y;
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        a[0] = z4;
+        a[1] = z4;
+    }
+}
+
+void launch_bwd_finish(const Geometry& G, const KfGradPtrs* grads, uint32_t lo, uint32_t hi, float* acc,
+                       const float* pose_part, float* d_pose, hipStream_t s) {
+    const int bpk = (G.N + kFinishThreads - 1) / kFinishThreads;
+    const int n_pose = d_pose ? G.n_jobs : 0;
+    hipLaunchKernelGGL(k_bwd_finish, dim3(n_pose + bpk * G.n_kf), dim3(kFinishThreads), 0, s, G.N, bpk, grads,
+                       lo, hi, acc, pose_part, G.ntiles, d_pose, n_pose);
 }
 
 template <int SUB>
@@ -668,9 +700,6 @@ bool launch_bwd8(const Geometry& G, const RenderBufs& B, const BwdArgs& A, int s
     if (sub == 32) bwd8_t<32>(G, B, A, s);
     else if (sub == 16) bwd8_t<16>(G, B, A, s);
     else return false;
-    const int bx = std::min((G.N + 1023) / 1024, 1024);
-    hipLaunchKernelGGL(k_grad_unpack, dim3(bx, G.n_kf), dim3(256), 0, s, G.N, A.grads, A.learn_lo, A.learn_hi,
-                       A.acc);
     return true;
 }
 

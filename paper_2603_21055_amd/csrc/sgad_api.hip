@@ -23,6 +23,8 @@ bool launch_fwd(const Geometry& G, const RenderBufs& B, float* rgb, float* depth
 bool launch_bwd(const Geometry& G, const RenderBufs& B, const float* g_rgb, const float* g_depth,
                 const float* g_alpha, const KfGradPtrs* grads, uint32_t lo, uint32_t hi, float* pose_part,
                 float* acc, float* d_pose, hipStream_t s);
+void launch_bwd_finish(const Geometry& G, const KfGradPtrs* grads, uint32_t lo, uint32_t hi, float* acc,
+                       const float* pose_part, float* d_pose, hipStream_t s);
 void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const float* t_rgb, const float* t_dep,
                float w_rgb, float w_dep, uint32_t* count, float* g_rgb, float* g_dep, double* loss,
                hipStream_t s);
@@ -974,6 +976,11 @@ sgad_status sgad_render_bwd(sgad_ctx* c, sgad_saved* S, const float* g_rgb, cons
         if (!launch_bwd(G, S->B, g_rgb, g_depth, g_alpha, (const KfGradPtrs*)S->gradptrs.p, learn_lo, learn_hi,
                         (float*)S->pose_part.p, (float*)S->gacc.p, d_pose, s))
             return fail(c, SGAD_EINVAL, "unsupported tile shape");
+    }
+    if (G.TW == 8 && G.TH == 8) {
+        TimeScope ts(c, "grad_finish", s);
+        launch_bwd_finish(G, (const KfGradPtrs*)S->gradptrs.p, learn_lo, learn_hi, (float*)S->gacc.p,
+                          (const float*)S->pose_part.p, d_pose, s);
     }
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
