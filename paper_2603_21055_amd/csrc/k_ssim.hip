@@ -9,7 +9,7 @@
 // Two launches per call, both over (16 x 16 tile, plane) with a 26 x 26 patch
 // (tile plus a 5-pixel halo) in LDS and the window applied as a row pass then
 // a column pass:
-//   k_ssim_maps: the five filtered moments, SSIM and the three partials
+//   k_ssim_maps: the filtered moments (x, y, x^2 + y^2, xy), SSIM and the three partials
 //     dS/dmu_y, dS/de_yy, dS/de_xy per pixel (written), the SSIM sum;
 //   k_ssim_grad: the adjoint of the correlation (the same symmetric window)
 //     applied to the three maps, giving
@@ -38,17 +38,31 @@ __constant__ double c_ssim_g[2 * kSsimR + 1] = {
     0.21300553771125369,   0.26601172486179436,  0.21300553771125369,  0.10936068950970002,
     0.036000772128430829,  0.007598758135239185, 0.0010283800844791101};
 
-// Patch of `n` planes at (blockIdx.x, blockIdx.y), zero outside the image.
+// Patch of NPL planes at (blockIdx.x, blockIdx.y), zero outside the image:
+// every thread issues all of its loads before its first LDS write, so the
+// block waits for one round trip to memory instead of three.
 template <int NPL>
 __device__ __forceinline__ void ssim_load(int H, int W, const float* const* src, float (*dst)[kSsimE][kSsimE + 1]) {
+    constexpr int N = kSsimE * kSsimE, IT = (N + 255) / 256;
     const int ox = (int)blockIdx.x * kSsimT - kSsimR, oy = (int)blockIdx.y * kSsimT - kSsimR;
-    for (int i = threadIdx.x; i < kSsimE * kSsimE; i += 256) {
+    float v[IT][NPL];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = (int)threadIdx.x + it * 256;
         const int r = i / kSsimE, c = i - r * kSsimE;
         const int gx = ox + c, gy = oy + r;
-        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-        const size_t o = (size_t)gy * W + gx;
+        const bool in = i < N && gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const size_t o = in ? (size_t)gy * W + gx : 0;
 #pragma unroll
-        for (int p = 0; p < NPL; ++p) dst[p][r][c] = in ? src[p][o] : 0.f;
+        for (int p = 0; p < NPL; ++p) v[it][p] = in ? src[p][o] : 0.f;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = (int)threadIdx.x + it * 256;
+        if (i >= N) continue;
+        const int r = i / kSsimE, c = i - r * kSsimE;
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) dst[p][r][c] = v[it][p];
     }
 }
 
@@ -60,6 +74,12 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Row pass over the patch: thread t < 4 * kSsimE filters row t / 4 for the
+// four outputs 4 (t % 4) .. 4 (t % 4) + 3, each of the 14 inputs loaded,
+// converted and (for the maps) squared once for the four outputs it feeds.
+// Every output sums its 11 taps in tap order, as a one-output loop would.
+constexpr int kRowItems = kSsimE * (kSsimT / 4);
+
 // grid (tiles x, tiles y, n_jobs * 3): plane z is colour channel z % 3 of job
 // z / 3.  dmap [n_jobs * 3][3][H][W]; part[z][tile] = the tile's SSIM sum
 // (written; k_ssim_grad adds them to the loss in a fixed order).
@@ -67,7 +87,9 @@ __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __
                                                    const float* __restrict__ t_rgb, float* __restrict__ dmap,
                                                    double* __restrict__ part) {
     __shared__ float s_in[2][kSsimE][kSsimE + 1];    // observed x, rendered y
-    __shared__ double s_h[5][kSsimE][kSsimT];        // row-filtered x, y, x^2, y^2, xy
+    // row-filtered x, y, x^2 + y^2, xy: SSIM needs the two variances only
+    // as their sum (18.9 KB of LDS per block, eight blocks per CU)
+    __shared__ double s_h[4][kSsimE][kSsimT];
     __shared__ double s_red[4];
     const int plane = blockIdx.z;
     const size_t P = (size_t)H * W;
@@ -75,45 +97,56 @@ __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __
     const double* s_g = c_ssim_g;
     ssim_load<2>(H, W, src, s_in);
     __syncthreads();
-    for (int i = threadIdx.x; i < kSsimE * kSsimT; i += 256) {
-        const int r = i / kSsimT, c = i - r * kSsimT;
-        double a = 0.0, b = 0.0, xx = 0.0, yy = 0.0, xy = 0.0;
+    if (threadIdx.x < kRowItems) {
+        const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 4;
+        double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, ss[4] = {0, 0, 0, 0}, xy[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int k = 0; k <= 2 * kSsimR; ++k) {
-            const double g = s_g[k];
-            const double x = (double)s_in[0][r][c + k], y = (double)s_in[1][r][c + k];
-            a += g * x;
-            b += g * y;
-            xx += g * (x * x);
-            yy += g * (y * y);
-            xy += g * (x * y);
+        for (int j = 0; j < 2 * kSsimR + 4; ++j) {
+            const double x = (double)s_in[0][r][c0 + j], y = (double)s_in[1][r][c0 + j];
+            const double s2 = x * x + y * y, xyv = x * y;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int k = j - o;
+                if (k < 0 || k > 2 * kSsimR) continue;
+                const double g = s_g[k];
+                a[o] += g * x;
+                b[o] += g * y;
+                ss[o] += g * s2;
+                xy[o] += g * xyv;
+            }
         }
-        s_h[0][r][c] = a;
-        s_h[1][r][c] = b;
-        s_h[2][r][c] = xx;
-        s_h[3][r][c] = yy;
-        s_h[4][r][c] = xy;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            s_h[0][r][c0 + o] = a[o];
+            s_h[1][r][c0 + o] = b[o];
+            s_h[2][r][c0 + o] = ss[o];
+            s_h[3][r][c0 + o] = xy[o];
+        }
     }
     __syncthreads();
     const int tx = threadIdx.x & (kSsimT - 1), ty = threadIdx.x >> 4;
-    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k <= 2 * kSsimR; ++k) {
         const double g = s_g[k];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) m[q] += g * s_h[q][ty + k][tx];
+        for (int q = 0; q < 4; ++q) m[q] += g * s_h[q][ty + k][tx];
     }
     const int px = (int)blockIdx.x * kSsimT + tx, py = (int)blockIdx.y * kSsimT + ty;
     double S = 0.0;
     if (px < W && py < H) {
         const double mx = m[0], my = m[1];
-        const double sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+        const double sxy = m[3] - mx * my;
         const double A1 = 2.0 * mx * my + kSsimC1, A2 = 2.0 * sxy + kSsimC2;
-        const double B1 = mx * mx + my * my + kSsimC1, B2 = sxx + syy + kSsimC2;
-        S = (A1 * A2) / (B1 * B2);
-        const double d_my = S * (2.0 * mx / A1 - 2.0 * mx / A2 - 2.0 * my / B1 + 2.0 * my / B2);
-        const double d_eyy = -S / B2;
-        const double d_exy = 2.0 * S / A2;
+        const double B1 = mx * mx + my * my + kSsimC1, B2 = (m[2] - (mx * mx + my * my)) + kSsimC2;
+        // one division: with q = 1 / (B1 B2), S = A1 A2 q, S / A1 = A2 q,
+        // S / A2 = A1 q, S / B1 = S B2 q, S / B2 = S B1 q (B1, B2 > 0; A2 may
+        // be 0)
+        const double q = 1.0 / (B1 * B2);
+        S = A1 * A2 * q;
+        const double d_my = 2.0 * q * (mx * (A2 - A1) + my * S * (B1 - B2));
+        const double d_eyy = -S * B1 * q;
+        const double d_exy = 2.0 * A1 * q;
         const size_t o = (size_t)py * W + px;
         float* dm = dmap + (size_t)plane * 3 * P;
         dm[o] = (float)d_my;
@@ -149,19 +182,29 @@ __global__ __launch_bounds__(256) void k_ssim_grad(int H, int W, const float* __
     const double* s_g = c_ssim_g;
     ssim_load<3>(H, W, src, s_in);
     __syncthreads();
-    for (int i = threadIdx.x; i < kSsimE * kSsimT; i += 256) {
-        const int r = i / kSsimT, c = i - r * kSsimT;
-        double a = 0.0, b = 0.0, d = 0.0;
+    if (threadIdx.x < kRowItems) {
+        const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 4;
+        double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, d[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int k = 0; k <= 2 * kSsimR; ++k) {
-            const double g = s_g[k];
-            a += g * (double)s_in[0][r][c + k];
-            b += g * (double)s_in[1][r][c + k];
-            d += g * (double)s_in[2][r][c + k];
+        for (int j = 0; j < 2 * kSsimR + 4; ++j) {
+            const double u = (double)s_in[0][r][c0 + j], v = (double)s_in[1][r][c0 + j],
+                         w = (double)s_in[2][r][c0 + j];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int k = j - o;
+                if (k < 0 || k > 2 * kSsimR) continue;
+                const double g = s_g[k];
+                a[o] += g * u;
+                b[o] += g * v;
+                d[o] += g * w;
+            }
         }
-        s_h[0][r][c] = a;
-        s_h[1][r][c] = b;
-        s_h[2][r][c] = d;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            s_h[0][r][c0 + o] = a[o];
+            s_h[1][r][c0 + o] = b[o];
+            s_h[2][r][c0 + o] = d[o];
+        }
     }
     __syncthreads();
     const int tx = threadIdx.x & (kSsimT - 1), ty = threadIdx.x >> 4;
