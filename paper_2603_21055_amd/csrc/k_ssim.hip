@@ -21,7 +21,7 @@
 // FP32.
 #include <hip/hip_runtime.h>
 
-#include "sgad_internal.h"
+#include "raster_common.h"
 
 namespace sgad {
 
@@ -38,13 +38,34 @@ __constant__ double c_ssim_g[2 * kSsimR + 1] = {
     0.21300553771125369,   0.26601172486179436,  0.21300553771125369,  0.10936068950970002,
     0.036000772128430829,  0.007598758135239185, 0.0010283800844791101};
 
-// Patch of NPL planes at (blockIdx.x, blockIdx.y), zero outside the image:
-// every thread issues all of its loads before its first LDS write, so the
-// block waits for one round trip to memory instead of three.
+// The block's output tile and colour plane.  The 1-D grid is spread over the
+// XCDs in contiguous ranges, so that neighbouring tiles, whose patches
+// overlap, share an L2.
+struct SsimTile {
+    int tx, ty, plane, ntx, nty;
+};
+
+__device__ __forceinline__ SsimTile ssim_tile(int H, int W) {
+    SsimTile t;
+    t.ntx = (W + kSsimT - 1) / kSsimT;
+    t.nty = (H + kSsimT - 1) / kSsimT;
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int per = t.ntx * t.nty;
+    t.plane = b / per;
+    const int r = b - t.plane * per;
+    t.ty = r / t.ntx;
+    t.tx = r - t.ty * t.ntx;
+    return t;
+}
+
+// Patch of NPL planes around tile t, zero outside the image: every thread
+// issues all of its loads before its first LDS write, so the block waits for
+// one round trip to memory instead of three.
 template <int NPL>
-__device__ __forceinline__ void ssim_load(int H, int W, const float* const* src, float (*dst)[kSsimE][kSsimE + 1]) {
+__device__ __forceinline__ void ssim_load(int H, int W, const SsimTile& t, const float* const* src,
+                                          float (*dst)[kSsimE][kSsimE + 1]) {
     constexpr int N = kSsimE * kSsimE, IT = (N + 255) / 256;
-    const int ox = (int)blockIdx.x * kSsimT - kSsimR, oy = (int)blockIdx.y * kSsimT - kSsimR;
+    const int ox = t.tx * kSsimT - kSsimR, oy = t.ty * kSsimT - kSsimR;
     float v[IT][NPL];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -80,9 +101,9 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
 // Every output sums its 11 taps in tap order, as a one-output loop would.
 constexpr int kRowItems = kSsimE * (kSsimT / 4);
 
-// grid (tiles x, tiles y, n_jobs * 3): plane z is colour channel z % 3 of job
-// z / 3.  dmap [n_jobs * 3][3][H][W]; part[z][tile] = the tile's SSIM sum
-// (written; k_ssim_grad adds them to the loss in a fixed order).
+// One block per (plane, tile), plane z = colour channel z % 3 of job z / 3.
+// dmap [n_jobs * 3][3][H][W]; part[z][tile] = the tile's SSIM sum (written;
+// k_ssim_grad adds them to the loss in a fixed order).
 __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __restrict__ rgb,
                                                    const float* __restrict__ t_rgb, float* __restrict__ dmap,
                                                    double* __restrict__ part) {
@@ -91,11 +112,12 @@ __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __
     // as their sum (18.9 KB of LDS per block, eight blocks per CU)
     __shared__ double s_h[4][kSsimE][kSsimT];
     __shared__ double s_red[4];
-    const int plane = blockIdx.z;
+    const SsimTile st = ssim_tile(H, W);
+    const int plane = st.plane;
     const size_t P = (size_t)H * W;
     const float* src[2] = {t_rgb + (size_t)plane * P, rgb + (size_t)plane * P};
     const double* s_g = c_ssim_g;
-    ssim_load<2>(H, W, src, s_in);
+    ssim_load<2>(H, W, st, src, s_in);
     __syncthreads();
     if (threadIdx.x < kRowItems) {
         const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 4;
@@ -132,7 +154,7 @@ __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __
 #pragma unroll
         for (int q = 0; q < 4; ++q) m[q] += g * s_h[q][ty + k][tx];
     }
-    const int px = (int)blockIdx.x * kSsimT + tx, py = (int)blockIdx.y * kSsimT + ty;
+    const int px = st.tx * kSsimT + tx, py = st.ty * kSsimT + ty;
     double S = 0.0;
     if (px < W && py < H) {
         const double mx = m[0], my = m[1];
@@ -154,7 +176,7 @@ __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __
         dm[2 * P + o] = (float)d_exy;
     }
     const double sum = block_sum_d(S, s_red);
-    if (threadIdx.x == 0) part[(size_t)plane * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = sum;
+    if (threadIdx.x == 0) part[(size_t)plane * st.ntx * st.nty + st.ty * st.ntx + st.tx] = sum;
 }
 
 // Same grid: g_rgb[plane] += -tau / (3 P) [G*d_my + 2 y G*d_eyy + x G*d_exy].
@@ -167,11 +189,12 @@ __global__ __launch_bounds__(256) void k_ssim_grad(int H, int W, const float* __
     __shared__ float s_in[3][kSsimE][kSsimE + 1];
     __shared__ double s_h[3][kSsimE][kSsimT];
     __shared__ double s_red[4];
-    const int plane = blockIdx.z;
+    const SsimTile st = ssim_tile(H, W);
+    const int plane = st.plane;
     const size_t P = (size_t)H * W;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && plane % 3 == 0) {
-        const int nt = (int)(gridDim.x * gridDim.y) * 3;
-        const double* pp = part + (size_t)plane * gridDim.x * gridDim.y;
+    if (st.tx == 0 && st.ty == 0 && plane % 3 == 0) {
+        const int nt = st.ntx * st.nty * 3;
+        const double* pp = part + (size_t)plane * st.ntx * st.nty;
         double acc = 0.0;
         for (int i = threadIdx.x; i < nt; i += 256) acc += pp[i];
         const double sum = block_sum_d(acc, s_red);
@@ -180,7 +203,7 @@ __global__ __launch_bounds__(256) void k_ssim_grad(int H, int W, const float* __
     const float* dm = dmap + (size_t)plane * 3 * P;
     const float* src[3] = {dm, dm + P, dm + 2 * P};
     const double* s_g = c_ssim_g;
-    ssim_load<3>(H, W, src, s_in);
+    ssim_load<3>(H, W, st, src, s_in);
     __syncthreads();
     if (threadIdx.x < kRowItems) {
         const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 4;
@@ -208,7 +231,7 @@ __global__ __launch_bounds__(256) void k_ssim_grad(int H, int W, const float* __
     }
     __syncthreads();
     const int tx = threadIdx.x & (kSsimT - 1), ty = threadIdx.x >> 4;
-    const int px = (int)blockIdx.x * kSsimT + tx, py = (int)blockIdx.y * kSsimT + ty;
+    const int px = st.tx * kSsimT + tx, py = st.ty * kSsimT + ty;
     if (px >= W || py >= H) return;
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
 #pragma unroll
@@ -236,7 +259,7 @@ size_t ssim_map_bytes(int n_jobs, int H, int W) {
 
 void launch_ssim(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
                  float* g_rgb, double* loss, hipStream_t s) {
-    const dim3 grid((W + kSsimT - 1) / kSsimT, (H + kSsimT - 1) / kSsimT, 3 * n_jobs), blk(256);
+    const dim3 grid((unsigned)(ssim_tiles(H, W) * 3 * n_jobs)), blk(256);
     float* dmap = (float*)ws;
     const size_t maps = (size_t)n_jobs * 9 * (size_t)H * W * sizeof(float);
     double* part = (double*)((char*)ws + ((maps + 255) & ~(size_t)255));
