@@ -455,7 +455,7 @@ __global__ __launch_bounds__(64) void k_sort(Geometry G, RenderBufs B) {
     const uint32_t st = B.tile_start[seg];
     const int n = (int)(B.tile_start[seg + 1] - st);
     uint64_t* g = B.keys + st;
-    sort_segment(g, n, threadIdx.x, G.sort_long != 0);
+    sort_segment<true>(g, n, threadIdx.x, G.sort_long != 0);
 }
 
 // Segments of 1025..4096 keys by a 256-thread workgroup: each of the four
@@ -472,7 +472,7 @@ __device__ __forceinline__ void sort_run(const uint64_t* g, int n, uint64_t* s, 
     const int b = wave * 64 * K + lane * K;
 #pragma unroll
     for (int r = 0; r < K; ++r) x[r] = b + r < n ? g[b + r] : ~0ull;
-    wave_sort_regs<K>(x, lane);
+    wave_sort_regs<K, true>(x, lane);
 #pragma unroll
     for (int r = 0; r < K; ++r) s[b + r] = x[r];
 }

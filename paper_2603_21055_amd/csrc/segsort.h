@@ -19,10 +19,62 @@ namespace sgad {
 // ---------------------------------------------------------------------------
 constexpr int kSortLds = 4096;
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const int lo = __shfl_xor((int)(uint32_t)v, m, 64);
-    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+// The value lane ^ m holds, for the lane masks the network uses, without a
+// trip through the LDS unit: DPP quad permutations and row mirrors inside a
+// row of 16 lanes, two DPP row shifts for a distance of 4 or 8, and the
+// row-swapping permutes for 16 and 32 (xor 2^k - 1 = a mirror inside the row,
+// then the rows swapped).  Every lane of the wave takes part.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t xor_rows16(uint32_t v, int lane) {
+    const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) ? p[0] : p[1];
+}
+
+__device__ __forceinline__ uint32_t xor_rows32(uint32_t v, int lane) {
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? p[0] : p[1];
+}
+
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int lane) {
+    if constexpr (M == 1) return dpp_u32<0xB1>(v);          // quad_perm [1, 0, 3, 2]
+    else if constexpr (M == 2) return dpp_u32<0x4E>(v);     // quad_perm [2, 3, 0, 1]
+    else if constexpr (M == 3) return dpp_u32<0x1B>(v);     // quad_perm [3, 2, 1, 0]
+    else if constexpr (M == 4) {
+        const uint32_t up = dpp_u32<0x104>(v), dn = dpp_u32<0x114>(v);   // row_shl:4, row_shr:4
+        return (lane & 4) ? dn : up;
+    } else if constexpr (M == 7) return dpp_u32<0x141>(v);  // row_half_mirror
+    else if constexpr (M == 8) {
+        const uint32_t up = dpp_u32<0x108>(v), dn = dpp_u32<0x118>(v);   // row_shl:8, row_shr:8
+        return (lane & 8) ? dn : up;
+    } else if constexpr (M == 15) return dpp_u32<0x140>(v);  // row_mirror
+    else if constexpr (M == 16) return xor_rows16(v, lane);
+    else if constexpr (M == 31) return xor_rows16(dpp_u32<0x140>(v), lane);
+    else if constexpr (M == 32) return xor_rows32(v, lane);
+    else {
+        static_assert(M == 63, "lane mask of the bitonic network");
+        return xor_rows32(xor_rows16(dpp_u32<0x140>(v), lane), lane);
+    }
+}
+
+// DPP = false: ds_bpermute shuffles instead, which cost no VALU issue slots;
+// the better choice inside kernels whose other waves keep the VALU busy
+// (the wave-tile forward sorts its tile while other waves walk theirs).
+template <int M, bool DPP>
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int lane) {
+    uint32_t lo, hi;
+    if constexpr (DPP) {
+        lo = xor_lane_u32<M>((uint32_t)v, lane);
+        hi = xor_lane_u32<M>((uint32_t)(v >> 32), lane);
+    } else {
+        lo = (uint32_t)__shfl_xor((int)(uint32_t)v, M, 64);
+        hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), M, 64);
+    }
+    return ((uint64_t)hi << 32) | lo;
 }
 
 template <int K>
@@ -38,55 +90,64 @@ __device__ __forceinline__ void sort_in_lane(uint64_t (&x)[K], int j) {
     }
 }
 
-// Ascending bitonic sort of the 64 K keys a wave holds in registers (key
-// i = lane * K + r in register r).
-template <int K>
-__device__ __forceinline__ void wave_sort_regs(uint64_t (&x)[K], int lane) {
+// Butterfly steps j, j / 2, ..., 1 of a bitonic merge over the 64 K keys a
+// wave holds in registers (key i = lane * K + r in register r).
+template <int K, int J, bool DPP>
+__device__ __forceinline__ void bitonic_steps(uint64_t (&x)[K], int lane) {
+    if constexpr (J < K) {
+        sort_in_lane<K>(x, J);
+    } else {
+        constexpr int lm = J / K;
+        const bool lower = (lane & lm) == 0;
 #pragma unroll
-    for (int k = 2; k <= 64 * K; k <<= 1) {
-        if (k <= K) {
-            // mirror step inside the lane: r <-> r ^ (k - 1)
-#pragma unroll
-            for (int r = 0; r < K; ++r) {
-                const int p = r ^ (k - 1);
-                if (p > r) {
-                    const uint64_t a = x[r], b = x[p];
-                    x[r] = a < b ? a : b;
-                    x[p] = a < b ? b : a;
-                }
-            }
-        } else {
-            // mirror step across lanes: (lane, r) <-> (lane ^ (k / K - 1), K - 1 - r),
-            // taken in register pairs (r, K - 1 - r)
-            const int lm = k / K - 1;
-            const bool lower = (lane & (k / (2 * K))) == 0;
-#pragma unroll
-            for (int r = 0; r < (K + 1) / 2; ++r) {
-                const int q = K - 1 - r;
-                const uint64_t ya = shfl_xor_u64(x[q], lm);
-                const uint64_t yb = shfl_xor_u64(x[r], lm);
-                x[r] = lower ? (x[r] < ya ? x[r] : ya) : (x[r] < ya ? ya : x[r]);
-                if (q != r) x[q] = lower ? (x[q] < yb ? x[q] : yb) : (x[q] < yb ? yb : x[q]);
-            }
-        }
-#pragma unroll
-        for (int j = k >> 2; j >= 1; j >>= 1) {
-            if (j < K) {
-                sort_in_lane<K>(x, j);
-            } else {
-                const int lm = j / K;
-                const bool lower = (lane & lm) == 0;
-#pragma unroll
-                for (int r = 0; r < K; ++r) {
-                    const uint64_t y = shfl_xor_u64(x[r], lm);
-                    x[r] = lower ? (x[r] < y ? x[r] : y) : (x[r] < y ? y : x[r]);
-                }
-            }
+        for (int r = 0; r < K; ++r) {
+            const uint64_t y = shfl_xor_u64<lm, DPP>(x[r], lane);
+            x[r] = lower ? (x[r] < y ? x[r] : y) : (x[r] < y ? y : x[r]);
         }
     }
+    if constexpr (J > 1) bitonic_steps<K, J / 2, DPP>(x, lane);
 }
 
-template <int K>
+// Merge stage of size KS (2 .. 64 K) and the stages after it.
+template <int K, int KS, bool DPP>
+__device__ __forceinline__ void bitonic_stages(uint64_t (&x)[K], int lane) {
+    if constexpr (KS <= K) {
+        // mirror step inside the lane: r <-> r ^ (KS - 1)
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int p = r ^ (KS - 1);
+            if (p > r) {
+                const uint64_t a = x[r], b = x[p];
+                x[r] = a < b ? a : b;
+                x[p] = a < b ? b : a;
+            }
+        }
+    } else {
+        // mirror step across lanes: (lane, r) <-> (lane ^ (KS / K - 1), K - 1 - r),
+        // taken in register pairs (r, K - 1 - r)
+        constexpr int lm = KS / K - 1;
+        const bool lower = (lane & (KS / (2 * K))) == 0;
+#pragma unroll
+        for (int r = 0; r < (K + 1) / 2; ++r) {
+            const int q = K - 1 - r;
+            const uint64_t ya = shfl_xor_u64<lm, DPP>(x[q], lane);
+            const uint64_t yb = shfl_xor_u64<lm, DPP>(x[r], lane);
+            x[r] = lower ? (x[r] < ya ? x[r] : ya) : (x[r] < ya ? ya : x[r]);
+            if (q != r) x[q] = lower ? (x[q] < yb ? x[q] : yb) : (x[q] < yb ? yb : x[q]);
+        }
+    }
+    if constexpr (KS >= 4) bitonic_steps<K, KS / 4, DPP>(x, lane);
+    if constexpr (2 * KS <= 64 * K) bitonic_stages<K, 2 * KS, DPP>(x, lane);
+}
+
+// Ascending bitonic sort of the 64 K keys a wave holds in registers (key
+// i = lane * K + r in register r).
+template <int K, bool DPP = false>
+__device__ __forceinline__ void wave_sort_regs(uint64_t (&x)[K], int lane) {
+    bitonic_stages<K, 2, DPP>(x, lane);
+}
+
+template <int K, bool DPP>
 __device__ __forceinline__ void wave_sort_segment(uint64_t* g, int n, int lane) {
     uint64_t x[K];
 #pragma unroll
@@ -94,7 +155,7 @@ __device__ __forceinline__ void wave_sort_segment(uint64_t* g, int n, int lane) 
         const int i = lane * K + r;
         x[r] = i < n ? g[i] : ~0ull;
     }
-    wave_sort_regs<K>(x, lane);
+    wave_sort_regs<K, DPP>(x, lane);
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         const int i = lane * K + r;
@@ -145,13 +206,14 @@ __device__ __forceinline__ void sort_global_segment(uint64_t* g, int n) {
 // a 64-thread workgroup).  Segments longer than 1024 keys are left to the
 // long-segment pass when `long_pass` is set, else sorted in place in global
 // memory.
+template <bool DPP = false>
 __device__ __forceinline__ void sort_segment(uint64_t* g, int n, int lane, bool long_pass) {
     if (n <= 1) return;
-    if (n <= 64) wave_sort_segment<1>(g, n, lane);
-    else if (n <= 128) wave_sort_segment<2>(g, n, lane);
-    else if (n <= 256) wave_sort_segment<4>(g, n, lane);
-    else if (n <= 512) wave_sort_segment<8>(g, n, lane);
-    else if (n <= 1024) wave_sort_segment<16>(g, n, lane);
+    if (n <= 64) wave_sort_segment<1, DPP>(g, n, lane);
+    else if (n <= 128) wave_sort_segment<2, DPP>(g, n, lane);
+    else if (n <= 256) wave_sort_segment<4, DPP>(g, n, lane);
+    else if (n <= 512) wave_sort_segment<8, DPP>(g, n, lane);
+    else if (n <= 1024) wave_sort_segment<16, DPP>(g, n, lane);
     else if (!long_pass) sort_global_segment(g, n);
 }
 
