@@ -454,7 +454,6 @@ __global__ void k_conv_weights(int cin, int cout, const float* w, __bf16* wb, __
     }
 }
 
-// Network input: (R, G, B, D / 5 m) as bf16 [H][W][4].
 // Network input (R, G, B, h): h = (D - mean of D over the in-image 3x3
 // neighbourhood) / 2 cm.  Depth in metres would be stored in bf16 with a
 // 4-31 mm spacing, as coarse as the sensor noise the offsets undo; the
