@@ -414,6 +414,64 @@ struct MapTarget {
     }
 };
 
+// The terms of one pair (source point i of the set src moved to X by the
+// pose (Rm, t), target j): H (upper triangle), g, e^T M e and the count, with
+// M = (C_b + R C_a R^T)^-1, J = [-I | [X]x], e = b - X.
+__device__ __forceinline__ void gicp_pair_terms(const double* __restrict__ src, int ns, int i, const double* Rm,
+                                                double X0, double X1, double X2, const double* __restrict__ tgt,
+                                                size_t nt, int j, double* acc) {
+#pragma clang fp contract(off)
+    // C = C_b + R C_a R^T
+    const double ca[9] = {src[(size_t)3 * ns + i], src[(size_t)4 * ns + i], src[(size_t)5 * ns + i],
+                          src[(size_t)4 * ns + i], src[(size_t)6 * ns + i], src[(size_t)7 * ns + i],
+                          src[(size_t)5 * ns + i], src[(size_t)7 * ns + i], src[(size_t)8 * ns + i]};
+    double RC[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            RC[r * 3 + c] = Rm[r * 3 + 0] * ca[0 * 3 + c] + Rm[r * 3 + 1] * ca[1 * 3 + c] + Rm[r * 3 + 2] * ca[2 * 3 + c];
+    double C[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            C[r * 3 + c] = RC[r * 3 + 0] * Rm[c * 3 + 0] + RC[r * 3 + 1] * Rm[c * 3 + 1] + RC[r * 3 + 2] * Rm[c * 3 + 2];
+    const double cb[6] = {tgt[3 * nt + j], tgt[4 * nt + j], tgt[5 * nt + j],
+                          tgt[6 * nt + j], tgt[7 * nt + j], tgt[8 * nt + j]};
+    C[0] += cb[0];
+    C[1] += cb[1];
+    C[2] += cb[2];
+    C[3] += cb[1];
+    C[4] += cb[3];
+    C[5] += cb[4];
+    C[6] += cb[2];
+    C[7] += cb[4];
+    C[8] += cb[5];
+    // M = C^-1 by the adjugate (C symmetric positive definite)
+    const double m00 = C[4] * C[8] - C[5] * C[7], m01 = C[2] * C[7] - C[1] * C[8], m02 = C[1] * C[5] - C[2] * C[4];
+    const double m11 = C[0] * C[8] - C[2] * C[6], m12 = C[2] * C[3] - C[0] * C[5], m22 = C[0] * C[4] - C[1] * C[3];
+    const double det = C[0] * m00 + C[1] * (C[5] * C[6] - C[3] * C[8]) + C[2] * (C[3] * C[7] - C[4] * C[6]);
+    const double id = 1.0 / det;
+    const double M[9] = {m00 * id, m01 * id, m02 * id, m01 * id, m11 * id, m12 * id, m02 * id, m12 * id, m22 * id};
+    const double e[3] = {tgt[j] - X0, tgt[nt + j] - X1, tgt[2 * nt + j] - X2};
+    // J = [-I | [X]x] (3 x 6)
+    const double X[3] = {X0, X1, X2};
+    double J[18];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) J[r * 6 + c] = (r == c) ? -1.0 : 0.0;
+    J[0 * 6 + 3] = 0.0;   J[0 * 6 + 4] = -X[2]; J[0 * 6 + 5] = X[1];
+    J[1 * 6 + 3] = X[2];  J[1 * 6 + 4] = 0.0;   J[1 * 6 + 5] = -X[0];
+    J[2 * 6 + 3] = -X[1]; J[2 * 6 + 4] = X[0];  J[2 * 6 + 5] = 0.0;
+    double MJ[18], Me[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 6; ++c) MJ[r * 6 + c] = M[r * 3 + 0] * J[0 * 6 + c] + M[r * 3 + 1] * J[1 * 6 + c] + M[r * 3 + 2] * J[2 * 6 + c];
+        Me[r] = M[r * 3 + 0] * e[0] + M[r * 3 + 1] * e[1] + M[r * 3 + 2] * e[2];
+    }
+    int q = 0;
+    for (int r = 0; r < 6; ++r)
+        for (int c = r; c < 6; ++c) acc[q++] = J[0 * 6 + r] * MJ[0 * 6 + c] + J[1 * 6 + r] * MJ[1 * 6 + c] + J[2 * 6 + r] * MJ[2 * 6 + c];
+    for (int r = 0; r < 6; ++r) acc[21 + r] = J[0 * 6 + r] * Me[0] + J[1 * 6 + r] * Me[1] + J[2 * 6 + r] * Me[2];
+    acc[27] = e[0] * Me[0] + e[1] * Me[1] + e[2] * Me[2];
+    acc[28] = 1.0;
+}
+
 // Pose P = (R row-major, t) at pose[0..11].
 template <int KM, class Target>
 __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict__ src, int ns, Target tg,
@@ -465,57 +523,7 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
             }
     }
     if (corr && in) corr[i] = j;
-    if (j >= 0) {
-        // C = C_b + R C_a R^T
-        const double ca[9] = {src[(size_t)3 * ns + i], src[(size_t)4 * ns + i], src[(size_t)5 * ns + i],
-                              src[(size_t)4 * ns + i], src[(size_t)6 * ns + i], src[(size_t)7 * ns + i],
-                              src[(size_t)5 * ns + i], src[(size_t)7 * ns + i], src[(size_t)8 * ns + i]};
-        double RC[9];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c)
-                RC[r * 3 + c] = Rm[r * 3 + 0] * ca[0 * 3 + c] + Rm[r * 3 + 1] * ca[1 * 3 + c] + Rm[r * 3 + 2] * ca[2 * 3 + c];
-        double C[9];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c)
-                C[r * 3 + c] = RC[r * 3 + 0] * Rm[c * 3 + 0] + RC[r * 3 + 1] * Rm[c * 3 + 1] + RC[r * 3 + 2] * Rm[c * 3 + 2];
-        const double cb[6] = {tgt[3 * nt + j], tgt[4 * nt + j], tgt[5 * nt + j],
-                              tgt[6 * nt + j], tgt[7 * nt + j], tgt[8 * nt + j]};
-        C[0] += cb[0];
-        C[1] += cb[1];
-        C[2] += cb[2];
-        C[3] += cb[1];
-        C[4] += cb[3];
-        C[5] += cb[4];
-        C[6] += cb[2];
-        C[7] += cb[4];
-        C[8] += cb[5];
-        // M = C^-1 by the adjugate (C symmetric positive definite)
-        const double m00 = C[4] * C[8] - C[5] * C[7], m01 = C[2] * C[7] - C[1] * C[8], m02 = C[1] * C[5] - C[2] * C[4];
-        const double m11 = C[0] * C[8] - C[2] * C[6], m12 = C[2] * C[3] - C[0] * C[5], m22 = C[0] * C[4] - C[1] * C[3];
-        const double det = C[0] * m00 + C[1] * (C[5] * C[6] - C[3] * C[8]) + C[2] * (C[3] * C[7] - C[4] * C[6]);
-        const double id = 1.0 / det;
-        const double M[9] = {m00 * id, m01 * id, m02 * id, m01 * id, m11 * id, m12 * id, m02 * id, m12 * id, m22 * id};
-        const double e[3] = {tgt[j] - X0, tgt[nt + j] - X1, tgt[2 * nt + j] - X2};
-        // J = [-I | [X]x] (3 x 6)
-        const double X[3] = {X0, X1, X2};
-        double J[18];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) J[r * 6 + c] = (r == c) ? -1.0 : 0.0;
-        J[0 * 6 + 3] = 0.0;   J[0 * 6 + 4] = -X[2]; J[0 * 6 + 5] = X[1];
-        J[1 * 6 + 3] = X[2];  J[1 * 6 + 4] = 0.0;   J[1 * 6 + 5] = -X[0];
-        J[2 * 6 + 3] = -X[1]; J[2 * 6 + 4] = X[0];  J[2 * 6 + 5] = 0.0;
-        double MJ[18], Me[3];
-        for (int r = 0; r < 3; ++r) {
-            for (int c = 0; c < 6; ++c) MJ[r * 6 + c] = M[r * 3 + 0] * J[0 * 6 + c] + M[r * 3 + 1] * J[1 * 6 + c] + M[r * 3 + 2] * J[2 * 6 + c];
-            Me[r] = M[r * 3 + 0] * e[0] + M[r * 3 + 1] * e[1] + M[r * 3 + 2] * e[2];
-        }
-        int q = 0;
-        for (int r = 0; r < 6; ++r)
-            for (int c = r; c < 6; ++c) acc[q++] = J[0 * 6 + r] * MJ[0 * 6 + c] + J[1 * 6 + r] * MJ[1 * 6 + c] + J[2 * 6 + r] * MJ[2 * 6 + c];
-        for (int r = 0; r < 6; ++r) acc[21 + r] = J[0 * 6 + r] * Me[0] + J[1 * 6 + r] * Me[1] + J[2 * 6 + r] * Me[2];
-        acc[27] = e[0] * Me[0] + e[1] * Me[1] + e[2] * Me[2];
-        acc[28] = 1.0;
-    }
+    if (j >= 0) gicp_pair_terms(src, ns, i, Rm, X0, X1, X2, tgt, nt, j, acc);
     // block sum: wave shuffles, then the four waves in order
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -531,16 +539,160 @@ __global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict
     }
 }
 
-// Sum of the partial records in block order (one thread per value).
-__device__ __forceinline__ void gicp_sum(const double* part, int nb, double* S) {
-    if (threadIdx.x < kGicpVals) {
-        double v = 0.0;
-        for (int b = 0; b < nb; ++b) v += part[(size_t)b * kGicpVals + threadIdx.x];
-        S[threadIdx.x] = v;
+// Double-precision (value, index) minimum over the wavefront, ties by index.
+__device__ __forceinline__ void wave_argmin(double& d, int& idx) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double od = __shfl_xor(d, o, 64);
+        const int oi = __shfl_xor(idx, o, 64);
+        if (od < d || (od == d && oi < idx)) {
+            d = od;
+            idx = oi;
+        }
     }
 }
 
-__global__ void k_gicp_sum(const double* part, int nb, double* out) {
+// GICP against the global set T, one wavefront per source point (four per
+// block).  The lanes split the voxels of each shell around X and keep their
+// own top-K lists; after a shell the wave stops once K candidates closer than
+// the distance to the scanned cube's faces are known (anything outside is at
+// least that far) or that distance passes D_MAX.  The K nearest are then taken
+// from the lanes' sorted lists in (distance, index) order, lane r receiving
+// the r-th; the lanes evaluate their candidate's surface distance, and the
+// pair's terms are formed by lane 0.  Same results as the one-thread search
+// of MapTarget::knn, with 64 times as many threads at work.
+template <int KM>
+__global__ __launch_bounds__(256) void k_gicp_linearise_map(const double* __restrict__ src, int ns, MapTarget tg,
+                                                            int k, const double* __restrict__ pose,
+                                                            double* __restrict__ part, int* __restrict__ corr) {
+#pragma clang fp contract(off)
+    __shared__ double s_acc[4][kGicpVals];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = (int)blockIdx.x * 4 + wave;
+    double Rm[9], tv[3];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) Rm[r] = pose[r];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) tv[r] = pose[9 + r];
+    const bool in = i < ns;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (in) {
+        a0 = src[i];
+        a1 = src[(size_t)ns + i];
+        a2 = src[2 * (size_t)ns + i];
+    }
+    const double X0 = ((Rm[0] * a0 + Rm[1] * a1) + Rm[2] * a2) + tv[0];
+    const double X1 = ((Rm[3] * a0 + Rm[4] * a1) + Rm[5] * a2) + tv[1];
+    const double X2 = ((Rm[6] * a0 + Rm[7] * a1) + Rm[8] * a2) + tv[2];
+    const double v = tg.voxel, dmax2 = kGicpDMax * kGicpDMax;
+    const double ux = X0 / v, uy = X1 / v, uz = X2 / v;
+    const double lim = (double)(kVoxelBias - kMapMaxShell - 1);
+    // wave-uniform: every lane holds the same point
+    const bool active = in && a2 != 0.0 && fabs(ux) < lim && fabs(uy) < lim && fabs(uz) < lim;
+    int j = -1;
+    if (active) {
+        TopK<KM> t;
+        topk_init(t);
+        int found = 0;
+        const long long cx = (long long)floor(ux), cy = (long long)floor(uy), cz = (long long)floor(uz);
+        for (int r = 0; r <= kMapMaxShell; ++r) {
+            const int side = 2 * r + 1, npos = side * side * side;
+            for (int p = lane; p < npos; p += 64) {
+                const int dz = p / (side * side) - r, rem = p % (side * side);
+                const int dy = rem / side - r, dx = rem % side - r;
+                if (max(abs(dx), max(abs(dy), abs(dz))) != r) continue;
+                tg.visit(cx + dx, cy + dy, cz + dz, X0, X1, X2, k, dmax2, t, found);
+            }
+            const double f = fmin(fmin(fmin(X0 - (double)(cx - r) * v, (double)(cx + r + 1) * v - X0),
+                                       fmin(X1 - (double)(cy - r) * v, (double)(cy + r + 1) * v - X1)),
+                                  fmin(X2 - (double)(cz - r) * v, (double)(cz + r + 1) * v - X2)) -
+                             1e-9;
+            if (f <= 0.0) continue;
+            const double f2 = f * f;
+            int c = 0;
+#pragma unroll
+            for (int q = 0; q < KM; ++q) c += (q < k && t.d[q] < f2) ? 1 : 0;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+            if (c >= k) break;
+            if (f2 > dmax2) break;
+        }
+        // the K nearest, one per round, into lanes 0 .. K-1
+        double cd = DBL_MAX;
+        int ci = INT_MAX;
+        for (int r = 0; r < k; ++r) {
+            double bd = t.d[0];
+            int bi = t.i[0];
+            wave_argmin(bd, bi);
+            if (bi == INT_MAX) break;
+            if (lane == r) {
+                cd = bd;
+                ci = bi;
+            }
+            if (t.i[0] == bi) {   // the owner drops its head
+#pragma unroll
+                for (int q = 0; q + 1 < KM; ++q) {
+                    t.d[q] = t.d[q + 1];
+                    t.i[q] = t.i[q + 1];
+                }
+                t.d[KM - 1] = DBL_MAX;
+                t.i[KM - 1] = INT_MAX;
+            }
+        }
+        // the closest surface element, first minimum in distance order
+        const double* tgt = tg.d;
+        const size_t nt = tg.stride;
+        double ds = DBL_MAX;
+        int rank = INT_MAX;
+        if (ci != INT_MAX) {
+            const int c2 = ci;
+            const double e0 = X0 - tgt[c2], e1 = X1 - tgt[nt + c2], e2 = X2 - tgt[2 * nt + c2];
+            const double n0 = tgt[9 * nt + c2], n1 = tgt[10 * nt + c2], n2 = tgt[11 * nt + c2];
+            const double dn = (n0 * e0 + n1 * e1) + n2 * e2;
+            const double ee = (e0 * e0 + e1 * e1) + e2 * e2;
+            ds = dn * dn + kGicpEps * ee;
+            rank = lane;
+        }
+        wave_argmin(ds, rank);
+        if (rank != INT_MAX) j = __shfl(ci, rank, 64);
+    }
+    double acc[kGicpVals];
+#pragma unroll
+    for (int q = 0; q < kGicpVals; ++q) acc[q] = 0.0;
+    if (lane == 0) {
+        if (corr && in) corr[i] = j;
+        if (j >= 0) gicp_pair_terms(src, ns, i, Rm, X0, X1, X2, tg.d, tg.stride, j, acc);
+#pragma unroll
+        for (int q = 0; q < kGicpVals; ++q) s_acc[wave][q] = acc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < kGicpVals) {
+        const int q = threadIdx.x;
+        part[(size_t)blockIdx.x * kGicpVals + q] = ((s_acc[0][q] + s_acc[1][q]) + s_acc[2][q]) + s_acc[3][q];
+    }
+}
+
+// Sum of the partial records in a fixed order (blocks of 256 threads): value
+// q's blocks b = r (mod 8) summed in block order by thread 8 q + r, then the
+// eight partial sums in r order.
+__device__ __forceinline__ void gicp_sum(const double* part, int nb, double* S) {
+    __shared__ double s_p[kGicpVals][8];
+    const int t = threadIdx.x;
+    if (t < kGicpVals * 8) {
+        const int q = t >> 3, r = t & 7;
+        double v = 0.0;
+        for (int b = r; b < nb; b += 8) v += part[(size_t)b * kGicpVals + q];
+        s_p[q][r] = v;
+    }
+    __syncthreads();
+    if (t < kGicpVals) {
+        double v = 0.0;
+        for (int r = 0; r < 8; ++r) v += s_p[t][r];
+        S[t] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gicp_sum(const double* part, int nb, double* out) {
     __shared__ double S[kGicpVals];
     gicp_sum(part, nb, S);
     __syncthreads();
@@ -563,7 +715,7 @@ __device__ bool gicp_chol6(const double* A, double* L) {
 }
 
 // One Gauss-Newton step on the device pose; trace record `it` if trace.
-__global__ void k_gicp_solve(const double* part, int nb, double* pose, double* trace, int it) {
+__global__ __launch_bounds__(256) void k_gicp_solve(const double* part, int nb, double* pose, double* trace, int it) {
     __shared__ double S[kGicpVals];
     gicp_sum(part, nb, S);
     __syncthreads();
@@ -705,10 +857,16 @@ void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt,
     linearise_t(src, ns, tg, k, pose, part, corr, s);
 }
 
+int gicp_map_blocks(int n) { return (n + 3) / 4; }
+
 void launch_gicp_linearise_map(const double* src, int ns, const sgad_gmap& m, int k, const double* pose,
                                double* part, int* corr, hipStream_t s) {
     MapTarget tg{m.data, (size_t)m.capacity, (const long long*)m.keys, m.vals, m.slots - 1, m.voxel};
-    linearise_t(src, ns, tg, k, pose, part, corr, s);
+    const dim3 grid(gicp_map_blocks(ns)), blk(256);
+    if (k <= 16)
+        hipLaunchKernelGGL((k_gicp_linearise_map<16>), grid, blk, 0, s, src, ns, tg, k, pose, part, corr);
+    else
+        hipLaunchKernelGGL((k_gicp_linearise_map<kGicpMaxK>), grid, blk, 0, s, src, ns, tg, k, pose, part, corr);
 }
 
 // ---------------------------------------------------------------------------
@@ -874,11 +1032,11 @@ void launch_fill_depth(int P, const float* depth, const float* rdepth, const flo
 }
 
 void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_gicp_sum, dim3(1), dim3(64), 0, s, part, nb, out);
+    hipLaunchKernelGGL(k_gicp_sum, dim3(1), dim3(256), 0, s, part, nb, out);
 }
 
 void launch_gicp_solve(const double* part, int nb, double* pose, double* trace, int it, hipStream_t s) {
-    hipLaunchKernelGGL(k_gicp_solve, dim3(1), dim3(64), 0, s, part, nb, pose, trace, it);
+    hipLaunchKernelGGL(k_gicp_solve, dim3(1), dim3(256), 0, s, part, nb, pose, trace, it);
 }
 
 }  // namespace sgad
