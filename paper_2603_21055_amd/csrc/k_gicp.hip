@@ -15,12 +15,15 @@
 //                  proves the window exact), their covariance, a cyclic
 //                  Jacobi eigen-decomposition, C' = U diag(max(l0/l2, eps),
 //                  max(l1/l2, eps), 1) U^T and the normal (smallest).
-// k_gicp_linearise one thread per source point: X = R a + t, its K_c
-//                  nearest target points, the one with the smallest
-//                  (n . e)^2 + eps |e|^2 (first minimum in distance rank),
-//                  pairs with |e|^2 <= D_MAX^2 kept; M = (C_b + R C_a R^T)^-1,
-//                  J = [-I | [X]x], per-block FP64 partial sums of
-//                  H = J^T M J (21), g = J^T M e (6), e^T M e and the count.
+// k_gicp_linearise_wave one wavefront per source point: X = R a + t, its
+//                  K_c nearest target points within D_MAX (the search split
+//                  over the lanes), the one with the smallest
+//                  (n . e)^2 + eps |e|^2 (first minimum in distance rank);
+//                  M = (C_b + R C_a R^T)^-1, J = [-I | [X]x], per-block FP64
+//                  partial sums of H = J^T M J (21), g = J^T M e (6),
+//                  e^T M e and the count.  The target is a frame's set
+//                  (windows of grid cells) or the global set T (shells of
+//                  voxels of a hash).
 // k_gicp_solve     one block: the partial sums in a fixed order, damped
 //                  Cholesky (1e-9 tr H, x10 per retry), dxi = -H^-1 g,
 //                  P <- Exp(dxi) P on the device pose, and a trace record.
@@ -344,22 +347,82 @@ __device__ __forceinline__ int map_find(const long long* keys, int mask, long lo
     return -1;
 }
 
+// Wave-wide count of the entries of the lanes' lists below b.
+template <int KM>
+__device__ __forceinline__ int wave_count_below(const TopK<KM>& t, int k, double b) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) c += (q < k && t.d[q] < b) ? 1 : 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    return c;
+}
+
 struct GridTarget {
     const double* d;
     size_t stride;
     int n;
     GicpGrid g;
+    // knn_grid's windows with the cells of each new ring split over the
+    // lanes of a wavefront (each lane keeping its own list); the window
+    // stops once the lanes together hold k entries below the bound, or the
+    // bound passes D_MAX.  Called by every lane with the same query.
     template <int KM>
-    __device__ void knn(int k, double x, double y, double z, TopK<KM>& t) const {
-        knn_grid(d, n, g, k, x, y, z, t, kGicpDMax * kGicpDMax);
+    __device__ void wave_knn(int k, double qx, double qy, double qz, int lane, TopK<KM>& t) const {
+#pragma clang fp contract(off)
+        topk_init(t);
+        const double dmax2 = kGicpDMax * kGicpDMax;
+        int cu = 0, cv = 0, w = g.gw + g.gh;
+        double u = 0.0, v = 0.0;
+        if (qz > 0.0) {
+            u = g.fx * (qx / qz) + g.cx;
+            v = g.fy * (qy / qz) + g.cy;
+            cu = (int)fmin(fmax(rint(u / g.R), 0.0), (double)(g.gw - 1));
+            cv = (int)fmin(fmax(rint(v / g.R), 0.0), (double)(g.gh - 1));
+            w = kGicpWin;
+        }
+        int lo_u = 1, hi_u = 0, lo_v = 1, hi_v = 0;
+        while (true) {
+            const int nlo_u = max(0, cu - w), nhi_u = min(g.gw - 1, cu + w);
+            const int nlo_v = max(0, cv - w), nhi_v = min(g.gh - 1, cv + w);
+            const int wu = nhi_u - nlo_u + 1, nc = wu * (nhi_v - nlo_v + 1);
+            for (int p = lane; p < nc; p += 64) {
+                const int j = nlo_v + p / wu, i = nlo_u + p % wu;
+                if (i >= lo_u && i <= hi_u && j >= lo_v && j <= hi_v) continue;
+                const int c = j * g.gw + i;
+                const double pz = d[2 * stride + c];
+                if (pz == 0.0) continue;
+                const double dx = qx - d[c], dy = qy - d[stride + c], dz = qz - pz;
+                const double dd = (dx * dx + dy * dy) + dz * dz;
+                if (!(dd <= dmax2)) continue;
+                if (dd < t.worst || (dd == t.worst && c < t.worst_i)) topk_insert(t, k, dd, c);
+            }
+            lo_u = nlo_u;
+            hi_u = nhi_u;
+            lo_v = nlo_v;
+            hi_v = nhi_v;
+            if (lo_u == 0 && hi_u == g.gw - 1 && lo_v == 0 && hi_v == g.gh - 1) return;
+            double D = DBL_MAX;
+            if (lo_u > 0) D = fmin(D, (u - (double)((lo_u - 1) * g.R)) / g.fx);
+            if (hi_u < g.gw - 1) D = fmin(D, ((double)((hi_u + 1) * g.R) - u) / g.fx);
+            if (lo_v > 0) D = fmin(D, (v - (double)((lo_v - 1) * g.R)) / g.fy);
+            if (hi_v < g.gh - 1) D = fmin(D, ((double)((hi_v + 1) * g.R) - v) / g.fy);
+            if (D > 0.0) {
+                const double lb = qz * D / g.m;
+                const double lb2 = lb * lb * (1.0 - 1e-12);
+                if (wave_count_below(t, k, lb2) >= k) return;
+                if (lb2 >= dmax2) return;
+            }
+            w *= 2;
+        }
     }
 };
 
 // The k nearest map Gaussians within D_MAX of q: shells of voxels at growing
 // Chebyshev distance r from q's voxel.  A Gaussian outside the cube of shells
 // scanned so far is at least the distance f from q to the cube's nearest face
-// (less 1e-9 m for the rounding of the voxel assignment), so the search ends
-// when the k-th distance is below f, or when f is beyond D_MAX.  Queries
+// (less 1e-9 m for the rounding of the voxel assignment), so the search can
+// end once k candidates are closer than f, or f is beyond D_MAX.  Queries
 // outside the map's coordinate range find nothing.
 struct MapTarget {
     const double* d;
@@ -384,8 +447,13 @@ struct MapTarget {
         if (dd < t.worst || (dd == t.worst && c < t.worst_i)) topk_insert(t, k, dd, c);
     }
 
+    // The shells with each shell's voxels split over the lanes of a
+    // wavefront, each lane keeping its own list; the shells stop once the
+    // lanes together hold k entries closer than the scanned cube's faces, or
+    // the faces pass D_MAX.  Called by every lane with the same query.
     template <int KM>
-    __device__ void knn(int k, double x, double y, double z, TopK<KM>& t) const {
+    __device__ void wave_knn(int k, double x, double y, double z, int lane, TopK<KM>& t) const {
+#pragma clang fp contract(off)
         topk_init(t);
         const double dmax2 = kGicpDMax * kGicpDMax;
         const double lim = (double)(kVoxelBias - kMapMaxShell - 1);
@@ -394,22 +462,21 @@ struct MapTarget {
         const long long cx = (long long)floor(ux), cy = (long long)floor(uy), cz = (long long)floor(uz);
         int found = 0;
         for (int r = 0; r <= kMapMaxShell; ++r) {
-            for (int dz = -r; dz <= r; ++dz)
-                for (int dy = -r; dy <= r; ++dy) {
-                    if (abs(dz) == r || abs(dy) == r) {
-                        for (int dx = -r; dx <= r; ++dx) visit(cx + dx, cy + dy, cz + dz, x, y, z, k, dmax2, t, found);
-                    } else {
-                        visit(cx - r, cy + dy, cz + dz, x, y, z, k, dmax2, t, found);
-                        if (r > 0) visit(cx + r, cy + dy, cz + dz, x, y, z, k, dmax2, t, found);
-                    }
-                }
+            const int side = 2 * r + 1, npos = side * side * side;
+            for (int p = lane; p < npos; p += 64) {
+                const int dz = p / (side * side) - r, rem = p % (side * side);
+                const int dy = rem / side - r, dx = rem % side - r;
+                if (max(abs(dx), max(abs(dy), abs(dz))) != r) continue;
+                visit(cx + dx, cy + dy, cz + dz, x, y, z, k, dmax2, t, found);
+            }
             const double f = fmin(fmin(fmin(x - (double)(cx - r) * voxel, (double)(cx + r + 1) * voxel - x),
                                        fmin(y - (double)(cy - r) * voxel, (double)(cy + r + 1) * voxel - y)),
                                   fmin(z - (double)(cz - r) * voxel, (double)(cz + r + 1) * voxel - z)) -
                              1e-9;
             if (f <= 0.0) continue;
-            if (found >= k && t.worst < f * f) return;
-            if (f * f > dmax2) return;
+            const double f2 = f * f;
+            if (wave_count_below(t, k, f2) >= k) return;
+            if (f2 > dmax2) return;
         }
     }
 };
@@ -472,73 +539,6 @@ __device__ __forceinline__ void gicp_pair_terms(const double* __restrict__ src, 
     acc[28] = 1.0;
 }
 
-// Pose P = (R row-major, t) at pose[0..11].
-template <int KM, class Target>
-__global__ __launch_bounds__(256) void k_gicp_linearise(const double* __restrict__ src, int ns, Target tg,
-                                                        int k, const double* __restrict__ pose,
-                                                        double* __restrict__ part, int* __restrict__ corr) {
-#pragma clang fp contract(off)
-    __shared__ double s_acc[4][kGicpVals];
-    const int i = (int)blockIdx.x * blockDim.x + threadIdx.x;
-    double Rm[9], tv[3];
-#pragma unroll
-    for (int r = 0; r < 9; ++r) Rm[r] = pose[r];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) tv[r] = pose[9 + r];
-    const bool in = i < ns;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    if (in) {
-        a0 = src[i];
-        a1 = src[(size_t)ns + i];
-        a2 = src[2 * (size_t)ns + i];
-    }
-    const bool active = in && a2 != 0.0;
-    const double X0 = ((Rm[0] * a0 + Rm[1] * a1) + Rm[2] * a2) + tv[0];
-    const double X1 = ((Rm[3] * a0 + Rm[4] * a1) + Rm[5] * a2) + tv[1];
-    const double X2 = ((Rm[6] * a0 + Rm[7] * a1) + Rm[8] * a2) + tv[2];
-    TopK<KM> t;
-    if (active) tg.knn(k, X0, X1, X2, t);
-    const double* tgt = tg.d;
-    const size_t nt = tg.stride;
-    double acc[kGicpVals];
-#pragma unroll
-    for (int q = 0; q < kGicpVals; ++q) acc[q] = 0.0;
-    // every listed candidate lies within D_MAX
-    int j = -1;
-    if (active) {
-        double best = DBL_MAX;
-#pragma unroll
-        for (int s = 0; s < KM; ++s)
-            if (s < k && t.i[s] != INT_MAX) {
-                const int c = t.i[s];
-                const double e0 = X0 - tgt[c], e1 = X1 - tgt[nt + c], e2 = X2 - tgt[2 * nt + c];
-                const double n0 = tgt[9 * nt + c], n1 = tgt[10 * nt + c], n2 = tgt[11 * nt + c];
-                const double dn = (n0 * e0 + n1 * e1) + n2 * e2;
-                const double ee = (e0 * e0 + e1 * e1) + e2 * e2;
-                const double ds = dn * dn + kGicpEps * ee;
-                if (ds < best) {
-                    best = ds;
-                    j = c;
-                }
-            }
-    }
-    if (corr && in) corr[i] = j;
-    if (j >= 0) gicp_pair_terms(src, ns, i, Rm, X0, X1, X2, tgt, nt, j, acc);
-    // block sum: wave shuffles, then the four waves in order
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < kGicpVals; ++q) {
-        double v = acc[q];
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) s_acc[wave][q] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < kGicpVals) {
-        const int q = threadIdx.x;
-        part[(size_t)blockIdx.x * kGicpVals + q] = ((s_acc[0][q] + s_acc[1][q]) + s_acc[2][q]) + s_acc[3][q];
-    }
-}
-
 // Double-precision (value, index) minimum over the wavefront, ties by index.
 __device__ __forceinline__ void wave_argmin(double& d, int& idx) {
 #pragma unroll
@@ -552,19 +552,17 @@ __device__ __forceinline__ void wave_argmin(double& d, int& idx) {
     }
 }
 
-// GICP against the global set T, one wavefront per source point (four per
-// block).  The lanes split the voxels of each shell around X and keep their
-// own top-K lists; after a shell the wave stops once K candidates closer than
-// the distance to the scanned cube's faces are known (anything outside is at
-// least that far) or that distance passes D_MAX.  The K nearest are then taken
-// from the lanes' sorted lists in (distance, index) order, lane r receiving
-// the r-th; the lanes evaluate their candidate's surface distance, and the
-// pair's terms are formed by lane 0.  Same results as the one-thread search
-// of MapTarget::knn, with 64 times as many threads at work.
-template <int KM>
-__global__ __launch_bounds__(256) void k_gicp_linearise_map(const double* __restrict__ src, int ns, MapTarget tg,
-                                                            int k, const double* __restrict__ pose,
-                                                            double* __restrict__ part, int* __restrict__ corr) {
+// GICP linearisation with one wavefront per source point (four per block):
+// the target's wave_knn splits the neighbour search over the lanes, each
+// keeping its own top-K list; the K nearest are then taken from the lanes'
+// sorted lists in (distance, index) order, lane r receiving the r-th; the
+// lanes evaluate their candidate's surface distance, and the pair's terms are
+// formed by lane 0.  Same results as the one-thread searches of the targets,
+// with 64 times as many threads at work.
+template <int KM, class Target>
+__global__ __launch_bounds__(256) void k_gicp_linearise_wave(const double* __restrict__ src, int ns, Target tg,
+                                                             int k, const double* __restrict__ pose,
+                                                             double* __restrict__ part, int* __restrict__ corr) {
 #pragma clang fp contract(off)
     __shared__ double s_acc[4][kGicpVals];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -584,39 +582,12 @@ __global__ __launch_bounds__(256) void k_gicp_linearise_map(const double* __rest
     const double X0 = ((Rm[0] * a0 + Rm[1] * a1) + Rm[2] * a2) + tv[0];
     const double X1 = ((Rm[3] * a0 + Rm[4] * a1) + Rm[5] * a2) + tv[1];
     const double X2 = ((Rm[6] * a0 + Rm[7] * a1) + Rm[8] * a2) + tv[2];
-    const double v = tg.voxel, dmax2 = kGicpDMax * kGicpDMax;
-    const double ux = X0 / v, uy = X1 / v, uz = X2 / v;
-    const double lim = (double)(kVoxelBias - kMapMaxShell - 1);
     // wave-uniform: every lane holds the same point
-    const bool active = in && a2 != 0.0 && fabs(ux) < lim && fabs(uy) < lim && fabs(uz) < lim;
+    const bool active = in && a2 != 0.0;
     int j = -1;
     if (active) {
         TopK<KM> t;
-        topk_init(t);
-        int found = 0;
-        const long long cx = (long long)floor(ux), cy = (long long)floor(uy), cz = (long long)floor(uz);
-        for (int r = 0; r <= kMapMaxShell; ++r) {
-            const int side = 2 * r + 1, npos = side * side * side;
-            for (int p = lane; p < npos; p += 64) {
-                const int dz = p / (side * side) - r, rem = p % (side * side);
-                const int dy = rem / side - r, dx = rem % side - r;
-                if (max(abs(dx), max(abs(dy), abs(dz))) != r) continue;
-                tg.visit(cx + dx, cy + dy, cz + dz, X0, X1, X2, k, dmax2, t, found);
-            }
-            const double f = fmin(fmin(fmin(X0 - (double)(cx - r) * v, (double)(cx + r + 1) * v - X0),
-                                       fmin(X1 - (double)(cy - r) * v, (double)(cy + r + 1) * v - X1)),
-                                  fmin(X2 - (double)(cz - r) * v, (double)(cz + r + 1) * v - X2)) -
-                             1e-9;
-            if (f <= 0.0) continue;
-            const double f2 = f * f;
-            int c = 0;
-#pragma unroll
-            for (int q = 0; q < KM; ++q) c += (q < k && t.d[q] < f2) ? 1 : 0;
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
-            if (c >= k) break;
-            if (f2 > dmax2) break;
-        }
+        tg.template wave_knn<KM>(k, X0, X1, X2, lane, t);
         // the K nearest, one per round, into lanes 0 .. K-1
         double cd = DBL_MAX;
         int ci = INT_MAX;
@@ -672,27 +643,30 @@ __global__ __launch_bounds__(256) void k_gicp_linearise_map(const double* __rest
     }
 }
 
-// Sum of the partial records in a fixed order (blocks of 256 threads): value
-// q's blocks b = r (mod 8) summed in block order by thread 8 q + r, then the
-// eight partial sums in r order.
+// Sum of the partial records in a fixed order (blocks of 1024 threads):
+// value q's blocks b = r (mod 32) summed in block order by thread 32 q + r,
+// then the 32 partial sums in r order.
+constexpr int kSumStrands = 32;
+
 __device__ __forceinline__ void gicp_sum(const double* part, int nb, double* S) {
-    __shared__ double s_p[kGicpVals][8];
+    __shared__ double s_p[kGicpVals][kSumStrands];
     const int t = threadIdx.x;
-    if (t < kGicpVals * 8) {
-        const int q = t >> 3, r = t & 7;
+    if (t < kGicpVals * kSumStrands) {
+        const int q = t / kSumStrands, r = t % kSumStrands;
         double v = 0.0;
-        for (int b = r; b < nb; b += 8) v += part[(size_t)b * kGicpVals + q];
+#pragma unroll 4
+        for (int b = r; b < nb; b += kSumStrands) v += part[(size_t)b * kGicpVals + q];
         s_p[q][r] = v;
     }
     __syncthreads();
     if (t < kGicpVals) {
         double v = 0.0;
-        for (int r = 0; r < 8; ++r) v += s_p[t][r];
+        for (int r = 0; r < kSumStrands; ++r) v += s_p[t][r];
         S[t] = v;
     }
 }
 
-__global__ __launch_bounds__(256) void k_gicp_sum(const double* part, int nb, double* out) {
+__global__ __launch_bounds__(1024) void k_gicp_sum(const double* part, int nb, double* out) {
     __shared__ double S[kGicpVals];
     gicp_sum(part, nb, S);
     __syncthreads();
@@ -715,7 +689,7 @@ __device__ bool gicp_chol6(const double* A, double* L) {
 }
 
 // One Gauss-Newton step on the device pose; trace record `it` if trace.
-__global__ __launch_bounds__(256) void k_gicp_solve(const double* part, int nb, double* pose, double* trace, int it) {
+__global__ __launch_bounds__(1024) void k_gicp_solve(const double* part, int nb, double* pose, double* trace, int it) {
     __shared__ double S[kGicpVals];
     gicp_sum(part, nb, S);
     __syncthreads();
@@ -840,33 +814,29 @@ void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam
     else hipLaunchKernelGGL(k_gicp_prepare<kGicpMaxK>, grid, blk, 0, s, k, set, n, gicp_grid(cam, R));
 }
 
+int gicp_wave_blocks(int n) { return (n + 3) / 4; }
+
 template <class Target>
-static void linearise_t(const double* src, int ns, const Target& tg, int k, const double* pose, double* part,
-                        int* corr, hipStream_t s) {
+static void linearise_wave(const double* src, int ns, const Target& tg, int k, const double* pose, double* part,
+                           int* corr, hipStream_t s) {
+    const dim3 grid(gicp_wave_blocks(ns)), blk(256);
     if (k <= 16)
-        hipLaunchKernelGGL((k_gicp_linearise<16, Target>), dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns, tg, k,
-                           pose, part, corr);
+        hipLaunchKernelGGL((k_gicp_linearise_wave<16, Target>), grid, blk, 0, s, src, ns, tg, k, pose, part, corr);
     else
-        hipLaunchKernelGGL((k_gicp_linearise<kGicpMaxK, Target>), dim3(gicp_blocks(ns)), dim3(256), 0, s, src, ns,
-                           tg, k, pose, part, corr);
+        hipLaunchKernelGGL((k_gicp_linearise_wave<kGicpMaxK, Target>), grid, blk, 0, s, src, ns, tg, k, pose, part,
+                           corr);
 }
 
 void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, const sgad_cam& tcam, int tR,
                            int k, const double* pose, double* part, int* corr, hipStream_t s) {
     GridTarget tg{tgt, (size_t)nt, nt, gicp_grid(tcam, tR)};
-    linearise_t(src, ns, tg, k, pose, part, corr, s);
+    linearise_wave(src, ns, tg, k, pose, part, corr, s);
 }
-
-int gicp_map_blocks(int n) { return (n + 3) / 4; }
 
 void launch_gicp_linearise_map(const double* src, int ns, const sgad_gmap& m, int k, const double* pose,
                                double* part, int* corr, hipStream_t s) {
     MapTarget tg{m.data, (size_t)m.capacity, (const long long*)m.keys, m.vals, m.slots - 1, m.voxel};
-    const dim3 grid(gicp_map_blocks(ns)), blk(256);
-    if (k <= 16)
-        hipLaunchKernelGGL((k_gicp_linearise_map<16>), grid, blk, 0, s, src, ns, tg, k, pose, part, corr);
-    else
-        hipLaunchKernelGGL((k_gicp_linearise_map<kGicpMaxK>), grid, blk, 0, s, src, ns, tg, k, pose, part, corr);
+    linearise_wave(src, ns, tg, k, pose, part, corr, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1032,11 +1002,11 @@ void launch_fill_depth(int P, const float* depth, const float* rdepth, const flo
 }
 
 void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_gicp_sum, dim3(1), dim3(256), 0, s, part, nb, out);
+    hipLaunchKernelGGL(k_gicp_sum, dim3(1), dim3(1024), 0, s, part, nb, out);
 }
 
 void launch_gicp_solve(const double* part, int nb, double* pose, double* trace, int it, hipStream_t s) {
-    hipLaunchKernelGGL(k_gicp_solve, dim3(1), dim3(256), 0, s, part, nb, pose, trace, it);
+    hipLaunchKernelGGL(k_gicp_solve, dim3(1), dim3(1024), 0, s, part, nb, pose, trace, it);
 }
 
 }  // namespace sgad

@@ -41,7 +41,7 @@ void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt,
 void launch_gicp_sum(const double* part, int nb, double* out, hipStream_t s);
 void launch_gicp_linearise_map(const double* src, int ns, const sgad_gmap& m, int k, const double* pose,
                                double* part, int* corr, hipStream_t s);
-int gicp_map_blocks(int n);
+int gicp_wave_blocks(int n);
 void launch_gmap_reset(const sgad_gmap& m, hipStream_t s);
 void launch_gmap_insert(const sgad_gmap& m, const double* set, int n, const double* pose, hipStream_t s);
 void launch_fill_depth(int P, const float* depth, const float* rdepth, const float* ralpha, float alpha_min,
@@ -1113,7 +1113,7 @@ sgad_status sgad_gicp_linearise(sgad_ctx* c, const double* src, int n_src, const
     if (!out) return fail(c, SGAD_EINVAL, "null pointer");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
-    const int nb = gicp_blocks(n_src);
+    const int nb = gicp_wave_blocks(n_src);
     HIPCHK(c, ensure_c(c, c->gicp_part, (size_t)nb * gicp_vals() * sizeof(double), s));
     double* part = (double*)c->gicp_part.p;
     TimeScope ts(c, "gicp_linearise", s);
@@ -1131,7 +1131,7 @@ sgad_status sgad_gicp_track(sgad_ctx* c, const double* src, int n_src, const dou
     if (iters < 1) return fail(c, SGAD_EINVAL, "iters must be >= 1");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
-    const int nb = gicp_blocks(n_src);
+    const int nb = gicp_wave_blocks(n_src);
     HIPCHK(c, ensure_c(c, c->gicp_part, (size_t)nb * gicp_vals() * sizeof(double), s));
     double* part = (double*)c->gicp_part.p;
     TimeScope ts(c, "gicp_iteration", s);
@@ -1194,7 +1194,7 @@ sgad_status sgad_gicp_linearise_map(sgad_ctx* c, const double* src, int n_src, c
     if (!out) return fail(c, SGAD_EINVAL, "null pointer");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
-    const int nb = gicp_map_blocks(n_src);
+    const int nb = gicp_wave_blocks(n_src);
     HIPCHK(c, ensure_c(c, c->gicp_part, (size_t)nb * gicp_vals() * sizeof(double), s));
     double* part = (double*)c->gicp_part.p;
     TimeScope ts(c, "gicp_linearise_map", s);
@@ -1211,7 +1211,7 @@ sgad_status sgad_gicp_track_map(sgad_ctx* c, const double* src, int n_src, const
     if (iters < 1) return fail(c, SGAD_EINVAL, "iters must be >= 1");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = pick_stream(c, stream);
-    const int nb = gicp_map_blocks(n_src);
+    const int nb = gicp_wave_blocks(n_src);
     HIPCHK(c, ensure_c(c, c->gicp_part, (size_t)nb * gicp_vals() * sizeof(double), s));
     double* part = (double*)c->gicp_part.p;
     TimeScope ts(c, "gicp_map_iteration", s);
