@@ -552,21 +552,25 @@ __device__ __forceinline__ void wave_argmin(double& d, int& idx) {
     }
 }
 
-// GICP linearisation with one wavefront per source point (four per block):
+// GICP linearisation with one wavefront per source point (eight per block):
 // the target's wave_knn splits the neighbour search over the lanes, each
 // keeping its own top-K list; the K nearest are then taken from the lanes'
 // sorted lists in (distance, index) order, lane r receiving the r-th; the
 // lanes evaluate their candidate's surface distance, and the pair's terms are
 // formed by lane 0.  Same results as the one-thread searches of the targets,
 // with 64 times as many threads at work.
+constexpr int kWavePoints = 8;   // source points (wavefronts) per block of the linearisation
+
 template <int KM, class Target>
-__global__ __launch_bounds__(256) void k_gicp_linearise_wave(const double* __restrict__ src, int ns, Target tg,
-                                                             int k, const double* __restrict__ pose,
-                                                             double* __restrict__ part, int* __restrict__ corr) {
+__global__ __launch_bounds__(64 * kWavePoints) void k_gicp_linearise_wave(const double* __restrict__ src, int ns,
+                                                                          Target tg, int k,
+                                                                          const double* __restrict__ pose,
+                                                                          double* __restrict__ part,
+                                                                          int* __restrict__ corr) {
 #pragma clang fp contract(off)
-    __shared__ double s_acc[4][kGicpVals];
+    __shared__ double s_acc[kWavePoints][kGicpVals];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = (int)blockIdx.x * 4 + wave;
+    const int i = (int)blockIdx.x * kWavePoints + wave;
     double Rm[9], tv[3];
 #pragma unroll
     for (int r = 0; r < 9; ++r) Rm[r] = pose[r];
@@ -639,7 +643,9 @@ __global__ __launch_bounds__(256) void k_gicp_linearise_wave(const double* __res
     __syncthreads();
     if (threadIdx.x < kGicpVals) {
         const int q = threadIdx.x;
-        part[(size_t)blockIdx.x * kGicpVals + q] = ((s_acc[0][q] + s_acc[1][q]) + s_acc[2][q]) + s_acc[3][q];
+        double v = 0.0;
+        for (int w = 0; w < kWavePoints; ++w) v += s_acc[w][q];
+        part[(size_t)blockIdx.x * kGicpVals + q] = v;
     }
 }
 
@@ -814,12 +820,12 @@ void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam
     else hipLaunchKernelGGL(k_gicp_prepare<kGicpMaxK>, grid, blk, 0, s, k, set, n, gicp_grid(cam, R));
 }
 
-int gicp_wave_blocks(int n) { return (n + 3) / 4; }
+int gicp_wave_blocks(int n) { return (n + kWavePoints - 1) / kWavePoints; }
 
 template <class Target>
 static void linearise_wave(const double* src, int ns, const Target& tg, int k, const double* pose, double* part,
                            int* corr, hipStream_t s) {
-    const dim3 grid(gicp_wave_blocks(ns)), blk(256);
+    const dim3 grid(gicp_wave_blocks(ns)), blk(64 * kWavePoints);
     if (k <= 16)
         hipLaunchKernelGGL((k_gicp_linearise_wave<16, Target>), grid, blk, 0, s, src, ns, tg, k, pose, part, corr);
     else
