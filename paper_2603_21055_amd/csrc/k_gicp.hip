@@ -8,7 +8,7 @@
 // (point in its camera's frame, normalised covariance, normal).  A grid
 // pixel without depth has z = 0 there and is never a neighbour or a source.
 //
-// k_gicp_prepare   one thread per grid point: back-projection, its K_c
+// k_gicp_prepare   one wavefront per grid point: back-projection, its K_c
 //                  nearest points of the set (squared distance ((dx^2 +
 //                  dy^2) + dz^2), ties by index, a register top-K, searched
 //                  in growing windows of grid cells until a distance bound
@@ -211,84 +211,6 @@ __device__ void jacobi3(double* a, double* w, double* v) {
     w[2] = a[8];
 }
 
-// Runs after k_gicp_points: reads the coordinate rows, writes rows 3..11.
-template <int KM>
-__global__ __launch_bounds__(256) void k_gicp_prepare(int k, double* __restrict__ set, int n, GicpGrid grid) {
-#pragma clang fp contract(off)
-    const int g = (int)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    const double qx = set[g], qy = set[(size_t)n + g], qz = set[2 * (size_t)n + g];
-    if (qz == 0.0) {
-        for (int r = 3; r < 12; ++r) set[(size_t)r * n + g] = 0.0;
-        return;
-    }
-    TopK<KM> t;
-    knn_grid(set, n, grid, k, qx, qy, qz, t, DBL_MAX);
-    int kk = 0;
-    double mx = 0.0, my = 0.0, mz = 0.0;
-#pragma unroll
-    for (int s = 0; s < KM; ++s)
-        if (s < k && t.i[s] != INT_MAX) {
-            const int j = t.i[s];
-            mx += set[j];
-            my += set[(size_t)n + j];
-            mz += set[2 * (size_t)n + j];
-            ++kk;
-        }
-    mx /= (double)kk;
-    my /= (double)kk;
-    mz /= (double)kk;
-    double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int s = 0; s < KM; ++s)
-        if (s < k && t.i[s] != INT_MAX) {
-            const int j = t.i[s];
-            const double dx = set[j] - mx, dy = set[(size_t)n + j] - my, dz = set[2 * (size_t)n + j] - mz;
-            c[0] += dx * dx;
-            c[1] += dx * dy;
-            c[2] += dx * dz;
-            c[4] += dy * dy;
-            c[5] += dy * dz;
-            c[8] += dz * dz;
-        }
-    for (int i = 0; i < 9; ++i) c[i] /= (double)kk;
-    c[3] = c[1];
-    c[6] = c[2];
-    c[7] = c[5];
-    double w[3], v[9];
-    jacobi3(c, w, v);
-    // ascending order of the eigenvalues
-    int o[3] = {0, 1, 2};
-    if (w[o[0]] > w[o[1]]) { const int x = o[0]; o[0] = o[1]; o[1] = x; }
-    if (w[o[1]] > w[o[2]]) { const int x = o[1]; o[1] = o[2]; o[2] = x; }
-    if (w[o[0]] > w[o[1]]) { const int x = o[0]; o[0] = o[1]; o[1] = x; }
-    const double l2 = w[o[2]];
-    double sc[3];
-    if (l2 > 0.0) {
-        sc[0] = fmax(w[o[0]] / l2, kGicpEps);
-        sc[1] = fmax(w[o[1]] / l2, kGicpEps);
-        sc[2] = 1.0;
-    } else {
-        sc[0] = kGicpEps;
-        sc[1] = kGicpEps;
-        sc[2] = 1.0;
-    }
-    double cn[6] = {0, 0, 0, 0, 0, 0};   // c00 c01 c02 c11 c12 c22
-    for (int e = 0; e < 3; ++e) {
-        const double ux = v[0 * 3 + o[e]], uy = v[1 * 3 + o[e]], uz = v[2 * 3 + o[e]];
-        cn[0] += sc[e] * ux * ux;
-        cn[1] += sc[e] * ux * uy;
-        cn[2] += sc[e] * ux * uz;
-        cn[3] += sc[e] * uy * uy;
-        cn[4] += sc[e] * uy * uz;
-        cn[5] += sc[e] * uz * uz;
-    }
-    for (int r = 0; r < 6; ++r) set[(size_t)(3 + r) * n + g] = cn[r];
-    set[(size_t)9 * n + g] = v[0 * 3 + o[0]];
-    set[(size_t)10 * n + g] = v[1 * 3 + o[0]];
-    set[(size_t)11 * n + g] = v[2 * 3 + o[0]];
-}
-
 // Grid point g = (gy, gx) of a stride-R grid: a = D ((u - cx) / fx, (v - cy) / fy, 1).
 __global__ __launch_bounds__(256) void k_gicp_points(const float* __restrict__ depth, int H, int W, int R,
                                                      double fx, double fy, double cx, double cy,
@@ -363,6 +285,7 @@ struct GridTarget {
     size_t stride;
     int n;
     GicpGrid g;
+    double dmax2;   // candidates within this squared distance (DBL_MAX: all)
     // knn_grid's windows with the cells of each new ring split over the
     // lanes of a wavefront (each lane keeping its own list); the window
     // stops once the lanes together hold k entries below the bound, or the
@@ -371,7 +294,6 @@ struct GridTarget {
     __device__ void wave_knn(int k, double qx, double qy, double qz, int lane, TopK<KM>& t) const {
 #pragma clang fp contract(off)
         topk_init(t);
-        const double dmax2 = kGicpDMax * kGicpDMax;
         int cu = 0, cv = 0, w = g.gw + g.gh;
         double u = 0.0, v = 0.0;
         if (qz > 0.0) {
@@ -552,6 +474,130 @@ __device__ __forceinline__ void wave_argmin(double& d, int& idx) {
     }
 }
 
+// The k smallest entries of the lanes' sorted lists, in (distance, index)
+// order: lane r < k receives the r-th (INT_MAX index past the last).
+template <int KM>
+__device__ __forceinline__ void wave_take_k(TopK<KM>& t, int k, int lane, double& cd, int& ci) {
+    cd = DBL_MAX;
+    ci = INT_MAX;
+    for (int r = 0; r < k; ++r) {
+        double bd = t.d[0];
+        int bi = t.i[0];
+        wave_argmin(bd, bi);
+        if (bi == INT_MAX) break;
+        if (lane == r) {
+            cd = bd;
+            ci = bi;
+        }
+        if (t.i[0] == bi) {   // the owner drops its head
+#pragma unroll
+            for (int q = 0; q + 1 < KM; ++q) {
+                t.d[q] = t.d[q + 1];
+                t.i[q] = t.i[q + 1];
+            }
+            t.d[KM - 1] = DBL_MAX;
+            t.i[KM - 1] = INT_MAX;
+        }
+    }
+}
+
+// Runs after k_gicp_points: reads the coordinate rows, writes rows 3..11.
+template <int KM>
+__global__ __launch_bounds__(512) void k_gicp_prepare(int k, double* __restrict__ set, int n, GicpGrid grid) {
+#pragma clang fp contract(off)
+    // one wavefront per grid point: the lanes split the neighbour search,
+    // lane 0 forms the covariance from the K_c nearest in order
+    __shared__ int s_nb[8][kGicpMaxK];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = (int)blockIdx.x * 8 + wave;
+    if (g >= n) return;   // wave-uniform
+    const double qx = set[g], qy = set[(size_t)n + g], qz = set[2 * (size_t)n + g];
+    if (qz == 0.0) {
+        if (lane >= 3 && lane < 12) set[(size_t)lane * n + g] = 0.0;
+        return;
+    }
+    TopK<KM> t;
+    {
+        GridTarget tg{set, (size_t)n, n, grid, DBL_MAX};
+        TopK<KM> tl;
+        tg.template wave_knn<KM>(k, qx, qy, qz, lane, tl);
+        double cd;
+        int ci;
+        wave_take_k(tl, k, lane, cd, ci);
+        if (lane < k) s_nb[wave][lane] = ci;
+    }
+    // lane 0 reads what the wave's lanes wrote: wait for the LDS stores
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    if (lane != 0) return;
+    topk_init(t);
+#pragma unroll
+    for (int q = 0; q < KM; ++q)
+        if (q < k) t.i[q] = s_nb[wave][q];
+    int kk = 0;
+    double mx = 0.0, my = 0.0, mz = 0.0;
+#pragma unroll
+    for (int s = 0; s < KM; ++s)
+        if (s < k && t.i[s] != INT_MAX) {
+            const int j = t.i[s];
+            mx += set[j];
+            my += set[(size_t)n + j];
+            mz += set[2 * (size_t)n + j];
+            ++kk;
+        }
+    mx /= (double)kk;
+    my /= (double)kk;
+    mz /= (double)kk;
+    double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KM; ++s)
+        if (s < k && t.i[s] != INT_MAX) {
+            const int j = t.i[s];
+            const double dx = set[j] - mx, dy = set[(size_t)n + j] - my, dz = set[2 * (size_t)n + j] - mz;
+            c[0] += dx * dx;
+            c[1] += dx * dy;
+            c[2] += dx * dz;
+            c[4] += dy * dy;
+            c[5] += dy * dz;
+            c[8] += dz * dz;
+        }
+    for (int i = 0; i < 9; ++i) c[i] /= (double)kk;
+    c[3] = c[1];
+    c[6] = c[2];
+    c[7] = c[5];
+    double w[3], v[9];
+    jacobi3(c, w, v);
+    // ascending order of the eigenvalues
+    int o[3] = {0, 1, 2};
+    if (w[o[0]] > w[o[1]]) { const int x = o[0]; o[0] = o[1]; o[1] = x; }
+    if (w[o[1]] > w[o[2]]) { const int x = o[1]; o[1] = o[2]; o[2] = x; }
+    if (w[o[0]] > w[o[1]]) { const int x = o[0]; o[0] = o[1]; o[1] = x; }
+    const double l2 = w[o[2]];
+    double sc[3];
+    if (l2 > 0.0) {
+        sc[0] = fmax(w[o[0]] / l2, kGicpEps);
+        sc[1] = fmax(w[o[1]] / l2, kGicpEps);
+        sc[2] = 1.0;
+    } else {
+        sc[0] = kGicpEps;
+        sc[1] = kGicpEps;
+        sc[2] = 1.0;
+    }
+    double cn[6] = {0, 0, 0, 0, 0, 0};   // c00 c01 c02 c11 c12 c22
+    for (int e = 0; e < 3; ++e) {
+        const double ux = v[0 * 3 + o[e]], uy = v[1 * 3 + o[e]], uz = v[2 * 3 + o[e]];
+        cn[0] += sc[e] * ux * ux;
+        cn[1] += sc[e] * ux * uy;
+        cn[2] += sc[e] * ux * uz;
+        cn[3] += sc[e] * uy * uy;
+        cn[4] += sc[e] * uy * uz;
+        cn[5] += sc[e] * uz * uz;
+    }
+    for (int r = 0; r < 6; ++r) set[(size_t)(3 + r) * n + g] = cn[r];
+    set[(size_t)9 * n + g] = v[0 * 3 + o[0]];
+    set[(size_t)10 * n + g] = v[1 * 3 + o[0]];
+    set[(size_t)11 * n + g] = v[2 * 3 + o[0]];
+}
+
 // GICP linearisation with one wavefront per source point (eight per block):
 // the target's wave_knn splits the neighbour search over the lanes, each
 // keeping its own top-K list; the K nearest are then taken from the lanes'
@@ -593,27 +639,9 @@ __global__ __launch_bounds__(64 * kWavePoints) void k_gicp_linearise_wave(const 
         TopK<KM> t;
         tg.template wave_knn<KM>(k, X0, X1, X2, lane, t);
         // the K nearest, one per round, into lanes 0 .. K-1
-        double cd = DBL_MAX;
-        int ci = INT_MAX;
-        for (int r = 0; r < k; ++r) {
-            double bd = t.d[0];
-            int bi = t.i[0];
-            wave_argmin(bd, bi);
-            if (bi == INT_MAX) break;
-            if (lane == r) {
-                cd = bd;
-                ci = bi;
-            }
-            if (t.i[0] == bi) {   // the owner drops its head
-#pragma unroll
-                for (int q = 0; q + 1 < KM; ++q) {
-                    t.d[q] = t.d[q + 1];
-                    t.i[q] = t.i[q + 1];
-                }
-                t.d[KM - 1] = DBL_MAX;
-                t.i[KM - 1] = INT_MAX;
-            }
-        }
+        double cd;
+        int ci;
+        wave_take_k(t, k, lane, cd, ci);
         // the closest surface element, first minimum in distance order
         const double* tgt = tg.d;
         const size_t nt = tg.stride;
@@ -816,8 +844,9 @@ void launch_gicp_prepare(const float* depth, int H, int W, int R, const sgad_cam
     const dim3 grid(gicp_blocks(n)), blk(256);
     hipLaunchKernelGGL(k_gicp_points, grid, blk, 0, s, depth, H, W, R, (double)cam.fx, (double)cam.fy,
                        (double)cam.cx, (double)cam.cy, set, n);
-    if (k <= 16) hipLaunchKernelGGL(k_gicp_prepare<16>, grid, blk, 0, s, k, set, n, gicp_grid(cam, R));
-    else hipLaunchKernelGGL(k_gicp_prepare<kGicpMaxK>, grid, blk, 0, s, k, set, n, gicp_grid(cam, R));
+    const dim3 wgrid((n + 7) / 8), wblk(512);
+    if (k <= 16) hipLaunchKernelGGL(k_gicp_prepare<16>, wgrid, wblk, 0, s, k, set, n, gicp_grid(cam, R));
+    else hipLaunchKernelGGL(k_gicp_prepare<kGicpMaxK>, wgrid, wblk, 0, s, k, set, n, gicp_grid(cam, R));
 }
 
 int gicp_wave_blocks(int n) { return (n + kWavePoints - 1) / kWavePoints; }
@@ -835,7 +864,7 @@ static void linearise_wave(const double* src, int ns, const Target& tg, int k, c
 
 void launch_gicp_linearise(const double* src, int ns, const double* tgt, int nt, const sgad_cam& tcam, int tR,
                            int k, const double* pose, double* part, int* corr, hipStream_t s) {
-    GridTarget tg{tgt, (size_t)nt, nt, gicp_grid(tcam, tR)};
+    GridTarget tg{tgt, (size_t)nt, nt, gicp_grid(tcam, tR), kGicpDMax * kGicpDMax};
     linearise_wave(src, ns, tg, k, pose, part, corr, s);
 }
 
