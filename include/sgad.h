@@ -344,19 +344,20 @@ int32_t sgad_gicp_set_size(int H, int W, int ratio);
 sgad_status sgad_gicp_prepare(sgad_ctx* ctx, const float* depth, const sgad_cam* cam, int ratio, int k,
                               double* set, void* stream);
 /* One linearisation of Eq. 2 at the device pose: each valid source point X
- * is matched among its K_c nearest target points (Euclidean, ties by index)
- * to the one minimising (n_b . e)^2 + 1e-3 |e|^2, e = X - b (first minimum in
- * distance order), and kept when |e|^2 <= 0.1^2 m^2; with M = (C_b + R C_a
- * R^T)^-1 and J = de/dxi = [-I | [X]x] for the left twist xi = (rho, phi):
- * out (device double[29]) = H = sum J^T M J (upper triangle, row-major, 21),
- * g = sum J^T M (b - X) (6), the cost sum e^T M e and the pair count,
- * WRITTEN.  corr (device int32[n_src], may be NULL): the matched target index
- * per source point, -1 for none.  Uses a context workspace of 29 doubles per
- * 256 source points.  tgt_cam / tgt_ratio: the camera and stride the target
- * set was prepared with (SGAD_EINVAL unless they give n_tgt grid points): the
- * neighbour search first scans the grid cells around the one X projects to
- * and falls back to all target points unless that window provably holds the
- * K_c nearest. */
+ * is matched among its K_c nearest target points within 0.1 m (Euclidean,
+ * ties by index; none: no pair) to the one minimising (n_b . e)^2 +
+ * 1e-3 |e|^2, e = X - b (first minimum in distance order); with M = (C_b +
+ * R C_a R^T)^-1 and J = de/dxi = [-I | [X]x] for the left twist
+ * xi = (rho, phi): out (device double[29]) = H = sum J^T M J (upper
+ * triangle, row-major, 21), g = sum J^T M (b - X) (6), the cost sum
+ * e^T M e and the pair count, WRITTEN.  corr (device int32[n_src], may be
+ * NULL): the matched target index per source point, -1 for none.  Uses a
+ * context workspace of 29 doubles per 8 source points (one wavefront per
+ * point).  tgt_cam / tgt_ratio: the camera and stride the target set was
+ * prepared with (SGAD_EINVAL unless they give n_tgt grid points): the
+ * neighbour search scans windows of grid cells around the one X projects
+ * to, growing until a distance bound proves that no point outside can be
+ * among the K_c nearest or within 0.1 m. */
 sgad_status sgad_gicp_linearise(sgad_ctx* ctx, const double* src, int n_src, const double* tgt, int n_tgt,
                                 const sgad_cam* tgt_cam, int tgt_ratio, int k, const double* pose, double* out,
                                 int32_t* corr, void* stream);
