@@ -14,35 +14,65 @@ namespace sgad {
 // (t < 0: none); lanes naming the same counter are served by one atomic from
 // their lowest lane, and each learns its rank among them.  Neighbouring
 // Gaussians overlap the same tiles, so a wave issues a handful of atomics
-// instead of one per lane.  The target is read with a scalar lane read and the
-// atomics' return values are collected after the loop, so the loop does not
-// wait on memory.  Returns the pre-increment value plus the rank (only
-// meaningful for lanes with t >= 0 when need_pos).
+// instead of one per lane.  The grouping is scalar work (lane reads and
+// ballots); all leaders then issue one atomic instruction together, whose
+// return stays in flight until agg_slot() reads it, so a caller can issue
+// several rounds before it waits on the first.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t wave_agg_add(uint32_t* ctr, int64_t t, bool need_pos) {
+struct AggRound {
+    uint32_t ret;    // the leader's pre-increment value (leaders only; in flight)
+    uint32_t rank;   // the lane's rank among the lanes naming its counter
+    int leader;      // the lowest lane naming the lane's counter
+};
+
+template <bool NEED_POS>
+__device__ __forceinline__ AggRound wave_agg_issue(uint32_t* ctr, int64_t t) {
     const int lane = threadIdx.x & 63;
     const int t_lo = (int)(uint32_t)(uint64_t)t, t_hi = (int)(uint32_t)((uint64_t)t >> 32);
     uint64_t active = __ballot(t >= 0);
-    uint32_t ret = 0, rank = 0;
-    int leader_of_mine = 0;
+    AggRound a{0u, 0u, 0};
+    uint32_t cnt = 0;   // nonzero on leader lanes: the size of their group
     while (active) {
         const int leader = (int)__builtin_ctzll(active);
         const int64_t tgt = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(t_hi, leader) << 32) |
                                       (uint32_t)__builtin_amdgcn_readlane(t_lo, leader));
         const uint64_t peers = __ballot(t == tgt) & active;
-        if (lane == leader) {
-            if (need_pos) ret = atomicAdd(&ctr[tgt], (uint32_t)__popcll(peers));
-            else atomicAdd(&ctr[tgt], (uint32_t)__popcll(peers));
-        }
+        if (lane == leader) cnt = (uint32_t)__popcll(peers);
         if ((peers >> lane) & 1ull) {
-            leader_of_mine = leader;
-            rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+            a.leader = leader;
+            a.rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
         }
         active &= ~peers;
     }
-    if (!need_pos) return 0u;
-    return (uint32_t)__shfl((int)ret, leader_of_mine, 64) + rank;
+    if (cnt != 0u) {
+        if (NEED_POS) a.ret = atomicAdd(&ctr[t], cnt);
+        else atomicAdd(&ctr[t], cnt);
+    }
+    return a;
 }
+
+// The lane's slot of a round: its leader's pre-increment value plus its rank
+// (meaningful for lanes that named a counter).
+__device__ __forceinline__ uint32_t agg_slot(const AggRound& a) {
+    return (uint32_t)__shfl((int)a.ret, a.leader, 64) + a.rank;
+}
+
+// The cells of a tile rectangle [x0, x1) x [y0, y1) in row order, one per
+// call of next(): the counter index base + y * ntx + x, or -1 past the end.
+struct RectWalk {
+    int x, y, x0, x1, y1;
+    __device__ __forceinline__ RectWalk(int x0_, int x1_, int y0_, int y1_, bool any)
+        : x(x0_), y(any && x0_ < x1_ ? y0_ : y1_), x0(x0_), x1(x1_), y1(y1_) {}
+    __device__ __forceinline__ int64_t next(int64_t base, int ntx) {
+        if (y >= y1) return -1;
+        const int64_t t = base + (int64_t)y * ntx + x;
+        if (++x == x1) {
+            x = x0;
+            ++y;
+        }
+        return t;
+    }
+};
 
 // Gaussian of this thread: each wavefront takes an 8x8 patch of one keyframe,
 // so its Gaussians overlap few distinct tiles per counting round.  Grid: x =
@@ -162,14 +192,11 @@ __global__ __launch_bounds__(256) void k_preprocess(Geometry G, RenderBufs B) {
     }
     {
         // count the overlapped tiles, one wave-aggregated round per rectangle cell
-        const int w = x1 - x0, n = ok ? w * (y1 - y0) : 0;
+        const int n = ok ? (x1 - x0) * (y1 - y0) : 0;
         const int nmax = wave_max_int(n);
         const int64_t base = (int64_t)pc.job * G.ntiles;
-        for (int k = 0; k < nmax; ++k) {
-            int64_t t = -1;
-            if (k < n) t = base + (int64_t)(y0 + k / w) * G.ntx + (x0 + k % w);
-            wave_agg_add(B.tile_count, t, false);
-        }
+        RectWalk rw(x0, x1, y0, y1, ok);
+        for (int k = 0; k < nmax; ++k) wave_agg_issue<false>(B.tile_count, rw.next(base, G.ntx));
     }
     if (!live) return;
     const float fz = ok ? (float)z : 0.f;
@@ -405,6 +432,8 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ count, uin
 // Key = float bits of z << 32 | gid; the order inside a segment is fixed later
 // by the sort, so the atomic slot order does not matter.
 // ---------------------------------------------------------------------------
+constexpr int kScatterBatch = 4;
+
 __global__ __launch_bounds__(256) void k_scatter(Geometry G, RenderBufs B) {
     const PatchPos pp = patch_pos(G);
     const size_t i = (size_t)pp.pair * G.N + pp.pix;
@@ -423,18 +452,33 @@ __global__ __launch_bounds__(256) void k_scatter(Geometry G, RenderBufs B) {
         key = ((uint64_t)__float_as_uint(B.pre.z[i]) << 32) | gid;
         base = (int64_t)pc.job * G.ntiles;
     }
-    const int w = x1 - x0;
-    const int n = (x0 < x1 && y0 < y1) ? w * (y1 - y0) : 0;
+    const int n = (x0 < x1 && y0 < y1) ? (x1 - x0) * (y1 - y0) : 0;
     const int nmax = wave_max_int(n);
     bool dropped = false;
-    for (int k = 0; k < nmax; ++k) {
-        int64_t t = -1;
-        if (k < n) t = base + (int64_t)(y0 + k / w) * G.ntx + (x0 + k % w);
-        const uint32_t r = wave_agg_add(B.tile_fill, t, true);
-        if (t >= 0) {
-            const uint32_t pos = B.tile_start[t] + r;
-            if (pos < B.capacity) B.keys[pos] = key;
-            else dropped = true;
+    RectWalk rw(x0, x1, y0, y1, pp.live);
+    // rounds are issued kScatterBatch at a time: their segment starts and
+    // fill atomics all in flight before the first slot is read
+    for (int k0 = 0; k0 < nmax; k0 += kScatterBatch) {
+        int64_t t[kScatterBatch];
+        uint32_t st0[kScatterBatch];
+        AggRound ar[kScatterBatch];
+#pragma unroll
+        for (int j = 0; j < kScatterBatch; ++j) {
+            t[j] = k0 + j < nmax ? rw.next(base, G.ntx) : -1;
+            st0[j] = t[j] >= 0 ? B.tile_start[t[j]] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kScatterBatch; ++j)
+            if (k0 + j < nmax) ar[j] = wave_agg_issue<true>(B.tile_fill, t[j]);
+#pragma unroll
+        for (int j = 0; j < kScatterBatch; ++j) {
+            if (k0 + j >= nmax) break;
+            const uint32_t r = agg_slot(ar[j]);
+            if (t[j] >= 0) {
+                const uint32_t pos = st0[j] + r;
+                if (pos < B.capacity) B.keys[pos] = key;
+                else dropped = true;
+            }
         }
     }
     // an instance that did not fit is the overflow the caller must hear of

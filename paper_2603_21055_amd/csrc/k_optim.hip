@@ -72,18 +72,20 @@ __device__ __forceinline__ double l1_pixel(float r0, float r1, float r2, float d
 
 // Loss value and upstream grads:
 //   L = w_rgb mean|rgb - t_rgb| + w_depth sum_U |D' - D_t| / |U|
-// Same grid as k_count_valid; each block first sums the job's partial counts.
+// Same grid as k_count_valid; each block first sums the job's nparts partial
+// counts (k_count_valid's per block, or the SSIM maps' per tile).
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const float* __restrict__ dep,
                                             const float* __restrict__ t_rgb, const float* __restrict__ t_dep,
                                             int P, float w_rgb, float w_dep, const uint32_t* __restrict__ part,
-                                            float* __restrict__ g_rgb, float* __restrict__ g_dep, double* loss) {
+                                            int nparts, float* __restrict__ g_rgb, float* __restrict__ g_dep,
+                                            double* loss) {
     const int job = blockIdx.y;
     __shared__ uint32_t s_c[4];
     __shared__ double s_a[4];
     {
         uint32_t c = 0;
-        for (int k = threadIdx.x; k < (int)gridDim.x; k += 256) c += part[(size_t)job * gridDim.x + k];
+        for (int k = threadIdx.x; k < nparts; k += 256) c += part[(size_t)job * nparts + k];
         c = wave_sum_u(c);
         if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = c;
         __syncthreads();
@@ -243,19 +245,22 @@ __global__ __launch_bounds__(256) void k_adam(AdamGroups A, float b1, float b2, 
 // `part` holds one u32 per (job, block): n_jobs * l1_blocks(P) entries.
 int l1_blocks(int P) { return (P + 1023) / 1024; }
 
+// nparts 0: count the valid target depths into part first; else part
+// already holds nparts counts per job and loss is already cleared.
 void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const float* t_rgb, const float* t_dep,
-               float w_rgb, float w_dep, uint32_t* part, float* g_rgb, float* g_dep, double* loss,
+               float w_rgb, float w_dep, uint32_t* part, int nparts, float* g_rgb, float* g_dep, double* loss,
                hipStream_t s) {
     const dim3 grid(l1_blocks(P), n_jobs);
     auto al = [](const void* q) { return ((uintptr_t)q & 15u) == 0; };
     const bool vec = P % 4 == 0 && al(rgb) && al(dep) && al(t_rgb) && al(t_dep) && al(g_rgb) && al(g_dep);
+    const int np = nparts > 0 ? nparts : (int)grid.x;
     if (vec) {
-        hipLaunchKernelGGL(k_count_valid<true>, grid, dim3(256), 0, s, t_dep, P, part, loss);
-        hipLaunchKernelGGL(k_l1<true>, grid, dim3(256), 0, s, rgb, dep, t_rgb, t_dep, P, w_rgb, w_dep, part,
+        if (nparts <= 0) hipLaunchKernelGGL(k_count_valid<true>, grid, dim3(256), 0, s, t_dep, P, part, loss);
+        hipLaunchKernelGGL(k_l1<true>, grid, dim3(256), 0, s, rgb, dep, t_rgb, t_dep, P, w_rgb, w_dep, part, np,
                            g_rgb, g_dep, loss);
     } else {
-        hipLaunchKernelGGL(k_count_valid<false>, grid, dim3(256), 0, s, t_dep, P, part, loss);
-        hipLaunchKernelGGL(k_l1<false>, grid, dim3(256), 0, s, rgb, dep, t_rgb, t_dep, P, w_rgb, w_dep, part,
+        if (nparts <= 0) hipLaunchKernelGGL(k_count_valid<false>, grid, dim3(256), 0, s, t_dep, P, part, loss);
+        hipLaunchKernelGGL(k_l1<false>, grid, dim3(256), 0, s, rgb, dep, t_rgb, t_dep, P, w_rgb, w_dep, part, np,
                            g_rgb, g_dep, loss);
     }
 }

@@ -103,18 +103,28 @@ constexpr int kRowItems = kSsimE * (kSsimT / 4);
 
 // One block per (plane, tile), plane z = colour channel z % 3 of job z / 3.
 // dmap [n_jobs * 3][3][H][W]; part[z][tile] = the tile's SSIM sum (written;
-// k_ssim_grad adds them to the loss in a fixed order).
+// k_ssim_grad adds them to the loss in a fixed order).  With cnt, the blocks
+// of each job's first plane also count the tile's valid target depths
+// (D > 0) into cnt[job][tile] for the masked depth term, and the job's first
+// tile clears loss[job], which the L1 and SSIM terms then add to.
 __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __restrict__ rgb,
                                                    const float* __restrict__ t_rgb, float* __restrict__ dmap,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part, const float* __restrict__ t_depth,
+                                                   uint32_t* __restrict__ cnt, double* loss) {
     __shared__ float s_in[2][kSsimE][kSsimE + 1];    // observed x, rendered y
     // row-filtered x, y, x^2 + y^2, xy: SSIM needs the two variances only
     // as their sum (18.9 KB of LDS per block, eight blocks per CU)
     __shared__ double s_h[4][kSsimE][kSsimT];
     __shared__ double s_red[4];
+    __shared__ uint32_t s_cnt[4];
     const SsimTile st = ssim_tile(H, W);
     const int plane = st.plane;
     const size_t P = (size_t)H * W;
+    const bool counts = cnt != nullptr && plane % 3 == 0;
+    const int cx = st.tx * kSsimT + (int)(threadIdx.x & (kSsimT - 1));
+    const int cy = st.ty * kSsimT + (int)(threadIdx.x >> 4);
+    float tdep = 0.f;   // loaded first, counted after the filtering
+    if (counts && cx < W && cy < H) tdep = t_depth[(size_t)(plane / 3) * P + (size_t)cy * W + cx];
     const float* src[2] = {t_rgb + (size_t)plane * P, rgb + (size_t)plane * P};
     const double* s_g = c_ssim_g;
     ssim_load<2>(H, W, st, src, s_in);
@@ -175,8 +185,20 @@ __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __
         dm[P + o] = (float)d_eyy;
         dm[2 * P + o] = (float)d_exy;
     }
-    const double sum = block_sum_d(S, s_red);
-    if (threadIdx.x == 0) part[(size_t)plane * st.ntx * st.nty + st.ty * st.ntx + st.tx] = sum;
+    if (counts) {
+        const uint32_t c = (uint32_t)__popcll(__ballot(tdep > 0.f));
+        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = c;
+    }
+    const double sum = block_sum_d(S, s_red);   // (its barrier also publishes s_cnt)
+    const int tile = st.ty * st.ntx + st.tx;
+    if (threadIdx.x == 0) {
+        part[(size_t)plane * st.ntx * st.nty + tile] = sum;
+        if (counts) {
+            const int job = plane / 3;
+            cnt[(size_t)job * st.ntx * st.nty + tile] = (s_cnt[0] + s_cnt[1]) + (s_cnt[2] + s_cnt[3]);
+            if (tile == 0) loss[job] = 0.0;
+        }
+    }
 }
 
 // Same grid: g_rgb[plane] += -tau / (3 P) [G*d_my + 2 y G*d_eyy + x G*d_exy].
@@ -247,7 +269,7 @@ __global__ __launch_bounds__(256) void k_ssim_grad(int H, int W, const float* __
     g_rgb[o] = (float)((double)g_rgb[o] + gr);
 }
 
-static size_t ssim_tiles(int H, int W) {
+size_t ssim_tiles(int H, int W) {
     return (size_t)((W + kSsimT - 1) / kSsimT) * (size_t)((H + kSsimT - 1) / kSsimT);
 }
 
@@ -257,14 +279,26 @@ size_t ssim_map_bytes(int n_jobs, int H, int W) {
     return ((maps + 255) & ~(size_t)255) + (size_t)n_jobs * 3 * ssim_tiles(H, W) * sizeof(double);
 }
 
-void launch_ssim(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
-                 float* g_rgb, double* loss, hipStream_t s) {
-    const dim3 grid((unsigned)(ssim_tiles(H, W) * 3 * n_jobs)), blk(256);
-    float* dmap = (float*)ws;
+static double* ssim_part(int n_jobs, int H, int W, void* ws) {
     const size_t maps = (size_t)n_jobs * 9 * (size_t)H * W * sizeof(float);
-    double* part = (double*)((char*)ws + ((maps + 255) & ~(size_t)255));
-    hipLaunchKernelGGL(k_ssim_maps, grid, blk, 0, s, H, W, rgb, t_rgb, dmap, part);
-    hipLaunchKernelGGL(k_ssim_grad, grid, blk, 0, s, H, W, rgb, t_rgb, dmap, part, (double)w_ssim, g_rgb, loss);
+    return (double*)((char*)ws + ((maps + 255) & ~(size_t)255));
+}
+
+// The two launches of the SSIM term; with cnt (n_jobs * ssim_tiles entries)
+// the first also counts the valid target depths and clears the loss, so that
+// the L1 launch can run between the two without a counting pass of its own.
+void launch_ssim_maps(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, void* ws,
+                      const float* t_depth, uint32_t* cnt, double* loss, hipStream_t s) {
+    const dim3 grid((unsigned)(ssim_tiles(H, W) * 3 * n_jobs)), blk(256);
+    hipLaunchKernelGGL(k_ssim_maps, grid, blk, 0, s, H, W, rgb, t_rgb, (float*)ws, ssim_part(n_jobs, H, W, ws),
+                       t_depth, cnt, loss);
+}
+
+void launch_ssim_grad(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
+                      float* g_rgb, double* loss, hipStream_t s) {
+    const dim3 grid((unsigned)(ssim_tiles(H, W) * 3 * n_jobs)), blk(256);
+    hipLaunchKernelGGL(k_ssim_grad, grid, blk, 0, s, H, W, rgb, t_rgb, (const float*)ws,
+                       ssim_part(n_jobs, H, W, ws), (double)w_ssim, g_rgb, loss);
 }
 
 }  // namespace sgad

@@ -26,10 +26,11 @@ bool launch_bwd(const Geometry& G, const RenderBufs& B, const float* g_rgb, cons
 void launch_bwd_finish(const Geometry& G, const KfGradPtrs* grads, uint32_t lo, uint32_t hi, float* acc,
                        const float* pose_part, float* d_pose, hipStream_t s);
 void launch_l1(int n_jobs, int P, const float* rgb, const float* dep, const float* t_rgb, const float* t_dep,
-               float w_rgb, float w_dep, uint32_t* count, float* g_rgb, float* g_dep, double* loss,
+               float w_rgb, float w_dep, uint32_t* count, int nparts, float* g_rgb, float* g_dep, double* loss,
                hipStream_t s);
 int l1_blocks(int P);
 size_t ssim_map_bytes(int n_jobs, int H, int W);
+size_t ssim_tiles(int H, int W);
 int gicp_grid_points(int H, int W, int R);
 int gicp_blocks(int n);
 int gicp_vals();
@@ -47,8 +48,10 @@ void launch_gmap_insert(const sgad_gmap& m, const double* set, int n, const doub
 void launch_fill_depth(int P, const float* depth, const float* rdepth, const float* ralpha, float alpha_min,
                        float* out, hipStream_t s);
 void launch_gicp_solve(const double* part, int nb, double* pose, double* trace, int it, hipStream_t s);
-void launch_ssim(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
-                 float* g_rgb, double* loss, hipStream_t s);
+void launch_ssim_maps(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, void* ws,
+                      const float* t_depth, uint32_t* cnt, double* loss, hipStream_t s);
+void launch_ssim_grad(int n_jobs, int H, int W, const float* rgb, const float* t_rgb, float w_ssim, void* ws,
+                      float* g_rgb, double* loss, hipStream_t s);
 void launch_adam(AdamGroups& A, float b1, float b2, float eps, float c1, float c2, int zero_grad,
                  float* cdev, hipStream_t s);
 bool launch_conv_fwd(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* bias,
@@ -1034,7 +1037,7 @@ sgad_status sgad_l1_loss(sgad_ctx* c, int n_jobs, int H, int W, const float* rgb
     HIPCHK(c, ensure_c(c, c->scratch, (size_t)n_jobs * l1_blocks(H * W) * 4, s));
     uint32_t* cnt = (uint32_t*)c->scratch.p;
     TimeScope ts(c, "l1_loss", s);
-    launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, g_rgb, g_depth, loss, s);
+    launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, 0, g_rgb, g_depth, loss, s);
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
 }
@@ -1052,16 +1055,27 @@ sgad_status sgad_eq1_loss(sgad_ctx* c, int n_jobs, int H, int W, const float* rg
     hipStream_t s = pick_stream(c, stream);
     HIPCHK(c, hipSetDevice(c->device));
     if ((int64_t)H * W > INT32_MAX / 2) return fail(c, SGAD_ERANGE, "image too large");
-    HIPCHK(c, ensure_c(c, c->scratch, (size_t)n_jobs * l1_blocks(H * W) * 4, s));
+    // valid-depth counts: one per (job, L1 block), or per (job, SSIM tile)
+    // when the SSIM maps count them
+    const size_t nparts = w_ssim != 0.f ? ssim_tiles(H, W) : (size_t)l1_blocks(H * W);
+    HIPCHK(c, ensure_c(c, c->scratch, (size_t)n_jobs * nparts * 4, s));
     if (w_ssim != 0.f) HIPCHK(c, ensure_c(c, c->ssim_maps, ssim_map_bytes(n_jobs, H, W), s));
     uint32_t* cnt = (uint32_t*)c->scratch.p;
-    {
-        TimeScope ts(c, "l1_loss", s);
-        launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, g_rgb, g_depth, loss, s);
-    }
     if (w_ssim != 0.f) {
-        TimeScope ts(c, "ssim_loss", s);
-        launch_ssim(n_jobs, H, W, rgb, t_rgb, w_ssim, c->ssim_maps.p, g_rgb, loss, s);
+        {
+            TimeScope ts(c, "ssim_maps", s);
+            launch_ssim_maps(n_jobs, H, W, rgb, t_rgb, c->ssim_maps.p, t_depth, cnt, loss, s);
+        }
+        {
+            TimeScope ts(c, "l1_loss", s);
+            launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, (int)nparts, g_rgb, g_depth,
+                      loss, s);
+        }
+        TimeScope ts(c, "ssim_grad", s);
+        launch_ssim_grad(n_jobs, H, W, rgb, t_rgb, w_ssim, c->ssim_maps.p, g_rgb, loss, s);
+    } else {
+        TimeScope ts(c, "l1_loss", s);
+        launch_l1(n_jobs, H * W, rgb, depth, t_rgb, t_depth, w_rgb, w_depth, cnt, 0, g_rgb, g_depth, loss, s);
     }
     HIPCHK(c, hipGetLastError());
     return SGAD_OK;
