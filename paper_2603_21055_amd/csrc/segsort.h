@@ -26,7 +26,17 @@ constexpr int kSortLds = 4096;
 // then the rows swapped).  Every lane of the wave takes part.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+    // every lane is written from a lane of its own row: no old value needed
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+
+// Two DPP moves into one register, each writing only its banks (groups of
+// four lanes in a row): lanes whose partner is N lanes up take row_shl:N,
+// the others row_shr:N, with no select between the two.
+template <int CTRL_A, int BANKS_A, int CTRL_B, int BANKS_B>
+__device__ __forceinline__ uint32_t dpp_banks(uint32_t v) {
+    const int t = __builtin_amdgcn_mov_dpp((int)v, CTRL_A, 0xF, BANKS_A, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, CTRL_B, 0xF, BANKS_B, false);
 }
 
 __device__ __forceinline__ uint32_t xor_rows16(uint32_t v, int lane) {
@@ -44,14 +54,10 @@ __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int lane) {
     if constexpr (M == 1) return dpp_u32<0xB1>(v);          // quad_perm [1, 0, 3, 2]
     else if constexpr (M == 2) return dpp_u32<0x4E>(v);     // quad_perm [2, 3, 0, 1]
     else if constexpr (M == 3) return dpp_u32<0x1B>(v);     // quad_perm [3, 2, 1, 0]
-    else if constexpr (M == 4) {
-        const uint32_t up = dpp_u32<0x104>(v), dn = dpp_u32<0x114>(v);   // row_shl:4, row_shr:4
-        return (lane & 4) ? dn : up;
-    } else if constexpr (M == 7) return dpp_u32<0x141>(v);  // row_half_mirror
-    else if constexpr (M == 8) {
-        const uint32_t up = dpp_u32<0x108>(v), dn = dpp_u32<0x118>(v);   // row_shl:8, row_shr:8
-        return (lane & 8) ? dn : up;
-    } else if constexpr (M == 15) return dpp_u32<0x140>(v);  // row_mirror
+    else if constexpr (M == 4) return dpp_banks<0x104, 0x5, 0x114, 0xA>(v);   // row_shl:4 / row_shr:4
+    else if constexpr (M == 7) return dpp_u32<0x141>(v);  // row_half_mirror
+    else if constexpr (M == 8) return dpp_banks<0x108, 0x3, 0x118, 0xC>(v);   // row_shl:8 / row_shr:8
+    else if constexpr (M == 15) return dpp_u32<0x140>(v);  // row_mirror
     else if constexpr (M == 16) return xor_rows16(v, lane);
     else if constexpr (M == 31) return xor_rows16(dpp_u32<0x140>(v), lane);
     else if constexpr (M == 32) return xor_rows32(v, lane);
@@ -77,16 +83,33 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int lane) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// One side of a compare-exchange across lanes: lanes marked `upper` keep the
+// larger of their key x and their partner's key y, the others the smaller.
+// One comparison and one select (keys are unique but for the all-ones
+// padding, so a tie keeps an equal value).
+__device__ __forceinline__ uint64_t keep_side(uint64_t x, uint64_t y, bool upper) {
+    return ((y < x) != upper) ? y : x;
+}
+
+// A compare-exchange of two registers of one lane: a, b = min, max.  The
+// swap flag is xored with a false the compiler cannot see through, so that
+// both selects use the one comparison instead of becoming a min and a max
+// that compare again.
+__device__ __forceinline__ void cx_in_lane(uint64_t& a, uint64_t& b) {
+    int z;
+    asm("s_mov_b32 %0, 0" : "=s"(z));
+    const bool sw = (b < a) != (z != 0);
+    const uint64_t lo = sw ? b : a, hi = sw ? a : b;
+    a = lo;
+    b = hi;
+}
+
 template <int K>
 __device__ __forceinline__ void sort_in_lane(uint64_t (&x)[K], int j) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         const int p = r ^ j;
-        if (p > r) {
-            const uint64_t a = x[r], b = x[p];
-            x[r] = a < b ? a : b;
-            x[p] = a < b ? b : a;
-        }
+        if (p > r) cx_in_lane(x[r], x[p]);
     }
 }
 
@@ -98,12 +121,9 @@ __device__ __forceinline__ void bitonic_steps(uint64_t (&x)[K], int lane) {
         sort_in_lane<K>(x, J);
     } else {
         constexpr int lm = J / K;
-        const bool lower = (lane & lm) == 0;
+        const bool upper = (lane & lm) != 0;
 #pragma unroll
-        for (int r = 0; r < K; ++r) {
-            const uint64_t y = shfl_xor_u64<lm, DPP>(x[r], lane);
-            x[r] = lower ? (x[r] < y ? x[r] : y) : (x[r] < y ? y : x[r]);
-        }
+        for (int r = 0; r < K; ++r) x[r] = keep_side(x[r], shfl_xor_u64<lm, DPP>(x[r], lane), upper);
     }
     if constexpr (J > 1) bitonic_steps<K, J / 2, DPP>(x, lane);
 }
@@ -116,24 +136,20 @@ __device__ __forceinline__ void bitonic_stages(uint64_t (&x)[K], int lane) {
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             const int p = r ^ (KS - 1);
-            if (p > r) {
-                const uint64_t a = x[r], b = x[p];
-                x[r] = a < b ? a : b;
-                x[p] = a < b ? b : a;
-            }
+            if (p > r) cx_in_lane(x[r], x[p]);
         }
     } else {
         // mirror step across lanes: (lane, r) <-> (lane ^ (KS / K - 1), K - 1 - r),
         // taken in register pairs (r, K - 1 - r)
         constexpr int lm = KS / K - 1;
-        const bool lower = (lane & (KS / (2 * K))) == 0;
+        const bool upper = (lane & (KS / (2 * K))) != 0;
 #pragma unroll
         for (int r = 0; r < (K + 1) / 2; ++r) {
             const int q = K - 1 - r;
             const uint64_t ya = shfl_xor_u64<lm, DPP>(x[q], lane);
             const uint64_t yb = shfl_xor_u64<lm, DPP>(x[r], lane);
-            x[r] = lower ? (x[r] < ya ? x[r] : ya) : (x[r] < ya ? ya : x[r]);
-            if (q != r) x[q] = lower ? (x[q] < yb ? x[q] : yb) : (x[q] < yb ? yb : x[q]);
+            x[r] = keep_side(x[r], ya, upper);
+            if (q != r) x[q] = keep_side(x[q], yb, upper);
         }
     }
     if constexpr (KS >= 4) bitonic_steps<K, KS / 4, DPP>(x, lane);
