@@ -95,11 +95,15 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Row pass over the patch: thread t < 4 * kSsimE filters row t / 4 for the
-// four outputs 4 (t % 4) .. 4 (t % 4) + 3, each of the 14 inputs loaded,
-// converted and (for the maps) squared once for the four outputs it feeds.
-// Every output sums its 11 taps in tap order, as a one-output loop would.
-constexpr int kRowItems = kSsimE * (kSsimT / 4);
+// Row pass over the patch: thread t < kRowItems filters row t / kRowThreads
+// for the kRowOut outputs starting at kRowOut (t % kRowThreads), each of the
+// 10 + kRowOut inputs loaded, converted and (for the maps) squared once for
+// the outputs it feeds.  Every output sums its 11 taps in tap order, as a
+// one-output loop would.
+constexpr int kRowOut = 4;
+constexpr int kRowThreads = kSsimT / kRowOut;   // items per patch row
+constexpr int kRowItems = kSsimE * kRowThreads;
+static_assert(kRowItems <= 256, "one row item per thread of the 256-thread block");
 
 // One block per (plane, tile), plane z = colour channel z % 3 of job z / 3.
 // dmap [n_jobs * 3][3][H][W]; part[z][tile] = the tile's SSIM sum (written;
@@ -130,14 +134,14 @@ __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __
     ssim_load<2>(H, W, st, src, s_in);
     __syncthreads();
     if (threadIdx.x < kRowItems) {
-        const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 4;
-        double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, ss[4] = {0, 0, 0, 0}, xy[4] = {0, 0, 0, 0};
+        const int r = threadIdx.x / kRowThreads, c0 = (threadIdx.x % kRowThreads) * kRowOut;
+        double a[kRowOut] = {}, b[kRowOut] = {}, ss[kRowOut] = {}, xy[kRowOut] = {};
 #pragma unroll
-        for (int j = 0; j < 2 * kSsimR + 4; ++j) {
+        for (int j = 0; j < 2 * kSsimR + kRowOut; ++j) {
             const double x = (double)s_in[0][r][c0 + j], y = (double)s_in[1][r][c0 + j];
             const double s2 = x * x + y * y, xyv = x * y;
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
+            for (int o = 0; o < kRowOut; ++o) {
                 const int k = j - o;
                 if (k < 0 || k > 2 * kSsimR) continue;
                 const double g = s_g[k];
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(256) void k_ssim_maps(int H, int W, const float* __
             }
         }
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
+        for (int o = 0; o < kRowOut; ++o) {
             s_h[0][r][c0 + o] = a[o];
             s_h[1][r][c0 + o] = b[o];
             s_h[2][r][c0 + o] = ss[o];
@@ -228,14 +232,14 @@ __global__ __launch_bounds__(256) void k_ssim_grad(int H, int W, const float* __
     ssim_load<3>(H, W, st, src, s_in);
     __syncthreads();
     if (threadIdx.x < kRowItems) {
-        const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 4;
-        double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, d[4] = {0, 0, 0, 0};
+        const int r = threadIdx.x / kRowThreads, c0 = (threadIdx.x % kRowThreads) * kRowOut;
+        double a[kRowOut] = {}, b[kRowOut] = {}, d[kRowOut] = {};
 #pragma unroll
-        for (int j = 0; j < 2 * kSsimR + 4; ++j) {
+        for (int j = 0; j < 2 * kSsimR + kRowOut; ++j) {
             const double u = (double)s_in[0][r][c0 + j], v = (double)s_in[1][r][c0 + j],
                          w = (double)s_in[2][r][c0 + j];
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
+            for (int o = 0; o < kRowOut; ++o) {
                 const int k = j - o;
                 if (k < 0 || k > 2 * kSsimR) continue;
                 const double g = s_g[k];
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(256) void k_ssim_grad(int H, int W, const float* __
             }
         }
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
+        for (int o = 0; o < kRowOut; ++o) {
             s_h[0][r][c0 + o] = a[o];
             s_h[1][r][c0 + o] = b[o];
             s_h[2][r][c0 + o] = d[o];
