@@ -57,7 +57,7 @@ __device__ __forceinline__ void publish_chunk(const ChunkRegs& c, bool valid, in
     if (valid) {
         const float4 eu = c.r0, eg = c.r1;
         se[lane][0] = eu;
-        se[lane][1] = eg;
+        se[lane][1] = make_float4(eg.x, eg.y + eg.y, eg.z, eg.w);   // b staged doubled
         se[lane][2] = c.r2;
         const float mx = (eu.x - fx0) + eu.z, my = (eu.y - fy0) + eu.w;
         const float det = eg.x * eg.z - eg.y * eg.y;
@@ -191,8 +191,8 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
                 const float4 eu1 = s_e[b1][0], eg1 = s_e[b1][1], ec1 = s_e[b1][2];
                 const float dx0 = (fpx - eu0.x) - eu0.z, dy0 = (fpy - eu0.y) - eu0.w;
                 const float dx1 = (fpx - eu1.x) - eu1.z, dy1 = (fpy - eu1.y) - eu1.w;
-                const float q0 = pair_q(dx0, dy0, eg0.x, eg0.y, eg0.z);
-                const float q1 = pair_q(dx1, dy1, eg1.x, eg1.y, eg1.z);
+                const float q0 = pair_q2b(dx0, dy0, eg0.x, eg0.y, eg0.z);
+                const float q1 = pair_q2b(dx1, dy1, eg1.x, eg1.y, eg1.z);
                 const float al0 = fminf(kAlphaMax, eg0.w * gauss_of_q(q0));
                 const float al1 = fminf(kAlphaMax, eg1.w * gauss_of_q(q1));
                 const bool v0 = q0 <= kQCut && al0 >= kAlphaMin;
@@ -317,8 +317,8 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
                 const float4 eu1 = s_e[e1][0], eg1 = s_e[e1][1], ec1 = s_e[e1][2];
                 const float dx0 = (fpx - eu0.x) - eu0.z, dy0 = (fpy - eu0.y) - eu0.w;
                 const float dx1 = (fpx - eu1.x) - eu1.z, dy1 = (fpy - eu1.y) - eu1.w;
-                const float q0 = pair_q(dx0, dy0, eg0.x, eg0.y, eg0.z);
-                const float q1 = pair_q(dx1, dy1, eg1.x, eg1.y, eg1.z);
+                const float q0 = pair_q2b(dx0, dy0, eg0.x, eg0.y, eg0.z);
+                const float q1 = pair_q2b(dx1, dy1, eg1.x, eg1.y, eg1.z);
                 const float al0 = fminf(kAlphaMax, eg0.w * gauss_of_q(q0));
                 const float al1 = fminf(kAlphaMax, eg1.w * gauss_of_q(q1));
                 const bool v0 = q0 <= kQCut && al0 >= kAlphaMin;
@@ -368,14 +368,16 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
 // sub-chunks of SUB entries from the back, in two phases per sub-chunk:
 //  A (lane = pixel): the reverse walk over the pixel's candidates carries the
 //    transmittance and the suffix colour sums and stores, per contributing
-//    pair, w = alpha T and gq = dL/dq into a [pixel][entry] LDS matrix;
+//    pair, w = alpha T and gq = -2 dL/dq into a [pixel][entry] LDS matrix;
 //  B (lane = entry, 64 / SUB lanes per entry): 64-bit ballots turn the
 //    per-pixel contribution masks into per-entry pixel sets, and each lane sums
 //    its entry's pairs over the contributing pixels of its columns.
 // The per-entry sums are gq-weighted moments of (dx, dy) and gradient-weighted
-// sums of w; the conic enters after the sum.  No LDS location is written by two
-// lanes at once, and the in-tile summation order is fixed.  After a chunk, lane
-// e applies the chain rule of entry e from the record it gathered.
+// sums of w; the conic and the factor -1/2 of dL/dq enter after the sum (a
+// power of two, so the results are those of scaling each term).  No LDS
+// location is written by two lanes at once, and the in-tile summation order
+// is fixed.  After a chunk, lane e applies the chain rule of entry e from the
+// record it gathered.
 template <int SUB>
 __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A) {
     constexpr int NS = 64 / SUB;        // sub-chunks per chunk = pixel groups in phase B
@@ -417,9 +419,10 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     const float fpx = (float)px, fpy = (float)py;
     const float fx0 = (float)(ti.tx * 8), fy0 = (float)(ti.ty * 8);
     const int sub = lane & (SUB - 1), grp = lane / SUB;
-    // g . S: the upstream colour/depth gradient dotted with the suffix sum of
-    // w c over the later contributors, carried as one scalar
-    float GS = 0.f;
+    // g . S - gA T_final, carried as one scalar: g . S is the upstream
+    // colour/depth gradient dotted with the suffix sum of w c over the later
+    // contributors
+    float H = -gATf;
     float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     wave_lds_sync();
     // the view's focal lengths (every pair of a job shares the view)
@@ -448,7 +451,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
         const int n = min(64, maxlast - c0);
         if (lane < n) {
             s_e[lane][0] = c0r;
-            s_e[lane][1] = c1r;
+            s_e[lane][1] = make_float4(c1r.x, c1r.y + c1r.y, c1r.z, c1r.w);   // b staged doubled
             s_e[lane][2] = c2r;
         }
         wave_lds_sync();
@@ -467,44 +470,47 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
             // phase A: reverse walk of this pixel's contributors in the sub-chunk
             // (the forward's decisions), two per round
             const int cut = lim - s * SUB;
-            uint32_t m = cut <= 0 ? 0u : (uint32_t)((mine >> (s * SUB)) & low_bits(min(cut, SUB)));
-            uint32_t cmask = 0u;   // entries of the sub-chunk this pixel contributed to
+            // entries of the sub-chunk this pixel contributed to
+            const uint32_t cmask = cut <= 0 ? 0u : (uint32_t)((mine >> (s * SUB)) & low_bits(min(cut, SUB)));
             // dL/dalpha = sum_c g_c (c T - S_c / (1 - alpha)) + gA T_final / (1 - alpha)
             //           = T (g . c) - (g . S - gA T_final) / (1 - alpha)
             // cell `bit` of the pixel's matrix row gets (w, gq); the row's
             // padding cell (bit = SUB) takes the write of an absent second
-            // candidate, whose alpha 0 leaves T and g . S exactly as they are
+            // candidate, whose alpha 0 leaves T and H exactly as they are
             auto contribute = [&](float alpha, float raw, float4 c, int bit) {
                 const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
                 T = T * inv;
                 const float w = alpha * T;
                 const float gc = gC0 * c.x + gC1 * c.y + gC2 * c.z + gD * c.w;
-                const float gal = T * gc - inv * (GS - gATf);
-                GS += w * gc;
-                const float gq = raw < kAlphaMax ? -0.5f * alpha * gal : 0.f;
+                const float gal = T * gc - inv * H;
+                H += w * gc;
+                const float gq = raw < kAlphaMax ? alpha * gal : 0.f;   // -2 dL/dq
                 *(float2*)&s_M[lane * LS + 2 * bit] = make_float2(w, gq);
             };
+            // walked from its last entry: bit-reversed, the next entry is the
+            // lowest set bit
+            uint32_t m = __builtin_bitreverse32(cmask);
             while (m != 0u) {
-                const int b0 = 31 - (int)__builtin_clz(m);
-                m &= ~(1u << b0);
+                const int z0 = (int)__builtin_ctz(m);
+                m &= m - 1u;
                 const bool two = m != 0u;
-                const int b1 = two ? 31 - (int)__builtin_clz(m) : b0;
-                m &= ~(1u << b1);
+                const int z1 = two ? (int)__builtin_ctz(m) : z0;
+                m &= m - 1u;
+                const int b0 = 31 - z0, b1 = 31 - z1;
                 const float4* r0 = s_e[s * SUB + b0];
                 const float4* r1 = s_e[s * SUB + b1];
                 const float4 eu0 = r0[0], eg0 = r0[1], ec0 = r0[2];
                 const float4 eu1 = r1[0], eg1 = r1[1], ec1 = r1[2];
                 const float dx0 = (fpx - eu0.x) - eu0.z, dy0 = (fpy - eu0.y) - eu0.w;
                 const float dx1 = (fpx - eu1.x) - eu1.z, dy1 = (fpy - eu1.y) - eu1.w;
-                const float q0 = pair_q(dx0, dy0, eg0.x, eg0.y, eg0.z);
-                const float q1 = pair_q(dx1, dy1, eg1.x, eg1.y, eg1.z);
+                const float q0 = pair_q2b(dx0, dy0, eg0.x, eg0.y, eg0.z);
+                const float q1 = pair_q2b(dx1, dy1, eg1.x, eg1.y, eg1.z);
                 const float raw0 = eg0.w * gauss_of_q(q0);
                 const float raw1 = eg1.w * gauss_of_q(q1);
                 const float al0 = fminf(kAlphaMax, raw0);
                 const float al1 = two ? fminf(kAlphaMax, raw1) : 0.f;
                 contribute(al0, raw0, ec0, b0);
                 contribute(al1, raw1, ec1, two ? b1 : SUB);
-                cmask |= (1u << b0) | (1u << b1);
             }
             // transpose the contributions: lane (grp, sub) takes the pixel set
             // of entry `sub` (one ballot per entry, published by lane 0)
@@ -570,12 +576,13 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
             if (any) {
                 const float4 eg = c1r;
                 float v[10];
-                v[0] = -2.f * (eg.x * r[5] + eg.y * r[6]);
-                v[1] = -2.f * (eg.y * r[5] + eg.z * r[6]);
-                v[2] = r[7];
-                v[3] = 2.f * r[8];
-                v[4] = r[9];
-                v[5] = r[4] != 0.f ? -2.f * r[4] / eg.w : 0.f;
+                // r[4..9] hold -2 x the dL/dq-weighted sums
+                v[0] = eg.x * r[5] + eg.y * r[6];
+                v[1] = eg.y * r[5] + eg.z * r[6];
+                v[2] = -0.5f * r[7];
+                v[3] = -r[8];
+                v[4] = -0.5f * r[9];
+                v[5] = r[4] != 0.f ? r[4] / eg.w : 0.f;
                 v[6] = r[3];
                 v[7] = r[0];
                 v[8] = r[1];

@@ -38,6 +38,14 @@ __device__ __forceinline__ float pair_q(float dx, float dy, float a, float b, fl
     return __builtin_fmaf(dx, t, (c * dy) * dy);
 }
 
+// The same with the conic's b given doubled (b2 = b + b, an exact product,
+// so the result is bit for bit pair_q's); the wave-tile walks stage b2.
+__device__ __forceinline__ float pair_q2b(float dx, float dy, float a, float b2, float c) {
+#pragma clang fp contract(off)
+    const float t = __builtin_fmaf(b2, dy, a * dx);
+    return __builtin_fmaf(dx, t, (c * dy) * dy);
+}
+
 __device__ __forceinline__ float gauss_of_q(float q) {
 #pragma clang fp contract(off)
     return __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
