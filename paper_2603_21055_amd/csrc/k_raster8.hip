@@ -201,14 +201,17 @@ __global__ __launch_bounds__(64) void k_fwd8(Geometry G, RenderBufs B, FwdOut O)
                 // T and the sums exactly as they are
                 const int ap = composite2(v0 ? al0 : 0.f, ec0, v1 ? al1 : 0.f, ec1, T, cr, cg, cb, dd);
                 const bool u0 = v0 && ap >= 1, u1 = v1 && ap == 2;
-                cnt += (u0 ? 1 : 0) + (u1 ? 1 : 0);
-                last = u1 ? (uint32_t)(c0 + b1 + 1) : (u0 ? (uint32_t)(c0 + b0 + 1) : last);
                 cm |= (u0 ? 1ull << b0 : 0ull) | (u1 ? 1ull << b1 : 0ull);
                 if (ap < 2) {
                     done = true;
                     break;
                 }
             }
+        }
+        // the count and the last entry taken follow from the chunk's mask
+        if (cm != 0ull) {
+            cnt += __popcll(cm);
+            last = (uint32_t)(c0 + 64 - __builtin_clzll(cm));
         }
         B.cmask[((size_t)cs + (size_t)(c0 >> 6)) * 64 + lane] = cm;
         if (__ballot(!done) == 0ull) break;
@@ -325,8 +328,6 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
                 const bool v1 = two && q1 <= kQCut && al1 >= kAlphaMin;
                 const int ap = composite2(v0 ? al0 : 0.f, ec0, v1 ? al1 : 0.f, ec1, T, cr, cg, cb, dd);
                 const bool u0 = v0 && ap >= 1, u1 = v1 && ap == 2;
-                cnt += (u0 ? 1 : 0) + (u1 ? 1 : 0);
-                last = u1 ? (uint32_t)(c0 + e1 + 1) : (u0 ? (uint32_t)(c0 + e0 + 1) : last);
 #pragma unroll
                 for (int i = 0; i < SCH; ++i)
                     cm[i] |= ((u0 && (e0 >> 6) == i) ? 1ull << (e0 & 63) : 0ull) |
@@ -338,8 +339,13 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
             }
         }
 #pragma unroll
-        for (int i = 0; i < SCH; ++i)
+        for (int i = 0; i < SCH; ++i) {
+            if (cm[i] != 0ull) {
+                cnt += __popcll(cm[i]);
+                last = (uint32_t)(c0 + 64 * i + 64 - __builtin_clzll(cm[i]));
+            }
             if (i < nch) B.cmask[((size_t)cs + (size_t)(c0 >> 6) + i) * 64 + lane] = cm[i];
+        }
         if (__ballot(!done) == 0ull) break;
         wave_lds_sync();
     }
