@@ -368,6 +368,41 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
     B.last[jp] = last;
 }
 
+// One butterfly step of a bit-matrix transpose across lanes: lanes l and
+// l ^ S swap the off-diagonal S x S blocks of their words (block rows in the
+// lanes, block columns in the bits).
+template <int S>
+__device__ __forceinline__ uint32_t transpose_step(uint32_t x, uint32_t full, int lane) {
+    constexpr uint32_t kM = S == 16 ? 0xFFFF0000u : S == 8 ? 0xFF00FF00u : S == 4 ? 0xF0F0F0F0u
+                          : S == 2  ? 0xCCCCCCCCu : 0xAAAAAAAAu;
+    const uint32_t m = kM & full;
+    const uint32_t y = xor_lane_u32<S>(x, lane);
+    return (lane & S) ? ((x & m) | ((y >> S) & ~m)) : ((x & ~m) | ((y << S) & m));
+}
+
+// The pixel set of entry lane % SUB of a sub-chunk from every lane's SUB-bit
+// contribution mask (bit e of lane p: pixel p contributed to entry e): the
+// SUB x SUB blocks of each group of SUB lanes are transposed by butterfly
+// exchanges (after which lane j of a group holds entry j's pixels of that
+// group), then the 64 / SUB pieces of an entry are joined across the groups.
+// Every lane takes part.
+template <int SUB>
+__device__ __forceinline__ uint64_t entry_pixel_set(uint32_t x, int lane) {
+    constexpr uint32_t full = SUB == 32 ? 0xFFFFFFFFu : (1u << SUB) - 1u;
+    if constexpr (SUB == 32) x = transpose_step<16>(x, full, lane);
+    x = transpose_step<8>(x, full, lane);
+    x = transpose_step<4>(x, full, lane);
+    x = transpose_step<2>(x, full, lane);
+    x = transpose_step<1>(x, full, lane);
+    uint32_t pair = x;   // the entry's pixels 0-31 (lanes 0-31) or 32-63 (lanes 32-63)
+    if constexpr (SUB == 16) {
+        const uint32_t u = xor_rows16(x, lane);
+        pair = (lane & 16) ? (u | (x << 16)) : (x | (u << 16));
+    }
+    const uint32_t v = xor_rows32(pair, lane);
+    return (lane & 32) ? (((uint64_t)pair << 32) | v) : (((uint64_t)v << 32) | pair);
+}
+
 // Backward of one 8x8 tile per wavefront.
 //
 // The tile's list is taken in 64-entry chunks from the back, each chunk in
@@ -375,9 +410,10 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
 //  A (lane = pixel): the reverse walk over the pixel's candidates carries the
 //    transmittance and the suffix colour sums and stores, per contributing
 //    pair, w = alpha T and gq = -2 dL/dq into a [pixel][entry] LDS matrix;
-//  B (lane = entry, 64 / SUB lanes per entry): 64-bit ballots turn the
-//    per-pixel contribution masks into per-entry pixel sets, and each lane sums
-//    its entry's pairs over the contributing pixels of its columns.
+//  B (lane = entry, 64 / SUB lanes per entry): a bit-matrix transpose across
+//    lanes turns the per-pixel contribution masks into per-entry pixel sets,
+//    and each lane sums its entry's pairs over the contributing pixels of its
+//    class.
 // The per-entry sums are gq-weighted moments of (dx, dy) and gradient-weighted
 // sums of w; the conic and the factor -1/2 of dL/dq enter after the sum (a
 // power of two, so the results are those of scaling each term).  No LDS
@@ -391,8 +427,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
     __shared__ float4 s_e[64][3];
     __shared__ float4 s_pc[64];
     __shared__ int s_pof[64];
-    __shared__ __align__(16) float s_M[64 * LS];
-    __shared__ uint64_t s_eb[SUB];                 // pixel set of each sub-chunk entry   // [pixel][entry] (w, gq); a cell is read only if written
+    __shared__ __align__(16) float s_M[64 * LS];   // [pixel][entry] (w, gq); a cell is read only if written
     const int lane = threadIdx.x;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     if (item >= G.n_jobs * G.ntiles) return;
@@ -519,17 +554,9 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 contribute(al1, raw1, ec1, two ? b1 : SUB);
             }
             // transpose the contributions: lane (grp, sub) takes the pixel set
-            // of entry `sub` (one ballot per entry, published by lane 0)
-            {
-                uint64_t bal[SUB];
-#pragma unroll
-                for (int e = 0; e < SUB; ++e) bal[e] = __ballot((cmask >> e) & 1u);
-                if (lane == 0)
-#pragma unroll
-                    for (int e = 0; e < SUB; ++e) s_eb[e] = bal[e];
-            }
-            wave_lds_sync();
-            const uint64_t emask = s_eb[sub];
+            // of entry `sub`
+            const uint64_t emask = entry_pixel_set<SUB>(cmask, lane);
+            wave_lds_sync();   // phase A's matrix cells, for the other lanes
             // phase B: lane = entry s * SUB + sub; the NS lanes of an entry
             // split its contributing pixels by a checkerboard class (NS = 4:
             // (x mod 2, y mod 2); NS = 2: (x + y) mod 2), which balances
