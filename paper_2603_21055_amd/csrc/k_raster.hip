@@ -21,7 +21,7 @@ namespace sgad {
 __device__ __forceinline__ void load_entry(const Geometry& G, const RenderBufs& B, int job, uint64_t key,
                                            float4& eu, float4& eg, float4& ec) {
     const uint32_t gid = (uint32_t)key;
-    const int kf = (int)(gid / (uint32_t)G.N);
+    const int kf = kf_of_gid(G, gid);
     const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
     const int pair = B.pair_of[job * G.n_kf + kf];
     const float4* rec = B.pre.rec + 4 * ((size_t)pair * G.N + pix);

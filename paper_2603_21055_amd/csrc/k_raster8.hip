@@ -41,7 +41,7 @@ __device__ __forceinline__ void fetch_record(const Geometry& G, const RenderBufs
                                              ChunkRegs& c) {
     if (!valid) return;
     const uint32_t gid = (uint32_t)c.key;
-    const int kf = (int)(gid / (uint32_t)G.N);
+    const int kf = kf_of_gid(G, gid);
     const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
     const size_t i = (size_t)pof[kf] * G.N + pix;
     const float4* rec = B.pre.rec + 4 * i;
@@ -84,7 +84,7 @@ __device__ __forceinline__ void fetch_bwd(const Geometry& G, const RenderBufs& B
                                           float4& d) {
     if (!valid) return;
     const uint32_t gid = (uint32_t)key;
-    const int kf = (int)(gid / (uint32_t)G.N);
+    const int kf = kf_of_gid(G, gid);
     const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
     const size_t i = (size_t)pof[kf] * G.N + pix;
     const float4* rec = B.pre.rec + 4 * i;
@@ -615,13 +615,13 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 v[2] = -0.5f * r[7];
                 v[3] = -r[8];
                 v[4] = -0.5f * r[9];
-                v[5] = r[4] != 0.f ? r[4] / eg.w : 0.f;
+                v[5] = r[4] != 0.f ? r[4] * __builtin_amdgcn_rcpf(eg.w) : 0.f;
                 v[6] = r[3];
                 v[7] = r[0];
                 v[8] = r[1];
                 v[9] = r[2];
                 const uint32_t gid = (uint32_t)ck;
-                const int kf = (int)(gid / (uint32_t)G.N);
+                const int kf = kf_of_gid(G, gid);
                 if (chain_rule_vals(A, vfx, vfy, kf, c2r.w, c3r, cdr, v, pose, gv)) gidx = (int)gid;
             }
         }

@@ -78,11 +78,19 @@ struct BwdArgs {
     float* acc;
 };
 
+// Keyframe of a Gaussian id gid = kf * N + pix.  (gid + 1/2) / N has its
+// fractional part at least 1/(2N) >= 2^-32 away from an integer; gid + 1/2 is
+// exact in FP64 and the rounding of 1/N and of the product move the quotient
+// (below 64) by less than 2^-45, so truncation gives the integer quotient.
+__device__ __forceinline__ int kf_of_gid(const Geometry& G, uint32_t gid) {
+    return (int)(((double)gid + 0.5) * G.inv_n);
+}
+
 // Record of the instance `key` of job `job`.
 __device__ __forceinline__ const float4* entry_record(const Geometry& G, const RenderBufs& B, int job,
                                                       uint64_t key) {
     const uint32_t gid = (uint32_t)key;
-    const int kf = (int)(gid / (uint32_t)G.N);
+    const int kf = kf_of_gid(G, gid);
     const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
     const int pair = B.pair_of[job * G.n_kf + kf];
     return B.pre.rec + 4 * ((size_t)pair * G.N + pix);
@@ -107,12 +115,14 @@ __device__ __forceinline__ bool chain_rule_vals(const BwdArgs& A, float fx, floa
                                                 float4 d, const float* v, float* pose, float* out) {
     const float x = r3.x, y = r3.y;
     const float r = r3.z;
-    const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz, iz4 = iz2 * iz2, iz5 = iz4 * iz;
+    // hardware reciprocals (about 1 ulp), far inside the FP32 rounding of the
+    // per-entry sums these gradients are formed from
+    const float iz = __builtin_amdgcn_rcpf(z), iz2 = iz * iz, iz3 = iz2 * iz, iz4 = iz2 * iz2, iz5 = iz4 * iz;
     const float tx = x * iz, ty = y * iz, jx = fx * iz, jy = fy * iz;
     const float k00 = jx * jx * (1.f + tx * tx), k01 = jx * jy * (tx * ty), k11 = jy * jy * (1.f + ty * ty);
     const float r2 = r * r;
     const float s00 = r2 * k00 + (float)kLowpass, s01 = r2 * k01, s11 = r2 * k11 + (float)kLowpass;
-    const float idet = 1.f / (s00 * s11 - s01 * s01);
+    const float idet = __builtin_amdgcn_rcpf(s00 * s11 - s01 * s01);
     const float q00 = s11 * idet, q01 = -s01 * idet, q11 = s00 * idet;
     const float ga = v[2], hb = 0.5f * v[3], gc = v[4];
     const float m00 = ga * q00 + hb * q01, m01 = ga * q01 + hb * q11;
@@ -163,7 +173,7 @@ __device__ __forceinline__ void chain_rule(const Geometry& G, const BwdArgs& A, 
 __device__ __forceinline__ void flush_entry(const Geometry& G, const RenderBufs& B, const BwdArgs& A, int job,
                                             uint64_t key, const float* v, float* pose) {
     const uint32_t gid = (uint32_t)key;
-    const int kf = (int)(gid / (uint32_t)G.N);
+    const int kf = kf_of_gid(G, gid);
     const int pix = (int)(gid - (uint32_t)kf * (uint32_t)G.N);
     const int pair = B.pair_of[job * G.n_kf + kf];
     const size_t i = (size_t)pair * G.N + pix;

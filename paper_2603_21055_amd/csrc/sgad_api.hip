@@ -747,6 +747,7 @@ sgad_status sgad_render_fwd(sgad_ctx* c, int n_kf, const sgad_keyframe* kf, int 
     G.Hk = k0.H;
     G.Wk = k0.W;
     G.N = (int)N;
+    G.inv_n = 1.0 / (double)N;
     G.Hv = vcam[0].H;
     G.Wv = vcam[0].W;
     G.P = G.Hv * G.Wv;
@@ -1493,6 +1494,7 @@ sgad_status sgad_track_gn(sgad_ctx* c, const sgad_keyframe* geo, const sgad_cam*
     G.Hk = geo->cam.H;
     G.Wk = geo->cam.W;
     G.N = (int)N;
+    G.inv_n = 1.0 / (double)N;
     G.Hv = vcam->H;
     G.Wv = vcam->W;
     G.P = G.Hv * G.Wv;

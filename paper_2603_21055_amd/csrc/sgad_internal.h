@@ -79,6 +79,7 @@ struct Geometry {
                        // 2048 keys, 2 up to 4096
     int sc_bwd = 16;   // backward sub-chunk of the 8x8 kernels (16 or 32 entries)
     int fuse_sort = 0; // the 8x8 forward sorts its own segment (no separate sort launch)
+    double inv_n = 0.0;   // 1 / N: the keyframe of a Gaussian id without an integer division
 };
 
 struct RenderBufs {
