@@ -50,31 +50,66 @@ __device__ __forceinline__ void fetch_record(const Geometry& G, const RenderBufs
     c.r2 = rec[2];
 }
 
-// Publish a chunk in LDS (records and coverage masks).
+// One butterfly step of a bit-matrix transpose across lanes: lanes l and
+// l ^ S swap the off-diagonal S x S blocks of their words (block rows in the
+// lanes, block columns in the bits).
+template <int S>
+__device__ __forceinline__ uint32_t transpose_step(uint32_t x, uint32_t full, int lane) {
+    constexpr uint32_t kM = S == 16 ? 0xFFFF0000u : S == 8 ? 0xFF00FF00u : S == 4 ? 0xF0F0F0F0u
+                          : S == 2  ? 0xCCCCCCCCu : 0xAAAAAAAAu;
+    const uint32_t m = kM & full;
+    const uint32_t y = xor_lane_u32<S>(x, lane);
+    return (lane & S) ? ((x & m) | ((y >> S) & ~m)) : ((x & ~m) | ((y << S) & m));
+}
+
+// Column lane % SUB of the 64 x SUB bit matrix whose row l is lane l's SUB-bit
+// word x, as a 64-bit mask over the lanes: the SUB x SUB blocks of each group
+// of SUB lanes are transposed by butterfly exchanges (after which lane j of a
+// group holds column j of that group's rows), then the 64 / SUB pieces of a
+// column are joined across the groups.  Every lane takes part.
+template <int SUB>
+__device__ __forceinline__ uint64_t bit_column(uint32_t x, int lane) {
+    constexpr uint32_t full = SUB == 32 ? 0xFFFFFFFFu : (1u << SUB) - 1u;
+    if constexpr (SUB == 32) x = transpose_step<16>(x, full, lane);
+    x = transpose_step<8>(x, full, lane);
+    x = transpose_step<4>(x, full, lane);
+    x = transpose_step<2>(x, full, lane);
+    x = transpose_step<1>(x, full, lane);
+    uint32_t pair = x;   // the entry's pixels 0-31 (lanes 0-31) or 32-63 (lanes 32-63)
+    if constexpr (SUB == 16) {
+        const uint32_t u = xor_rows16(x, lane);
+        pair = (lane & 16) ? (u | (x << 16)) : (x | (u << 16));
+    }
+    const uint32_t v = xor_rows32(pair, lane);
+    return (lane & 32) ? (((uint64_t)pair << 32) | v) : (((uint64_t)v << 32) | pair);
+}
+
+// Publish a chunk in LDS (records and coverage masks).  sm[k] (k < 8) is the
+// set of the chunk's entries whose pixel rectangle covers tile column k,
+// sm[8 + k] those covering tile row k: each entry lane forms its 8 column
+// bits and 8 row bits, and one transpose across lanes gives lane j the set
+// of column j of those 16-bit rows.  The rectangle is the 3-sigma extent
+// plus 1e-3 pixels, which covers the ~1 ulp of the hardware reciprocal and
+// square root; pixels inside it are tested exactly by the walk.
 __device__ __forceinline__ void publish_chunk(const ChunkRegs& c, bool valid, int lane, float fx0, float fy0,
                                               float4 (*se)[3], uint64_t* sm) {
-    int x0 = 8, x1 = -1, y0 = 8, y1 = -1;
+    uint32_t cover = 0u;   // bits 0-7: tile columns, 8-15: tile rows
     if (valid) {
         const float4 eu = c.r0, eg = c.r1;
         se[lane][0] = eu;
         se[lane][1] = make_float4(eg.x, eg.y + eg.y, eg.z, eg.w);   // b staged doubled
         se[lane][2] = c.r2;
         const float mx = (eu.x - fx0) + eu.z, my = (eu.y - fy0) + eu.w;
-        const float det = eg.x * eg.z - eg.y * eg.y;
-        const float ex = 3.f * sqrtf(eg.z / det) + 1e-3f;
-        const float ey = 3.f * sqrtf(eg.x / det) + 1e-3f;
-        x0 = max(0, (int)ceilf(mx - ex));
-        x1 = min(7, (int)floorf(mx + ex));
-        y0 = max(0, (int)ceilf(my - ey));
-        y1 = min(7, (int)floorf(my + ey));
+        const float idet = __builtin_amdgcn_rcpf(eg.x * eg.z - eg.y * eg.y);
+        const float ex = 3.f * __builtin_amdgcn_sqrtf(eg.z * idet) + 1e-3f;
+        const float ey = 3.f * __builtin_amdgcn_sqrtf(eg.x * idet) + 1e-3f;
+        const int x0 = max(0, (int)ceilf(mx - ex)), x1 = min(7, (int)floorf(mx + ex));
+        const int y0 = max(0, (int)ceilf(my - ey)), y1 = min(7, (int)floorf(my + ey));
+        if (x0 <= x1 && y0 <= y1)
+            cover = ((0xFFu << x0) & (0xFFu >> (7 - x1))) | (((0xFFu << y0) & (0xFFu >> (7 - y1))) << 8);
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const uint64_t cm = __ballot(valid && x0 <= k && k <= x1);
-        const uint64_t rm = __ballot(valid && y0 <= k && k <= y1);
-        if (lane == k) sm[k] = cm;
-        if (lane == 8 + k) sm[8 + k] = rm;
-    }
+    const uint64_t col = bit_column<16>(cover, lane);
+    if (lane < 16) sm[lane] = col;
 }
 
 // The backward's gather of one record (separate values rather than a struct,
@@ -368,41 +403,6 @@ __global__ __launch_bounds__(64) void k_fwd8s(Geometry G, RenderBufs B, FwdOut O
     B.last[jp] = last;
 }
 
-// One butterfly step of a bit-matrix transpose across lanes: lanes l and
-// l ^ S swap the off-diagonal S x S blocks of their words (block rows in the
-// lanes, block columns in the bits).
-template <int S>
-__device__ __forceinline__ uint32_t transpose_step(uint32_t x, uint32_t full, int lane) {
-    constexpr uint32_t kM = S == 16 ? 0xFFFF0000u : S == 8 ? 0xFF00FF00u : S == 4 ? 0xF0F0F0F0u
-                          : S == 2  ? 0xCCCCCCCCu : 0xAAAAAAAAu;
-    const uint32_t m = kM & full;
-    const uint32_t y = xor_lane_u32<S>(x, lane);
-    return (lane & S) ? ((x & m) | ((y >> S) & ~m)) : ((x & ~m) | ((y << S) & m));
-}
-
-// The pixel set of entry lane % SUB of a sub-chunk from every lane's SUB-bit
-// contribution mask (bit e of lane p: pixel p contributed to entry e): the
-// SUB x SUB blocks of each group of SUB lanes are transposed by butterfly
-// exchanges (after which lane j of a group holds entry j's pixels of that
-// group), then the 64 / SUB pieces of an entry are joined across the groups.
-// Every lane takes part.
-template <int SUB>
-__device__ __forceinline__ uint64_t entry_pixel_set(uint32_t x, int lane) {
-    constexpr uint32_t full = SUB == 32 ? 0xFFFFFFFFu : (1u << SUB) - 1u;
-    if constexpr (SUB == 32) x = transpose_step<16>(x, full, lane);
-    x = transpose_step<8>(x, full, lane);
-    x = transpose_step<4>(x, full, lane);
-    x = transpose_step<2>(x, full, lane);
-    x = transpose_step<1>(x, full, lane);
-    uint32_t pair = x;   // the entry's pixels 0-31 (lanes 0-31) or 32-63 (lanes 32-63)
-    if constexpr (SUB == 16) {
-        const uint32_t u = xor_rows16(x, lane);
-        pair = (lane & 16) ? (u | (x << 16)) : (x | (u << 16));
-    }
-    const uint32_t v = xor_rows32(pair, lane);
-    return (lane & 32) ? (((uint64_t)pair << 32) | v) : (((uint64_t)v << 32) | pair);
-}
-
 // Backward of one 8x8 tile per wavefront.
 //
 // The tile's list is taken in 64-entry chunks from the back, each chunk in
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
             }
             // transpose the contributions: lane (grp, sub) takes the pixel set
             // of entry `sub`
-            const uint64_t emask = entry_pixel_set<SUB>(cmask, lane);
+            const uint64_t emask = bit_column<SUB>(cmask, lane);
             wave_lds_sync();   // phase A's matrix cells, for the other lanes
             // phase B: lane = entry s * SUB + sub; the NS lanes of an entry
             // split its contributing pixels by a checkerboard class (NS = 4:
