@@ -372,27 +372,26 @@ __global__ __launch_bounds__(256) void k_track8(Geometry G, RenderBufs B, const 
     uint64_t key = lane < len ? B.keys[st + lane] : 0ull;
     for (int c0 = 0; c0 < len; c0 += 64) {
         const int n = min(64, len - c0);
-        int x0 = 8, x1 = -1, y0 = 8, y1 = -1;
+        // tile columns (bits 0-7) and rows (bits 8-15) the entry's 3-sigma
+        // rectangle (plus 1e-3 px, which covers the hardware reciprocal and
+        // square root) overlaps; sm[k] / sm[8 + k]: the entries covering
+        // column / row k, by one transpose across lanes
+        uint32_t cover = 0u;
         if (lane < n) {
             TrackEntry e;
             load_track_entry(G, B, key, e);
             se[lane] = e;
             const float mx = (e.u.x - fx0) + e.u.z, my = (e.u.y - fy0) + e.u.w;
-            const float det = e.g.x * e.g.z - e.g.y * e.g.y;
-            const float ex = 3.f * sqrtf(e.g.z / det) + 1e-3f;
-            const float ey = 3.f * sqrtf(e.g.x / det) + 1e-3f;
-            x0 = max(0, (int)ceilf(mx - ex));
-            x1 = min(7, (int)floorf(mx + ex));
-            y0 = max(0, (int)ceilf(my - ey));
-            y1 = min(7, (int)floorf(my + ey));
+            const float idet = __builtin_amdgcn_rcpf(e.g.x * e.g.z - e.g.y * e.g.y);
+            const float ex = 3.f * __builtin_amdgcn_sqrtf(e.g.z * idet) + 1e-3f;
+            const float ey = 3.f * __builtin_amdgcn_sqrtf(e.g.x * idet) + 1e-3f;
+            const int x0 = max(0, (int)ceilf(mx - ex)), x1 = min(7, (int)floorf(mx + ex));
+            const int y0 = max(0, (int)ceilf(my - ey)), y1 = min(7, (int)floorf(my + ey));
+            if (x0 <= x1 && y0 <= y1)
+                cover = ((0xFFu << x0) & (0xFFu >> (7 - x1))) | (((0xFFu << y0) & (0xFFu >> (7 - y1))) << 8);
         }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint64_t cm = __ballot(lane < n && x0 <= k && k <= x1);
-            const uint64_t rm = __ballot(lane < n && y0 <= k && k <= y1);
-            if (lane == k) sm[k] = cm;
-            if (lane == 8 + k) sm[8 + k] = rm;
-        }
+        const uint64_t col = bit_column<16>(cover, lane);
+        if (lane < 16) sm[lane] = col;
         wave_lds_sync();   // (this wave's own LDS region)
         // the next chunk's key while this one is walked
         key = lane < len - c0 - 64 ? B.keys[st + (uint32_t)(c0 + 64 + lane)] : 0ull;

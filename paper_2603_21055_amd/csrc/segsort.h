@@ -1,5 +1,8 @@
-// Segment sort of 64-bit instance keys by one wavefront (shared by the sort
-// kernel and the wave-tile forward, which sorts its own tile's segment).
+// Cross-lane exchanges of a wavefront (DPP and the gfx950 row-swap permutes),
+// the segment sort of 64-bit instance keys by one wavefront (shared by the
+// sort kernel and the wave-tile forward, which sorts its own tile's segment)
+// and a bit-matrix transpose across lanes (the wave-tile walks' coverage and
+// contribution masks).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -65,6 +68,40 @@ __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int lane) {
         static_assert(M == 63, "lane mask of the bitonic network");
         return xor_rows32(xor_rows16(dpp_u32<0x140>(v), lane), lane);
     }
+}
+
+// One butterfly step of a bit-matrix transpose across lanes: lanes l and
+// l ^ S swap the off-diagonal S x S blocks of their words (block rows in the
+// lanes, block columns in the bits).
+template <int S>
+__device__ __forceinline__ uint32_t transpose_step(uint32_t x, uint32_t full, int lane) {
+    constexpr uint32_t kM = S == 16 ? 0xFFFF0000u : S == 8 ? 0xFF00FF00u : S == 4 ? 0xF0F0F0F0u
+                          : S == 2  ? 0xCCCCCCCCu : 0xAAAAAAAAu;
+    const uint32_t m = kM & full;
+    const uint32_t y = xor_lane_u32<S>(x, lane);
+    return (lane & S) ? ((x & m) | ((y >> S) & ~m)) : ((x & ~m) | ((y << S) & m));
+}
+
+// Column lane % SUB of the 64 x SUB bit matrix whose row l is lane l's SUB-bit
+// word x, as a 64-bit mask over the lanes: the SUB x SUB blocks of each group
+// of SUB lanes are transposed by butterfly exchanges (after which lane j of a
+// group holds column j of that group's rows), then the 64 / SUB pieces of a
+// column are joined across the groups.  Every lane takes part.
+template <int SUB>
+__device__ __forceinline__ uint64_t bit_column(uint32_t x, int lane) {
+    constexpr uint32_t full = SUB == 32 ? 0xFFFFFFFFu : (1u << SUB) - 1u;
+    if constexpr (SUB == 32) x = transpose_step<16>(x, full, lane);
+    x = transpose_step<8>(x, full, lane);
+    x = transpose_step<4>(x, full, lane);
+    x = transpose_step<2>(x, full, lane);
+    x = transpose_step<1>(x, full, lane);
+    uint32_t pair = x;   // the entry's pixels 0-31 (lanes 0-31) or 32-63 (lanes 32-63)
+    if constexpr (SUB == 16) {
+        const uint32_t u = xor_rows16(x, lane);
+        pair = (lane & 16) ? (u | (x << 16)) : (x | (u << 16));
+    }
+    const uint32_t v = xor_rows32(pair, lane);
+    return (lane & 32) ? (((uint64_t)pair << 32) | v) : (((uint64_t)v << 32) | pair);
 }
 
 // DPP = false: ds_bpermute shuffles instead, which cost no VALU issue slots;
