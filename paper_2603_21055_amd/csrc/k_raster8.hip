@@ -469,9 +469,9 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
         }
         const uint64_t key2 = c0 >= 128 ? B.keys[st + (uint32_t)(c0 - 128 + lane)] : 0ull;
         const int lim = min(n, last - c0);   // this pixel's entries are e < lim
-        float r[10];
-#pragma unroll
-        for (int k = 0; k < 10; ++k) r[k] = 0.f;
+        // partial sums of each sub-chunk's entries over this lane's pixel
+        // class; summed over the NS classes after the last sub-chunk
+        float acc[NS][10];
 #pragma unroll
         for (int s = NS - 1; s >= 0; --s) {
             // phase A: reverse walk of this pixel's contributors in the sub-chunk
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
             const uint64_t cls = NS == 4   ? 0x0055005500550055ull << ((grp & 1) + 8 * (grp >> 1))
                                  : NS == 2 ? (grp ? ~0xAA55AA55AA55AA55ull : 0xAA55AA55AA55AA55ull)
                                            : ~0ull;
-            float a[10];
+            float* a = acc[s];
 #pragma unroll
             for (int k = 0; k < 10; ++k) a[k] = 0.f;
             uint64_t pm = emask & cls;
@@ -556,14 +556,37 @@ __global__ __launch_bounds__(64) void k_bwd8(Geometry G, RenderBufs B, BwdArgs A
                 a[8] += u * dy;
                 a[9] += v * dy;
             }
-#pragma unroll
-            for (int o = SUB; o < 64; o <<= 1)
-#pragma unroll
-                for (int k = 0; k < 10; ++k) a[k] += __shfl_xor(a[k], o, 64);
-            if (grp == s)
-#pragma unroll
-                for (int k = 0; k < 10; ++k) r[k] = a[k];
             wave_lds_sync();
+        }
+        // reduce-scatter over the classes: lane (grp, sub) ends with the sums
+        // of entry grp * SUB + sub; each exchange halves what a lane holds
+        float r[10];
+        if constexpr (NS == 4) {
+            const bool hi32 = (lane & 32) != 0, hi16 = (lane & 16) != 0;
+            float h[2][10];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int k = 0; k < 10; ++k) {
+                    const float keep = hi32 ? acc[2 + j][k] : acc[j][k];
+                    const float send = hi32 ? acc[j][k] : acc[2 + j][k];
+                    h[j][k] = keep + __shfl_xor(send, 32, 64);
+                }
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                const float keep = hi16 ? h[1][k] : h[0][k];
+                const float send = hi16 ? h[0][k] : h[1][k];
+                r[k] = keep + __shfl_xor(send, 16, 64);
+            }
+        } else {
+            static_assert(NS == 2, "sub-chunks of 16 or 32 entries");
+            const bool hi32 = (lane & 32) != 0;
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                const float keep = hi32 ? acc[1][k] : acc[0][k];
+                const float send = hi32 ? acc[0][k] : acc[1][k];
+                r[k] = keep + __shfl_xor(send, 32, 64);
+            }
         }
         // lane = chunk entry: chain rule to the keyframe parameters and the pose
         int gidx = -1;   // the entry's keyframe Gaussian when it has parameter gradients
