@@ -83,9 +83,36 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const
     const int job = blockIdx.y;
     __shared__ uint32_t s_c[4];
     __shared__ double s_a[4];
+    const size_t jp = (size_t)job * P, j3 = (size_t)job * 3 * P;
+    const int i0 = blockIdx.x * 1024;
+    // VEC: the thread's four pixels are loaded first, so that their loads
+    // and those of the depth counts are in flight together
+    const int iv = i0 + 4 * (int)threadIdx.x;
+    const bool vin = VEC && iv < P;
+    float4 r[3], t[3], d, td;
+    if (vin) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r[c] = *reinterpret_cast<const float4*>(rgb + j3 + (size_t)c * P + iv);
+            t[c] = *reinterpret_cast<const float4*>(t_rgb + j3 + (size_t)c * P + iv);
+        }
+        d = *reinterpret_cast<const float4*>(dep + jp + iv);
+        td = *reinterpret_cast<const float4*>(t_dep + jp + iv);
+    }
     {
+        // eight count loads in flight per thread before any is waited on
         uint32_t c = 0;
-        for (int k = threadIdx.x; k < nparts; k += 256) c += part[(size_t)job * nparts + k];
+        const uint32_t* pj = part + (size_t)job * nparts;
+        for (int k0 = 0; k0 < nparts; k0 += 256 * 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u * 256 + (int)threadIdx.x;
+                v[u] = k < nparts ? pj[k] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c += v[u];
+        }
         c = wave_sum_u(c);
         if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = c;
         __syncthreads();
@@ -93,20 +120,10 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const
     const uint32_t nv = s_c[0] + s_c[1] + s_c[2] + s_c[3];
     const float inv_rgb = w_rgb / (3.f * (float)P);
     const float inv_dep = nv ? w_dep / (float)nv : 0.f;
-    const size_t jp = (size_t)job * P, j3 = (size_t)job * 3 * P;
-    const int i0 = blockIdx.x * 1024;
     double acc = 0.0;
     if (VEC) {
-        const int i = i0 + 4 * (int)threadIdx.x;
-        if (i < P) {
-            float4 r[3], t[3], g[3], gd;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                r[c] = *reinterpret_cast<const float4*>(rgb + j3 + (size_t)c * P + i);
-                t[c] = *reinterpret_cast<const float4*>(t_rgb + j3 + (size_t)c * P + i);
-            }
-            const float4 d = *reinterpret_cast<const float4*>(dep + jp + i);
-            const float4 td = *reinterpret_cast<const float4*>(t_dep + jp + i);
+        if (vin) {
+            float4 g[3], gd;
             acc += l1_pixel(r[0].x, r[1].x, r[2].x, d.x, t[0].x, t[1].x, t[2].x, td.x, inv_rgb, inv_dep, g[0].x,
                             g[1].x, g[2].x, gd.x);
             acc += l1_pixel(r[0].y, r[1].y, r[2].y, d.y, t[0].y, t[1].y, t[2].y, td.y, inv_rgb, inv_dep, g[0].y,
@@ -116,8 +133,8 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ rgb, const
             acc += l1_pixel(r[0].w, r[1].w, r[2].w, d.w, t[0].w, t[1].w, t[2].w, td.w, inv_rgb, inv_dep, g[0].w,
                             g[1].w, g[2].w, gd.w);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) *reinterpret_cast<float4*>(g_rgb + j3 + (size_t)c * P + i) = g[c];
-            *reinterpret_cast<float4*>(g_dep + jp + i) = gd;
+            for (int c = 0; c < 3; ++c) *reinterpret_cast<float4*>(g_rgb + j3 + (size_t)c * P + iv) = g[c];
+            *reinterpret_cast<float4*>(g_dep + jp + iv) = gd;
         }
     } else {
 #pragma unroll
