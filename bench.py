@@ -51,10 +51,10 @@ KERNEL_SOURCES = {
     "offsetnet_forward": ("k_conv.hip",),
 }
 PMC = {    # kernel -> counters per dispatch and the sources they were taken on
-    "composite_bwd": dict(fetch_kib=26810.2, write_kib=27550.4, tile=(8, 8), variant=(1, 16),
-                          sha="1023348c47295e9890a7a783c4161c7e24f110777a7cac0bdf2e6cff5fd830eb"),
-    "composite_fwd": dict(fetch_kib=16038.9, write_kib=29018.6, tile=(8, 8), variant=(1, 16),
-                          sha="1023348c47295e9890a7a783c4161c7e24f110777a7cac0bdf2e6cff5fd830eb"),
+    "composite_bwd": dict(fetch_kib=26810.9, write_kib=27550.4, tile=(8, 8), variant=(1, 16),
+                          sha="8ff2fb3020c100110ef593f1573357487122f3ca8905f6f761151e8a10fe9b32"),
+    "composite_fwd": dict(fetch_kib=16038.5, write_kib=29013.2, tile=(8, 8), variant=(1, 16),
+                          sha="8ff2fb3020c100110ef593f1573357487122f3ca8905f6f761151e8a10fe9b32"),
     # the warm-start net's forward at 640x480: k_net_input + the six conv
     # launches, counters summed over the seven dispatches
     "offsetnet_forward": dict(fetch_kib=67801.5, write_kib=99600.0,

@@ -95,7 +95,7 @@ __device__ __forceinline__ uint64_t bit_column(uint32_t x, int lane) {
     x = transpose_step<4>(x, full, lane);
     x = transpose_step<2>(x, full, lane);
     x = transpose_step<1>(x, full, lane);
-    uint32_t pair = x;   // the entry's pixels 0-31 (lanes 0-31) or 32-63 (lanes 32-63)
+    uint32_t pair = x;   // the column's bits of rows 0-31 (lanes 0-31) or 32-63 (lanes 32-63)
     if constexpr (SUB == 16) {
         const uint32_t u = xor_rows16(x, lane);
         pair = (lane & 16) ? (u | (x << 16)) : (x | (u << 16));
